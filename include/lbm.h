@@ -1,0 +1,163 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) shaped-EOS pseudopotential lattice
+ * Boltzmann library (liblbm.so).
+ *
+ * Method: Czelusniak, Mapelli, Cabezas Gomez, Wagner, "Shaping the equation
+ * of state to improve numerical accuracy and stability of the
+ * pseudopotential lattice Boltzmann method".  One time step is Eq. LBE with
+ * the MRT operator (Eq. OperatorMRT, Eq. MatrixMRT, Eq. RelaxationMatrix),
+ * the equilibrium of Eq. EquilibriumDistribution, the Shan-Chen force
+ * (Eq. ShanChenForce) on the pseudopotential of Eq. InteractionPotential
+ * with a shaped EOS (Sec. III.D "Smooth", Eq. PengEOS), and the forcing of
+ * Eq. LiFS (Eq. GFS at sigma = 0).
+ *
+ * Conventions common to every entry point
+ *  - Device pointers are CALLER-OWNED (typically torch tensors).  The library
+ *    never allocates or frees device memory; it keeps a small host context.
+ *  - Layouts.  Scalar fields are [ny][nx] row-major float64 (x fastest).
+ *    Population buffers are planes of [ny][ld] (ld = row pitch >= nx, chosen
+ *    by lbm_layout): for LBM_FP64, 9 float64 planes in the D2Q9 order of
+ *    Eq. VelocitySet; for LBM_FP32_SHIFTED, planes 1..8 hold float32
+ *    g_i = f_i - w_i rho_ref and a final float64 plane holds g_0 (the rest
+ *    population, kept in FP64 so that each node's mass is exact).
+ *  - The population buffers hold POST-collision values (pull streaming):
+ *    the distributions of Eq. LBE at time t are obtained by pulling from
+ *    the neighbours, with half-way bounce-back at walls.
+ *  - `stream` is a hipStream_t passed as void*; 0 means the null stream.
+ *    Calls are asynchronous unless stated.
+ *  - Return value: 0 (LBM_OK) or a negative lbm_status; lbm_last_error()
+ *    returns a thread-local message for the last failure.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* invalid argument or parameter combination */
+    LBM_EUNSTABLE = -2, /* psi^2 < 0, non-finite or non-positive density met on the device */
+    LBM_EHIP = -3,      /* a HIP runtime call failed */
+    LBM_ESTATE = -4,    /* call out of order (e.g. adjoint without checkpointing) */
+    LBM_ENOROOT = -5    /* host thermodynamics: no root in the admissible bracket */
+} lbm_status;
+
+typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_prec;
+typedef enum { LBM_BASE_CS = 0, LBM_BASE_PR = 1 } lbm_base;
+typedef enum {
+    LBM_SHAPE_NONE = 0,      /* the base EOS itself */
+    LBM_SHAPE_SMOOTH = 1,    /* Sec. III.D: ellipse / cubic / ellipse, p_max from Eq. MaxwellRule */
+    LBM_SHAPE_MODSMOOTH = 2, /* Sec. IV.C: same loop, p_max from Eq. ShanVaporLiqEq (eps = 0) */
+    LBM_SHAPE_PENG = 3       /* Eq. PengEOS with Eq. PengTheta, rho_m from Eq. ShanVaporLiqEq */
+} lbm_shape;
+
+/*
+ * Equation of state.  Inputs are set by the caller; lbm_eos_build fills the
+ * derived block (FP64, host only).  Base EOS: Carnahan-Starling (Eq. CS) or
+ * the textbook Peng-Robinson form, times `scale` (the "standard procedure"
+ * of Sec. III.B).  The shaped loop replaces the base EOS on (rho_v, rho_l);
+ * the vapor branch is k_vap times the base EOS and the liquid branch is the
+ * base EOS plus dP_liq = (k_vap - 1) p_sat (raised vapor sound speed,
+ * Sec. III.D); p_min = p_sat_new - alpha (p_sat - p_min_base).
+ */
+typedef struct {
+    /* inputs */
+    int base, shape;
+    double a, b, R, omega, Tr, scale, alpha, k_vap, r_theta;
+    /* derived by lbm_eos_build */
+    double Tc, T;
+    double rho_v, rho_l, p_sat;       /* Maxwell coexistence of the scaled base EOS */
+    double rho_max, p_max_base;       /* local maximum (spinodal) of the base EOS */
+    double rho_min, p_min_base;       /* local minimum (spinodal) of the base EOS */
+    double p_sat_new, dP_liq;
+    double slope_v, slope_l;          /* dp/drho of the shaped EOS at rho_v, rho_l */
+    double p_max, p_min;              /* interior knots (rho_max, p_max), (rho_min, p_min) */
+    double a1sq, b1, a3sq, b3;        /* ellipse coefficients of regions 1 and 3 */
+    double rho_m, theta;              /* Peng loop */
+    double eps;                       /* root of Eq. VaporLiqEq (0 for the Guo-forcing shapes) */
+} lbm_eos;
+
+/* Host precompute (Sec. III.A, III.D, IV.C): critical point, Maxwell
+ * coexistence, spinodals, shaped-loop coefficients, eps and
+ * sigma = -eps/(16 G).  G must be negative.  Returns LBM_EINVAL for bad
+ * inputs or a non-real ellipse, LBM_ENOROOT when a root is not bracketed. */
+int lbm_eos_build(lbm_eos* e, double G, double* sigma_out);
+/* Host evaluation of the built EOS p(rho) and dp/drho (FP64). */
+double lbm_eos_pressure(const lbm_eos* e, double rho);
+double lbm_eos_slope(const lbm_eos* e, double rho);
+
+typedef struct {
+    int nx, ny;          /* lattice size (nx, ny >= 1) */
+    int walls;           /* 0: periodic in y; 1: half-way bounce-back below row 0 and above row ny-1 */
+    int prec;            /* lbm_prec */
+    int var_tau;         /* 1: s[7] = s[8] = 1/tau(rho) of Eq. RelaxationTime (clamped to [tau_v, tau_l]) */
+    int reduce_every;    /* >0: FP64 mass/momentum reduction every this many steps (history in workspace) */
+    double rho_wall_lo, rho_wall_hi; /* densities of the solid nodes in Eq. ShanChenForce (walls = 1) */
+    double G, sigma;     /* interaction constant (< 0) and Eq. LiFS sigma (0 = Eq. GFS) */
+    double tau[9];       /* relaxation times, moment order of Eq. RelaxationMatrix; tau > 1/2 */
+    double tau_l, tau_v, rho_v_tau, rho_l_tau; /* Eq. RelaxationTime */
+    double rho_ref;      /* shift of the FP32 storage (LBM_FP32_SHIFTED), > 0 */
+    lbm_eos eos;         /* built by lbm_eos_build */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Layout query: row pitch, bytes of ONE population buffer (the caller
+ * allocates two), and bytes of the workspace. */
+int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* ws_bytes_out);
+
+/* Create a context over caller buffers f_a, f_b (lbm_layout bytes each) and
+ * workspace ws, and write the initial state f_i(0) = f^eq_i(rho0, u0)
+ * (Sec. III.A) into f_a.  rho0, ux0, uy0: device float64 [ny][nx]; ux0/uy0
+ * may be NULL (u = 0).  Validates parameters (LBM_EINVAL): tau > 1/2,
+ * rho_ref > 0 in FP32 mode, G < 0, buffers non-NULL and distinct. */
+int lbm_init(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes,
+             const double* rho0, const double* ux0, const double* uy0, void* stream);
+
+/* Advance nsteps time steps (Eq. LBE).  Asynchronous: device-side
+ * instability is latched in the workspace and reported by lbm_status_check
+ * or lbm_macros. */
+int lbm_step(lbm_ctx* ctx, int64_t nsteps, void* stream);
+
+/* Synchronise `stream` and return LBM_EUNSTABLE if the device error word is
+ * set (the message names the first failing step), else LBM_OK. */
+int lbm_status_check(lbm_ctx* ctx, void* stream);
+
+/* Macroscopic fields at the current time t: rho (Eq. Density), u (Eq.
+ * Momentum, forced velocity), psi (Eq. InteractionPotential), p_EOS and the
+ * Shan-Chen force F.  Any output may be NULL.  host_mass_mom (may be NULL)
+ * receives {sum rho, sum rho u_x, sum rho u_y} (FP64, fixed-order
+ * reduction).  Synchronises `stream`. */
+int lbm_macros(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* psi, double* p,
+               double* Fx, double* Fy, double* host_mass_mom, void* stream);
+
+/* Distributions f_i(t, x) of Eq. LBE at the current time (pulled), as
+ * float64 [9][ny][nx] on the device.  Asynchronous. */
+int lbm_populations(lbm_ctx* ctx, double* f_out, void* stream);
+
+/* FP64 reduction history written by lbm_step when reduce_every > 0:
+ * copies up to max_rows rows {step, mass, mom_x, mom_y} to host memory and
+ * returns the row count through n_out.  Synchronises `stream`. */
+int lbm_history(lbm_ctx* ctx, double* host_rows, int max_rows, int* n_out, void* stream);
+
+/* Current step counter and the buffer that holds the current state (0: f_a, 1: f_b). */
+int lbm_state(lbm_ctx* ctx, int64_t* step_out, int* cur_out);
+
+/* Checkpoint / restore of the whole population state to caller memory
+ * (device or host pointer of lbm_layout bytes).  Synchronous. */
+int lbm_save(lbm_ctx* ctx, void* dst, void* stream);
+int lbm_load(lbm_ctx* ctx, const void* src, int64_t step, void* stream);
+
+void lbm_destroy(lbm_ctx* ctx);
+const char* lbm_strerror(int code);
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,817 @@
+// liblbm.so device code and C-ABI entry points (gfx950 / CDNA4).
+//
+// One time step of the pseudopotential LBM (Eq. LBE) as ONE fused kernel:
+//   pull-stream (half-way bounce-back at walls)  ->  rho, j (Eq. Density,
+//   Eq. Momentum)  ->  shaped p_EOS(rho) (Sec. III.D, Eq. PengEOS)  ->
+//   psi (Eq. InteractionPotential)  ->  Shan-Chen force (Eq. ShanChenForce)
+//   ->  forced velocity  ->  MRT relaxation in moment space (Eq. OperatorMRT,
+//   Eq. MatrixMRT, Eq. RelaxationMatrix, Eq. RelaxationTime) with the source
+//   of Eq. LiFS (Eq. GFS at sigma = 0)  ->  store of the post-collision
+//   populations.
+//
+// Work decomposition.  A wavefront owns a strip of 62 columns and a band of
+// H rows.  Its 64 lanes hold columns x0-1 .. x0+62, so the two edge lanes
+// are the psi halo in x; the wave marches up the band keeping three rows of
+// psi in registers (rows y-1, y, y+1), so every population is pulled once
+// (plus the 2/62 column halo and the 2/H row halo, which hit L2), psi never
+// goes to memory, and the x-neighbours of psi come from lane shuffles.
+// Memory traffic per cell update is the algorithmic minimum: 9 loads and 9
+// stores of the populations.  Workgroups are remapped so that consecutive
+// bands land on the same XCD (shared L2 for the row halo).
+//
+// Storage (chosen per lbm_prec): FP64 populations, or FP32 deviations
+// g_i = f_i - w_i rho_ref with the rest population g_0 kept in FP64 and set
+// after collision to (pre-collision node mass) - sum of the stored moving
+// populations, so that every node's mass is exact to FP64 rounding.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+namespace {
+
+constexpr int kStripW = 62;   // interior columns per wave
+constexpr int kWaves = 4;     // waves per workgroup
+constexpr int kHistCap = 4096;
+
+// ----------------------------------------------------------------- device EOS
+struct DevEos {
+    int base, shape;
+    double RT, aal, b, scale, k_vap, dP;
+    double rho_v, rho_l, rho_max, rho_min;
+    double p0, p_max, p_min, inv_a1sq, b1, inv_a3sq, b3, inv_L, rho_m, theta;
+};
+
+__device__ __forceinline__ double dev_base_p(const DevEos& E, double r)
+{
+    if (E.base == LBM_BASE_CS) {
+        const double n = 0.25 * E.b * r, m = 1.0 - n;
+        return E.scale * (E.RT * r * (1.0 + n * (1.0 + n * (1.0 - n))) / (m * m * m) - E.aal * r * r);
+    }
+    const double br = E.b * r;
+    return E.scale * (E.RT * r / (1.0 - br) - E.aal * r * r / (1.0 + br * (2.0 - br)));
+}
+
+__device__ __forceinline__ double dev_eos_p(const DevEos& E, double r)
+{
+    if (E.shape == LBM_SHAPE_NONE) return dev_base_p(E, r);
+    if (r <= E.rho_v) return E.k_vap * dev_base_p(E, r);
+    if (r >= E.rho_l) return dev_base_p(E, r) + E.dP;
+    if (E.shape == LBM_SHAPE_PENG) return E.p0 + E.theta * (r - E.rho_v) * (r - E.rho_l) * (r - E.rho_m);
+    if (r <= E.rho_max) {
+        const double d = r - E.rho_max;
+        return E.p_max - E.b1 * (1.0 - sqrt(1.0 - d * d * E.inv_a1sq));
+    }
+    if (r < E.rho_min) {
+        const double t = (r - E.rho_max) * E.inv_L;
+        return E.p_max + (E.p_min - E.p_max) * t * t * (3.0 - 2.0 * t);
+    }
+    const double d = r - E.rho_min;
+    return E.p_min + E.b3 * (1.0 - sqrt(1.0 - d * d * E.inv_a3sq));
+}
+
+// ----------------------------------------------------------------- kernel arguments
+struct StepArgs {
+    const void* src;
+    void* dst;
+    size_t plane;            // elements per population plane (ny * ld)
+    int nx, ny, ld, walls;
+    int strips, seg_h, nseg, nwork;
+    int var_tau, pad0;
+    double G, sigma;
+    double s[9];             // relaxation rates 1/tau
+    double tau_v, dtau_drho, tau_lo, tau_hi, rho_v_tau;
+    double rho_ref;
+    double psi_lo, psi_hi;
+    DevEos eos;
+    double* partials;        // [nwork][3] FP64 per-wave sums
+    unsigned* err;           // [0] flag, [1] first failing step
+    long long step;
+    // lbm_macros outputs (MODE_MACROS)
+    double *o_rho, *o_ux, *o_uy, *o_psi, *o_p, *o_fx, *o_fy;
+};
+
+enum { MODE_STEP = 0, MODE_STEP_REDUCE = 1, MODE_MACROS = 2 };
+
+__constant__ double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+template <typename T>
+struct Plane;
+template <>
+struct Plane<double> {
+    __device__ static const double* mov(const void* base, size_t plane, int i) { return (const double*)base + i * plane; }
+    __device__ static double* movw(void* base, size_t plane, int i) { return (double*)base + i * plane; }
+    __device__ static const double* rest(const void* base, size_t plane) { return (const double*)base; }
+    __device__ static double* restw(void* base, size_t plane) { return (double*)base; }
+};
+template <>
+struct Plane<float> {
+    // planes 1..8: float32 at (i-1)*plane; rest population: float64 after the 8 float planes
+    __device__ static const float* mov(const void* base, size_t plane, int i) { return (const float*)base + (i - 1) * plane; }
+    __device__ static float* movw(void* base, size_t plane, int i) { return (float*)base + (i - 1) * plane; }
+    __device__ static const double* rest(const void* base, size_t plane) { return (const double*)((const float*)base + 8 * plane); }
+    __device__ static double* restw(void* base, size_t plane) { return (double*)((float*)base + 8 * plane); }
+};
+
+// Pull the nine populations of fluid node (x, y): f_i(x) = f*_i(x - c_i), or
+// f*_opp(i)(x) when x - c_i is a solid node (half-way bounce-back).
+template <typename T>
+__device__ __forceinline__ void pull(const StepArgs& A, int x, int xm, int xp, int y, double& g0, T g[9])
+{
+    const size_t r0 = (size_t)y * A.ld;
+    const bool bot = A.walls && y == 0;
+    const bool top = A.walls && y == A.ny - 1;
+    const int ym = y == 0 ? A.ny - 1 : y - 1;
+    const int yp = y == A.ny - 1 ? 0 : y + 1;
+    const size_t rm = (size_t)ym * A.ld, rp = (size_t)yp * A.ld;
+    const void* S = A.src;
+    const size_t P = A.plane;
+    g0 = Plane<T>::rest(S, P)[r0 + x];
+    g[1] = Plane<T>::mov(S, P, 1)[r0 + xm];
+    g[3] = Plane<T>::mov(S, P, 3)[r0 + xp];
+    g[2] = bot ? Plane<T>::mov(S, P, 4)[r0 + x] : Plane<T>::mov(S, P, 2)[rm + x];
+    g[5] = bot ? Plane<T>::mov(S, P, 7)[r0 + x] : Plane<T>::mov(S, P, 5)[rm + xm];
+    g[6] = bot ? Plane<T>::mov(S, P, 8)[r0 + x] : Plane<T>::mov(S, P, 6)[rm + xp];
+    g[4] = top ? Plane<T>::mov(S, P, 2)[r0 + x] : Plane<T>::mov(S, P, 4)[rp + x];
+    g[7] = top ? Plane<T>::mov(S, P, 5)[r0 + x] : Plane<T>::mov(S, P, 7)[rp + xp];
+    g[8] = top ? Plane<T>::mov(S, P, 6)[r0 + x] : Plane<T>::mov(S, P, 8)[rp + xm];
+}
+
+// deviation of the node density from rho_ref, exact sum in FP64
+template <typename T>
+__device__ __forceinline__ double node_drho(double g0, const T g[9])
+{
+    return g0 + (((double)g[1] + (double)g[2]) + ((double)g[3] + (double)g[4])) +
+           (((double)g[5] + (double)g[6]) + ((double)g[7] + (double)g[8]));
+}
+
+__device__ __forceinline__ double node_psi(const StepArgs& A, double rho, bool check)
+{
+    const double p = dev_eos_p(A.eos, rho);
+    const double q = 2.0 * (p - rho * (1.0 / 3.0)) / A.G;
+    if (check && !(q >= 0.0 && rho > 0.0)) {
+        atomicOr(A.err, 1u);
+        atomicMin(A.err + 1, (unsigned)A.step);
+    }
+    return q > 0.0 ? sqrt(q) : 0.0;
+}
+
+template <typename T>
+__device__ __forceinline__ T psi_of_row(const StepArgs& A, int y, int x, int xm, int xp, bool valid)
+{
+    if (A.walls && y < 0) return (T)A.psi_lo;
+    if (A.walls && y >= A.ny) return (T)A.psi_hi;
+    const int yy = y < 0 ? y + A.ny : (y >= A.ny ? y - A.ny : y);
+    double g0;
+    T g[9];
+    pull<T>(A, x, xm, xp, yy, g0, g);
+    return (T)node_psi(A, A.rho_ref + node_drho<T>(g0, g), valid);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_step(StepArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int nb = gridDim.x;
+    const int logical = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);  // XCD-contiguous bands
+    const int w = logical * kWaves + (threadIdx.x >> 6);
+    if (w >= A.nwork) return;
+    const int strip = w % A.strips, seg = w / A.strips;
+    const int x0 = strip * kStripW;
+    const int W = min(kStripW, A.nx - x0);
+    const int xr = x0 - 1 + lane;
+    const bool valid = lane <= W + 1;
+    const bool interior = lane >= 1 && lane <= W;
+    int x = xr < 0 ? xr + A.nx : (xr >= A.nx ? xr - A.nx : xr);
+    if (!valid) x = 0;
+    const int xm = x == 0 ? A.nx - 1 : x - 1;
+    const int xp = x == A.nx - 1 ? 0 : x + 1;
+    const int y0 = seg * A.seg_h;
+    const int y1 = min(A.ny, y0 + A.seg_h);
+
+    const T G = (T)A.G;
+    const T third = (T)(1.0 / 3.0), twelfth = (T)(1.0 / 12.0);
+    double accm = 0.0, accx = 0.0, accy = 0.0;
+
+    T psm = psi_of_row<T>(A, y0 - 1, x, xm, xp, valid);
+    double g0c;
+    T gc[9];
+    pull<T>(A, x, xm, xp, y0, g0c, gc);
+    double drc = node_drho<T>(g0c, gc);
+    T psc = (T)node_psi(A, A.rho_ref + drc, valid);
+
+    for (int y = y0; y < y1; ++y) {
+        double g0n = 0.0, drn = 0.0;
+        T gn[9];
+        T psn;
+        if (y + 1 < y1) {
+            pull<T>(A, x, xm, xp, y + 1, g0n, gn);
+            drn = node_drho<T>(g0n, gn);
+            psn = (T)node_psi(A, A.rho_ref + drn, valid);
+        } else {
+            psn = psi_of_row<T>(A, y + 1, x, xm, xp, valid);
+        }
+        // psi of the x-neighbours from the adjacent lanes (all lanes take part)
+        const T lm = __shfl(psm, lane - 1, 64), rm = __shfl(psm, lane + 1, 64);
+        const T lc = __shfl(psc, lane - 1, 64), rc = __shfl(psc, lane + 1, 64);
+        const T ln = __shfl(psn, lane - 1, 64), rn = __shfl(psn, lane + 1, 64);
+        // Eq. ShanChenForce / psi(x): F~ = -G sum_i w(|c_i|^2) psi(x + c_i) c_i, written as differences
+        const T Ftx = -G * ((rc - lc) * third + ((rn - ln) + (rm - lm)) * twelfth);
+        const T Fty = -G * ((psn - psm) * third + ((rn + ln) - (rm + lm)) * twelfth);
+
+        if (interior) {
+            const double rho_d = A.rho_ref + drc;
+            const T rho = (T)rho_d;
+            const T dr = (T)drc;
+            const T Fx = psc * Ftx, Fy = psc * Fty;
+            const T g0t = (T)g0c;
+            // moments m = M g (Eq. MatrixMRT rows)
+            const T s14 = (gc[1] + gc[2]) + (gc[3] + gc[4]);
+            const T s58 = (gc[5] + gc[6]) + (gc[7] + gc[8]);
+            const T jx = (gc[1] - gc[3]) + ((gc[5] - gc[6]) - (gc[7] - gc[8]));
+            const T jy = (gc[2] - gc[4]) + ((gc[5] + gc[6]) - (gc[7] + gc[8]));
+            const T me = -4 * g0t - s14 + 2 * s58;
+            const T mq = 4 * g0t - 2 * s14 + s58;
+            const T mqx = -2 * (gc[1] - gc[3]) + ((gc[5] - gc[6]) - (gc[7] - gc[8]));
+            const T mqy = -2 * (gc[2] - gc[4]) + ((gc[5] + gc[6]) - (gc[7] + gc[8]));
+            const T mxx = (gc[1] - gc[2]) + (gc[3] - gc[4]);
+            const T mxy = (gc[5] - gc[6]) + (gc[7] - gc[8]);
+            // forced velocity (Eq. Momentum)
+            const T inv_rho = (T)1 / rho;
+            const T ux = (jx + (T)0.5 * Fx) * inv_rho, uy = (jy + (T)0.5 * Fy) * inv_rho;
+
+            if (MODE == MODE_MACROS) {
+                const size_t o = (size_t)y * A.nx + x;
+                if (A.o_rho) A.o_rho[o] = rho_d;
+                if (A.o_ux) A.o_ux[o] = (double)ux;
+                if (A.o_uy) A.o_uy[o] = (double)uy;
+                if (A.o_psi) A.o_psi[o] = (double)psc;
+                if (A.o_p) A.o_p[o] = dev_eos_p(A.eos, rho_d);
+                if (A.o_fx) A.o_fx[o] = (double)Fx;
+                if (A.o_fy) A.o_fy[o] = (double)Fy;
+                accm += rho_d;
+                accx += (double)rho * (double)ux;
+                accy += (double)rho * (double)uy;
+            } else {
+                if (MODE == MODE_STEP_REDUCE) {
+                    accm += rho_d;
+                    accx += (double)rho * (double)ux;
+                    accy += (double)rho * (double)uy;
+                }
+                // rates (Eq. RelaxationMatrix; Eq. RelaxationTime on the shear moments)
+                const T se = (T)A.s[1], sq = (T)A.s[2], sqx = (T)A.s[4], sqy = (T)A.s[6];
+                T snu = (T)A.s[7];
+                if (A.var_tau) {
+                    double tau = A.tau_v + A.dtau_drho * (rho_d - A.rho_v_tau);
+                    tau = fmin(fmax(tau, A.tau_lo), A.tau_hi);
+                    snu = (T)(1.0 / tau);
+                }
+                const T u2 = ux * ux + uy * uy;
+                const T uF = ux * Fx + uy * Fy;
+                const T F2 = Ftx * Ftx + Fty * Fty;  // |F|^2/psi^2
+                // equilibrium deviation moments (M f^eq minus the rho_ref rest state)
+                const T eqe = -2 * dr + 3 * rho * u2;
+                const T eqq = dr - 3 * rho * u2;
+                const T eqxx = rho * (ux * ux - uy * uy);
+                const T eqxy = rho * ux * uy;
+                // Eq. LiFS source, multiplied by (I - Lambda/2)
+                const T sig12 = (T)(12.0 * A.sigma) * F2;
+                const T Se = ((T)6 * uF + sig12 / ((T)1 / se - (T)0.5)) * ((T)1 - (T)0.5 * se);
+                const T Sq = (-(T)6 * uF - sig12 / ((T)1 / sq - (T)0.5)) * ((T)1 - (T)0.5 * sq);
+                // relaxed moments m* = m - Lambda (m - m^eq) + (I - Lambda/2) S
+                const T ne = (me - se * (me - eqe) + Se) * (T)(1.0 / 36.0);
+                const T nq = (mq - sq * (mq - eqq) + Sq) * (T)(1.0 / 36.0);
+                const T nqx = (mqx - sqx * (mqx + rho * ux) - ((T)1 - (T)0.5 * sqx) * Fx) * (T)(1.0 / 12.0);
+                const T nqy = (mqy - sqy * (mqy + rho * uy) - ((T)1 - (T)0.5 * sqy) * Fy) * (T)(1.0 / 12.0);
+                const T nxx = (mxx - snu * (mxx - eqxx) + ((T)1 - (T)0.5 * snu) * (T)2 * (ux * Fx - uy * Fy)) * (T)0.25;
+                const T nxy = (mxy - snu * (mxy - eqxy) + ((T)1 - (T)0.5 * snu) * (ux * Fy + uy * Fx)) * (T)0.25;
+                const T n0 = dr * (T)(1.0 / 9.0);
+                const T njx = (jx + Fx) * (T)(1.0 / 6.0);
+                const T njy = (jy + Fy) * (T)(1.0 / 6.0);
+                // f* = M^-1 m* = M^T diag(1/9,1/36,1/36,1/6,1/12,1/6,1/12,1/4,1/4) m*
+                const T a14 = n0 - ne - 2 * nq;
+                const T a58 = n0 + 2 * ne + nq;
+                T o[9];
+                o[1] = a14 + njx - 2 * nqx + nxx;
+                o[2] = a14 + njy - 2 * nqy - nxx;
+                o[3] = a14 - njx + 2 * nqx + nxx;
+                o[4] = a14 - njy + 2 * nqy - nxx;
+                o[5] = a58 + njx + nqx + njy + nqy + nxy;
+                o[6] = a58 - njx - nqx + njy + nqy - nxy;
+                o[7] = a58 - njx - nqx - njy - nqy + nxy;
+                o[8] = a58 + njx + nqx - njy - nqy - nxy;
+                const size_t off = (size_t)y * A.ld + x;
+                const size_t P = A.plane;
+#pragma unroll
+                for (int i = 1; i < 9; ++i) Plane<T>::movw(A.dst, P, i)[off] = o[i];
+                // rest population: exact node mass in FP64 (conserved by the collision)
+                const double o0 = drc - ((((double)o[1] + (double)o[2]) + ((double)o[3] + (double)o[4])) +
+                                         (((double)o[5] + (double)o[6]) + ((double)o[7] + (double)o[8])));
+                Plane<T>::restw(A.dst, P)[off] = o0;
+            }
+        }
+        psm = psc;
+        psc = psn;
+        g0c = g0n;
+        drc = drn;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) gc[i] = gn[i];
+    }
+    if (MODE != MODE_STEP) {
+        accm = wave_sum(accm);
+        accx = wave_sum(accx);
+        accy = wave_sum(accy);
+        if (lane == 0) {
+            A.partials[3 * w + 0] = accm;
+            A.partials[3 * w + 1] = accx;
+            A.partials[3 * w + 2] = accy;
+        }
+    }
+}
+
+// fixed-order FP64 reduction of the per-wave partials (one workgroup)
+__global__ __launch_bounds__(256) void k_reduce(const double* partials, int n, double* out, long long step, int with_step)
+{
+    __shared__ double sh[3][256];
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += 256)
+        for (int k = 0; k < 3; ++k) a[k] += partials[3 * i + k];
+    for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int o = 0;
+        if (with_step) out[o++] = (double)step;
+        for (int k = 0; k < 3; ++k) out[o + k] = sh[k][0];
+    }
+}
+
+// initial state: store A_j(z) such that the pull of the first step yields f^eq(rho0, u0)
+template <typename T>
+__global__ void k_init(StepArgs A, const double* rho0, const double* ux0, const double* uy0)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= A.nx || y >= A.ny) return;
+    const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const int op[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    const size_t off = (size_t)y * A.ld + x;
+    for (int j = 0; j < 9; ++j) {
+        int sx = x + cx[j], sy = y + cy[j], k = j;
+        if (A.walls && (sy < 0 || sy >= A.ny)) {
+            sx = x;
+            sy = y;
+            k = op[j];
+        }
+        sx = sx < 0 ? sx + A.nx : (sx >= A.nx ? sx - A.nx : sx);
+        sy = sy < 0 ? sy + A.ny : (sy >= A.ny ? sy - A.ny : sy);
+        const size_t c = (size_t)sy * A.nx + sx;
+        const double r = rho0[c], ux = ux0 ? ux0[c] : 0.0, uy = uy0 ? uy0[c] : 0.0;
+        const double cu = cx[k] * ux + cy[k] * uy;
+        const double feq = kW[k] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
+        const double g = feq - kW[k] * A.rho_ref;
+        if (j == 0) Plane<T>::restw(A.dst, A.plane)[off] = g;
+        else Plane<T>::movw(A.dst, A.plane, j)[off] = (T)g;
+    }
+}
+
+// f_i(t, x) of Eq. LBE as FP64 [9][ny][nx]
+template <typename T>
+__global__ void k_populations(StepArgs A, double* out)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= A.nx || y >= A.ny) return;
+    const int xm = x == 0 ? A.nx - 1 : x - 1;
+    const int xp = x == A.nx - 1 ? 0 : x + 1;
+    double g0;
+    T g[9];
+    pull<T>(A, x, xm, xp, y, g0, g);
+    const size_t n = (size_t)A.nx * A.ny, o = (size_t)y * A.nx + x;
+    out[o] = g0 + kW[0] * A.rho_ref;
+    for (int i = 1; i < 9; ++i) out[i * n + o] = (double)g[i] + kW[i] * A.rho_ref;
+}
+
+}  // namespace
+
+// ===================================================================== host side
+struct lbm_ctx {
+    lbm_params P;
+    StepArgs args;
+    int ld;
+    size_t plane, pop_bytes;
+    void* buf[2];
+    int cur;
+    int64_t step;
+    char* ws;
+    size_t ws_bytes;
+    unsigned* err;
+    double* partials;
+    double* hist;
+    double* red;
+    int64_t hist_count;
+    int grid;
+};
+
+namespace {
+
+bool hip_ok(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return true;
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+    lbm_set_error(buf);
+    return false;
+}
+
+void decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg)
+{
+    *strips = (p.nx + kStripW - 1) / kStripW;
+    // band height: aim for ~4096 waves when the lattice allows, 4..64 rows
+    int h = 64;
+    while (h > 4 && (long long)(*strips) * ((p.ny + h - 1) / h) < 4096) h >>= 1;
+    *seg_h = h;
+    *nseg = (p.ny + h - 1) / h;
+}
+
+size_t ws_layout(int nwork, size_t* off_part, size_t* off_hist, size_t* off_red)
+{
+    size_t o = 256;  // error word
+    *off_part = o;
+    o += ((size_t)nwork * 3 * sizeof(double) + 255) & ~(size_t)255;
+    *off_hist = o;
+    o += (size_t)kHistCap * 4 * sizeof(double);
+    *off_red = o;
+    o += 256;
+    return o;
+}
+
+DevEos dev_eos(const lbm_eos& e)
+{
+    DevEos E{};
+    E.base = e.base;
+    E.shape = e.shape;
+    E.RT = e.R * e.T;
+    if (e.base == LBM_BASE_PR) {
+        const double kap = 0.37464 + 1.54226 * e.omega - 0.26992 * e.omega * e.omega;
+        const double t = 1.0 + kap * (1.0 - std::sqrt(e.T / e.Tc));
+        E.aal = e.a * t * t;
+    } else {
+        E.aal = e.a;
+    }
+    E.b = e.b;
+    E.scale = e.scale;
+    E.k_vap = e.k_vap;
+    E.dP = e.dP_liq;
+    E.rho_v = e.rho_v;
+    E.rho_l = e.rho_l;
+    E.rho_max = e.rho_max;
+    E.rho_min = e.rho_min;
+    E.p0 = e.p_sat;
+    E.p_max = e.p_max;
+    E.p_min = e.p_min;
+    E.inv_a1sq = e.a1sq > 0 ? 1.0 / e.a1sq : 0.0;
+    E.b1 = e.b1;
+    E.inv_a3sq = e.a3sq > 0 ? 1.0 / e.a3sq : 0.0;
+    E.b3 = e.b3;
+    E.inv_L = e.rho_min > e.rho_max ? 1.0 / (e.rho_min - e.rho_max) : 0.0;
+    E.rho_m = e.rho_m;
+    E.theta = e.theta;
+    return E;
+}
+
+int validate(const lbm_params* p)
+{
+    if (!p || p->nx < 1 || p->ny < 1 || (p->prec != LBM_FP64 && p->prec != LBM_FP32_SHIFTED)) {
+        lbm_set_error("lbm: invalid lattice size or precision");
+        return LBM_EINVAL;
+    }
+    if ((long long)p->nx * p->ny > (1LL << 31)) {
+        lbm_set_error("lbm: lattice larger than 2^31 nodes");
+        return LBM_EINVAL;
+    }
+    if (!(p->G < 0.0)) {
+        lbm_set_error("lbm: G must be negative (Eq. InteractionPotential with p_EOS < rho c_s^2)");
+        return LBM_EINVAL;
+    }
+    for (int k = 0; k < 9; ++k)
+        if (!(p->tau[k] > 0.5)) {
+            lbm_set_error("lbm: every relaxation time must exceed 1/2");
+            return LBM_EINVAL;
+        }
+    if (p->tau[7] != p->tau[8]) {
+        lbm_set_error("lbm: Eq. RelaxationMatrix relaxes both shear moments with tau_nu (tau[7] == tau[8])");
+        return LBM_EINVAL;
+    }
+    if (p->var_tau && !(p->tau_l > 0.5 && p->tau_v > 0.5 && p->rho_l_tau != p->rho_v_tau)) {
+        lbm_set_error("lbm: Eq. RelaxationTime needs tau_l, tau_v > 1/2 and rho_l != rho_v");
+        return LBM_EINVAL;
+    }
+    if (p->prec == LBM_FP32_SHIFTED && !(p->rho_ref > 0.0)) {
+        lbm_set_error("lbm: FP32-shifted storage needs rho_ref > 0");
+        return LBM_EINVAL;
+    }
+    if (!(p->eos.T > 0.0)) {
+        lbm_set_error("lbm: EOS not built (call lbm_eos_build first)");
+        return LBM_EINVAL;
+    }
+    return LBM_OK;
+}
+
+void fill_args(lbm_ctx* c)
+{
+    const lbm_params& p = c->P;
+    StepArgs& A = c->args;
+    std::memset(&A, 0, sizeof(A));
+    A.plane = c->plane;
+    A.nx = p.nx;
+    A.ny = p.ny;
+    A.ld = c->ld;
+    A.walls = p.walls;
+    decompose(p, &A.strips, &A.seg_h, &A.nseg);
+    A.nwork = A.strips * A.nseg;
+    A.var_tau = p.var_tau;
+    A.G = p.G;
+    A.sigma = p.sigma;
+    for (int k = 0; k < 9; ++k) A.s[k] = 1.0 / p.tau[k];
+    A.tau_v = p.tau_v;
+    A.rho_v_tau = p.rho_v_tau;
+    A.dtau_drho = p.var_tau ? (p.tau_l - p.tau_v) / (p.rho_l_tau - p.rho_v_tau) : 0.0;
+    A.tau_lo = std::fmin(p.tau_l, p.tau_v);
+    A.tau_hi = std::fmax(p.tau_l, p.tau_v);
+    A.rho_ref = p.prec == LBM_FP32_SHIFTED ? p.rho_ref : 0.0;
+    A.eos = dev_eos(p.eos);
+    auto psi_host = [&](double r) {
+        const double q = 2.0 * (lbm_eos_pressure(&p.eos, r) - r / 3.0) / p.G;
+        return q > 0 ? std::sqrt(q) : 0.0;
+    };
+    A.psi_lo = p.walls ? psi_host(p.rho_wall_lo) : 0.0;
+    A.psi_hi = p.walls ? psi_host(p.rho_wall_hi) : 0.0;
+    A.partials = c->partials;
+    A.err = c->err;
+    const int blocks = (A.nwork + kWaves - 1) / kWaves;
+    c->grid = (blocks + 7) & ~7;
+}
+
+template <typename T>
+bool launch_step(lbm_ctx* c, int mode, hipStream_t s)
+{
+    StepArgs A = c->args;
+    A.src = c->buf[c->cur];
+    A.dst = c->buf[c->cur ^ 1];
+    A.step = c->step;
+    if (mode == MODE_STEP) hipLaunchKernelGGL((k_step<T, MODE_STEP>), dim3(c->grid), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL((k_step<T, MODE_STEP_REDUCE>), dim3(c->grid), dim3(256), 0, s, A);
+    return hip_ok(hipGetLastError(), "k_step launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_strerror(int code)
+{
+    switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_EUNSTABLE: return "unstable (psi^2 < 0 or non-finite density)";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_ESTATE: return "call out of order";
+    case LBM_ENOROOT: return "no root in the admissible bracket";
+    default: return "unknown error";
+    }
+}
+
+int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* ws_bytes_out)
+{
+    if (!p || p->nx < 1 || p->ny < 1) {
+        lbm_set_error("lbm_layout: invalid lattice size");
+        return LBM_EINVAL;
+    }
+    const int ld = (p->nx + 63) & ~63;
+    const size_t plane = (size_t)ld * p->ny;
+    const size_t bytes = p->prec == LBM_FP32_SHIFTED ? plane * (8 * sizeof(float) + sizeof(double)) : plane * 9 * sizeof(double);
+    int strips, seg_h, nseg;
+    decompose(*p, &strips, &seg_h, &nseg);
+    size_t a, b, d;
+    const size_t ws = ws_layout(strips * nseg, &a, &b, &d);
+    if (ld_out) *ld_out = ld;
+    if (pop_bytes_out) *pop_bytes_out = bytes;
+    if (ws_bytes_out) *ws_bytes_out = ws;
+    return LBM_OK;
+}
+
+int lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes,
+             const double* rho0, const double* ux0, const double* uy0, void* stream)
+{
+    if (!out) {
+        lbm_set_error("lbm_init: null context pointer");
+        return LBM_EINVAL;
+    }
+    *out = nullptr;
+    int st = validate(p);
+    if (st != LBM_OK) return st;
+    if (!f_a || !f_b || f_a == f_b || !ws || !rho0) {
+        lbm_set_error("lbm_init: population buffers must be non-NULL and distinct; ws and rho0 non-NULL");
+        return LBM_EINVAL;
+    }
+    int ld;
+    size_t pop_bytes, need;
+    lbm_layout(p, &ld, &pop_bytes, &need);
+    if (ws_bytes < need) {
+        lbm_set_error("lbm_init: workspace smaller than lbm_layout requires");
+        return LBM_EINVAL;
+    }
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_EINVAL;
+    c->P = *p;
+    c->ld = ld;
+    c->plane = (size_t)ld * p->ny;
+    c->pop_bytes = pop_bytes;
+    c->buf[0] = f_a;
+    c->buf[1] = f_b;
+    c->cur = 0;
+    c->step = 0;
+    c->ws = (char*)ws;
+    c->ws_bytes = ws_bytes;
+    int strips, seg_h, nseg;
+    decompose(*p, &strips, &seg_h, &nseg);
+    size_t op, oh, orr;
+    ws_layout(strips * nseg, &op, &oh, &orr);
+    c->err = (unsigned*)c->ws;
+    c->partials = (double*)(c->ws + op);
+    c->hist = (double*)(c->ws + oh);
+    c->red = (double*)(c->ws + orr);
+    c->hist_count = 0;
+    fill_args(c);
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned init_err[2] = {0u, 0xffffffffu};
+    if (!hip_ok(hipMemcpyAsync(c->err, init_err, sizeof(init_err), hipMemcpyHostToDevice, s), "lbm_init error word") ||
+        !hip_ok(hipStreamSynchronize(s), "lbm_init sync")) {
+        delete c;
+        return LBM_EHIP;
+    }
+    StepArgs A = c->args;
+    A.dst = c->buf[0];
+    dim3 g((p->nx + 127) / 128, p->ny);
+    if (p->prec == LBM_FP32_SHIFTED) hipLaunchKernelGGL(k_init<float>, g, dim3(128), 0, s, A, rho0, ux0, uy0);
+    else hipLaunchKernelGGL(k_init<double>, g, dim3(128), 0, s, A, rho0, ux0, uy0);
+    if (!hip_ok(hipGetLastError(), "k_init launch")) {
+        delete c;
+        return LBM_EHIP;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
+{
+    if (!c || nsteps < 0) {
+        lbm_set_error("lbm_step: invalid arguments");
+        return LBM_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const bool f32 = c->P.prec == LBM_FP32_SHIFTED;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const bool red = c->P.reduce_every > 0 && (c->step % c->P.reduce_every) == 0;
+        const int mode = red ? MODE_STEP_REDUCE : MODE_STEP;
+        if (!(f32 ? launch_step<float>(c, mode, s) : launch_step<double>(c, mode, s))) return LBM_EHIP;
+        if (red) {
+            double* row = c->hist + 4 * (c->hist_count % kHistCap);
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, (const double*)c->partials, c->args.nwork, row,
+                               (long long)c->step, 1);
+            if (!hip_ok(hipGetLastError(), "k_reduce launch")) return LBM_EHIP;
+            c->hist_count++;
+        }
+        c->cur ^= 1;
+        c->step++;
+    }
+    return LBM_OK;
+}
+
+int lbm_status_check(lbm_ctx* c, void* stream)
+{
+    if (!c) return LBM_EINVAL;
+    unsigned h[2];
+    hipStream_t s = (hipStream_t)stream;
+    if (!hip_ok(hipMemcpyAsync(h, c->err, sizeof(h), hipMemcpyDeviceToHost, s), "status copy") ||
+        !hip_ok(hipStreamSynchronize(s), "status sync"))
+        return LBM_EHIP;
+    if (h[0]) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "lbm: psi^2 < 0 or non-positive density first met at step %u", h[1]);
+        lbm_set_error(buf);
+        return LBM_EUNSTABLE;
+    }
+    return LBM_OK;
+}
+
+int lbm_macros(lbm_ctx* c, double* rho, double* ux, double* uy, double* psi, double* p, double* Fx, double* Fy,
+               double* host_mass_mom, void* stream)
+{
+    if (!c) return LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    StepArgs A = c->args;
+    A.src = c->buf[c->cur];
+    A.dst = nullptr;
+    A.step = c->step;
+    A.o_rho = rho;
+    A.o_ux = ux;
+    A.o_uy = uy;
+    A.o_psi = psi;
+    A.o_p = p;
+    A.o_fx = Fx;
+    A.o_fy = Fy;
+    if (c->P.prec == LBM_FP32_SHIFTED) hipLaunchKernelGGL((k_step<float, MODE_MACROS>), dim3(c->grid), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL((k_step<double, MODE_MACROS>), dim3(c->grid), dim3(256), 0, s, A);
+    if (!hip_ok(hipGetLastError(), "k_step(macros) launch")) return LBM_EHIP;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, (const double*)c->partials, c->args.nwork, c->red, 0LL, 0);
+    if (!hip_ok(hipGetLastError(), "k_reduce launch")) return LBM_EHIP;
+    double h[3];
+    if (!hip_ok(hipMemcpyAsync(h, c->red, sizeof(h), hipMemcpyDeviceToHost, s), "macros copy") ||
+        !hip_ok(hipStreamSynchronize(s), "macros sync"))
+        return LBM_EHIP;
+    if (host_mass_mom) std::memcpy(host_mass_mom, h, sizeof(h));
+    return lbm_status_check(c, stream);
+}
+
+int lbm_populations(lbm_ctx* c, double* f_out, void* stream)
+{
+    if (!c || !f_out) return LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    StepArgs A = c->args;
+    A.src = c->buf[c->cur];
+    dim3 g((c->P.nx + 127) / 128, c->P.ny);
+    if (c->P.prec == LBM_FP32_SHIFTED) hipLaunchKernelGGL(k_populations<float>, g, dim3(128), 0, s, A, f_out);
+    else hipLaunchKernelGGL(k_populations<double>, g, dim3(128), 0, s, A, f_out);
+    return hip_ok(hipGetLastError(), "k_populations launch") ? LBM_OK : LBM_EHIP;
+}
+
+int lbm_history(lbm_ctx* c, double* host_rows, int max_rows, int* n_out, void* stream)
+{
+    if (!c || !host_rows || max_rows < 0) return LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t avail = c->hist_count < kHistCap ? c->hist_count : kHistCap;
+    const int n = (int)(avail < max_rows ? avail : max_rows);
+    // newest n rows, oldest first
+    for (int k = 0; k < n; ++k) {
+        const int64_t idx = (c->hist_count - n + k) % kHistCap;
+        if (!hip_ok(hipMemcpyAsync(host_rows + 4 * k, c->hist + 4 * idx, 4 * sizeof(double), hipMemcpyDeviceToHost, s),
+                    "history copy"))
+            return LBM_EHIP;
+    }
+    if (!hip_ok(hipStreamSynchronize(s), "history sync")) return LBM_EHIP;
+    if (n_out) *n_out = n;
+    return LBM_OK;
+}
+
+int lbm_state(lbm_ctx* c, int64_t* step_out, int* cur_out)
+{
+    if (!c) return LBM_EINVAL;
+    if (step_out) *step_out = c->step;
+    if (cur_out) *cur_out = c->cur;
+    return LBM_OK;
+}
+
+int lbm_save(lbm_ctx* c, void* dst, void* stream)
+{
+    if (!c || !dst) return LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (!hip_ok(hipMemcpyAsync(dst, c->buf[c->cur], c->pop_bytes, hipMemcpyDefault, s), "lbm_save copy") ||
+        !hip_ok(hipStreamSynchronize(s), "lbm_save sync"))
+        return LBM_EHIP;
+    return LBM_OK;
+}
+
+int lbm_load(lbm_ctx* c, const void* src, int64_t step, void* stream)
+{
+    if (!c || !src || step < 0) return LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (!hip_ok(hipMemcpyAsync(c->buf[c->cur], src, c->pop_bytes, hipMemcpyDefault, s), "lbm_load copy") ||
+        !hip_ok(hipStreamSynchronize(s), "lbm_load sync"))
+        return LBM_EHIP;
+    c->step = step;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+}  // extern "C"

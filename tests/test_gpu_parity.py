@@ -1,0 +1,229 @@
+"""GPU parity: the HIP hot path (through the C ABI) against the FP64 CPU oracle.
+
+FP64 storage: elementwise agreement of the distributions to 1e-12 relative (only the
+rounding order differs: moment-space collision and fused multiply-adds on the GPU).
+FP32-shifted storage: the stated targets -- rho_v relative error <= 1e-3, rho_l <= 1e-5,
+L_inf(u) <= 1e-5, relative mass drift <= 1e-10 -- plus a one-step elementwise bound
+derived from FP32 rounding (see the test docstrings).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from lbm_inputs import droplet_density, droplet_on_film, planar_density, random_field
+
+pytestmark = pytest.mark.gpu
+
+TAU_MRT = [1.0, 1.1, 1.25, 1.0, 1.15, 1.0, 1.15, 0.8, 0.8]
+
+
+def both_eos(lbm, **kw):
+    e, s = lbm.eos_build(lbm.make_eos(**kw))
+    eo, so = O.eos_build(O.make_eos(**kw))
+    return e, s, eo, so
+
+
+def run_pair(lbm, nx, ny, kw, rho0, steps, tau=None, prec=None, ux0=None, uy0=None, walls=False,
+             var_tau=False, tau_l=1.0, tau_v=1.0, forcing_li=True, rho_ref=None, wall=(0.0, 0.0)):
+    e, s, eo, so = both_eos(lbm, **kw)
+    sig, sigo = (s, so) if forcing_li else (0.0, 0.0)
+    prec = lbm.FP64 if prec is None else prec
+    P = lbm.make_params(nx, ny, e, sigma=sig, tau=tau, prec=prec, rho_ref=rho_ref, walls=walls,
+                        rho_wall_lo=wall[0], rho_wall_hi=wall[1], var_tau=var_tau, tau_l=tau_l, tau_v=tau_v)
+    L = lbm.Lattice(P, rho0, ux0, uy0, device="cuda:0")
+    L.step(steps)
+    OP = O.make_params(nx, ny, eo, sigma=sigo, tau=tau, forcing=O.FORCING_LI if forcing_li else O.FORCING_GUO,
+                       walls=walls, rho_wall_lo=wall[0], rho_wall_hi=wall[1], var_tau=var_tau, tau_l=tau_l,
+                       tau_v=tau_v)
+    OL = O.Lattice(OP)
+    OL.init_eq(rho0, ux0, uy0)
+    OL.run(steps)
+    return L, OL, e, eo
+
+
+def rel_f_err(L, OL):
+    g = L.populations().cpu().numpy()
+    o = OL.get_f()
+    return np.abs(g - o).max() / np.abs(o).max()
+
+
+# ---------------------------------------------------------------- FP64 elementwise parity
+@pytest.mark.parametrize("nx,ny", [(130, 37), (62, 5), (63, 9), (2, 200), (256, 4), (1, 7), (5, 1)])
+def test_fp64_planar_and_ragged_shapes(gpu_lib, nx, ny):
+    """Ragged strips (62-column waves), ragged bands, 1-wide and 1-tall lattices."""
+    kw = dict(Tr=0.7)
+    e, _, _, _ = both_eos(gpu_lib, **kw)
+    rho0 = planar_density(nx, ny, e.rho_v, e.rho_l, W=5, axis=1 if ny >= nx else 0)
+    rho0 = rho0 * (1 + 0.01 * random_field(nx, ny, 1.0, 1.0, seed=nx * 1000 + ny))
+    for steps in (1, 40):
+        L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, steps, tau=TAU_MRT)
+        assert rel_f_err(L, OL) < 1e-12, (nx, ny, steps)
+
+
+@pytest.mark.parametrize("shape_kw", [
+    dict(Tr=0.5, shape=1, alpha=0.61),
+    dict(Tr=0.5, shape=1, alpha=0.207, k_vap=4.0),
+    dict(Tr=0.6, a=0.387, shape=3, r_theta=0.45),
+    dict(Tr=0.6, a=0.387, shape=2, alpha=0.446, k_vap=2 / 0.387),
+    dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0),
+], ids=["smooth", "smooth-raised-vapor", "peng", "mod-smooth", "PR-shaped"])
+def test_fp64_shaped_eos_droplet(gpu_lib, shape_kw):
+    """Every EOS branch (vapor, ellipse 1, cubic, ellipse 3, liquid; Peng cubic) on a droplet."""
+    nx, ny = 80, 70
+    e, _, _, _ = both_eos(gpu_lib, **shape_kw)
+    rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=18, W=14)
+    li = shape_kw.get("shape", 0) in (0, 1)
+    L, OL, _, _ = run_pair(gpu_lib, nx, ny, shape_kw, rho0, 60, tau=TAU_MRT, forcing_li=li)
+    assert rel_f_err(L, OL) < 1e-12
+
+
+def test_fp64_walls_variable_tau_moving_droplet(gpu_lib):
+    """Bounce-back walls with ghost psi, Eq. RelaxationTime, a moving droplet over a film."""
+    kw = dict(Tr=0.6, a=0.387, shape=1, alpha=0.834, k_vap=2 / 0.387)
+    e, _, _, _ = both_eos(gpu_lib, **kw)
+    nx, ny = 96, 64
+    rho0, ux0, uy0 = droplet_on_film(nx, ny, e.rho_v, e.rho_l, R=12, h=8, gap=4, V=0.05, W=8)
+    tau_l = 0.7
+    L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, 80, tau=[1, 1, 1, 1, 1, 1, 1, tau_l, tau_l], ux0=ux0,
+                           uy0=uy0, walls=True, wall=(e.rho_l, e.rho_v), var_tau=True, tau_l=tau_l,
+                           tau_v=0.5 + 5 * (tau_l - 0.5))
+    assert rel_f_err(L, OL) < 1e-12
+
+
+def test_fp64_macros_match_oracle(gpu_lib):
+    kw = dict(Tr=0.6)
+    e, _, _, _ = both_eos(gpu_lib, **kw)
+    nx, ny = 75, 66
+    rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=15, W=6)
+    L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, 30, tau=TAU_MRT)
+    g = {k: v.cpu().numpy() if hasattr(v, "cpu") else v for k, v in L.macros().items()}
+    m = OL.macros()
+    for k in ("rho", "ux", "uy", "psi", "p", "Fx", "Fy"):
+        scale = np.abs(m[k]).max() + 1e-300
+        assert np.abs(g[k] - m[k]).max() / scale < 1e-11, k
+    mass, mx, my = g["mass_mom"]
+    assert mass == pytest.approx(m["rho"].sum(), rel=1e-13)
+    assert abs(mx) < 1e-12 * mass and abs(my) < 1e-12 * mass
+
+
+# ---------------------------------------------------------------- FP32-shifted against the FP64 oracle
+def test_fp32_planar_interface_targets(gpu_lib):
+    """C-S a=0.5, Tr=0.7, 256x4 periodic, BGK tau=1, Li sigma from eps, tanh width 5 along x."""
+    kw = dict(Tr=0.7)
+    e, _, _, _ = both_eos(gpu_lib, **kw)
+    nx, ny = 256, 4
+    rho0 = planar_density(nx, ny, e.rho_v, e.rho_l, W=5, axis=0)
+    steps = 3000
+    L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, steps, prec=gpu_lib.FP32_SHIFTED)
+    g = {k: v.cpu().numpy() for k, v in L.macros().items() if k != "mass_mom"}
+    m = OL.macros()
+    rv_g, rv_o = g["rho"][0, 0], m["rho"][0, 0]
+    rl_g, rl_o = g["rho"][0, nx // 2], m["rho"][0, nx // 2]
+    assert abs(rv_g - rv_o) / rv_o <= 1e-3
+    assert abs(rl_g - rl_o) / rl_o <= 1e-5
+    assert np.abs(g["ux"] - m["ux"]).max() <= 1e-5
+    assert np.abs(g["uy"] - m["uy"]).max() <= 1e-5
+
+
+def test_fp32_one_step_elementwise(gpu_lib):
+    """One FP32-shifted step from an FP32-representable state against the FP64 oracle step.
+
+    Inputs are identical, so the difference is the FP32 arithmetic of one collision: each
+    stored deviation carries ~2^-24 relative rounding of the moment terms it sums; the
+    bound 2e-6 * max|f - w rho_ref| allows ~30 roundings of the largest term.
+    """
+    kw = dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
+    e, s, eo, so = both_eos(gpu_lib, **kw)
+    nx, ny = 128, 96
+    rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=25, W=20)
+    P = gpu_lib.make_params(nx, ny, e, sigma=s, tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7], prec=gpu_lib.FP32_SHIFTED)
+    L = gpu_lib.Lattice(P, rho0, device="cuda:0")
+    L.step(50)
+    f_t = L.populations().cpu().numpy()
+    L.step(1)
+    f_g = L.populations().cpu().numpy()
+    OL = O.Lattice(O.make_params(nx, ny, eo, sigma=so, tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]))
+    OL.set_f(f_t)
+    OL.run(1)
+    f_o = OL.get_f()
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+    dev = np.abs(f_o - w * e.rho_v).max()
+    assert np.abs(f_g - f_o).max() <= 2e-6 * dev
+
+
+def test_fp32_mass_drift_droplet(gpu_lib):
+    """FP64 per-node rest population keeps the FP32-shifted mass exact: drift <= 1e-10 relative."""
+    kw = dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
+    e, s = gpu_lib.eos_build(gpu_lib.make_eos(**kw))
+    nx = ny = 256
+    rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=60, W=20)
+    P = gpu_lib.make_params(nx, ny, e, sigma=s, tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7], prec=gpu_lib.FP32_SHIFTED,
+                            reduce_every=500)
+    L = gpu_lib.Lattice(P, rho0, device="cuda:0")
+    L.step(5001)
+    L.check()
+    h = L.history()
+    assert h.shape[0] == 11
+    mass = h[:, 1]
+    assert np.abs(mass / mass[0] - 1).max() <= 1e-10
+    assert np.abs(h[:, 2:]).max() <= 1e-9 * mass[0]
+
+
+# ---------------------------------------------------------------- the paper's printed result on the GPU
+def test_table4_cs_on_gpu(gpu_lib):
+    """Table IV C-S a=0.363, Tr=0.5: the GPU FP64 path reproduces E_a = 35.67 %, w = 7."""
+    e, s = gpu_lib.eos_build(gpu_lib.make_eos(Tr=0.5, a=0.363))
+    nx, ny = 2, 200
+    P = gpu_lib.make_params(nx, ny, e, sigma=s)
+    L = gpu_lib.Lattice(P, planar_density(nx, ny, e.rho_v, e.rho_l, W=10), device="cuda:0")
+    prev = L.macros()["rho"].cpu().numpy()
+    for _ in range(1500):
+        L.step(100)
+        cur = L.macros()["rho"].cpu().numpy()
+        res = np.abs(cur - prev).sum() / np.abs(cur).sum()
+        prev = cur
+        if res < 1e-6:
+            break
+    prof = cur[:, 0]
+    E = 100 * (prof[0] - e.rho_v) / e.rho_v
+    assert E == pytest.approx(35.67, rel=0.01)
+    phi = (prof[: ny // 2 + 1] - prof[0]) / (prof[ny // 2] - prof[0])
+    assert int(((phi > 0.01) & (phi < 0.99)).sum()) == 7
+
+
+# ---------------------------------------------------------------- error paths
+def test_unstable_state_is_reported(gpu_lib):
+    e, _ = gpu_lib.eos_build(gpu_lib.make_eos(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5))
+    P = gpu_lib.make_params(8, 8, e)
+    L = gpu_lib.Lattice(P, np.full((8, 8), 1.1 * e.rho_l), device="cuda:0")
+    L.step(2)
+    with pytest.raises(gpu_lib.LbmError) as ei:
+        L.check()
+    assert ei.value.code == gpu_lib.LBM_EUNSTABLE
+
+
+def test_invalid_parameters_rejected(gpu_lib):
+    e, _ = gpu_lib.eos_build(gpu_lib.make_eos(Tr=0.7))
+    for bad in (dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.5, 0.5]), dict(G=1.0), dict(prec=1, rho_ref=-1.0),
+                dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.8, 0.9])):
+        P = gpu_lib.make_params(8, 8, e, **bad)
+        with pytest.raises(gpu_lib.LbmError) as ei:
+            gpu_lib.Lattice(P, np.full((8, 8), e.rho_v), device="cuda:0")
+        assert ei.value.code == gpu_lib.LBM_EINVAL
+
+
+def test_save_load_roundtrip(gpu_lib):
+    e, s = gpu_lib.eos_build(gpu_lib.make_eos(Tr=0.7))
+    nx, ny = 64, 32
+    rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=8, W=5)
+    P = gpu_lib.make_params(nx, ny, e, sigma=s, prec=gpu_lib.FP32_SHIFTED)
+    L = gpu_lib.Lattice(P, rho0, device="cuda:0")
+    L.step(10)
+    buf, step = L.save()
+    L.step(25)
+    a = L.populations().cpu().numpy()
+    L.load_state(buf, step)
+    L.step(25)
+    b = L.populations().cpu().numpy()
+    assert np.array_equal(a, b)
+    assert L.state()[0] == 35
