@@ -1,0 +1,219 @@
+"""Throughput of the fused shaped-EOS pseudopotential D2Q9 step on one MI355X.
+
+Default workload (the quoted configuration): static droplet on a 512x512 periodic lattice,
+shaped Peng-Robinson EOS (a=2/49, b=2/21, omega=0.344) at Tr=0.5 with the Smooth vdW-loop
+replacement (alpha=0.3), raised vapor sound speed (k_vap=4), EOS scale 0.25, MRT with
+tau_nu=0.7 and Li forcing with sigma from eps; FP32-shifted storage (rho_ref = rho_v) with
+FP64 mass/momentum reductions every 100 steps.  One "step" is one time step of the whole
+hot path.  Inputs are resident in HBM before the timed region starts.
+
+Prints ONE JSON line (rank 0).  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS + HBM GB/s (%roofline), FP32-shifted vs FP64 D2Q9; adjoint/fwd time"
+# algorithmic bytes per cell update: 8 moving populations read + written, rest population FP64 read + written
+BYTES = {"fp32": 8 * 4 * 2 + 8 * 2, "fp64": 9 * 8 * 2}
+
+EOS_KW = dict(base=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
+TAU = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]
+
+
+def workload_name(n, R):
+    return ("static droplet %dx%d periodic, R=%d, shaped PR Tr=0.5 (Smooth alpha=0.3, k_vap=4, scale 0.25), "
+            "MRT tau_nu=0.7, Li forcing" % (n, n, R))
+
+
+def make_lattice(lbm, n, prec, R=None, reduce_every=100, band_rows=0, variant=0):
+    from lbm_inputs import droplet_density
+
+    e, s = lbm.eos_build(lbm.make_eos(**EOS_KW))
+    R = n // 6 if R is None else R
+    rho0 = droplet_density(n, n, e.rho_v, e.rho_l, R=R, W=20)
+    P = lbm.make_params(n, n, e, sigma=s, tau=TAU, prec=lbm.FP32_SHIFTED if prec == "fp32" else lbm.FP64,
+                        reduce_every=reduce_every, band_rows=band_rows, kernel_variant=variant)
+    return lbm.Lattice(P, rho0, device="cuda:0"), e, s, rho0
+
+
+def time_steps(L, steps, warmup):
+    import torch
+
+    L.step(warmup)
+    torch.cuda.synchronize()
+    stream = L.stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    L.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / 1e3, wall
+
+
+def copy_bandwidth(nbytes=1 << 31, reps=20):
+    """Read+write bandwidth of a plain device copy (torch's copy kernel) of `nbytes`."""
+    import torch
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_moved": 2 * nbytes, "GB/s": 2 * nbytes / sec / 1e9, "us": sec * 1e6}
+
+
+def cpu_baseline(n, steps):
+    """The FP64 oracle on a bounded sample of the same workload (single thread)."""
+    import oracle as O
+    from lbm_inputs import droplet_density
+
+    eo, so = O.eos_build(O.make_eos(**EOS_KW))
+    rho0 = droplet_density(n, n, eo.rho_v, eo.rho_l, R=n // 6, W=20)
+    L = O.Lattice(O.make_params(n, n, eo, sigma=so, tau=TAU))
+    L.init_eq(rho0)
+    t0 = time.perf_counter()
+    L.run(steps)
+    dt = time.perf_counter() - t0
+    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "%dx%d droplet, %d time steps from the same initial state (FP64, single thread, %.1f s)"
+                      % (n, n, steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--n", type=int, default=512, help="lattice side of the timed workload")
+    ap.add_argument("--sweep", default="2048,4096,8192", help="extra lattice sides for the HBM roofline ('' = none)")
+    ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", default="", help="fp32 | fp64: time just one precision of the main workload")
+    ap.add_argument("--band-rows", type=int, default=0, help="rows per wave band (0 = the library's choice)")
+    ap.add_argument("--sweep-band-rows", default="", help="comma list of band heights to time in the sweep")
+    ap.add_argument("--calib-only", action="store_true", help="only measure the plain copy bandwidth")
+    ap.add_argument("--variant", type=int, default=0, help="step-kernel decomposition: 0 auto, 1 row march, 2 row block")
+    ap.add_argument("--sweep-variants", default="", help="comma list of kernel variants for the sweep")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs the hot path on ONE GPU; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2107_06355_amd import lbm
+
+    lbm.load()
+    torch.cuda.set_device(0)
+    calib = copy_bandwidth()
+    print("# device copy: %.0f GB/s (read+write, %d MiB buffers)" % (calib["GB/s"], calib["bytes_moved"] >> 21),
+          file=sys.stderr, flush=True)
+    if args.calib_only:
+        print(json.dumps({"copy": calib}), flush=True)
+        return
+    n = args.n
+    res = {}
+    for prec in ("fp32", "fp64"):
+        if args.only and prec != args.only:
+            continue
+        L, e, s, _ = make_lattice(lbm, n, prec, band_rows=args.band_rows, variant=args.variant)
+        var, rows, waves = lbm.describe(L.P)
+        sec, wall = time_steps(L, args.steps, args.warmup)
+        L.check()
+        cells = n * n
+        mlups = cells * args.steps / sec / 1e6
+        gbs = BYTES[prec] * cells * args.steps / sec / 1e9
+        res[prec] = {"MLUPS": mlups, "GB/s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+                     "ms_per_step": sec * 1e3 / args.steps, "wall_s": wall,
+                     "avg_launch_us": sec * 1e6 / args.steps,
+                     "kernel": ("k_step_blk<%s>" if var == lbm.VARIANT_BLOCK else "k_step<%s>")
+                               % ("float" if prec == "fp32" else "double"),
+                     "rows_per_block": rows, "waves": waves}
+        print("# %s %dx%d: %.1f MLUPS, %.1f GB/s algorithmic (%.1f%% of 8 TB/s), %.2f us/step"
+              % (prec, n, n, mlups, gbs, 100 * gbs / HBM_PEAK_GBS, sec * 1e6 / args.steps), file=sys.stderr, flush=True)
+        L.close()
+        del L
+        torch.cuda.empty_cache()
+
+    sweep = []
+    bands = [int(v) for v in args.sweep_band_rows.split(",") if v.strip()] or [0]
+    variants = [int(v) for v in args.sweep_variants.split(",") if v.strip()] or [args.variant]
+    combos = [(v, b) for v in variants for b in (bands if v == 1 else [0])]
+    for side in [int(v) for v in args.sweep.split(",") if v.strip()]:
+        for prec in ("fp32", "fp64"):
+            if args.only and prec != args.only:
+                continue
+            for variant, band in combos:
+                L, e, s, _ = make_lattice(lbm, side, prec, reduce_every=0, band_rows=band, variant=variant)
+                sec, wall = time_steps(L, args.sweep_steps, 20)
+                L.check()
+                cells = side * side
+                gbs = BYTES[prec] * cells * args.sweep_steps / sec / 1e9
+                sweep.append({"n": side, "prec": prec, "variant": variant, "band_rows": band,
+                              "MLUPS": cells * args.sweep_steps / sec / 1e6,
+                              "GB/s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+                              "avg_launch_us": sec * 1e6 / args.sweep_steps})
+                print("# sweep %s %dx%d variant=%d band=%d: %.0f MLUPS, %.0f GB/s (%.1f%%), %.2f us/step" % (
+                    prec, side, side, variant, band, sweep[-1]["MLUPS"], gbs, 100 * gbs / HBM_PEAK_GBS,
+                    sweep[-1]["avg_launch_us"]), file=sys.stderr, flush=True)
+                L.close()
+                del L
+                torch.cuda.empty_cache()
+
+    main_prec = "fp32" if "fp32" in res else "fp64"
+    r = res[main_prec]
+    out = {
+        "metric": METRIC,
+        "value": r["MLUPS"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if main_prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": workload_name(n, n // 6), "lattice": [n, n], "storage": main_prec,
+                   "reduce_every": 100},
+        "roofline": {"bound": "hbm", "achieved": r["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r["GB/s"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": r["kernel"], "bytes_per_cell": BYTES[main_prec],
+                     "avg_launch_us": r["avg_launch_us"]},
+        "fp64": res.get("fp64"),
+        "fp32": res.get("fp32"),
+        "sweep": sweep,
+        "copy_calibration": calib,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

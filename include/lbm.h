@@ -48,6 +48,11 @@ typedef enum {
 } lbm_status;
 
 typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_prec;
+/* Step-kernel decompositions (identical results up to FP rounding order):
+ * ROW_MARCH: one wavefront marches up a band of rows of a 62-column strip
+ * with two rows of loads in flight; ROW_BLOCK: a 16-wavefront workgroup loads
+ * 16 rows of a strip, one per wavefront, and shares psi through LDS. */
+typedef enum { LBM_VARIANT_AUTO = 0, LBM_VARIANT_MARCH = 1, LBM_VARIANT_BLOCK = 2 } lbm_variant;
 typedef enum { LBM_BASE_CS = 0, LBM_BASE_PR = 1 } lbm_base;
 typedef enum {
     LBM_SHAPE_NONE = 0,      /* the base EOS itself */
@@ -97,6 +102,8 @@ typedef struct {
     int prec;            /* lbm_prec */
     int var_tau;         /* 1: s[7] = s[8] = 1/tau(rho) of Eq. RelaxationTime (clamped to [tau_v, tau_l]) */
     int reduce_every;    /* >0: FP64 mass/momentum reduction every this many steps (history in workspace) */
+    int band_rows;       /* row-march kernel: rows per wavefront band (0 = automatic) */
+    int kernel_variant;  /* lbm_variant: step-kernel decomposition (0 = automatic) */
     double rho_wall_lo, rho_wall_hi; /* densities of the solid nodes in Eq. ShanChenForce (walls = 1) */
     double G, sigma;     /* interaction constant (< 0) and Eq. LiFS sigma (0 = Eq. GFS) */
     double tau[9];       /* relaxation times, moment order of Eq. RelaxationMatrix; tau > 1/2 */
@@ -110,6 +117,10 @@ typedef struct lbm_ctx lbm_ctx;
 /* Layout query: row pitch, bytes of ONE population buffer (the caller
  * allocates two), and bytes of the workspace. */
 int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* ws_bytes_out);
+
+/* Which step-kernel decomposition the parameters select (the automatic
+ * choice resolved), the rows per band or block, and the wavefront count. */
+int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int* waves_out);
 
 /* Create a context over caller buffers f_a, f_b (lbm_layout bytes each) and
  * workspace ws, and write the initial state f_i(0) = f^eq_i(rho0, u0)

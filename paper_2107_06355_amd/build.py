@@ -35,27 +35,29 @@ def _hip_runtime_dir() -> str:
     return d
 
 
-def build(verbose: bool = False) -> str:
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, defines=(), out: str | None = None) -> str:
+    """Compile and link liblbm.so (or `out`), with optional extra -D tuning macros."""
+    lib = out or LIB
+    objdir = os.path.join(os.path.dirname(lib), "_build" if out is None else "_build_" + os.path.basename(lib))
     os.makedirs(objdir, exist_ok=True)
     objs = []
     for s in SOURCES:
         o = os.path.join(objdir, os.path.splitext(s)[0] + ".o")
         lang = ["-x", "hip"] if s.endswith(".hip") else []
-        cmd = [HIPCC, *FLAGS, "-c", *lang, "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
+        cmd = [HIPCC, *FLAGS, *["-D" + d for d in defines], "-c", *lang, "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
                os.path.join(CSRC, s), "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(o)
     rt = _hip_runtime_dir()
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     link = ["g++", "-shared", "-o", tmp, *objs, "-L" + rt, "-lamdhip64", "-Wl,--disable-new-dtags", "-Wl,-rpath," + rt, "-Wl,--no-undefined"]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -36,6 +36,16 @@
 
 namespace {
 
+// build-time tuning: occupancy hint for the step kernel (waves per SIMD, 0 = none)
+#ifndef LBM_WAVES_PER_EU
+#define LBM_WAVES_PER_EU 0
+#endif
+#if LBM_WAVES_PER_EU > 0
+#define LBM_OCCUPANCY_HINT __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
+#else
+#define LBM_OCCUPANCY_HINT
+#endif
+
 constexpr int kStripW = 62;   // interior columns per wave
 constexpr int kWaves = 4;     // waves per workgroup
 constexpr int kHistCap = 4096;
@@ -83,7 +93,7 @@ struct StepArgs {
     size_t plane;            // elements per population plane (ny * ld)
     int nx, ny, ld, walls;
     int strips, seg_h, nseg, nwork;
-    int var_tau, pad0;
+    int var_tau, blk;        // blk: 1 = row-block (LDS) kernel, 0 = row-march kernel
     double G, sigma;
     double s[9];             // relaxation rates 1/tau
     double tau_v, dtau_drho, tau_lo, tau_hi, rho_v_tau;
@@ -120,28 +130,77 @@ struct Plane<float> {
     __device__ static double* restw(void* base, size_t plane) { return (double*)((float*)base + 8 * plane); }
 };
 
-// Pull the nine populations of fluid node (x, y): f_i(x) = f*_i(x - c_i), or
-// f*_opp(i)(x) when x - c_i is a solid node (half-way bounce-back).
+// Read-only and writable views of one population buffer: uniform per-plane base
+// pointers (scalar registers) addressed with 32-bit per-lane byte offsets.
 template <typename T>
-__device__ __forceinline__ void pull(const StepArgs& A, int x, int xm, int xp, int y, double& g0, T g[9])
+struct View {
+    const char* mv[9];   // planes 1..8 of the moving populations (index 0 unused)
+    const char* rest;    // rest population (FP64)
+};
+template <typename T>
+struct WView {
+    char* mv[9];
+    char* rest;
+};
+
+template <typename T>
+__device__ __forceinline__ View<T> make_view(const void* base, size_t plane)
 {
-    const size_t r0 = (size_t)y * A.ld;
+    View<T> V;
+    V.mv[0] = nullptr;
+    for (int i = 1; i < 9; ++i) V.mv[i] = (const char*)Plane<T>::mov(base, plane, i);
+    V.rest = (const char*)Plane<T>::rest(base, plane);
+    return V;
+}
+template <typename T>
+__device__ __forceinline__ WView<T> make_wview(void* base, size_t plane)
+{
+    WView<T> V;
+    V.mv[0] = nullptr;
+    for (int i = 1; i < 9; ++i) V.mv[i] = (char*)Plane<T>::movw(base, plane, i);
+    V.rest = (char*)Plane<T>::restw(base, plane);
+    return V;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_at(const char* base, uint32_t elem)
+{
+    return *(const T*)(base + elem * (uint32_t)sizeof(T));
+}
+
+// Pull the nine populations of fluid node (x, y): f_i(x) = f*_i(x - c_i), or
+// f*_opp(i)(x) when x - c_i is a solid node (half-way bounce-back).  The
+// wall test depends on the row only, so the plane choice is a scalar select
+// and every load keeps a scalar base with a 32-bit lane offset.
+template <typename T>
+__device__ __forceinline__ void pull(const View<T>& V, const StepArgs& A, int x, int xm, int xp, int y, double& g0,
+                                     T g[9])
+{
+    const uint32_t ld = (uint32_t)A.ld;
+    const uint32_t r0 = (uint32_t)y * ld;
     const bool bot = A.walls && y == 0;
     const bool top = A.walls && y == A.ny - 1;
-    const int ym = y == 0 ? A.ny - 1 : y - 1;
-    const int yp = y == A.ny - 1 ? 0 : y + 1;
-    const size_t rm = (size_t)ym * A.ld, rp = (size_t)yp * A.ld;
-    const void* S = A.src;
-    const size_t P = A.plane;
-    g0 = Plane<T>::rest(S, P)[r0 + x];
-    g[1] = Plane<T>::mov(S, P, 1)[r0 + xm];
-    g[3] = Plane<T>::mov(S, P, 3)[r0 + xp];
-    g[2] = bot ? Plane<T>::mov(S, P, 4)[r0 + x] : Plane<T>::mov(S, P, 2)[rm + x];
-    g[5] = bot ? Plane<T>::mov(S, P, 7)[r0 + x] : Plane<T>::mov(S, P, 5)[rm + xm];
-    g[6] = bot ? Plane<T>::mov(S, P, 8)[r0 + x] : Plane<T>::mov(S, P, 6)[rm + xp];
-    g[4] = top ? Plane<T>::mov(S, P, 2)[r0 + x] : Plane<T>::mov(S, P, 4)[rp + x];
-    g[7] = top ? Plane<T>::mov(S, P, 5)[r0 + x] : Plane<T>::mov(S, P, 7)[rp + xp];
-    g[8] = top ? Plane<T>::mov(S, P, 6)[r0 + x] : Plane<T>::mov(S, P, 8)[rp + xm];
+    const uint32_t rm = (uint32_t)(y == 0 ? A.ny - 1 : y - 1) * ld;
+    const uint32_t rp = (uint32_t)(y == A.ny - 1 ? 0 : y + 1) * ld;
+    const uint32_t ux = (uint32_t)x, um = (uint32_t)xm, up = (uint32_t)xp;
+    g0 = ld_at<double>(V.rest, r0 + ux);
+    g[1] = ld_at<T>(V.mv[1], r0 + um);
+    g[3] = ld_at<T>(V.mv[3], r0 + up);
+    if (!(bot || top)) {
+        g[2] = ld_at<T>(V.mv[2], rm + ux);
+        g[5] = ld_at<T>(V.mv[5], rm + um);
+        g[6] = ld_at<T>(V.mv[6], rm + up);
+        g[4] = ld_at<T>(V.mv[4], rp + ux);
+        g[7] = ld_at<T>(V.mv[7], rp + up);
+        g[8] = ld_at<T>(V.mv[8], rp + um);
+    } else {
+        g[2] = bot ? ld_at<T>(V.mv[4], r0 + ux) : ld_at<T>(V.mv[2], rm + ux);
+        g[5] = bot ? ld_at<T>(V.mv[7], r0 + ux) : ld_at<T>(V.mv[5], rm + um);
+        g[6] = bot ? ld_at<T>(V.mv[8], r0 + ux) : ld_at<T>(V.mv[6], rm + up);
+        g[4] = top ? ld_at<T>(V.mv[2], r0 + ux) : ld_at<T>(V.mv[4], rp + ux);
+        g[7] = top ? ld_at<T>(V.mv[5], r0 + ux) : ld_at<T>(V.mv[7], rp + up);
+        g[8] = top ? ld_at<T>(V.mv[6], r0 + ux) : ld_at<T>(V.mv[8], rp + um);
+    }
 }
 
 // deviation of the node density from rho_ref, exact sum in FP64
@@ -152,27 +211,44 @@ __device__ __forceinline__ double node_drho(double g0, const T g[9])
            (((double)g[5] + (double)g[6]) + ((double)g[7] + (double)g[8]));
 }
 
-__device__ __forceinline__ double node_psi(const StepArgs& A, double rho, bool check)
+__device__ __forceinline__ void flag_unstable(const StepArgs& A)
 {
-    const double p = dev_eos_p(A.eos, rho);
-    const double q = 2.0 * (p - rho * (1.0 / 3.0)) / A.G;
-    if (check && !(q >= 0.0 && rho > 0.0)) {
-        atomicOr(A.err, 1u);
-        atomicMin(A.err + 1, (unsigned)A.step);
-    }
-    return q > 0.0 ? sqrt(q) : 0.0;
+    atomicOr(A.err, 1u);
+    atomicMin(A.err + 1, (unsigned)A.step);
 }
 
-template <typename T>
-__device__ __forceinline__ T psi_of_row(const StepArgs& A, int y, int x, int xm, int xp, bool valid)
+// base EOS in FP32 (bulk branches of the FP32 path)
+__device__ __forceinline__ float dev_base_pf(const DevEos& E, float r)
 {
-    if (A.walls && y < 0) return (T)A.psi_lo;
-    if (A.walls && y >= A.ny) return (T)A.psi_hi;
-    const int yy = y < 0 ? y + A.ny : (y >= A.ny ? y - A.ny : y);
-    double g0;
-    T g[9];
-    pull<T>(A, x, xm, xp, yy, g0, g);
-    return (T)node_psi(A, A.rho_ref + node_drho<T>(g0, g), valid);
+    if (E.base == LBM_BASE_CS) {
+        const float n = 0.25f * (float)E.b * r, m = 1.0f - n;
+        return (float)E.scale * ((float)E.RT * r * (1.0f + n * (1.0f + n * (1.0f - n))) / (m * m * m) - (float)E.aal * r * r);
+    }
+    const float br = (float)E.b * r;
+    return (float)E.scale * ((float)E.RT * r / (1.0f - br) - (float)E.aal * r * r / (1.0f + br * (2.0f - br)));
+}
+
+// psi (Eq. InteractionPotential, c = 1) of a node with density rho_ref + drho.
+// FP64 path: everything in FP64.  FP32 path: the bulk vapor/liquid branches in
+// FP32, the shaped loop between rho_v and rho_l (the branch junctions) in FP64.
+template <typename T>
+__device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check)
+{
+    const double rho = A.rho_ref + drho;
+    const DevEos& E = A.eos;
+    if (sizeof(T) == 4 && E.shape != LBM_SHAPE_NONE && (rho <= E.rho_v || rho >= E.rho_l)) {
+        const float r = (float)rho;
+        const float pb = dev_base_pf(E, r);
+        const float p = rho <= E.rho_v ? (float)E.k_vap * pb : pb + (float)E.dP;
+        const float q = 2.0f * (p - r * (1.0f / 3.0f)) / (float)A.G;
+        if (check && !(q >= 0.0f && r > 0.0f)) flag_unstable(A);
+        return (T)(q > 0.0f ? sqrtf(q) : 0.0f);
+    }
+    const double p = dev_eos_p(E, rho);
+    const double q = 2.0 * (p - rho * (1.0 / 3.0)) / A.G;
+    if (check && !(q >= 0.0 && rho > 0.0)) flag_unstable(A);
+    if (sizeof(T) == 4) return (T)(q > 0.0 ? sqrtf((float)q) : 0.0f);
+    return (T)(q > 0.0 ? sqrt(q) : 0.0);
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -181,163 +257,311 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_step(StepArgs A)
+template <typename T>
+struct Row {
+    double g0;
+    T g[9];
+};
+
+struct Lane {
+    int lane, x, xm, xp;
+    bool valid, interior;
+};
+
+struct Acc {
+    double m, x, y;
+};
+
+// row index that is always safe to load: periodic wrap, or clamped at walls
+__device__ __forceinline__ int load_index(const StepArgs& A, int r)
 {
-    const int lane = threadIdx.x & 63;
+    if (A.walls) return r < 0 ? 0 : (r >= A.ny ? A.ny - 1 : r);
+    return r < 0 ? r + A.ny : (r >= A.ny ? r % A.ny : r);
+}
+
+// Collide row y (populations P, density deviation drp) with psi of rows y-1, y, y+1.
+// Node update of an interior lane: moments, forced velocity, MRT relaxation with
+// the Eq. LiFS source, inverse transform and store (or the macroscopic outputs).
+// psB = psi(x, y); Ftx, Fty = F~ = F/psi(x) from Eq. ShanChenForce.
+template <typename T, int MODE>
+__device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, int y, const Row<T>& P, double drp,
+                                            T psB, T Ftx, T Fty, Acc& acc)
+{
+    const T* gp = P.g;
+    const int x = L.x;
+    const double rho_d = A.rho_ref + drp;
+    const T rho = (T)rho_d;
+    const T dr = (T)drp;
+    const T Fx = psB * Ftx, Fy = psB * Fty;
+    const T g0t = (T)P.g0;
+    // moments m = M g (Eq. MatrixMRT rows)
+    const T s14 = (gp[1] + gp[2]) + (gp[3] + gp[4]);
+    const T s58 = (gp[5] + gp[6]) + (gp[7] + gp[8]);
+    const T jx = (gp[1] - gp[3]) + ((gp[5] - gp[6]) - (gp[7] - gp[8]));
+    const T jy = (gp[2] - gp[4]) + ((gp[5] + gp[6]) - (gp[7] + gp[8]));
+    const T me = -4 * g0t - s14 + 2 * s58;
+    const T mq = 4 * g0t - 2 * s14 + s58;
+    const T mqx = -2 * (gp[1] - gp[3]) + ((gp[5] - gp[6]) - (gp[7] - gp[8]));
+    const T mqy = -2 * (gp[2] - gp[4]) + ((gp[5] + gp[6]) - (gp[7] + gp[8]));
+    const T mxx = (gp[1] - gp[2]) + (gp[3] - gp[4]);
+    const T mxy = (gp[5] - gp[6]) + (gp[7] - gp[8]);
+    // forced velocity (Eq. Momentum)
+    const T inv_rho = (T)1 / rho;
+    const T ux = (jx + (T)0.5 * Fx) * inv_rho, uy = (jy + (T)0.5 * Fy) * inv_rho;
+
+    if (MODE == MODE_MACROS) {
+        const size_t o = (size_t)y * A.nx + x;
+        if (A.o_rho) A.o_rho[o] = rho_d;
+        if (A.o_ux) A.o_ux[o] = (double)ux;
+        if (A.o_uy) A.o_uy[o] = (double)uy;
+        if (A.o_psi) A.o_psi[o] = (double)psB;
+        if (A.o_p) A.o_p[o] = dev_eos_p(A.eos, rho_d);
+        if (A.o_fx) A.o_fx[o] = (double)Fx;
+        if (A.o_fy) A.o_fy[o] = (double)Fy;
+    }
+    if (MODE != MODE_STEP) {
+        acc.m += rho_d;
+        acc.x += (double)rho * (double)ux;
+        acc.y += (double)rho * (double)uy;
+    }
+    if (MODE == MODE_MACROS) return;
+    // rates (Eq. RelaxationMatrix; Eq. RelaxationTime on the shear moments)
+    const T se = (T)A.s[1], sq = (T)A.s[2], sqx = (T)A.s[4], sqy = (T)A.s[6];
+    T snu = (T)A.s[7];
+    if (A.var_tau) {
+        double tau = A.tau_v + A.dtau_drho * (rho_d - A.rho_v_tau);
+        tau = fmin(fmax(tau, A.tau_lo), A.tau_hi);
+        snu = (T)(1.0 / tau);
+    }
+    const T u2 = ux * ux + uy * uy;
+    const T uF = ux * Fx + uy * Fy;
+    const T F2 = Ftx * Ftx + Fty * Fty;  // |F|^2/psi^2
+    // equilibrium deviation moments (M f^eq minus the rho_ref rest state)
+    const T eqe = -2 * dr + 3 * rho * u2;
+    const T eqq = dr - 3 * rho * u2;
+    const T eqxx = rho * (ux * ux - uy * uy);
+    const T eqxy = rho * ux * uy;
+    // Eq. LiFS source, multiplied by (I - Lambda/2)
+    const T sig12 = (T)(12.0 * A.sigma) * F2;
+    const T Se = ((T)6 * uF + sig12 / ((T)1 / se - (T)0.5)) * ((T)1 - (T)0.5 * se);
+    const T Sq = (-(T)6 * uF - sig12 / ((T)1 / sq - (T)0.5)) * ((T)1 - (T)0.5 * sq);
+    // relaxed moments m* = m - Lambda (m - m^eq) + (I - Lambda/2) S
+    const T ne = (me - se * (me - eqe) + Se) * (T)(1.0 / 36.0);
+    const T nq = (mq - sq * (mq - eqq) + Sq) * (T)(1.0 / 36.0);
+    const T nqx = (mqx - sqx * (mqx + rho * ux) - ((T)1 - (T)0.5 * sqx) * Fx) * (T)(1.0 / 12.0);
+    const T nqy = (mqy - sqy * (mqy + rho * uy) - ((T)1 - (T)0.5 * sqy) * Fy) * (T)(1.0 / 12.0);
+    const T nxx = (mxx - snu * (mxx - eqxx) + ((T)1 - (T)0.5 * snu) * (T)2 * (ux * Fx - uy * Fy)) * (T)0.25;
+    const T nxy = (mxy - snu * (mxy - eqxy) + ((T)1 - (T)0.5 * snu) * (ux * Fy + uy * Fx)) * (T)0.25;
+    const T n0 = dr * (T)(1.0 / 9.0);
+    const T njx = (jx + Fx) * (T)(1.0 / 6.0);
+    const T njy = (jy + Fy) * (T)(1.0 / 6.0);
+    // f* = M^-1 m* = M^T diag(1/9,1/36,1/36,1/6,1/12,1/6,1/12,1/4,1/4) m*
+    const T a14 = n0 - ne - 2 * nq;
+    const T a58 = n0 + 2 * ne + nq;
+    T o[9];
+    o[1] = a14 + njx - 2 * nqx + nxx;
+    o[2] = a14 + njy - 2 * nqy - nxx;
+    o[3] = a14 - njx + 2 * nqx + nxx;
+    o[4] = a14 - njy + 2 * nqy - nxx;
+    o[5] = a58 + njx + nqx + njy + nqy + nxy;
+    o[6] = a58 - njx - nqx + njy + nqy - nxy;
+    o[7] = a58 - njx - nqx - njy - nqy + nxy;
+    o[8] = a58 + njx + nqx - njy - nqy - nxy;
+    const WView<T> D = make_wview<T>(A.dst, A.plane);
+    const uint32_t off = (uint32_t)y * (uint32_t)A.ld + (uint32_t)x;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) *(T*)(D.mv[i] + off * (uint32_t)sizeof(T)) = o[i];
+    // rest population: exact node mass in FP64 (conserved by the collision)
+    const double o0 = drp - ((((double)o[1] + (double)o[2]) + ((double)o[3] + (double)o[4])) +
+                             (((double)o[5] + (double)o[6]) + ((double)o[7] + (double)o[8])));
+    *(double*)(D.rest + off * 8u) = o0;
+}
+
+// Eq. ShanChenForce / psi(x): F~ = -G sum_i w(|c_i|^2) psi(x + c_i) c_i, written as
+// differences; arguments are psi at (x-1, x, x+1) of rows y-1 (m), y (c), y+1 (n).
+template <typename T>
+__device__ __forceinline__ void force_tilde(const StepArgs& A, T lm, T cm, T rm_, T lc, T rc, T ln, T cn, T rn_,
+                                            T& Ftx, T& Fty)
+{
+    const T G = (T)A.G;
+    const T third = (T)(1.0 / 3.0), twelfth = (T)(1.0 / 12.0);
+    Ftx = -G * ((rc - lc) * third + ((rn_ - ln) + (rm_ - lm)) * twelfth);
+    Fty = -G * ((cn - cm) * third + ((rn_ + ln) - (rm_ + lm)) * twelfth);
+}
+
+// Collide row y of a marching wave: psi of the x-neighbours comes from the
+// adjacent lanes (all lanes take part in the shuffles).
+template <typename T, int MODE>
+__device__ __forceinline__ void collide_row(const StepArgs& A, const Lane& L, int y, const Row<T>& P, double drp,
+                                            T psA, T psB, T ps, Acc& acc)
+{
+    const T lm = __shfl(psA, L.lane - 1, 64), rm_ = __shfl(psA, L.lane + 1, 64);
+    const T lc = __shfl(psB, L.lane - 1, 64), rc = __shfl(psB, L.lane + 1, 64);
+    const T ln = __shfl(ps, L.lane - 1, 64), rn_ = __shfl(ps, L.lane + 1, 64);
+    T Ftx, Fty;
+    force_tilde<T>(A, lm, psA, rm_, lc, rc, ln, ps, rn_, Ftx, Fty);
+    if (!L.interior) return;
+    update_node<T, MODE>(A, L, y, P, drp, psB, Ftx, Fty, acc);
+}
+
+// One row of the march.  Rp holds row r-1 (collision), Rc row r (psi now), Rn
+// row r+1 (loads in flight since the previous row) and the loads of row r+2 are
+// issued into Rf before anything waits on memory: two rows stay in flight.
+template <typename T, int MODE>
+__device__ __forceinline__ void march_row(const StepArgs& A, const View<T>& V, const Lane& L, int r, int y0, int y1,
+                                          Row<T>& Rp, Row<T>& Rc, Row<T>& Rf, double& drp, double& drc, T& psA,
+                                          T& psB, Acc& acc)
+{
+    if (r > y1) return;
+    if (r + 2 <= y1) pull<T>(V, A, L.x, L.xm, L.xp, load_index(A, r + 2), Rf.g0, Rf.g);
+    drc = node_drho<T>(Rc.g0, Rc.g);
+    T ps;
+    if (A.walls && r < 0) ps = (T)A.psi_lo;
+    else if (A.walls && r >= A.ny) ps = (T)A.psi_hi;
+    else ps = node_psi<T>(A, drc, L.valid);
+    if (r - 1 >= y0) collide_row<T, MODE>(A, L, r - 1, Rp, drp, psA, psB, ps, acc);
+    psA = psB;
+    psB = ps;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) LBM_OCCUPANCY_HINT void k_step(StepArgs A)
+{
     const int nb = gridDim.x;
     const int logical = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);  // XCD-contiguous bands
-    const int w = logical * kWaves + (threadIdx.x >> 6);
+    // the wave index is uniform across the wave: keep it (and everything derived
+    // from it: band, rows, wall tests, plane selects) in scalar registers
+    const int w = logical * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (w >= A.nwork) return;
+    Lane L;
+    L.lane = threadIdx.x & 63;
     const int strip = w % A.strips, seg = w / A.strips;
     const int x0 = strip * kStripW;
     const int W = min(kStripW, A.nx - x0);
-    const int xr = x0 - 1 + lane;
-    const bool valid = lane <= W + 1;
-    const bool interior = lane >= 1 && lane <= W;
+    const int xr = x0 - 1 + L.lane;
+    L.valid = L.lane <= W + 1;
+    L.interior = L.lane >= 1 && L.lane <= W;
     int x = xr < 0 ? xr + A.nx : (xr >= A.nx ? xr - A.nx : xr);
-    if (!valid) x = 0;
-    const int xm = x == 0 ? A.nx - 1 : x - 1;
-    const int xp = x == A.nx - 1 ? 0 : x + 1;
+    if (!L.valid) x = 0;
+    L.x = x;
+    L.xm = x == 0 ? A.nx - 1 : x - 1;
+    L.xp = x == A.nx - 1 ? 0 : x + 1;
     const int y0 = seg * A.seg_h;
     const int y1 = min(A.ny, y0 + A.seg_h);
+    const View<T> V = make_view<T>(A.src, A.plane);
+    Acc acc = {0.0, 0.0, 0.0};
 
-    const T G = (T)A.G;
-    const T third = (T)(1.0 / 3.0), twelfth = (T)(1.0 / 12.0);
-    double accm = 0.0, accx = 0.0, accy = 0.0;
-
-    T psm = psi_of_row<T>(A, y0 - 1, x, xm, xp, valid);
-    double g0c;
-    T gc[9];
-    pull<T>(A, x, xm, xp, y0, g0c, gc);
-    double drc = node_drho<T>(g0c, gc);
-    T psc = (T)node_psi(A, A.rho_ref + drc, valid);
-
-    for (int y = y0; y < y1; ++y) {
-        double g0n = 0.0, drn = 0.0;
-        T gn[9];
-        T psn;
-        if (y + 1 < y1) {
-            pull<T>(A, x, xm, xp, y + 1, g0n, gn);
-            drn = node_drho<T>(g0n, gn);
-            psn = (T)node_psi(A, A.rho_ref + drn, valid);
-        } else {
-            psn = psi_of_row<T>(A, y + 1, x, xm, xp, valid);
-        }
-        // psi of the x-neighbours from the adjacent lanes (all lanes take part)
-        const T lm = __shfl(psm, lane - 1, 64), rm = __shfl(psm, lane + 1, 64);
-        const T lc = __shfl(psc, lane - 1, 64), rc = __shfl(psc, lane + 1, 64);
-        const T ln = __shfl(psn, lane - 1, 64), rn = __shfl(psn, lane + 1, 64);
-        // Eq. ShanChenForce / psi(x): F~ = -G sum_i w(|c_i|^2) psi(x + c_i) c_i, written as differences
-        const T Ftx = -G * ((rc - lc) * third + ((rn - ln) + (rm - lm)) * twelfth);
-        const T Fty = -G * ((psn - psm) * third + ((rn + ln) - (rm + lm)) * twelfth);
-
-        if (interior) {
-            const double rho_d = A.rho_ref + drc;
-            const T rho = (T)rho_d;
-            const T dr = (T)drc;
-            const T Fx = psc * Ftx, Fy = psc * Fty;
-            const T g0t = (T)g0c;
-            // moments m = M g (Eq. MatrixMRT rows)
-            const T s14 = (gc[1] + gc[2]) + (gc[3] + gc[4]);
-            const T s58 = (gc[5] + gc[6]) + (gc[7] + gc[8]);
-            const T jx = (gc[1] - gc[3]) + ((gc[5] - gc[6]) - (gc[7] - gc[8]));
-            const T jy = (gc[2] - gc[4]) + ((gc[5] + gc[6]) - (gc[7] + gc[8]));
-            const T me = -4 * g0t - s14 + 2 * s58;
-            const T mq = 4 * g0t - 2 * s14 + s58;
-            const T mqx = -2 * (gc[1] - gc[3]) + ((gc[5] - gc[6]) - (gc[7] - gc[8]));
-            const T mqy = -2 * (gc[2] - gc[4]) + ((gc[5] + gc[6]) - (gc[7] + gc[8]));
-            const T mxx = (gc[1] - gc[2]) + (gc[3] - gc[4]);
-            const T mxy = (gc[5] - gc[6]) + (gc[7] - gc[8]);
-            // forced velocity (Eq. Momentum)
-            const T inv_rho = (T)1 / rho;
-            const T ux = (jx + (T)0.5 * Fx) * inv_rho, uy = (jy + (T)0.5 * Fy) * inv_rho;
-
-            if (MODE == MODE_MACROS) {
-                const size_t o = (size_t)y * A.nx + x;
-                if (A.o_rho) A.o_rho[o] = rho_d;
-                if (A.o_ux) A.o_ux[o] = (double)ux;
-                if (A.o_uy) A.o_uy[o] = (double)uy;
-                if (A.o_psi) A.o_psi[o] = (double)psc;
-                if (A.o_p) A.o_p[o] = dev_eos_p(A.eos, rho_d);
-                if (A.o_fx) A.o_fx[o] = (double)Fx;
-                if (A.o_fy) A.o_fy[o] = (double)Fy;
-                accm += rho_d;
-                accx += (double)rho * (double)ux;
-                accy += (double)rho * (double)uy;
-            } else {
-                if (MODE == MODE_STEP_REDUCE) {
-                    accm += rho_d;
-                    accx += (double)rho * (double)ux;
-                    accy += (double)rho * (double)uy;
-                }
-                // rates (Eq. RelaxationMatrix; Eq. RelaxationTime on the shear moments)
-                const T se = (T)A.s[1], sq = (T)A.s[2], sqx = (T)A.s[4], sqy = (T)A.s[6];
-                T snu = (T)A.s[7];
-                if (A.var_tau) {
-                    double tau = A.tau_v + A.dtau_drho * (rho_d - A.rho_v_tau);
-                    tau = fmin(fmax(tau, A.tau_lo), A.tau_hi);
-                    snu = (T)(1.0 / tau);
-                }
-                const T u2 = ux * ux + uy * uy;
-                const T uF = ux * Fx + uy * Fy;
-                const T F2 = Ftx * Ftx + Fty * Fty;  // |F|^2/psi^2
-                // equilibrium deviation moments (M f^eq minus the rho_ref rest state)
-                const T eqe = -2 * dr + 3 * rho * u2;
-                const T eqq = dr - 3 * rho * u2;
-                const T eqxx = rho * (ux * ux - uy * uy);
-                const T eqxy = rho * ux * uy;
-                // Eq. LiFS source, multiplied by (I - Lambda/2)
-                const T sig12 = (T)(12.0 * A.sigma) * F2;
-                const T Se = ((T)6 * uF + sig12 / ((T)1 / se - (T)0.5)) * ((T)1 - (T)0.5 * se);
-                const T Sq = (-(T)6 * uF - sig12 / ((T)1 / sq - (T)0.5)) * ((T)1 - (T)0.5 * sq);
-                // relaxed moments m* = m - Lambda (m - m^eq) + (I - Lambda/2) S
-                const T ne = (me - se * (me - eqe) + Se) * (T)(1.0 / 36.0);
-                const T nq = (mq - sq * (mq - eqq) + Sq) * (T)(1.0 / 36.0);
-                const T nqx = (mqx - sqx * (mqx + rho * ux) - ((T)1 - (T)0.5 * sqx) * Fx) * (T)(1.0 / 12.0);
-                const T nqy = (mqy - sqy * (mqy + rho * uy) - ((T)1 - (T)0.5 * sqy) * Fy) * (T)(1.0 / 12.0);
-                const T nxx = (mxx - snu * (mxx - eqxx) + ((T)1 - (T)0.5 * snu) * (T)2 * (ux * Fx - uy * Fy)) * (T)0.25;
-                const T nxy = (mxy - snu * (mxy - eqxy) + ((T)1 - (T)0.5 * snu) * (ux * Fy + uy * Fx)) * (T)0.25;
-                const T n0 = dr * (T)(1.0 / 9.0);
-                const T njx = (jx + Fx) * (T)(1.0 / 6.0);
-                const T njy = (jy + Fy) * (T)(1.0 / 6.0);
-                // f* = M^-1 m* = M^T diag(1/9,1/36,1/36,1/6,1/12,1/6,1/12,1/4,1/4) m*
-                const T a14 = n0 - ne - 2 * nq;
-                const T a58 = n0 + 2 * ne + nq;
-                T o[9];
-                o[1] = a14 + njx - 2 * nqx + nxx;
-                o[2] = a14 + njy - 2 * nqy - nxx;
-                o[3] = a14 - njx + 2 * nqx + nxx;
-                o[4] = a14 - njy + 2 * nqy - nxx;
-                o[5] = a58 + njx + nqx + njy + nqy + nxy;
-                o[6] = a58 - njx - nqx + njy + nqy - nxy;
-                o[7] = a58 - njx - nqx - njy - nqy + nxy;
-                o[8] = a58 + njx + nqx - njy - nqy - nxy;
-                const size_t off = (size_t)y * A.ld + x;
-                const size_t P = A.plane;
+    if (A.seg_h == 1) {
+        // One-row bands (small lattices): all three rows are loaded at once and
+        // their psi evaluated as independent chains, so each wave waits on memory
+        // only once.
+        Row<T> Rm, Rc, Rp;
+        pull<T>(V, A, L.x, L.xm, L.xp, load_index(A, y0 - 1), Rm.g0, Rm.g);
+        pull<T>(V, A, L.x, L.xm, L.xp, y0, Rc.g0, Rc.g);
+        pull<T>(V, A, L.x, L.xm, L.xp, load_index(A, y0 + 1), Rp.g0, Rp.g);
+        const double dm = node_drho<T>(Rm.g0, Rm.g), dc = node_drho<T>(Rc.g0, Rc.g), dp = node_drho<T>(Rp.g0, Rp.g);
+        const T psm = (A.walls && y0 == 0) ? (T)A.psi_lo : node_psi<T>(A, dm, L.valid);
+        const T psc = node_psi<T>(A, dc, L.valid);
+        const T psp = (A.walls && y0 == A.ny - 1) ? (T)A.psi_hi : node_psi<T>(A, dp, L.valid);
+        collide_row<T, MODE>(A, L, y0, Rc, dc, psm, psc, psp, acc);
+    } else {
+    // March over rows r = y0-1 .. y1 (row r-1 is collided once psi(r) is known),
+    // unrolled four times so that the four row registers change roles without copies.
+    Row<T> R0, R1, R2, R3;
+    R3.g0 = 0.0;
 #pragma unroll
-                for (int i = 1; i < 9; ++i) Plane<T>::movw(A.dst, P, i)[off] = o[i];
-                // rest population: exact node mass in FP64 (conserved by the collision)
-                const double o0 = drc - ((((double)o[1] + (double)o[2]) + ((double)o[3] + (double)o[4])) +
-                                         (((double)o[5] + (double)o[6]) + ((double)o[7] + (double)o[8])));
-                Plane<T>::restw(A.dst, P)[off] = o0;
-            }
-        }
-        psm = psc;
-        psc = psn;
-        g0c = g0n;
-        drc = drn;
-#pragma unroll
-        for (int i = 1; i < 9; ++i) gc[i] = gn[i];
+    for (int i = 0; i < 9; ++i) R3.g[i] = (T)0;
+    pull<T>(V, A, L.x, L.xm, L.xp, load_index(A, y0 - 1), R0.g0, R0.g);
+    pull<T>(V, A, L.x, L.xm, L.xp, load_index(A, y0), R1.g0, R1.g);
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;  // density deviations of the rows in R0..R3
+    T psA = (T)0, psB = (T)0;
+    for (int r = y0 - 1; r <= y1; r += 4) {
+        march_row<T, MODE>(A, V, L, r, y0, y1, R3, R0, R2, d3, d0, psA, psB, acc);
+        march_row<T, MODE>(A, V, L, r + 1, y0, y1, R0, R1, R3, d0, d1, psA, psB, acc);
+        march_row<T, MODE>(A, V, L, r + 2, y0, y1, R1, R2, R0, d1, d2, psA, psB, acc);
+        march_row<T, MODE>(A, V, L, r + 3, y0, y1, R2, R3, R1, d2, d3, psA, psB, acc);
+    }
     }
     if (MODE != MODE_STEP) {
-        accm = wave_sum(accm);
-        accx = wave_sum(accx);
-        accy = wave_sum(accy);
-        if (lane == 0) {
-            A.partials[3 * w + 0] = accm;
-            A.partials[3 * w + 1] = accx;
-            A.partials[3 * w + 2] = accy;
+        acc.m = wave_sum(acc.m);
+        acc.x = wave_sum(acc.x);
+        acc.y = wave_sum(acc.y);
+        if (L.lane == 0) {
+            A.partials[3 * w + 0] = acc.m;
+            A.partials[3 * w + 1] = acc.x;
+            A.partials[3 * w + 2] = acc.y;
+        }
+    }
+}
+
+// Row-block variant: a workgroup of 12 waves owns 12 consecutive rows of one
+// strip (10 output rows and the two psi halo rows).  Every wave pulls ONE row,
+// evaluates psi once per node into LDS, and after one barrier the 10 inner
+// waves read the 3x3 psi stencil from LDS and update their nodes.  psi is thus
+// evaluated 12/10 times per output node, with one row of loads per wave; two
+// workgroups fit on a CU at the kernel's scalar-register occupancy.
+#ifndef LBM_BLK_WAVES
+#define LBM_BLK_WAVES 12
+#endif
+constexpr int kBlkWaves = LBM_BLK_WAVES;
+constexpr int kBlkRows = kBlkWaves - 2;
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
+{
+    __shared__ T sps[kBlkWaves][64];
+    const int nb = gridDim.x;
+    const int logical = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);  // XCD-contiguous blocks
+    if (logical * kBlkWaves >= A.nwork) return;  // whole workgroup leaves together
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    Lane L;
+    L.lane = threadIdx.x & 63;
+    const int strip = logical % A.strips, band = logical / A.strips;
+    const int x0 = strip * kStripW;
+    const int W = min(kStripW, A.nx - x0);
+    const int xr = x0 - 1 + L.lane;
+    L.valid = L.lane <= W + 1;
+    L.interior = L.lane >= 1 && L.lane <= W;
+    int x = xr < 0 ? xr + A.nx : (xr >= A.nx ? xr - A.nx : xr);
+    if (!L.valid) x = 0;
+    L.x = x;
+    L.xm = x == 0 ? A.nx - 1 : x - 1;
+    L.xp = x == A.nx - 1 ? 0 : x + 1;
+    const int y0 = band * kBlkRows;
+    const int y1 = min(A.ny, y0 + kBlkRows);
+    const int r = y0 - 1 + k;  // this wave's row; rows y0-1 .. y1 are needed
+    const View<T> V = make_view<T>(A.src, A.plane);
+    Acc acc = {0.0, 0.0, 0.0};
+
+    Row<T> R;
+    double dr = 0.0;
+    T ps = (T)0;
+    if (r <= y1) {
+        if (A.walls && r < 0) ps = (T)A.psi_lo;
+        else if (A.walls && r >= A.ny) ps = (T)A.psi_hi;
+        else {
+            pull<T>(V, A, L.x, L.xm, L.xp, load_index(A, r), R.g0, R.g);
+            dr = node_drho<T>(R.g0, R.g);
+            ps = node_psi<T>(A, dr, L.valid);
+        }
+    }
+    sps[k][L.lane] = ps;
+    __syncthreads();
+    if (r >= y0 && r < y1 && L.interior) {
+        T Ftx, Fty;
+        force_tilde<T>(A, sps[k - 1][L.lane - 1], sps[k - 1][L.lane], sps[k - 1][L.lane + 1], sps[k][L.lane - 1],
+                       sps[k][L.lane + 1], sps[k + 1][L.lane - 1], sps[k + 1][L.lane], sps[k + 1][L.lane + 1], Ftx, Fty);
+        update_node<T, MODE>(A, L, r, R, dr, ps, Ftx, Fty, acc);
+    }
+    if (MODE != MODE_STEP) {
+        acc.m = wave_sum(acc.m);
+        acc.x = wave_sum(acc.x);
+        acc.y = wave_sum(acc.y);
+        if (L.lane == 0) {
+            const int wv = logical * kBlkWaves + k;
+            A.partials[3 * wv + 0] = acc.m;
+            A.partials[3 * wv + 1] = acc.x;
+            A.partials[3 * wv + 2] = acc.y;
         }
     }
 }
@@ -404,7 +628,8 @@ __global__ void k_populations(StepArgs A, double* out)
     const int xp = x == A.nx - 1 ? 0 : x + 1;
     double g0;
     T g[9];
-    pull<T>(A, x, xm, xp, y, g0, g);
+    const View<T> V = make_view<T>(A.src, A.plane);
+    pull<T>(V, A, x, xm, xp, y, g0, g);
     const size_t n = (size_t)A.nx * A.ny, o = (size_t)y * A.nx + x;
     out[o] = g0 + kW[0] * A.rho_ref;
     for (int i = 1; i < 9; ++i) out[i * n + o] = (double)g[i] + kW[i] * A.rho_ref;
@@ -442,14 +667,31 @@ bool hip_ok(hipError_t e, const char* what)
     return false;
 }
 
-void decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg)
+// Work decomposition.  Returns the number of waves (partial-sum slots).
+// Row-march kernel: one wave per (strip, band of seg_h rows).  Row-block
+// kernel: one 16-wave workgroup per (strip, band of 14 rows).
+int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk)
 {
     *strips = (p.nx + kStripW - 1) / kStripW;
-    // band height: aim for ~4096 waves when the lattice allows, 4..64 rows
-    int h = 64;
-    while (h > 4 && (long long)(*strips) * ((p.ny + h - 1) / h) < 4096) h >>= 1;
+    int v = p.kernel_variant;
+    if (v == 0) {
+        // measured on MI355X: the row block wins while the lattice is cache-resident or
+        // the step is FP64; large FP32 lattices prefer the row march (4-row bands)
+        const long long cells = (long long)p.nx * p.ny;
+        const long long limit = p.prec == LBM_FP32_SHIFTED ? (5LL << 20) : (40LL << 20);
+        v = cells <= limit ? LBM_VARIANT_BLOCK : LBM_VARIANT_MARCH;
+    }
+    *blk = v == LBM_VARIANT_BLOCK;
+    if (*blk) {
+        *seg_h = kBlkRows;
+        *nseg = (p.ny + kBlkRows - 1) / kBlkRows;
+        return *strips * *nseg * kBlkWaves;
+    }
+    int h = p.band_rows;
+    if (h <= 0) h = p.prec == LBM_FP32_SHIFTED ? 4 : 8;  // best band heights measured on MI355X
     *seg_h = h;
     *nseg = (p.ny + h - 1) / h;
+    return *strips * *nseg;
 }
 
 size_t ws_layout(int nwork, size_t* off_part, size_t* off_hist, size_t* off_red)
@@ -504,8 +746,8 @@ int validate(const lbm_params* p)
         lbm_set_error("lbm: invalid lattice size or precision");
         return LBM_EINVAL;
     }
-    if ((long long)p->nx * p->ny > (1LL << 31)) {
-        lbm_set_error("lbm: lattice larger than 2^31 nodes");
+    if ((long long)((p->nx + 63) & ~63) * p->ny * 8 >= (1LL << 32)) {
+        lbm_set_error("lbm: one population plane must stay below 4 GiB (lattice too large)");
         return LBM_EINVAL;
     }
     if (!(p->G < 0.0)) {
@@ -517,6 +759,14 @@ int validate(const lbm_params* p)
             lbm_set_error("lbm: every relaxation time must exceed 1/2");
             return LBM_EINVAL;
         }
+    if (p->kernel_variant < 0 || p->kernel_variant > LBM_VARIANT_BLOCK) {
+        lbm_set_error("lbm: kernel_variant must be 0 (automatic), 1 (row march) or 2 (row block)");
+        return LBM_EINVAL;
+    }
+    if (p->band_rows < 0 || p->band_rows > 4096) {
+        lbm_set_error("lbm: band_rows must be in [0, 4096] (0 = automatic)");
+        return LBM_EINVAL;
+    }
     if (p->tau[7] != p->tau[8]) {
         lbm_set_error("lbm: Eq. RelaxationMatrix relaxes both shear moments with tau_nu (tau[7] == tau[8])");
         return LBM_EINVAL;
@@ -546,8 +796,7 @@ void fill_args(lbm_ctx* c)
     A.ny = p.ny;
     A.ld = c->ld;
     A.walls = p.walls;
-    decompose(p, &A.strips, &A.seg_h, &A.nseg);
-    A.nwork = A.strips * A.nseg;
+    A.nwork = decompose(p, &A.strips, &A.seg_h, &A.nseg, &A.blk);
     A.var_tau = p.var_tau;
     A.G = p.G;
     A.sigma = p.sigma;
@@ -567,7 +816,7 @@ void fill_args(lbm_ctx* c)
     A.psi_hi = p.walls ? psi_host(p.rho_wall_hi) : 0.0;
     A.partials = c->partials;
     A.err = c->err;
-    const int blocks = (A.nwork + kWaves - 1) / kWaves;
+    const int blocks = A.blk ? A.nwork / kBlkWaves : (A.nwork + kWaves - 1) / kWaves;
     c->grid = (blocks + 7) & ~7;
 }
 
@@ -578,8 +827,13 @@ bool launch_step(lbm_ctx* c, int mode, hipStream_t s)
     A.src = c->buf[c->cur];
     A.dst = c->buf[c->cur ^ 1];
     A.step = c->step;
-    if (mode == MODE_STEP) hipLaunchKernelGGL((k_step<T, MODE_STEP>), dim3(c->grid), dim3(256), 0, s, A);
-    else hipLaunchKernelGGL((k_step<T, MODE_STEP_REDUCE>), dim3(c->grid), dim3(256), 0, s, A);
+    if (A.blk) {
+        if (mode == MODE_STEP) hipLaunchKernelGGL((k_step_blk<T, MODE_STEP>), dim3(c->grid), dim3(64 * kBlkWaves), 0, s, A);
+        else hipLaunchKernelGGL((k_step_blk<T, MODE_STEP_REDUCE>), dim3(c->grid), dim3(64 * kBlkWaves), 0, s, A);
+    } else {
+        if (mode == MODE_STEP) hipLaunchKernelGGL((k_step<T, MODE_STEP>), dim3(c->grid), dim3(256), 0, s, A);
+        else hipLaunchKernelGGL((k_step<T, MODE_STEP_REDUCE>), dim3(c->grid), dim3(256), 0, s, A);
+    }
     return hip_ok(hipGetLastError(), "k_step launch");
 }
 
@@ -609,13 +863,27 @@ int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* 
     const int ld = (p->nx + 63) & ~63;
     const size_t plane = (size_t)ld * p->ny;
     const size_t bytes = p->prec == LBM_FP32_SHIFTED ? plane * (8 * sizeof(float) + sizeof(double)) : plane * 9 * sizeof(double);
-    int strips, seg_h, nseg;
-    decompose(*p, &strips, &seg_h, &nseg);
+    int strips, seg_h, nseg, blk;
+    const int nwaves = decompose(*p, &strips, &seg_h, &nseg, &blk);
     size_t a, b, d;
-    const size_t ws = ws_layout(strips * nseg, &a, &b, &d);
+    const size_t ws = ws_layout(nwaves, &a, &b, &d);
     if (ld_out) *ld_out = ld;
     if (pop_bytes_out) *pop_bytes_out = bytes;
     if (ws_bytes_out) *ws_bytes_out = ws;
+    return LBM_OK;
+}
+
+int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int* waves_out)
+{
+    if (!p || p->nx < 1 || p->ny < 1) {
+        lbm_set_error("lbm_describe: invalid lattice size");
+        return LBM_EINVAL;
+    }
+    int strips, seg_h, nseg, blk;
+    const int nw = decompose(*p, &strips, &seg_h, &nseg, &blk);
+    if (variant_out) *variant_out = blk ? LBM_VARIANT_BLOCK : LBM_VARIANT_MARCH;
+    if (band_rows_out) *band_rows_out = seg_h;
+    if (waves_out) *waves_out = nw;
     return LBM_OK;
 }
 
@@ -652,10 +920,10 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* ws,
     c->step = 0;
     c->ws = (char*)ws;
     c->ws_bytes = ws_bytes;
-    int strips, seg_h, nseg;
-    decompose(*p, &strips, &seg_h, &nseg);
+    int strips, seg_h, nseg, blk;
+    const int nwaves = decompose(*p, &strips, &seg_h, &nseg, &blk);
     size_t op, oh, orr;
-    ws_layout(strips * nseg, &op, &oh, &orr);
+    ws_layout(nwaves, &op, &oh, &orr);
     c->err = (unsigned*)c->ws;
     c->partials = (double*)(c->ws + op);
     c->hist = (double*)(c->ws + oh);
@@ -740,8 +1008,14 @@ int lbm_macros(lbm_ctx* c, double* rho, double* ux, double* uy, double* psi, dou
     A.o_p = p;
     A.o_fx = Fx;
     A.o_fy = Fy;
-    if (c->P.prec == LBM_FP32_SHIFTED) hipLaunchKernelGGL((k_step<float, MODE_MACROS>), dim3(c->grid), dim3(256), 0, s, A);
-    else hipLaunchKernelGGL((k_step<double, MODE_MACROS>), dim3(c->grid), dim3(256), 0, s, A);
+    const bool f32 = c->P.prec == LBM_FP32_SHIFTED;
+    if (A.blk) {
+        if (f32) hipLaunchKernelGGL((k_step_blk<float, MODE_MACROS>), dim3(c->grid), dim3(64 * kBlkWaves), 0, s, A);
+        else hipLaunchKernelGGL((k_step_blk<double, MODE_MACROS>), dim3(c->grid), dim3(64 * kBlkWaves), 0, s, A);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_step<float, MODE_MACROS>), dim3(c->grid), dim3(256), 0, s, A);
+        else hipLaunchKernelGGL((k_step<double, MODE_MACROS>), dim3(c->grid), dim3(256), 0, s, A);
+    }
     if (!hip_ok(hipGetLastError(), "k_step(macros) launch")) return LBM_EHIP;
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, (const double*)c->partials, c->args.nwork, c->red, 0LL, 0);
     if (!hip_ok(hipGetLastError(), "k_reduce launch")) return LBM_EHIP;

@@ -12,13 +12,15 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbm.so")
+# LBM_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_HERE, "liblbm.so")
 _lib = None
 
 LBM_OK, LBM_EINVAL, LBM_EUNSTABLE, LBM_EHIP, LBM_ESTATE, LBM_ENOROOT = 0, -1, -2, -3, -4, -5
 FP64, FP32_SHIFTED = 0, 1
 BASE_CS, BASE_PR = 0, 1
 SHAPE_NONE, SHAPE_SMOOTH, SHAPE_MODSMOOTH, SHAPE_PENG = 0, 1, 2, 3
+VARIANT_AUTO, VARIANT_MARCH, VARIANT_BLOCK = 0, 1, 2
 
 
 class LbmEos(C.Structure):
@@ -42,7 +44,7 @@ class LbmEos(C.Structure):
 class LbmParams(C.Structure):
     _fields_ = [
         ("nx", C.c_int), ("ny", C.c_int), ("walls", C.c_int), ("prec", C.c_int),
-        ("var_tau", C.c_int), ("reduce_every", C.c_int),
+        ("var_tau", C.c_int), ("reduce_every", C.c_int), ("band_rows", C.c_int), ("kernel_variant", C.c_int),
         ("rho_wall_lo", C.c_double), ("rho_wall_hi", C.c_double),
         ("G", C.c_double), ("sigma", C.c_double),
         ("tau", C.c_double * 9),
@@ -68,6 +70,7 @@ def _signatures():
         "lbm_eos_pressure": ([C.POINTER(LbmEos), d], d),
         "lbm_eos_slope": ([C.POINTER(LbmEos), d], d),
         "lbm_layout": ([C.POINTER(LbmParams), C.POINTER(C.c_int), C.POINTER(sz), C.POINTER(sz)], i),
+        "lbm_describe": ([C.POINTER(LbmParams), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], i),
         "lbm_init": ([C.POINTER(vp), C.POINTER(LbmParams), vp, vp, vp, sz, vp, vp, vp, vp], i),
         "lbm_step": ([vp, C.c_int64, vp], i),
         "lbm_status_check": ([vp, vp], i),
@@ -143,9 +146,11 @@ def eos_slope(e: LbmEos, rho: float) -> float:
 
 def make_params(nx, ny, eos: LbmEos, G=-1.0, sigma=0.0, tau=None, prec=FP64, rho_ref=None, walls=False,
                 rho_wall_lo=0.0, rho_wall_hi=0.0, var_tau=False, tau_l=1.0, tau_v=1.0, rho_v_tau=None,
-                rho_l_tau=None, reduce_every=0) -> LbmParams:
+                rho_l_tau=None, reduce_every=0, band_rows=0, kernel_variant=0) -> LbmParams:
     P = LbmParams()
     P.nx, P.ny, P.walls, P.prec, P.var_tau, P.reduce_every = nx, ny, int(walls), prec, int(var_tau), reduce_every
+    P.band_rows = band_rows
+    P.kernel_variant = kernel_variant
     P.rho_wall_lo, P.rho_wall_hi = rho_wall_lo, rho_wall_hi
     P.G, P.sigma = G, sigma
     t = [1.0] * 9 if tau is None else list(tau)
@@ -163,6 +168,13 @@ def layout(P: LbmParams) -> tuple[int, int, int]:
     ld, pb, wb = C.c_int(0), C.c_size_t(0), C.c_size_t(0)
     _check(load().lbm_layout(C.byref(P), C.byref(ld), C.byref(pb), C.byref(wb)), "lbm_layout")
     return ld.value, pb.value, wb.value
+
+
+def describe(P: LbmParams) -> tuple[int, int, int]:
+    """(kernel variant, rows per band/block, wavefronts) the library picks for P."""
+    v, b, w = C.c_int(0), C.c_int(0), C.c_int(0)
+    _check(load().lbm_describe(C.byref(P), C.byref(v), C.byref(b), C.byref(w)), "lbm_describe")
+    return v.value, b.value, w.value
 
 
 # ---------------------------------------------------------------------------- lattice

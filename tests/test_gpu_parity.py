@@ -24,12 +24,14 @@ def both_eos(lbm, **kw):
 
 
 def run_pair(lbm, nx, ny, kw, rho0, steps, tau=None, prec=None, ux0=None, uy0=None, walls=False,
-             var_tau=False, tau_l=1.0, tau_v=1.0, forcing_li=True, rho_ref=None, wall=(0.0, 0.0)):
+             var_tau=False, tau_l=1.0, tau_v=1.0, forcing_li=True, rho_ref=None, wall=(0.0, 0.0), variant=0,
+             band_rows=0):
     e, s, eo, so = both_eos(lbm, **kw)
     sig, sigo = (s, so) if forcing_li else (0.0, 0.0)
     prec = lbm.FP64 if prec is None else prec
     P = lbm.make_params(nx, ny, e, sigma=sig, tau=tau, prec=prec, rho_ref=rho_ref, walls=walls,
-                        rho_wall_lo=wall[0], rho_wall_hi=wall[1], var_tau=var_tau, tau_l=tau_l, tau_v=tau_v)
+                        rho_wall_lo=wall[0], rho_wall_hi=wall[1], var_tau=var_tau, tau_l=tau_l, tau_v=tau_v,
+                        kernel_variant=variant, band_rows=band_rows)
     L = lbm.Lattice(P, rho0, ux0, uy0, device="cuda:0")
     L.step(steps)
     OP = O.make_params(nx, ny, eo, sigma=sigo, tau=tau, forcing=O.FORCING_LI if forcing_li else O.FORCING_GUO,
@@ -48,15 +50,20 @@ def rel_f_err(L, OL):
 
 
 # ---------------------------------------------------------------- FP64 elementwise parity
-@pytest.mark.parametrize("nx,ny", [(130, 37), (62, 5), (63, 9), (2, 200), (256, 4), (1, 7), (5, 1)])
-def test_fp64_planar_and_ragged_shapes(gpu_lib, nx, ny):
-    """Ragged strips (62-column waves), ragged bands, 1-wide and 1-tall lattices."""
+VARIANTS = [(1, 0), (1, 1), (1, 3), (2, 0)]  # (kernel variant, band rows): march auto/1/3 rows, row block
+VARIANT_IDS = ["march", "march-h1", "march-h3", "block"]
+
+
+@pytest.mark.parametrize("variant,band", VARIANTS, ids=VARIANT_IDS)
+@pytest.mark.parametrize("nx,ny", [(130, 37), (62, 5), (63, 9), (2, 200), (256, 4), (1, 7), (5, 1), (70, 29)])
+def test_fp64_planar_and_ragged_shapes(gpu_lib, nx, ny, variant, band):
+    """Ragged strips (62-column waves), ragged bands / blocks, 1-wide and 1-tall lattices."""
     kw = dict(Tr=0.7)
     e, _, _, _ = both_eos(gpu_lib, **kw)
     rho0 = planar_density(nx, ny, e.rho_v, e.rho_l, W=5, axis=1 if ny >= nx else 0)
     rho0 = rho0 * (1 + 0.01 * random_field(nx, ny, 1.0, 1.0, seed=nx * 1000 + ny))
     for steps in (1, 40):
-        L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, steps, tau=TAU_MRT)
+        L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, steps, tau=TAU_MRT, variant=variant, band_rows=band)
         assert rel_f_err(L, OL) < 1e-12, (nx, ny, steps)
 
 
@@ -77,7 +84,8 @@ def test_fp64_shaped_eos_droplet(gpu_lib, shape_kw):
     assert rel_f_err(L, OL) < 1e-12
 
 
-def test_fp64_walls_variable_tau_moving_droplet(gpu_lib):
+@pytest.mark.parametrize("variant,band", VARIANTS, ids=VARIANT_IDS)
+def test_fp64_walls_variable_tau_moving_droplet(gpu_lib, variant, band):
     """Bounce-back walls with ghost psi, Eq. RelaxationTime, a moving droplet over a film."""
     kw = dict(Tr=0.6, a=0.387, shape=1, alpha=0.834, k_vap=2 / 0.387)
     e, _, _, _ = both_eos(gpu_lib, **kw)
@@ -86,16 +94,17 @@ def test_fp64_walls_variable_tau_moving_droplet(gpu_lib):
     tau_l = 0.7
     L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, 80, tau=[1, 1, 1, 1, 1, 1, 1, tau_l, tau_l], ux0=ux0,
                            uy0=uy0, walls=True, wall=(e.rho_l, e.rho_v), var_tau=True, tau_l=tau_l,
-                           tau_v=0.5 + 5 * (tau_l - 0.5))
+                           tau_v=0.5 + 5 * (tau_l - 0.5), variant=variant, band_rows=band)
     assert rel_f_err(L, OL) < 1e-12
 
 
-def test_fp64_macros_match_oracle(gpu_lib):
+@pytest.mark.parametrize("variant", [1, 2], ids=["march", "block"])
+def test_fp64_macros_match_oracle(gpu_lib, variant):
     kw = dict(Tr=0.6)
     e, _, _, _ = both_eos(gpu_lib, **kw)
     nx, ny = 75, 66
     rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=15, W=6)
-    L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, 30, tau=TAU_MRT)
+    L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, 30, tau=TAU_MRT, variant=variant)
     g = {k: v.cpu().numpy() if hasattr(v, "cpu") else v for k, v in L.macros().items()}
     m = OL.macros()
     for k in ("rho", "ux", "uy", "psi", "p", "Fx", "Fy"):
@@ -125,7 +134,8 @@ def test_fp32_planar_interface_targets(gpu_lib):
     assert np.abs(g["uy"] - m["uy"]).max() <= 1e-5
 
 
-def test_fp32_one_step_elementwise(gpu_lib):
+@pytest.mark.parametrize("variant", [1, 2], ids=["march", "block"])
+def test_fp32_one_step_elementwise(gpu_lib, variant):
     """One FP32-shifted step from an FP32-representable state against the FP64 oracle step.
 
     Inputs are identical, so the difference is the FP32 arithmetic of one collision: each
@@ -136,7 +146,8 @@ def test_fp32_one_step_elementwise(gpu_lib):
     e, s, eo, so = both_eos(gpu_lib, **kw)
     nx, ny = 128, 96
     rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=25, W=20)
-    P = gpu_lib.make_params(nx, ny, e, sigma=s, tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7], prec=gpu_lib.FP32_SHIFTED)
+    P = gpu_lib.make_params(nx, ny, e, sigma=s, tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7], prec=gpu_lib.FP32_SHIFTED,
+                            kernel_variant=variant)
     L = gpu_lib.Lattice(P, rho0, device="cuda:0")
     L.step(50)
     f_t = L.populations().cpu().numpy()
@@ -151,14 +162,15 @@ def test_fp32_one_step_elementwise(gpu_lib):
     assert np.abs(f_g - f_o).max() <= 2e-6 * dev
 
 
-def test_fp32_mass_drift_droplet(gpu_lib):
+@pytest.mark.parametrize("variant", [1, 2], ids=["march", "block"])
+def test_fp32_mass_drift_droplet(gpu_lib, variant):
     """FP64 per-node rest population keeps the FP32-shifted mass exact: drift <= 1e-10 relative."""
     kw = dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
     e, s = gpu_lib.eos_build(gpu_lib.make_eos(**kw))
     nx = ny = 256
     rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=60, W=20)
     P = gpu_lib.make_params(nx, ny, e, sigma=s, tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7], prec=gpu_lib.FP32_SHIFTED,
-                            reduce_every=500)
+                            reduce_every=500, kernel_variant=variant)
     L = gpu_lib.Lattice(P, rho0, device="cuda:0")
     L.step(5001)
     L.check()
