@@ -165,6 +165,32 @@ int lbm_save(lbm_ctx* ctx, void* dst, void* stream);
 int lbm_load(lbm_ctx* ctx, const void* src, int64_t step, void* stream);
 
 void lbm_destroy(lbm_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Batched lattices: B independent lattices (own size, EOS, relaxation times,
+ * FP32 shift; one storage precision for all) advanced by ONE persistent
+ * launch in which one workgroup owns one lattice and loops over the steps.
+ * The launch is captured in a HIP graph and replayed.  Population buffers
+ * hold the lattices back to back (lbm_batch_layout gives the sizes); scalar
+ * fields are packed in lattice order, lattice b occupying
+ * [cell_offsets[b], cell_offsets[b+1]) as [ny_b][nx_b].
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+/* Sizes for B lattices with parameters p[0..B-1]: bytes of ONE population
+ * buffer, bytes of the workspace, and (if non-NULL) cell_offsets[B+1]. */
+int lbm_batch_layout(int B, const lbm_params* p, size_t* pop_bytes_out, size_t* ws_bytes_out, int64_t* cell_offsets);
+/* Initial state f^eq(rho0, u0) of every lattice; rho0/ux0/uy0 packed device
+ * float64 fields (ux0, uy0 may be NULL).  Validates every lattice. */
+int lbm_init_batched(lbm_batch** ctx, int B, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes,
+                     const double* rho0, const double* ux0, const double* uy0, void* stream);
+/* nsteps time steps of every lattice in one persistent launch (asynchronous). */
+int lbm_step_batched(lbm_batch* ctx, int64_t nsteps, void* stream);
+/* Packed rho and forced u of every lattice (outputs may be NULL); synchronises. */
+int lbm_macros_batched(lbm_batch* ctx, double* rho, double* ux, double* uy, void* stream);
+/* LBM_EUNSTABLE if any lattice met psi^2 < 0; first_bad_out = its index or -1. */
+int lbm_status_batched(lbm_batch* ctx, int* first_bad_out, void* stream);
+void lbm_destroy_batched(lbm_batch* ctx);
 const char* lbm_strerror(int code);
 const char* lbm_last_error(void);
 

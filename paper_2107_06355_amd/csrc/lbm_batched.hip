@@ -1,0 +1,367 @@
+// liblbm.so: many independent small lattices advanced by ONE persistent launch.
+//
+// Each lattice (its own size, EOS, relaxation times and FP32 shift) is owned
+// by one workgroup of 16 wavefronts that loops over the time steps with a
+// workgroup barrier between steps: neighbouring nodes of a lattice are only
+// ever touched by that workgroup, so no grid-wide synchronisation is needed.
+// Populations of all lattices are packed back to back in one pair of buffers;
+// scalar fields are packed in the same lattice order ([ny_b][nx_b] each).
+// The per-node arithmetic is the fused step of lbm_device.h: pull with
+// half-way bounce-back, shaped EOS, psi (Eq. InteractionPotential), the
+// Shan-Chen stencil (Eq. ShanChenForce) and the MRT update with Eq. LiFS.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace {
+
+using namespace lbmk;
+
+constexpr int kBatchWaves = 16;
+
+struct BatchItem {
+    StepArgs A;           // per-lattice arguments (src/dst filled in the kernel)
+    size_t off_bytes;     // byte offset of the lattice in each population buffer
+    long long cell_off;   // offset of the lattice in the packed scalar fields
+};
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(64 * kBatchWaves) void k_batch(const BatchItem* items, char* buf0, char* buf1, int cur0,
+                                                            long long nsteps, long long step0, double* o_rho,
+                                                            double* o_ux, double* o_uy)
+{
+    StepArgs A = items[blockIdx.x].A;
+    const size_t off = items[blockIdx.x].off_bytes;
+    const long long coff = items[blockIdx.x].cell_off;
+    if (MODE == MODE_MACROS) {
+        A.o_rho = o_rho ? o_rho + coff : nullptr;
+        A.o_ux = o_ux ? o_ux + coff : nullptr;
+        A.o_uy = o_uy ? o_uy + coff : nullptr;
+        A.o_psi = A.o_p = A.o_fx = A.o_fy = nullptr;
+    }
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int work = A.strips * A.ny;  // one item = one row of one 62-column strip
+    int cur = cur0;
+    Acc acc = {0.0, 0.0, 0.0};
+    for (long long t = 0; t < nsteps; ++t) {
+        A.src = (cur ? buf1 : buf0) + off;
+        A.dst = (cur ? buf0 : buf1) + off;
+        A.step = step0 + t;
+        const View<T> V = make_view<T>(A.src, A.plane);
+        for (int w = wv; w < work; w += kBatchWaves) {
+            const int strip = w % A.strips, y = w / A.strips;
+            Lane L;
+            L.lane = threadIdx.x & 63;
+            const int x0 = strip * kStripW;
+            const int W = min(kStripW, A.nx - x0);
+            const int xr = x0 - 1 + L.lane;
+            L.valid = L.lane <= W + 1;
+            L.interior = L.lane >= 1 && L.lane <= W;
+            int x = xr < 0 ? xr + A.nx : (xr >= A.nx ? xr - A.nx : xr);
+            if (!L.valid) x = 0;
+            L.x = x;
+            L.xm = x == 0 ? A.nx - 1 : x - 1;
+            L.xp = x == A.nx - 1 ? 0 : x + 1;
+            Row<T> Rm, Rc, Rp;
+            pull<T>(V, A, L.x, L.xm, L.xp, load_index(A, y - 1), Rm.g0, Rm.g);
+            pull<T>(V, A, L.x, L.xm, L.xp, y, Rc.g0, Rc.g);
+            pull<T>(V, A, L.x, L.xm, L.xp, load_index(A, y + 1), Rp.g0, Rp.g);
+            const double dm = node_drho<T>(Rm.g0, Rm.g), dc = node_drho<T>(Rc.g0, Rc.g), dp = node_drho<T>(Rp.g0, Rp.g);
+            const T psm = (A.walls && y == 0) ? (T)A.psi_lo : node_psi<T>(A, dm, L.valid);
+            const T psc = node_psi<T>(A, dc, L.valid);
+            const T psp = (A.walls && y == A.ny - 1) ? (T)A.psi_hi : node_psi<T>(A, dp, L.valid);
+            collide_row<T, MODE>(A, L, y, Rc, dc, psm, psc, psp, acc);
+        }
+        if (MODE == MODE_MACROS) break;
+        __syncthreads();  // this lattice's step t is complete before any wave pulls for t+1
+        cur ^= 1;
+    }
+}
+
+template <typename T>
+__global__ void k_batch_init(const BatchItem* items, char* buf0, const double* rho0, const double* ux0,
+                             const double* uy0)
+{
+    const StepArgs& A = items[blockIdx.y].A;
+    const size_t off = items[blockIdx.y].off_bytes;
+    const long long coff = items[blockIdx.y].cell_off;
+    const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const int op[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    const double w9[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+    void* dst = buf0 + off;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < A.nx * A.ny; c += gridDim.x * blockDim.x) {
+        const int x = c % A.nx, y = c / A.nx;
+        const size_t o = (size_t)y * A.ld + x;
+        for (int j = 0; j < 9; ++j) {
+            // A_j(z) such that the first pull yields f^eq(rho0, u0)
+            int sx = x + cx[j], sy = y + cy[j], k = j;
+            if (A.walls && (sy < 0 || sy >= A.ny)) {
+                sx = x;
+                sy = y;
+                k = op[j];
+            }
+            sx = sx < 0 ? sx + A.nx : (sx >= A.nx ? sx - A.nx : sx);
+            sy = sy < 0 ? sy + A.ny : (sy >= A.ny ? sy - A.ny : sy);
+            const long long s = coff + (long long)sy * A.nx + sx;
+            const double r = rho0[s], ux = ux0 ? ux0[s] : 0.0, uy = uy0 ? uy0[s] : 0.0;
+            const double cu = cx[k] * ux + cy[k] * uy;
+            const double feq = w9[k] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
+            const double g = feq - w9[k] * A.rho_ref;
+            if (j == 0) Plane<T>::restw(dst, A.plane)[o] = g;
+            else Plane<T>::movw(dst, A.plane, j)[o] = (T)g;
+        }
+    }
+}
+
+bool hip_ok(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return true;
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+    lbm_set_error(buf);
+    return false;
+}
+
+struct Layout {
+    std::vector<size_t> off;        // [B+1] byte offsets in a population buffer
+    std::vector<long long> cells;   // [B+1] cell offsets in the packed fields
+    std::vector<int> ld;
+    size_t ws_bytes;
+};
+
+int batch_layout(int B, const lbm_params* p, Layout& L)
+{
+    if (B < 1 || !p) {
+        lbm_set_error("lbm batched: need at least one lattice");
+        return LBM_EINVAL;
+    }
+    L.off.assign(B + 1, 0);
+    L.cells.assign(B + 1, 0);
+    L.ld.assign(B, 0);
+    for (int b = 0; b < B; ++b) {
+        if (p[b].prec != p[0].prec) {
+            lbm_set_error("lbm batched: every lattice must use the same storage precision");
+            return LBM_EINVAL;
+        }
+        const int st = validate(&p[b]);
+        if (st != LBM_OK) return st;
+        const int ld = (p[b].nx + 63) & ~63;
+        const size_t plane = (size_t)ld * p[b].ny;
+        const size_t bytes = p[b].prec == LBM_FP32_SHIFTED ? plane * (8 * sizeof(float) + sizeof(double))
+                                                           : plane * 9 * sizeof(double);
+        L.ld[b] = ld;
+        L.off[b + 1] = L.off[b] + ((bytes + 255) & ~(size_t)255);
+        L.cells[b + 1] = L.cells[b] + (long long)p[b].nx * p[b].ny;
+    }
+    // workspace: per-lattice error words, then the item records
+    L.ws_bytes = (((size_t)B * 2 * sizeof(unsigned) + 255) & ~(size_t)255) + (size_t)B * sizeof(BatchItem) + 256;
+    return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_batch {
+    int B;
+    int prec;
+    Layout L;
+    char* buf[2];
+    int cur;
+    int64_t step;
+    unsigned* err;
+    BatchItem* items;
+    hipStream_t cap;        // capture stream (default priority)
+    hipGraphExec_t exec[2]; // one persistent launch of `graph_steps` steps, per starting buffer
+    int64_t graph_steps;
+};
+
+extern "C" {
+
+int lbm_batch_layout(int B, const lbm_params* p, size_t* pop_bytes_out, size_t* ws_bytes_out, int64_t* cell_offsets)
+{
+    Layout L;
+    const int st = batch_layout(B, p, L);
+    if (st != LBM_OK) return st;
+    if (pop_bytes_out) *pop_bytes_out = L.off[B];
+    if (ws_bytes_out) *ws_bytes_out = L.ws_bytes;
+    if (cell_offsets)
+        for (int b = 0; b <= B; ++b) cell_offsets[b] = L.cells[b];
+    return LBM_OK;
+}
+
+int lbm_init_batched(lbm_batch** out, int B, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes,
+                     const double* rho0, const double* ux0, const double* uy0, void* stream)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    Layout L;
+    int st = batch_layout(B, p, L);
+    if (st != LBM_OK) return st;
+    if (!f_a || !f_b || f_a == f_b || !ws || !rho0 || ws_bytes < L.ws_bytes) {
+        lbm_set_error("lbm_init_batched: buffers must be non-NULL and distinct, workspace as lbm_batch_layout says");
+        return LBM_EINVAL;
+    }
+    lbm_batch* c = new (std::nothrow) lbm_batch();
+    if (!c) return LBM_EINVAL;
+    c->B = B;
+    c->prec = p[0].prec;
+    c->L = L;
+    c->buf[0] = (char*)f_a;
+    c->buf[1] = (char*)f_b;
+    c->err = (unsigned*)ws;
+    c->items = (BatchItem*)((char*)ws + (((size_t)B * 2 * sizeof(unsigned) + 255) & ~(size_t)255));
+    std::vector<BatchItem> host(B);
+    std::vector<unsigned> err0(2 * (size_t)B);
+    for (int b = 0; b < B; ++b) {
+        const lbm_params& P = p[b];
+        StepArgs& A = host[b].A;
+        std::memset(&A, 0, sizeof(A));
+        A.plane = (size_t)L.ld[b] * P.ny;
+        A.nx = P.nx;
+        A.ny = P.ny;
+        A.ld = L.ld[b];
+        A.walls = P.walls;
+        A.strips = (P.nx + kStripW - 1) / kStripW;
+        A.seg_h = 1;
+        A.nseg = P.ny;
+        A.nwork = A.strips * P.ny;
+        A.var_tau = P.var_tau;
+        A.G = P.G;
+        A.sigma = P.sigma;
+        for (int k = 0; k < 9; ++k) A.s[k] = 1.0 / P.tau[k];
+        A.tau_v = P.tau_v;
+        A.rho_v_tau = P.rho_v_tau;
+        A.dtau_drho = P.var_tau ? (P.tau_l - P.tau_v) / (P.rho_l_tau - P.rho_v_tau) : 0.0;
+        A.tau_lo = P.tau_l < P.tau_v ? P.tau_l : P.tau_v;
+        A.tau_hi = P.tau_l < P.tau_v ? P.tau_v : P.tau_l;
+        A.rho_ref = P.prec == LBM_FP32_SHIFTED ? P.rho_ref : 0.0;
+        A.eos = dev_eos(P.eos);
+        auto psi_host = [&](double r) {
+            const double q = 2.0 * (lbm_eos_pressure(&P.eos, r) - r / 3.0) / P.G;
+            return q > 0 ? std::sqrt(q) : 0.0;
+        };
+        A.psi_lo = P.walls ? psi_host(P.rho_wall_lo) : 0.0;
+        A.psi_hi = P.walls ? psi_host(P.rho_wall_hi) : 0.0;
+        A.err = c->err + 2 * b;
+        host[b].off_bytes = L.off[b];
+        host[b].cell_off = L.cells[b];
+        err0[2 * b] = 0u;
+        err0[2 * b + 1] = 0xffffffffu;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!hip_ok(hipMemcpyAsync(c->items, host.data(), sizeof(BatchItem) * B, hipMemcpyHostToDevice, s), "batch items") ||
+        !hip_ok(hipMemcpyAsync(c->err, err0.data(), sizeof(unsigned) * 2 * B, hipMemcpyHostToDevice, s), "batch errors") ||
+        !hip_ok(hipStreamSynchronize(s), "batch init sync")) {
+        delete c;
+        return LBM_EHIP;
+    }
+    if (c->prec == LBM_FP32_SHIFTED)
+        hipLaunchKernelGGL(k_batch_init<float>, dim3(64, B), dim3(256), 0, s, (const BatchItem*)c->items, c->buf[0], rho0,
+                           ux0, uy0);
+    else
+        hipLaunchKernelGGL(k_batch_init<double>, dim3(64, B), dim3(256), 0, s, (const BatchItem*)c->items, c->buf[0], rho0,
+                           ux0, uy0);
+    if (!hip_ok(hipGetLastError(), "k_batch_init launch") ||
+        !hip_ok(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "capture stream")) {
+        delete c;
+        return LBM_EHIP;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+static bool launch_batch(lbm_batch* c, int64_t nsteps, hipStream_t s)
+{
+    if (c->prec == LBM_FP32_SHIFTED)
+        hipLaunchKernelGGL((k_batch<float, MODE_STEP>), dim3(c->B), dim3(64 * kBatchWaves), 0, s,
+                           (const BatchItem*)c->items, c->buf[0], c->buf[1], c->cur, (long long)nsteps, (long long)c->step,
+                           (double*)nullptr, (double*)nullptr, (double*)nullptr);
+    else
+        hipLaunchKernelGGL((k_batch<double, MODE_STEP>), dim3(c->B), dim3(64 * kBatchWaves), 0, s,
+                           (const BatchItem*)c->items, c->buf[0], c->buf[1], c->cur, (long long)nsteps, (long long)c->step,
+                           (double*)nullptr, (double*)nullptr, (double*)nullptr);
+    return hip_ok(hipGetLastError(), "k_batch launch");
+}
+
+int lbm_step_batched(lbm_batch* c, int64_t nsteps, void* stream)
+{
+    if (!c || nsteps < 0) return LBM_EINVAL;
+    if (nsteps == 0) return LBM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // the persistent launch is captured once per (step count, starting buffer) and replayed
+    if (c->graph_steps != nsteps) {
+        for (int k = 0; k < 2; ++k)
+            if (c->exec[k]) {
+                (void)hipGraphExecDestroy(c->exec[k]);
+                c->exec[k] = nullptr;
+            }
+        c->graph_steps = nsteps;
+    }
+    if (!c->exec[c->cur]) {
+        hipGraph_t g = nullptr;
+        if (!hip_ok(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "batch capture begin")) return LBM_EHIP;
+        const bool ok = launch_batch(c, nsteps, c->cap);
+        if (!hip_ok(hipStreamEndCapture(c->cap, &g), "batch capture end") || !ok) return LBM_EHIP;
+        const bool inst = hip_ok(hipGraphInstantiate(&c->exec[c->cur], g, nullptr, nullptr, 0), "batch graph instantiate");
+        (void)hipGraphDestroy(g);
+        if (!inst) return LBM_EHIP;
+    }
+    if (!hip_ok(hipGraphLaunch(c->exec[c->cur], s), "batch graph launch")) return LBM_EHIP;
+    c->step += nsteps;
+    if (nsteps & 1) c->cur ^= 1;
+    return LBM_OK;
+}
+
+int lbm_macros_batched(lbm_batch* c, double* rho, double* ux, double* uy, void* stream)
+{
+    if (!c) return LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (c->prec == LBM_FP32_SHIFTED)
+        hipLaunchKernelGGL((k_batch<float, MODE_MACROS>), dim3(c->B), dim3(64 * kBatchWaves), 0, s,
+                           (const BatchItem*)c->items, c->buf[0], c->buf[1], c->cur, 1LL, (long long)c->step, rho, ux, uy);
+    else
+        hipLaunchKernelGGL((k_batch<double, MODE_MACROS>), dim3(c->B), dim3(64 * kBatchWaves), 0, s,
+                           (const BatchItem*)c->items, c->buf[0], c->buf[1], c->cur, 1LL, (long long)c->step, rho, ux, uy);
+    if (!hip_ok(hipGetLastError(), "k_batch(macros) launch") || !hip_ok(hipStreamSynchronize(s), "batch macros sync"))
+        return LBM_EHIP;
+    return LBM_OK;
+}
+
+int lbm_status_batched(lbm_batch* c, int* first_bad_out, void* stream)
+{
+    if (!c) return LBM_EINVAL;
+    std::vector<unsigned> h(2 * (size_t)c->B);
+    hipStream_t s = (hipStream_t)stream;
+    if (!hip_ok(hipMemcpyAsync(h.data(), c->err, sizeof(unsigned) * h.size(), hipMemcpyDeviceToHost, s), "batch status") ||
+        !hip_ok(hipStreamSynchronize(s), "batch status sync"))
+        return LBM_EHIP;
+    if (first_bad_out) *first_bad_out = -1;
+    for (int b = 0; b < c->B; ++b)
+        if (h[2 * b]) {
+            if (first_bad_out) *first_bad_out = b;
+            char buf[160];
+            std::snprintf(buf, sizeof(buf), "lbm batched: lattice %d unstable from step %u", b, h[2 * b + 1]);
+            lbm_set_error(buf);
+            return LBM_EUNSTABLE;
+        }
+    return LBM_OK;
+}
+
+void lbm_destroy_batched(lbm_batch* c)
+{
+    if (!c) return;
+    for (int k = 0; k < 2; ++k)
+        if (c->exec[k]) (void)hipGraphExecDestroy(c->exec[k]);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,466 @@
+// Device building blocks of the fused D2Q9 step (included by the .hip sources of
+// liblbm.so): shaped-EOS evaluation, the population pull with half-way
+// bounce-back, the pseudopotential psi, the Shan-Chen force stencil and the
+// MRT node update with the Li et al. source.  See lbm_step.hip for the
+// kernels that assemble them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+namespace lbmk {
+
+// build-time tuning: occupancy hint for the step kernel (waves per SIMD, 0 = none)
+#ifndef LBM_WAVES_PER_EU
+#define LBM_WAVES_PER_EU 0
+#endif
+#if LBM_WAVES_PER_EU > 0
+#define LBM_OCCUPANCY_HINT __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
+#else
+#define LBM_OCCUPANCY_HINT
+#endif
+
+constexpr int kStripW = 62;   // interior columns per wave (lanes 0 and 63 are the psi halo)
+
+// ----------------------------------------------------------------- device EOS
+struct DevEos {
+    int base, shape;
+    double RT, aal, b, scale, k_vap, dP;
+    double rho_v, rho_l, rho_max, rho_min;
+    double p0, p_max, p_min, inv_a1sq, b1, inv_a3sq, b3, inv_L, rho_m, theta;
+};
+
+__device__ __forceinline__ double dev_base_p(const DevEos& E, double r)
+{
+    if (E.base == LBM_BASE_CS) {
+        const double n = 0.25 * E.b * r, m = 1.0 - n;
+        return E.scale * (E.RT * r * (1.0 + n * (1.0 + n * (1.0 - n))) / (m * m * m) - E.aal * r * r);
+    }
+    const double br = E.b * r;
+    return E.scale * (E.RT * r / (1.0 - br) - E.aal * r * r / (1.0 + br * (2.0 - br)));
+}
+
+__device__ __forceinline__ double dev_eos_p(const DevEos& E, double r)
+{
+    if (E.shape == LBM_SHAPE_NONE) return dev_base_p(E, r);
+    if (r <= E.rho_v) return E.k_vap * dev_base_p(E, r);
+    if (r >= E.rho_l) return dev_base_p(E, r) + E.dP;
+    if (E.shape == LBM_SHAPE_PENG) return E.p0 + E.theta * (r - E.rho_v) * (r - E.rho_l) * (r - E.rho_m);
+    if (r <= E.rho_max) {
+        const double d = r - E.rho_max;
+        return E.p_max - E.b1 * (1.0 - sqrt(1.0 - d * d * E.inv_a1sq));
+    }
+    if (r < E.rho_min) {
+        const double t = (r - E.rho_max) * E.inv_L;
+        return E.p_max + (E.p_min - E.p_max) * t * t * (3.0 - 2.0 * t);
+    }
+    const double d = r - E.rho_min;
+    return E.p_min + E.b3 * (1.0 - sqrt(1.0 - d * d * E.inv_a3sq));
+}
+
+// ----------------------------------------------------------------- kernel arguments
+struct StepArgs {
+    const void* src;
+    void* dst;
+    size_t plane;            // elements per population plane (ny * ld)
+    int nx, ny, ld, walls;
+    int strips, seg_h, nseg, nwork;
+    int var_tau, blk;        // blk: 1 = row-block (LDS) kernel, 0 = row-march kernel
+    double G, sigma;
+    double s[9];             // relaxation rates 1/tau
+    double tau_v, dtau_drho, tau_lo, tau_hi, rho_v_tau;
+    double rho_ref;
+    double psi_lo, psi_hi;
+    DevEos eos;
+    double* partials;        // [nwork][3] FP64 per-wave sums
+    unsigned* err;           // [0] flag, [1] first failing step
+    long long step;
+    // lbm_macros outputs (MODE_MACROS)
+    double *o_rho, *o_ux, *o_uy, *o_psi, *o_p, *o_fx, *o_fy;
+};
+
+enum { MODE_STEP = 0, MODE_STEP_REDUCE = 1, MODE_MACROS = 2 };
+
+__constant__ double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+template <typename T>
+struct Plane;
+template <>
+struct Plane<double> {
+    __device__ static const double* mov(const void* base, size_t plane, int i) { return (const double*)base + i * plane; }
+    __device__ static double* movw(void* base, size_t plane, int i) { return (double*)base + i * plane; }
+    __device__ static const double* rest(const void* base, size_t plane) { return (const double*)base; }
+    __device__ static double* restw(void* base, size_t plane) { return (double*)base; }
+};
+template <>
+struct Plane<float> {
+    // planes 1..8: float32 at (i-1)*plane; rest population: float64 after the 8 float planes
+    __device__ static const float* mov(const void* base, size_t plane, int i) { return (const float*)base + (i - 1) * plane; }
+    __device__ static float* movw(void* base, size_t plane, int i) { return (float*)base + (i - 1) * plane; }
+    __device__ static const double* rest(const void* base, size_t plane) { return (const double*)((const float*)base + 8 * plane); }
+    __device__ static double* restw(void* base, size_t plane) { return (double*)((float*)base + 8 * plane); }
+};
+
+// Read-only and writable views of one population buffer: uniform per-plane base
+// pointers (scalar registers) addressed with 32-bit per-lane byte offsets.
+template <typename T>
+struct View {
+    const char* mv[9];   // planes 1..8 of the moving populations (index 0 unused)
+    const char* rest;    // rest population (FP64)
+};
+template <typename T>
+struct WView {
+    char* mv[9];
+    char* rest;
+};
+
+template <typename T>
+__device__ __forceinline__ View<T> make_view(const void* base, size_t plane)
+{
+    View<T> V;
+    V.mv[0] = nullptr;
+    for (int i = 1; i < 9; ++i) V.mv[i] = (const char*)Plane<T>::mov(base, plane, i);
+    V.rest = (const char*)Plane<T>::rest(base, plane);
+    return V;
+}
+template <typename T>
+__device__ __forceinline__ WView<T> make_wview(void* base, size_t plane)
+{
+    WView<T> V;
+    V.mv[0] = nullptr;
+    for (int i = 1; i < 9; ++i) V.mv[i] = (char*)Plane<T>::movw(base, plane, i);
+    V.rest = (char*)Plane<T>::restw(base, plane);
+    return V;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_at(const char* base, uint32_t elem)
+{
+    return *(const T*)(base + elem * (uint32_t)sizeof(T));
+}
+
+// Pull the nine populations of fluid node (x, y): f_i(x) = f*_i(x - c_i), or
+// f*_opp(i)(x) when x - c_i is a solid node (half-way bounce-back).  The
+// wall test depends on the row only, so the plane choice is a scalar select
+// and every load keeps a scalar base with a 32-bit lane offset.
+template <typename T>
+__device__ __forceinline__ void pull(const View<T>& V, const StepArgs& A, int x, int xm, int xp, int y, double& g0,
+                                     T g[9])
+{
+    const uint32_t ld = (uint32_t)A.ld;
+    const uint32_t r0 = (uint32_t)y * ld;
+    const bool bot = A.walls && y == 0;
+    const bool top = A.walls && y == A.ny - 1;
+    const uint32_t rm = (uint32_t)(y == 0 ? A.ny - 1 : y - 1) * ld;
+    const uint32_t rp = (uint32_t)(y == A.ny - 1 ? 0 : y + 1) * ld;
+    const uint32_t ux = (uint32_t)x, um = (uint32_t)xm, up = (uint32_t)xp;
+    g0 = ld_at<double>(V.rest, r0 + ux);
+    g[1] = ld_at<T>(V.mv[1], r0 + um);
+    g[3] = ld_at<T>(V.mv[3], r0 + up);
+    if (!(bot || top)) {
+        g[2] = ld_at<T>(V.mv[2], rm + ux);
+        g[5] = ld_at<T>(V.mv[5], rm + um);
+        g[6] = ld_at<T>(V.mv[6], rm + up);
+        g[4] = ld_at<T>(V.mv[4], rp + ux);
+        g[7] = ld_at<T>(V.mv[7], rp + up);
+        g[8] = ld_at<T>(V.mv[8], rp + um);
+    } else {
+        g[2] = bot ? ld_at<T>(V.mv[4], r0 + ux) : ld_at<T>(V.mv[2], rm + ux);
+        g[5] = bot ? ld_at<T>(V.mv[7], r0 + ux) : ld_at<T>(V.mv[5], rm + um);
+        g[6] = bot ? ld_at<T>(V.mv[8], r0 + ux) : ld_at<T>(V.mv[6], rm + up);
+        g[4] = top ? ld_at<T>(V.mv[2], r0 + ux) : ld_at<T>(V.mv[4], rp + ux);
+        g[7] = top ? ld_at<T>(V.mv[5], r0 + ux) : ld_at<T>(V.mv[7], rp + up);
+        g[8] = top ? ld_at<T>(V.mv[6], r0 + ux) : ld_at<T>(V.mv[8], rp + um);
+    }
+}
+
+// deviation of the node density from rho_ref, exact sum in FP64
+template <typename T>
+__device__ __forceinline__ double node_drho(double g0, const T g[9])
+{
+    return g0 + (((double)g[1] + (double)g[2]) + ((double)g[3] + (double)g[4])) +
+           (((double)g[5] + (double)g[6]) + ((double)g[7] + (double)g[8]));
+}
+
+__device__ __forceinline__ void flag_unstable(const StepArgs& A)
+{
+    atomicOr(A.err, 1u);
+    atomicMin(A.err + 1, (unsigned)A.step);
+}
+
+// base EOS in FP32 (bulk branches of the FP32 path)
+__device__ __forceinline__ float dev_base_pf(const DevEos& E, float r)
+{
+    if (E.base == LBM_BASE_CS) {
+        const float n = 0.25f * (float)E.b * r, m = 1.0f - n;
+        return (float)E.scale * ((float)E.RT * r * (1.0f + n * (1.0f + n * (1.0f - n))) / (m * m * m) - (float)E.aal * r * r);
+    }
+    const float br = (float)E.b * r;
+    return (float)E.scale * ((float)E.RT * r / (1.0f - br) - (float)E.aal * r * r / (1.0f + br * (2.0f - br)));
+}
+
+// psi (Eq. InteractionPotential, c = 1) of a node with density rho_ref + drho.
+// FP64 path: everything in FP64.  FP32 path: the bulk vapor/liquid branches in
+// FP32, the shaped loop between rho_v and rho_l (the branch junctions) in FP64.
+template <typename T>
+__device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check)
+{
+    const double rho = A.rho_ref + drho;
+    const DevEos& E = A.eos;
+    if (sizeof(T) == 4 && E.shape != LBM_SHAPE_NONE && (rho <= E.rho_v || rho >= E.rho_l)) {
+        const float r = (float)rho;
+        const float pb = dev_base_pf(E, r);
+        const float p = rho <= E.rho_v ? (float)E.k_vap * pb : pb + (float)E.dP;
+        const float q = 2.0f * (p - r * (1.0f / 3.0f)) / (float)A.G;
+        if (check && !(q >= 0.0f && r > 0.0f)) flag_unstable(A);
+        return (T)(q > 0.0f ? sqrtf(q) : 0.0f);
+    }
+    const double p = dev_eos_p(E, rho);
+    const double q = 2.0 * (p - rho * (1.0 / 3.0)) / A.G;
+    if (check && !(q >= 0.0 && rho > 0.0)) flag_unstable(A);
+    if (sizeof(T) == 4) return (T)(q > 0.0 ? sqrtf((float)q) : 0.0f);
+    return (T)(q > 0.0 ? sqrt(q) : 0.0);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T>
+struct Row {
+    double g0;
+    T g[9];
+};
+
+struct Lane {
+    int lane, x, xm, xp;
+    bool valid, interior;
+};
+
+struct Acc {
+    double m, x, y;
+};
+
+// row index that is always safe to load: periodic wrap, or clamped at walls
+__device__ __forceinline__ int load_index(const StepArgs& A, int r)
+{
+    if (A.walls) return r < 0 ? 0 : (r >= A.ny ? A.ny - 1 : r);
+    return r < 0 ? r + A.ny : (r >= A.ny ? r % A.ny : r);
+}
+
+// Collide row y (populations P, density deviation drp) with psi of rows y-1, y, y+1.
+// Node update of an interior lane: moments, forced velocity, MRT relaxation with
+// the Eq. LiFS source, inverse transform and store (or the macroscopic outputs).
+// psB = psi(x, y); Ftx, Fty = F~ = F/psi(x) from Eq. ShanChenForce.
+template <typename T, int MODE>
+__device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, int y, const Row<T>& P, double drp,
+                                            T psB, T Ftx, T Fty, Acc& acc)
+{
+    const T* gp = P.g;
+    const int x = L.x;
+    const double rho_d = A.rho_ref + drp;
+    const T rho = (T)rho_d;
+    const T dr = (T)drp;
+    const T Fx = psB * Ftx, Fy = psB * Fty;
+    const T g0t = (T)P.g0;
+    // moments m = M g (Eq. MatrixMRT rows)
+    const T s14 = (gp[1] + gp[2]) + (gp[3] + gp[4]);
+    const T s58 = (gp[5] + gp[6]) + (gp[7] + gp[8]);
+    const T jx = (gp[1] - gp[3]) + ((gp[5] - gp[6]) - (gp[7] - gp[8]));
+    const T jy = (gp[2] - gp[4]) + ((gp[5] + gp[6]) - (gp[7] + gp[8]));
+    const T me = -4 * g0t - s14 + 2 * s58;
+    const T mq = 4 * g0t - 2 * s14 + s58;
+    const T mqx = -2 * (gp[1] - gp[3]) + ((gp[5] - gp[6]) - (gp[7] - gp[8]));
+    const T mqy = -2 * (gp[2] - gp[4]) + ((gp[5] + gp[6]) - (gp[7] + gp[8]));
+    const T mxx = (gp[1] - gp[2]) + (gp[3] - gp[4]);
+    const T mxy = (gp[5] - gp[6]) + (gp[7] - gp[8]);
+    // forced velocity (Eq. Momentum)
+    const T inv_rho = (T)1 / rho;
+    const T ux = (jx + (T)0.5 * Fx) * inv_rho, uy = (jy + (T)0.5 * Fy) * inv_rho;
+
+    if (MODE == MODE_MACROS) {
+        const size_t o = (size_t)y * A.nx + x;
+        if (A.o_rho) A.o_rho[o] = rho_d;
+        if (A.o_ux) A.o_ux[o] = (double)ux;
+        if (A.o_uy) A.o_uy[o] = (double)uy;
+        if (A.o_psi) A.o_psi[o] = (double)psB;
+        if (A.o_p) A.o_p[o] = dev_eos_p(A.eos, rho_d);
+        if (A.o_fx) A.o_fx[o] = (double)Fx;
+        if (A.o_fy) A.o_fy[o] = (double)Fy;
+    }
+    if (MODE != MODE_STEP) {
+        acc.m += rho_d;
+        acc.x += (double)rho * (double)ux;
+        acc.y += (double)rho * (double)uy;
+    }
+    if (MODE == MODE_MACROS) return;
+    // rates (Eq. RelaxationMatrix; Eq. RelaxationTime on the shear moments)
+    const T se = (T)A.s[1], sq = (T)A.s[2], sqx = (T)A.s[4], sqy = (T)A.s[6];
+    T snu = (T)A.s[7];
+    if (A.var_tau) {
+        double tau = A.tau_v + A.dtau_drho * (rho_d - A.rho_v_tau);
+        tau = fmin(fmax(tau, A.tau_lo), A.tau_hi);
+        snu = (T)(1.0 / tau);
+    }
+    const T u2 = ux * ux + uy * uy;
+    const T uF = ux * Fx + uy * Fy;
+    const T F2 = Ftx * Ftx + Fty * Fty;  // |F|^2/psi^2
+    // equilibrium deviation moments (M f^eq minus the rho_ref rest state)
+    const T eqe = -2 * dr + 3 * rho * u2;
+    const T eqq = dr - 3 * rho * u2;
+    const T eqxx = rho * (ux * ux - uy * uy);
+    const T eqxy = rho * ux * uy;
+    // Eq. LiFS source, multiplied by (I - Lambda/2)
+    const T sig12 = (T)(12.0 * A.sigma) * F2;
+    const T Se = ((T)6 * uF + sig12 / ((T)1 / se - (T)0.5)) * ((T)1 - (T)0.5 * se);
+    const T Sq = (-(T)6 * uF - sig12 / ((T)1 / sq - (T)0.5)) * ((T)1 - (T)0.5 * sq);
+    // relaxed moments m* = m - Lambda (m - m^eq) + (I - Lambda/2) S
+    const T ne = (me - se * (me - eqe) + Se) * (T)(1.0 / 36.0);
+    const T nq = (mq - sq * (mq - eqq) + Sq) * (T)(1.0 / 36.0);
+    const T nqx = (mqx - sqx * (mqx + rho * ux) - ((T)1 - (T)0.5 * sqx) * Fx) * (T)(1.0 / 12.0);
+    const T nqy = (mqy - sqy * (mqy + rho * uy) - ((T)1 - (T)0.5 * sqy) * Fy) * (T)(1.0 / 12.0);
+    const T nxx = (mxx - snu * (mxx - eqxx) + ((T)1 - (T)0.5 * snu) * (T)2 * (ux * Fx - uy * Fy)) * (T)0.25;
+    const T nxy = (mxy - snu * (mxy - eqxy) + ((T)1 - (T)0.5 * snu) * (ux * Fy + uy * Fx)) * (T)0.25;
+    const T n0 = dr * (T)(1.0 / 9.0);
+    const T njx = (jx + Fx) * (T)(1.0 / 6.0);
+    const T njy = (jy + Fy) * (T)(1.0 / 6.0);
+    // f* = M^-1 m* = M^T diag(1/9,1/36,1/36,1/6,1/12,1/6,1/12,1/4,1/4) m*
+    const T a14 = n0 - ne - 2 * nq;
+    const T a58 = n0 + 2 * ne + nq;
+    T o[9];
+    o[1] = a14 + njx - 2 * nqx + nxx;
+    o[2] = a14 + njy - 2 * nqy - nxx;
+    o[3] = a14 - njx + 2 * nqx + nxx;
+    o[4] = a14 - njy + 2 * nqy - nxx;
+    o[5] = a58 + njx + nqx + njy + nqy + nxy;
+    o[6] = a58 - njx - nqx + njy + nqy - nxy;
+    o[7] = a58 - njx - nqx - njy - nqy + nxy;
+    o[8] = a58 + njx + nqx - njy - nqy - nxy;
+    const WView<T> D = make_wview<T>(A.dst, A.plane);
+    const uint32_t off = (uint32_t)y * (uint32_t)A.ld + (uint32_t)x;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) *(T*)(D.mv[i] + off * (uint32_t)sizeof(T)) = o[i];
+    // rest population: exact node mass in FP64 (conserved by the collision)
+    const double o0 = drp - ((((double)o[1] + (double)o[2]) + ((double)o[3] + (double)o[4])) +
+                             (((double)o[5] + (double)o[6]) + ((double)o[7] + (double)o[8])));
+    *(double*)(D.rest + off * 8u) = o0;
+}
+
+// Eq. ShanChenForce / psi(x): F~ = -G sum_i w(|c_i|^2) psi(x + c_i) c_i, written as
+// differences; arguments are psi at (x-1, x, x+1) of rows y-1 (m), y (c), y+1 (n).
+template <typename T>
+__device__ __forceinline__ void force_tilde(const StepArgs& A, T lm, T cm, T rm_, T lc, T rc, T ln, T cn, T rn_,
+                                            T& Ftx, T& Fty)
+{
+    const T G = (T)A.G;
+    const T third = (T)(1.0 / 3.0), twelfth = (T)(1.0 / 12.0);
+    Ftx = -G * ((rc - lc) * third + ((rn_ - ln) + (rm_ - lm)) * twelfth);
+    Fty = -G * ((cn - cm) * third + ((rn_ + ln) - (rm_ + lm)) * twelfth);
+}
+
+// Collide row y of a marching wave: psi of the x-neighbours comes from the
+// adjacent lanes (all lanes take part in the shuffles).
+template <typename T, int MODE>
+__device__ __forceinline__ void collide_row(const StepArgs& A, const Lane& L, int y, const Row<T>& P, double drp,
+                                            T psA, T psB, T ps, Acc& acc)
+{
+    const T lm = __shfl(psA, L.lane - 1, 64), rm_ = __shfl(psA, L.lane + 1, 64);
+    const T lc = __shfl(psB, L.lane - 1, 64), rc = __shfl(psB, L.lane + 1, 64);
+    const T ln = __shfl(ps, L.lane - 1, 64), rn_ = __shfl(ps, L.lane + 1, 64);
+    T Ftx, Fty;
+    force_tilde<T>(A, lm, psA, rm_, lc, rc, ln, ps, rn_, Ftx, Fty);
+    if (!L.interior) return;
+    update_node<T, MODE>(A, L, y, P, drp, psB, Ftx, Fty, acc);
+}
+
+
+// ----------------------------------------------------------------- host helpers
+inline DevEos dev_eos(const lbm_eos& e)
+{
+    DevEos E{};
+    E.base = e.base;
+    E.shape = e.shape;
+    E.RT = e.R * e.T;
+    if (e.base == LBM_BASE_PR) {
+        const double kap = 0.37464 + 1.54226 * e.omega - 0.26992 * e.omega * e.omega;
+        const double t = 1.0 + kap * (1.0 - std::sqrt(e.T / e.Tc));
+        E.aal = e.a * t * t;
+    } else {
+        E.aal = e.a;
+    }
+    E.b = e.b;
+    E.scale = e.scale;
+    E.k_vap = e.k_vap;
+    E.dP = e.dP_liq;
+    E.rho_v = e.rho_v;
+    E.rho_l = e.rho_l;
+    E.rho_max = e.rho_max;
+    E.rho_min = e.rho_min;
+    E.p0 = e.p_sat;
+    E.p_max = e.p_max;
+    E.p_min = e.p_min;
+    E.inv_a1sq = e.a1sq > 0 ? 1.0 / e.a1sq : 0.0;
+    E.b1 = e.b1;
+    E.inv_a3sq = e.a3sq > 0 ? 1.0 / e.a3sq : 0.0;
+    E.b3 = e.b3;
+    E.inv_L = e.rho_min > e.rho_max ? 1.0 / (e.rho_min - e.rho_max) : 0.0;
+    E.rho_m = e.rho_m;
+    E.theta = e.theta;
+    return E;
+}
+
+inline int validate(const lbm_params* p)
+{
+    if (!p || p->nx < 1 || p->ny < 1 || (p->prec != LBM_FP64 && p->prec != LBM_FP32_SHIFTED)) {
+        lbm_set_error("lbm: invalid lattice size or precision");
+        return LBM_EINVAL;
+    }
+    if ((long long)((p->nx + 63) & ~63) * p->ny * 8 >= (1LL << 32)) {
+        lbm_set_error("lbm: one population plane must stay below 4 GiB (lattice too large)");
+        return LBM_EINVAL;
+    }
+    if (!(p->G < 0.0)) {
+        lbm_set_error("lbm: G must be negative (Eq. InteractionPotential with p_EOS < rho c_s^2)");
+        return LBM_EINVAL;
+    }
+    for (int k = 0; k < 9; ++k)
+        if (!(p->tau[k] > 0.5)) {
+            lbm_set_error("lbm: every relaxation time must exceed 1/2");
+            return LBM_EINVAL;
+        }
+    if (p->kernel_variant < 0 || p->kernel_variant > LBM_VARIANT_BLOCK) {
+        lbm_set_error("lbm: kernel_variant must be 0 (automatic), 1 (row march) or 2 (row block)");
+        return LBM_EINVAL;
+    }
+    if (p->band_rows < 0 || p->band_rows > 4096) {
+        lbm_set_error("lbm: band_rows must be in [0, 4096] (0 = automatic)");
+        return LBM_EINVAL;
+    }
+    if (p->tau[7] != p->tau[8]) {
+        lbm_set_error("lbm: Eq. RelaxationMatrix relaxes both shear moments with tau_nu (tau[7] == tau[8])");
+        return LBM_EINVAL;
+    }
+    if (p->var_tau && !(p->tau_l > 0.5 && p->tau_v > 0.5 && p->rho_l_tau != p->rho_v_tau)) {
+        lbm_set_error("lbm: Eq. RelaxationTime needs tau_l, tau_v > 1/2 and rho_l != rho_v");
+        return LBM_EINVAL;
+    }
+    if (p->prec == LBM_FP32_SHIFTED && !(p->rho_ref > 0.0)) {
+        lbm_set_error("lbm: FP32-shifted storage needs rho_ref > 0");
+        return LBM_EINVAL;
+    }
+    if (!(p->eos.T > 0.0)) {
+        lbm_set_error("lbm: EOS not built (call lbm_eos_build first)");
+        return LBM_EINVAL;
+    }
+    return LBM_OK;
+}
+
+}  // namespace lbmk

@@ -81,6 +81,12 @@ def _signatures():
         "lbm_save": ([vp, vp, vp], i),
         "lbm_load": ([vp, vp, C.c_int64, vp], i),
         "lbm_destroy": ([vp], None),
+        "lbm_batch_layout": ([i, C.POINTER(LbmParams), C.POINTER(sz), C.POINTER(sz), C.POINTER(C.c_int64)], i),
+        "lbm_init_batched": ([C.POINTER(vp), i, C.POINTER(LbmParams), vp, vp, vp, sz, vp, vp, vp, vp], i),
+        "lbm_step_batched": ([vp, C.c_int64, vp], i),
+        "lbm_macros_batched": ([vp, vp, vp, vp, vp], i),
+        "lbm_status_batched": ([vp, C.POINTER(C.c_int), vp], i),
+        "lbm_destroy_batched": ([vp], None),
         "lbm_strerror": ([i], C.c_char_p),
         "lbm_last_error": ([], C.c_char_p),
     }
@@ -277,3 +283,64 @@ class Lattice:
 
     def load_state(self, buf, step: int):
         _check(load().lbm_load(self._h, buf.data_ptr(), int(step), self._s()), "lbm_load")
+
+
+# ---------------------------------------------------------------------------- batched lattices
+class Batch:
+    """B independent lattices advanced by one persistent launch (lbm_*_batched)."""
+
+    def __init__(self, params, rho0s, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.B = len(params)
+        self.P = (LbmParams * self.B)(*params)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        pb, wb = C.c_size_t(0), C.c_size_t(0)
+        offs = (C.c_int64 * (self.B + 1))()
+        _check(load().lbm_batch_layout(self.B, self.P, C.byref(pb), C.byref(wb), offs), "lbm_batch_layout")
+        self.offsets = [offs[i] for i in range(self.B + 1)]
+        self.shapes = [(p.ny, p.nx) for p in params]
+        self.f = [torch.empty(pb.value, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.ws = torch.zeros(wb.value, dtype=torch.uint8, device=self.device)
+        packed = np.concatenate([np.ascontiguousarray(r, dtype=np.float64).reshape(-1) for r in rho0s])
+        assert packed.size == self.offsets[-1]
+        self._rho0 = torch.as_tensor(packed, device=self.device)
+        h = C.c_void_p(0)
+        _check(load().lbm_init_batched(C.byref(h), self.B, self.P, self.f[0].data_ptr(), self.f[1].data_ptr(),
+                                       self.ws.data_ptr(), wb.value, self._rho0.data_ptr(), None, None,
+                                       C.c_void_p(self.stream.cuda_stream)), "lbm_init_batched")
+        self._h = h
+
+    def step(self, n: int):
+        _check(load().lbm_step_batched(self._h, int(n), C.c_void_p(self.stream.cuda_stream)), "lbm_step_batched")
+
+    def check(self):
+        bad = C.c_int(-1)
+        _check(load().lbm_status_batched(self._h, C.byref(bad), C.c_void_p(self.stream.cuda_stream)),
+               "lbm_status_batched")
+
+    def macros(self):
+        t = self.torch
+        n = self.offsets[-1]
+        rho, ux, uy = (t.empty(n, dtype=t.float64, device=self.device) for _ in range(3))
+        _check(load().lbm_macros_batched(self._h, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(),
+                                         C.c_void_p(self.stream.cuda_stream)), "lbm_macros_batched")
+        out = []
+        r, u, v = rho.cpu().numpy(), ux.cpu().numpy(), uy.cpu().numpy()
+        for b, (ny, nx) in enumerate(self.shapes):
+            sl = slice(self.offsets[b], self.offsets[b + 1])
+            out.append({"rho": r[sl].reshape(ny, nx), "ux": u[sl].reshape(ny, nx), "uy": v[sl].reshape(ny, nx)})
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lbm_destroy_batched(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
