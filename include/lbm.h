@@ -167,6 +167,37 @@ int lbm_load(lbm_ctx* ctx, const void* src, int64_t step, void* stream);
 void lbm_destroy(lbm_ctx* ctx);
 
 /* ------------------------------------------------------------------------
+ * Adjoint (discrete adjoint of lbm_step).  The loss is a function of the
+ * final density field; the caller supplies dL/drho(x, T).  Gradients are
+ * returned with respect to the four knots of the Smooth loop (Sec. III.D:
+ * rho_max, p_max, rho_min, p_min, as independent parameters; the ellipse
+ * coefficients follow them), the interaction constant G and the Eq. LiFS
+ * sigma (held fixed while G varies).  The forward must run from step 0 with
+ * checkpointing enabled; the adjoint recomputes each K-step segment from its
+ * checkpoint.  Eq. RelaxationTime (var_tau) is not differentiated.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the per-segment record (K steps of drho, j, psi) and of the
+ * adjoint workspace for parameters p and checkpoint interval K. */
+int lbm_adjoint_layout(const lbm_params* p, int K, size_t* rec_bytes, size_t* adj_bytes);
+/* Store the state every K steps into ckpt_buf (device, ckpt_bytes; one slot
+ * is lbm_layout's pop_bytes).  Call before the first lbm_step; K = 0 turns
+ * checkpointing off.  lbm_step returns LBM_ESTATE when the slots run out. */
+int lbm_set_checkpointing(lbm_ctx* ctx, void* ckpt_buf, size_t ckpt_bytes, int K);
+/* Gradient of L(rho(T)) given dL_drho_T (device float64 [ny][nx]).
+ * grad_out (host, 6 doubles): dL/d{rho_max, p_max, rho_min, p_min, G, sigma}
+ * (knot entries are 0 unless the shape is Smooth or Modified Smooth).
+ * dL_drho0 (device [ny][nx], may be NULL): gradient with respect to the
+ * initial density of f^eq(rho0, u = 0).  Synchronises; the forward state at
+ * T is restored on return. */
+int lbm_adjoint(lbm_ctx* ctx, const double* dL_drho_T, void* rec_buf, size_t rec_bytes, void* adj_buf, size_t adj_bytes,
+                double* grad_out, double* dL_drho0, void* stream);
+/* Replace the four interior knots of a built Smooth / Modified Smooth EOS and
+ * recompute its ellipse coefficients (Sec. III.D); LBM_EINVAL when the knots
+ * are out of order or an ellipse would not be real. */
+int lbm_eos_set_knots(lbm_eos* e, double rho_max, double p_max, double rho_min, double p_min);
+
+/* ------------------------------------------------------------------------
  * Batched lattices: B independent lattices (own size, EOS, relaxation times,
  * FP32 shift; one storage precision for all) advanced by ONE persistent
  * launch in which one workgroup owns one lattice and loops over the steps.

@@ -423,6 +423,23 @@ static void region3_coeffs(or_eos* e)
     e->b3 = dpl / (1.0 - sqrt(1.0 - D * D / e->a3sq));
 }
 
+/* Replace the four interior knots of a built Smooth loop and refit both
+ * ellipses (Sec. III.D).  Used to differentiate by finite differences with
+ * the knots treated as independent parameters. */
+int or_eos_set_knots(or_eos* e, double rho_max, double p_max, double rho_min, double p_min)
+{
+    if (e->shape != OR_SHAPE_SMOOTH && e->shape != OR_SHAPE_MODSMOOTH) return OR_EINVAL;
+    if (!(e->rho_v < rho_max && rho_max < rho_min && rho_min < e->rho_l)) return OR_EINVAL;
+    e->rho_max = rho_max;
+    e->p_max = p_max;
+    e->rho_min = rho_min;
+    e->p_min = p_min;
+    region1_coeffs(e);
+    region3_coeffs(e);
+    if (!(e->a1sq > 0) || !(e->a3sq > 0) || !isfinite(e->b1) || !isfinite(e->b3)) return OR_EINVAL;
+    return OR_OK;
+}
+
 static double smooth_maxwell_of_pmax(double pmax, const void* v)
 {
     or_eos* e = (or_eos*)v;

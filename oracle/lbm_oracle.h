@@ -75,6 +75,7 @@ typedef struct {
 
 /* thermodynamics (host precompute, FP64) */
 int    or_eos_build(or_eos* e, double G, double* sigma_out);
+int    or_eos_set_knots(or_eos* e, double rho_max, double p_max, double rho_min, double p_min);
 double or_base_p(const or_eos* e, double rho);
 double or_base_dp(const or_eos* e, double rho);
 double or_eos_p(const or_eos* e, double rho);

@@ -84,6 +84,8 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.or_eos_build.argtypes = [C.POINTER(OrEos), d, dp]
         L.or_eos_build.restype = i
+        L.or_eos_set_knots.argtypes = [C.POINTER(OrEos), d, d, d, d]
+        L.or_eos_set_knots.restype = i
         for name in ("or_base_p", "or_base_dp", "or_eos_p", "or_eos_dp"):
             getattr(L, name).argtypes = [C.POINTER(OrEos), d]
             getattr(L, name).restype = d
@@ -142,6 +144,16 @@ def eos_build(e: OrEos, G: float = -1.0) -> tuple[OrEos, float]:
     if st != OR_OK:
         raise OracleError("or_eos_build failed with status %d" % st)
     return e, s.value
+
+
+def eos_set_knots(e: OrEos, rho_max: float, p_max: float, rho_min: float, p_min: float) -> OrEos:
+    """Copy of a built Smooth loop with its four knots replaced and both ellipses refitted."""
+    out = OrEos()
+    C.memmove(C.byref(out), C.byref(e), C.sizeof(OrEos))
+    st = lib().or_eos_set_knots(C.byref(out), rho_max, p_max, rho_min, p_min)
+    if st != OR_OK:
+        raise OracleError("or_eos_set_knots failed with status %d" % st)
+    return out
 
 
 def eos_p(e: OrEos, rho) -> np.ndarray:

@@ -1,0 +1,515 @@
+// liblbm.so: discrete adjoint of the fused D2Q9 step (gradients of a loss on
+// the final density field with respect to the four knots of the shaped EOS
+// loop (Sec. III.D), the interaction constant G and the Eq. LiFS sigma).
+//
+// The forward stores its state every K steps (lbm_set_checkpointing).  The
+// adjoint walks the segments backwards: it restores a checkpoint, re-runs the
+// segment with a recording step that keeps (rho - rho_ref, j, psi) per node and
+// step, and then applies the transpose of each step in reverse.  One adjoint
+// step is two kernels:
+//   pass A  per node: lambda^{t+1} pulled from the downstream nodes (bounce-back
+//           at walls), transposed moment transform and MRT relaxation, Eq. LiFS
+//           and Eq. EquilibriumDistribution derivatives -> dL/dF~(x) and the
+//           local dL/dpsi(x); dL/dsigma and the F~ part of dL/dG.
+//   pass B  per node: the same local adjoint, plus dL/dpsi(x) gathered from the
+//           neighbours' dL/dF~ (transpose of Eq. ShanChenForce), through
+//           psi'(rho) (Eq. InteractionPotential) into lambda^t; dL/dp(rho(x))
+//           accumulates the derivatives with respect to the loop coefficients
+//           and the psi part of dL/dG.
+// Parameter gradients are summed in FP64 per workgroup in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_ctx.h"
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace {
+
+using namespace lbmk;
+
+enum { A_PMAX, A_RMAX, A_PMIN, A_RMIN, A_B1, A_A1, A_B3, A_A3, A_G, A_SIG, kAcc };
+
+struct AdjArgs {
+    StepArgs S;          // forward parameters (EOS, rates, G, sigma, walls, shift)
+    const void* lam_in;  // lambda^{t+1}: 9 planes [ny][ld]
+    void* lam_out;       // lambda^t
+    const void* rec;     // step t: drho, j_x, j_y, psi planes [ny][nx]
+    void* dft;           // dL/dF~_x, dL/dF~_y, local dL/dpsi planes [ny][nx]
+    double* acc;         // [blocks][kAcc] running sums
+    size_t lplane, rplane;
+    double c_e, c_q;     // 1/(tau_e - 1/2), 1/(tau_eps - 1/2) of Eq. LiFS
+};
+
+template <typename T>
+struct LocalAdj {
+    T df[9];
+    T dftx, dfty, dpsi;
+    double dsig;
+};
+
+template <typename T>
+__device__ __forceinline__ T ldT(const void* base, size_t i)
+{
+    return ((const T*)base)[i];
+}
+
+// node coordinates with periodic wrap in x and y (walls handled by the callers)
+__device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
+
+// psi and F~ at (x, y) from the recorded psi planes (ghost psi at walls)
+template <typename T>
+__device__ __forceinline__ void rec_force(const AdjArgs& A, int x, int y, T& psi, T& ftx, T& fty)
+{
+    const StepArgs& S = A.S;
+    const T* ps = (const T*)A.rec + 3 * A.rplane;
+    auto P = [&](int xx, int yy) -> T {
+        if (S.walls && yy < 0) return (T)S.psi_lo;
+        if (S.walls && yy >= S.ny) return (T)S.psi_hi;
+        yy = yy < 0 ? yy + S.ny : (yy >= S.ny ? yy - S.ny : yy);
+        return ps[(size_t)yy * S.nx + wrapx(xx, S.nx)];
+    };
+    psi = P(x, y);
+    force_tilde<T>(S, P(x - 1, y - 1), P(x, y - 1), P(x + 1, y - 1), P(x - 1, y), P(x + 1, y), P(x - 1, y + 1),
+                   P(x, y + 1), P(x + 1, y + 1), ftx, fty);
+}
+
+// mu_i = dL/df*_i(x) = lambda^{t+1}_i(x + c_i), or lambda^{t+1}_opp(i)(x) when x + c_i is solid
+template <typename T>
+__device__ __forceinline__ void pull_adjoint(const AdjArgs& A, int x, int y, T mu[9])
+{
+    const StepArgs& S = A.S;
+    const T* L = (const T*)A.lam_in;
+    const size_t P = A.lplane;
+    const int ld = S.ld;
+    const bool top = S.walls && y == S.ny - 1, bot = S.walls && y == 0;
+    const int yp = y == S.ny - 1 ? 0 : y + 1, ym = y == 0 ? S.ny - 1 : y - 1;
+    const int xp = wrapx(x + 1, S.nx), xm = wrapx(x - 1, S.nx);
+    const size_t r0 = (size_t)y * ld, rp = (size_t)yp * ld, rm = (size_t)ym * ld;
+    mu[0] = L[r0 + x];
+    mu[1] = L[1 * P + r0 + xp];
+    mu[3] = L[3 * P + r0 + xm];
+    mu[2] = top ? L[4 * P + r0 + x] : L[2 * P + rp + x];
+    mu[5] = top ? L[7 * P + r0 + x] : L[5 * P + rp + xp];
+    mu[6] = top ? L[8 * P + r0 + x] : L[6 * P + rp + xm];
+    mu[4] = bot ? L[2 * P + r0 + x] : L[4 * P + rm + x];
+    mu[7] = bot ? L[5 * P + r0 + x] : L[7 * P + rm + xm];
+    mu[8] = bot ? L[6 * P + r0 + x] : L[8 * P + rm + xp];
+}
+
+// Transpose of the node update (moments, MRT relaxation, Eq. LiFS source,
+// equilibrium, forced velocity) for fixed psi(x) and F~(x).
+template <typename T>
+__device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T dr, T jx, T jy, T psi, T ftx, T fty,
+                                              LocalAdj<T>& o)
+{
+    const StepArgs& S = A.S;
+    const T rho = (T)(S.rho_ref + (double)dr);
+    const T Fx = psi * ftx, Fy = psi * fty;
+    const T inv = (T)1 / rho;
+    const T ux = (jx + (T)0.5 * Fx) * inv, uy = (jy + (T)0.5 * Fy) * inv;
+    // nu = D^-1 M mu  (adjoint of f* = M^T D^-1 m*)
+    const T m14 = (mu[1] + mu[2]) + (mu[3] + mu[4]);
+    const T m58 = (mu[5] + mu[6]) + (mu[7] + mu[8]);
+    const T n0 = (mu[0] + m14 + m58) * (T)(1.0 / 9.0);
+    const T n1 = (-4 * mu[0] - m14 + 2 * m58) * (T)(1.0 / 36.0);
+    const T n2 = (4 * mu[0] - 2 * m14 + m58) * (T)(1.0 / 36.0);
+    const T a13 = mu[1] - mu[3], a24 = mu[2] - mu[4];
+    const T a5678x = (mu[5] - mu[6]) - (mu[7] - mu[8]);
+    const T a5678y = (mu[5] + mu[6]) - (mu[7] + mu[8]);
+    const T n3 = (a13 + a5678x) * (T)(1.0 / 6.0);
+    const T n4 = (-2 * a13 + a5678x) * (T)(1.0 / 12.0);
+    const T n5 = (a24 + a5678y) * (T)(1.0 / 6.0);
+    const T n6 = (-2 * a24 + a5678y) * (T)(1.0 / 12.0);
+    const T n7 = ((mu[1] - mu[2]) + (mu[3] - mu[4])) * (T)0.25;
+    const T n8 = ((mu[5] - mu[6]) + (mu[7] - mu[8])) * (T)0.25;
+    const T se = (T)S.s[1], sq = (T)S.s[2], sqx = (T)S.s[4], sqy = (T)S.s[6], snu = (T)S.s[7];
+    // m*_k = m_k - s_k (m_k - m^eq_k) + (1 - s_k/2) S_k: direct, equilibrium and source adjoints
+    const T d1 = n1 * ((T)1 - se), E1 = n1 * se, Q1 = n1 * ((T)1 - (T)0.5 * se);
+    const T d2 = n2 * ((T)1 - sq), E2 = n2 * sq, Q2 = n2 * ((T)1 - (T)0.5 * sq);
+    const T d4 = n4 * ((T)1 - sqx), E4 = n4 * sqx, Q4 = n4 * ((T)1 - (T)0.5 * sqx);
+    const T d6 = n6 * ((T)1 - sqy), E6 = n6 * sqy, Q6 = n6 * ((T)1 - (T)0.5 * sqy);
+    const T d7 = n7 * ((T)1 - snu), E7 = n7 * snu, Q7 = n7 * ((T)1 - (T)0.5 * snu);
+    const T d8 = n8 * ((T)1 - snu), E8 = n8 * snu, Q8 = n8 * ((T)1 - (T)0.5 * snu);
+    // conserved moments: m*_0 = rho, m*_3 = j_x + F_x, m*_5 = j_y + F_y
+    T drho = n0, djx = n3, djy = n5, dFx = n3, dFy = n5;
+    // equilibrium moments (Eq. EquilibriumDistribution in the moment basis)
+    const T u2 = ux * ux + uy * uy;
+    drho += E1 * (3 * u2 - 2) + E2 * (1 - 3 * u2) - E4 * ux - E6 * uy + E7 * (ux * ux - uy * uy) + E8 * ux * uy;
+    T dux = 6 * rho * ux * (E1 - E2) - E4 * rho + 2 * rho * ux * E7 + rho * uy * E8;
+    T duy = 6 * rho * uy * (E1 - E2) - E6 * rho - 2 * rho * uy * E7 + rho * ux * E8;
+    // Eq. LiFS source terms
+    const T q12 = 6 * (Q1 - Q2);
+    dux += Fx * q12 + 2 * Fx * Q7 + Fy * Q8;
+    duy += Fy * q12 - 2 * Fy * Q7 + Fx * Q8;
+    dFx += ux * q12 - Q4 + 2 * ux * Q7 + uy * Q8;
+    dFy += uy * q12 - Q6 - 2 * uy * Q7 + ux * Q8;
+    const T z = 12 * ((T)A.c_e * Q1 - (T)A.c_q * Q2);  // sigma |F~|^2 enters S_e and S_eps
+    T dftx = 2 * (T)S.sigma * z * ftx, dfty = 2 * (T)S.sigma * z * fty;
+    o.dsig = (double)z * ((double)ftx * (double)ftx + (double)fty * (double)fty);
+    // u = (j + F/2)/rho (Eq. Momentum)
+    djx += dux * inv;
+    djy += duy * inv;
+    dFx += (T)0.5 * dux * inv;
+    dFy += (T)0.5 * duy * inv;
+    drho -= (dux * ux + duy * uy) * inv;
+    // F = psi F~
+    dftx += psi * dFx;
+    dfty += psi * dFy;
+    o.dpsi = dFx * ftx + dFy * fty;
+    o.dftx = dftx;
+    o.dfty = dfty;
+    // rho = sum f, j = sum f c, m_k = sum M_ki f_i
+    o.df[0] = drho - 4 * d1 + 4 * d2;
+    const T b14 = drho - d1 - 2 * d2;
+    o.df[1] = b14 + djx - 2 * d4 + d7;
+    o.df[2] = b14 + djy - 2 * d6 - d7;
+    o.df[3] = b14 - djx + 2 * d4 + d7;
+    o.df[4] = b14 - djy + 2 * d6 - d7;
+    const T b58 = drho + 2 * d1 + d2;
+    o.df[5] = b58 + djx + d4 + djy + d6 + d8;
+    o.df[6] = b58 - djx - d4 + djy + d6 - d8;
+    o.df[7] = b58 - djx - d4 - djy - d6 + d8;
+    o.df[8] = b58 + djx + d4 - djy - d6 - d8;
+}
+
+__device__ __forceinline__ void block_accumulate(const double v[kAcc], double* acc)
+{
+    __shared__ double sh[kAcc][256];
+    const int t = threadIdx.y * blockDim.x + threadIdx.x;
+    for (int k = 0; k < kAcc; ++k) sh[k][t] = v[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < kAcc; ++k) sh[k][t] += sh[k][t + s];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double* a = acc + (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * kAcc;
+        for (int k = 0; k < kAcc; ++k) a[k] += sh[k][0];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_a(AdjArgs A)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    double v[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (x < A.S.nx && y < A.S.ny) {
+        const size_t o = (size_t)y * A.S.nx + x;
+        T mu[9];
+        pull_adjoint<T>(A, x, y, mu);
+        T psi, ftx, fty;
+        rec_force<T>(A, x, y, psi, ftx, fty);
+        LocalAdj<T> L;
+        local_adjoint<T>(A, mu, ldT<T>(A.rec, o), ldT<T>(A.rec, A.rplane + o), ldT<T>(A.rec, 2 * A.rplane + o), psi, ftx,
+                         fty, L);
+        T* d = (T*)A.dft;
+        d[o] = L.dftx;
+        d[A.rplane + o] = L.dfty;
+        d[2 * A.rplane + o] = L.dpsi;
+        v[A_SIG] = L.dsig;
+        v[A_G] = ((double)ftx * (double)L.dftx + (double)fty * (double)L.dfty) / A.S.G;  // F~ = -G sum(...)
+    }
+    block_accumulate(v, A.acc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_b(AdjArgs A)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
+    double v[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (x < A.S.nx && y < A.S.ny) {
+        const StepArgs& S = A.S;
+        const size_t o = (size_t)y * S.nx + x;
+        T mu[9];
+        pull_adjoint<T>(A, x, y, mu);
+        T psi, ftx, fty;
+        rec_force<T>(A, x, y, psi, ftx, fty);
+        const T dr = ldT<T>(A.rec, o);
+        LocalAdj<T> L;
+        local_adjoint<T>(A, mu, dr, ldT<T>(A.rec, A.rplane + o), ldT<T>(A.rec, 2 * A.rplane + o), psi, ftx, fty, L);
+        // transpose of Eq. ShanChenForce: dL/dpsi(x) += sum_k (-G w_k c_k) . dL/dF~(x - c_k)
+        const T* d = (const T*)A.dft;
+        const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+        const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        const T G = (T)S.G;
+        T dpsi = L.dpsi;
+        double dpsi_lo = 0.0, dpsi_hi = 0.0;
+        for (int k = 1; k < 9; ++k) {
+            const T wk = (k < 5) ? (T)(1.0 / 3.0) : (T)(1.0 / 12.0);
+            const int sy = y - cy[k];
+            if (!(S.walls && (sy < 0 || sy >= S.ny))) {
+                const int yy = sy < 0 ? sy + S.ny : (sy >= S.ny ? sy - S.ny : sy);
+                const size_t q = (size_t)yy * S.nx + wrapx(x - cx[k], S.nx);
+                dpsi += -G * wk * ((T)cx[k] * d[q] + (T)cy[k] * d[A.rplane + q]);
+            }
+            // ghost solid node x + c_k (walls): its psi is psi(rho_wall), which depends on G
+            const int gy = y + cy[k];
+            if (S.walls && (gy < 0 || gy >= S.ny)) {
+                const double g = -(double)G * (double)wk *
+                                 ((double)cx[k] * (double)L.dftx + (double)cy[k] * (double)L.dfty);
+                if (gy < 0) dpsi_lo += g;
+                else dpsi_hi += g;
+            }
+        }
+        // psi(rho) (Eq. InteractionPotential): psi' = (p' - 1/3)/(G psi), dpsi/dp = 1/(G psi)
+        const double rho = S.rho_ref + (double)dr;
+        double drho_eos = 0.0;
+        if (psi > (T)0) {
+            const double inv_gpsi = 1.0 / (S.G * (double)psi);
+            const double dp = dev_eos_dp(S.eos, rho);
+            drho_eos = (dp - 1.0 / 3.0) * inv_gpsi * (double)dpsi;
+            const double P = (double)dpsi * inv_gpsi;  // dL/dp(rho(x))
+            const DevEos& E = S.eos;
+            if ((E.shape == LBM_SHAPE_SMOOTH || E.shape == LBM_SHAPE_MODSMOOTH) && rho > E.rho_v && rho < E.rho_l) {
+                if (rho <= E.rho_max) {
+                    const double dd = rho - E.rho_max, sq = sqrt(1.0 - dd * dd * E.inv_a1sq);
+                    v[A_PMAX] += P;
+                    v[A_B1] += -P * (1.0 - sq);
+                    v[A_A1] += P * E.b1 * dd * dd * E.inv_a1sq * E.inv_a1sq / (2.0 * sq);
+                    v[A_RMAX] += P * E.b1 * dd * E.inv_a1sq / sq;
+                } else if (rho < E.rho_min) {
+                    const double t = (rho - E.rho_max) * E.inv_L;
+                    const double h = t * t * (3.0 - 2.0 * t), hp = 6.0 * t * (1.0 - t);
+                    v[A_PMAX] += P * (1.0 - h);
+                    v[A_PMIN] += P * h;
+                    v[A_RMAX] += P * (E.p_min - E.p_max) * hp * (t - 1.0) * E.inv_L;
+                    v[A_RMIN] += P * (E.p_min - E.p_max) * hp * (-t) * E.inv_L;
+                } else {
+                    const double dd = rho - E.rho_min, sq = sqrt(1.0 - dd * dd * E.inv_a3sq);
+                    v[A_PMIN] += P;
+                    v[A_B3] += P * (1.0 - sq);
+                    v[A_A3] += -P * E.b3 * dd * dd * E.inv_a3sq * E.inv_a3sq / (2.0 * sq);
+                    v[A_RMIN] += -P * E.b3 * dd * E.inv_a3sq / sq;
+                }
+            }
+            v[A_G] += (double)dpsi * (-(double)psi / (2.0 * S.G));
+        }
+        v[A_G] += dpsi_lo * (-S.psi_lo / (2.0 * S.G)) + dpsi_hi * (-S.psi_hi / (2.0 * S.G));
+        T* Lo = (T*)A.lam_out;
+        const size_t li = (size_t)y * S.ld + x;
+        const T de = (T)drho_eos;
+        for (int i = 0; i < 9; ++i) Lo[i * A.lplane + li] = L.df[i] + de;
+    }
+    block_accumulate(v, A.acc);
+}
+
+template <typename T>
+__global__ void k_adj_seed(int nx, int ny, int ld, size_t lplane, const double* dL, void* lam)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= nx || y >= ny) return;
+    const T v = (T)dL[(size_t)y * nx + x];
+    T* L = (T*)lam;
+    for (int i = 0; i < 9; ++i) L[i * lplane + (size_t)y * ld + x] = v;
+}
+
+// dL/drho0(x) = sum_i w_i lambda^0_i(x)  (initial state f^eq(rho0, u = 0))
+template <typename T>
+__global__ void k_adj_rho0(int nx, int ny, int ld, size_t lplane, const void* lam, double* out)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= nx || y >= ny) return;
+    const double w[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+    const T* L = (const T*)lam;
+    double s = 0.0;
+    for (int i = 0; i < 9; ++i) s += w[i] * (double)L[i * lplane + (size_t)y * ld + x];
+    out[(size_t)y * nx + x] = s;
+}
+
+__global__ void k_zero(double* p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+struct AdjLayout {
+    size_t tsz, rec_bytes, off_fT, off_lam0, off_lam1, off_dft, off_acc, total;
+    int bx, by;
+};
+
+AdjLayout adj_layout(const lbm_params& p, int ld, size_t pop_bytes, int K)
+{
+    AdjLayout L;
+    L.tsz = p.prec == LBM_FP32_SHIFTED ? sizeof(float) : sizeof(double);
+    const size_t nn = (size_t)p.nx * p.ny, lp = (size_t)ld * p.ny;
+    L.rec_bytes = (size_t)K * 4 * nn * L.tsz;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    L.bx = (p.nx + 63) / 64;
+    L.by = (p.ny + 3) / 4;
+    size_t o = 0;
+    L.off_fT = o;
+    o += al(pop_bytes);
+    L.off_lam0 = o;
+    o += al(9 * lp * L.tsz);
+    L.off_lam1 = o;
+    o += al(9 * lp * L.tsz);
+    L.off_dft = o;
+    o += al(3 * nn * L.tsz);
+    L.off_acc = o;
+    o += al((size_t)L.bx * L.by * kAcc * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+void launch_adj(lbm_ctx* c, AdjArgs& A, const AdjLayout& L, hipStream_t s, bool pass_b)
+{
+    const dim3 g(L.bx, L.by), b(64, 4);
+    if (pass_b) hipLaunchKernelGGL(k_adj_b<T>, g, b, 0, s, A);
+    else hipLaunchKernelGGL(k_adj_a<T>, g, b, 0, s, A);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_adjoint_layout(const lbm_params* p, int K, size_t* rec_bytes, size_t* adj_bytes)
+{
+    if (!p || K < 1) {
+        lbm_set_error("lbm_adjoint_layout: need parameters and K >= 1");
+        return LBM_EINVAL;
+    }
+    int ld;
+    size_t pop, ws;
+    const int st = lbm_layout(p, &ld, &pop, &ws);
+    if (st != LBM_OK) return st;
+    const AdjLayout L = adj_layout(*p, ld, pop, K);
+    if (rec_bytes) *rec_bytes = L.rec_bytes;
+    if (adj_bytes) *adj_bytes = L.total;
+    return LBM_OK;
+}
+
+int lbm_set_checkpointing(lbm_ctx* c, void* ckpt_buf, size_t ckpt_bytes, int K)
+{
+    if (!c || (K > 0 && !ckpt_buf)) return LBM_EINVAL;
+    if (c->step != 0) {
+        lbm_set_error("lbm_set_checkpointing: enable checkpointing before the first step");
+        return LBM_ESTATE;
+    }
+    c->ckpt = ckpt_buf;
+    c->ckpt_K = K > 0 ? K : 0;
+    c->ckpt_slots = K > 0 ? (int64_t)(ckpt_bytes / c->pop_bytes) : 0;
+    if (K > 0 && c->ckpt_slots < 1) {
+        lbm_set_error("lbm_set_checkpointing: buffer smaller than one population buffer");
+        return LBM_EINVAL;
+    }
+    return LBM_OK;
+}
+
+int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_bytes, void* adj_buf, size_t adj_bytes,
+                double* grad_out, double* dL_drho0, void* stream)
+{
+    if (!c || !dL_drho_T || !rec_buf || !adj_buf || !grad_out) return LBM_EINVAL;
+    const lbm_params& P = c->P;
+    if (c->ckpt_K < 1 || c->step < 1) {
+        lbm_set_error("lbm_adjoint: run the forward with checkpointing enabled (lbm_set_checkpointing) first");
+        return LBM_ESTATE;
+    }
+    if (P.var_tau) {
+        lbm_set_error("lbm_adjoint: density-dependent relaxation (Eq. RelaxationTime) is not differentiated");
+        return LBM_EINVAL;
+    }
+    const int K = c->ckpt_K;
+    const int64_t T_end = c->step;
+    const int64_t S = (T_end + K - 1) / K;
+    if (S > c->ckpt_slots) return LBM_ESTATE;
+    const AdjLayout L = adj_layout(P, c->ld, c->pop_bytes, K);
+    if (rec_bytes < L.rec_bytes || adj_bytes < L.total) {
+        lbm_set_error("lbm_adjoint: record or adjoint workspace smaller than lbm_adjoint_layout requires");
+        return LBM_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char* ab = (char*)adj_buf;
+    const bool f32 = P.prec == LBM_FP32_SHIFTED;
+    const size_t nn = (size_t)P.nx * P.ny, lp = (size_t)c->ld * P.ny;
+    // keep the final forward state; the recomputation overwrites the buffers
+    if (!hip_ok(hipMemcpyAsync(ab + L.off_fT, c->buf[c->cur], c->pop_bytes, hipMemcpyDeviceToDevice, s), "save f(T)"))
+        return LBM_EHIP;
+    void* lam[2] = {ab + L.off_lam0, ab + L.off_lam1};
+    double* acc = (double*)(ab + L.off_acc);
+    const size_t nacc = (size_t)L.bx * L.by * kAcc;
+    hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, acc, nacc);
+    dim3 g1((P.nx + 127) / 128, P.ny);
+    if (f32) hipLaunchKernelGGL(k_adj_seed<float>, g1, dim3(128), 0, s, P.nx, P.ny, c->ld, lp, dL_drho_T, lam[0]);
+    else hipLaunchKernelGGL(k_adj_seed<double>, g1, dim3(128), 0, s, P.nx, P.ny, c->ld, lp, dL_drho_T, lam[0]);
+    if (!hip_ok(hipGetLastError(), "adjoint seed")) return LBM_EHIP;
+
+    AdjArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.S = c->args;
+    A.dft = ab + L.off_dft;
+    A.acc = acc;
+    A.lplane = lp;
+    A.rplane = nn;
+    A.c_e = 1.0 / (P.tau[1] - 0.5);
+    A.c_q = 1.0 / (P.tau[2] - 0.5);
+    int li = 0;
+    for (int64_t k = S - 1; k >= 0; --k) {
+        const int64_t t0 = k * K;
+        const int n = (int)((T_end - t0) < K ? (T_end - t0) : K);
+        if (!hip_ok(hipMemcpyAsync(c->buf[c->cur], (char*)c->ckpt + k * c->pop_bytes, c->pop_bytes,
+                                   hipMemcpyDeviceToDevice, s),
+                    "restore checkpoint"))
+            return LBM_EHIP;
+        c->step = t0;
+        for (int j = 0; j < n; ++j) {
+            if (!launch_record_step(c, (char*)rec_buf + (size_t)j * 4 * nn * L.tsz, s)) return LBM_EHIP;
+            c->cur ^= 1;
+            c->step++;
+        }
+        for (int j = n - 1; j >= 0; --j) {
+            A.rec = (const char*)rec_buf + (size_t)j * 4 * nn * L.tsz;
+            A.lam_in = lam[li];
+            A.lam_out = lam[li ^ 1];
+            if (f32) {
+                launch_adj<float>(c, A, L, s, false);
+                launch_adj<float>(c, A, L, s, true);
+            } else {
+                launch_adj<double>(c, A, L, s, false);
+                launch_adj<double>(c, A, L, s, true);
+            }
+            if (!hip_ok(hipGetLastError(), "adjoint step launch")) return LBM_EHIP;
+            li ^= 1;
+        }
+    }
+    // restore the forward state at T
+    if (!hip_ok(hipMemcpyAsync(c->buf[c->cur], ab + L.off_fT, c->pop_bytes, hipMemcpyDeviceToDevice, s), "restore f(T)"))
+        return LBM_EHIP;
+    c->step = T_end;
+    if (dL_drho0) {
+        if (f32) hipLaunchKernelGGL(k_adj_rho0<float>, g1, dim3(128), 0, s, P.nx, P.ny, c->ld, lp, (const void*)lam[li], dL_drho0);
+        else hipLaunchKernelGGL(k_adj_rho0<double>, g1, dim3(128), 0, s, P.nx, P.ny, c->ld, lp, (const void*)lam[li], dL_drho0);
+    }
+    std::vector<double> h(nacc);
+    if (!hip_ok(hipMemcpyAsync(h.data(), acc, nacc * sizeof(double), hipMemcpyDeviceToHost, s), "gradient copy") ||
+        !hip_ok(hipStreamSynchronize(s), "adjoint sync"))
+        return LBM_EHIP;
+    double a[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (size_t b = 0; b < (size_t)L.bx * L.by; ++b)
+        for (int k = 0; k < kAcc; ++k) a[k] += h[b * kAcc + k];
+    // chain the loop coefficients (b1, a1^2), (b3, a3^2) back to the four knots
+    double gk[4] = {0, 0, 0, 0};
+    if (P.eos.shape == LBM_SHAPE_SMOOTH || P.eos.shape == LBM_SHAPE_MODSMOOTH) {
+        double J1[2][2], J3[2][2];
+        lbm_knot_jacobians(&P.eos, J1, J3);
+        gk[0] = a[A_RMAX] + a[A_B1] * J1[0][0] + a[A_A1] * J1[1][0];
+        gk[1] = a[A_PMAX] + a[A_B1] * J1[0][1] + a[A_A1] * J1[1][1];
+        gk[2] = a[A_RMIN] + a[A_B3] * J3[0][0] + a[A_A3] * J3[1][0];
+        gk[3] = a[A_PMIN] + a[A_B3] * J3[0][1] + a[A_A3] * J3[1][1];
+    }
+    grad_out[0] = gk[0];
+    grad_out[1] = gk[1];
+    grad_out[2] = gk[2];
+    grad_out[3] = gk[3];
+    grad_out[4] = a[A_G];
+    grad_out[5] = a[A_SIG];
+    return lbm_status_check(c, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,35 @@
+// Host context of liblbm.so (internal).
+#pragma once
+
+#include "lbm_device.h"
+
+struct lbm_ctx {
+    lbm_params P;
+    lbmk::StepArgs args;
+    int ld;
+    size_t plane, pop_bytes;
+    void* buf[2];
+    int cur;
+    int64_t step;
+    char* ws;
+    size_t ws_bytes;
+    unsigned* err;
+    double* partials;
+    double* redblk;
+    double* hist;
+    double* red;
+    int64_t hist_count;
+    int grid;
+    // checkpoints for the adjoint: the state f*(t) at every t = K*slot
+    void* ckpt;
+    int64_t ckpt_slots;
+    int ckpt_K;
+};
+
+
+namespace lbmk {
+bool hip_ok(hipError_t e, const char* what);
+bool launch_reduce(lbm_ctx* c, double* out, long long step, int with_step, hipStream_t s);
+bool launch_record_step(lbm_ctx* c, void* rec, hipStream_t s);
+int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk);
+}  // namespace lbmk

@@ -63,6 +63,39 @@ __device__ __forceinline__ double dev_eos_p(const DevEos& E, double r)
     return E.p_min + E.b3 * (1.0 - sqrt(1.0 - d * d * E.inv_a3sq));
 }
 
+__device__ __forceinline__ double dev_base_dp(const DevEos& E, double r)
+{
+    if (E.base == LBM_BASE_CS) {
+        const double n = 0.25 * E.b * r, m = 1.0 - n;
+        const double m2 = m * m;
+        return E.scale * (E.RT * (1.0 + n * (4.0 + n * (4.0 + n * (-4.0 + n)))) / (m2 * m2) - 2.0 * E.aal * r);
+    }
+    const double br = E.b * r, m = 1.0 - br, D = 1.0 + br * (2.0 - br);
+    return E.scale * (E.RT / (m * m) - 2.0 * E.aal * r * (1.0 + br) / (D * D));
+}
+
+// dp/drho of the shaped EOS (FP64)
+__device__ __forceinline__ double dev_eos_dp(const DevEos& E, double r)
+{
+    if (E.shape == LBM_SHAPE_NONE) return dev_base_dp(E, r);
+    if (r <= E.rho_v) return E.k_vap * dev_base_dp(E, r);
+    if (r >= E.rho_l) return dev_base_dp(E, r);
+    if (E.shape == LBM_SHAPE_PENG) {
+        const double u = r - E.rho_v, v = r - E.rho_l, w = r - E.rho_m;
+        return E.theta * (u * v + v * w + w * u);
+    }
+    if (r <= E.rho_max) {
+        const double d = r - E.rho_max;
+        return -E.b1 * d * E.inv_a1sq / sqrt(1.0 - d * d * E.inv_a1sq);
+    }
+    if (r < E.rho_min) {
+        const double t = (r - E.rho_max) * E.inv_L;
+        return (E.p_min - E.p_max) * 6.0 * t * (1.0 - t) * E.inv_L;
+    }
+    const double d = r - E.rho_min;
+    return E.b3 * d * E.inv_a3sq / sqrt(1.0 - d * d * E.inv_a3sq);
+}
+
 // ----------------------------------------------------------------- kernel arguments
 struct StepArgs {
     const void* src;
@@ -82,9 +115,12 @@ struct StepArgs {
     long long step;
     // lbm_macros outputs (MODE_MACROS)
     double *o_rho, *o_ux, *o_uy, *o_psi, *o_p, *o_fx, *o_fy;
+    // forward record for the adjoint (MODE_RECORD): planes drho, j_x, j_y, psi of [ny][nx]
+    void* rec;
+    size_t rec_plane;
 };
 
-enum { MODE_STEP = 0, MODE_STEP_REDUCE = 1, MODE_MACROS = 2 };
+enum { MODE_STEP = 0, MODE_STEP_REDUCE = 1, MODE_MACROS = 2, MODE_RECORD = 3 };
 
 __constant__ double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
@@ -296,7 +332,16 @@ __device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, in
         if (A.o_fx) A.o_fx[o] = (double)Fx;
         if (A.o_fy) A.o_fy[o] = (double)Fy;
     }
-    if (MODE != MODE_STEP) {
+    if (MODE == MODE_RECORD) {
+        // pre-collision state the adjoint of this step needs: drho, j (unforced), psi
+        T* rc = (T*)A.rec;
+        const size_t o = (size_t)y * A.nx + x;
+        rc[o] = dr;
+        rc[A.rec_plane + o] = jx;
+        rc[2 * A.rec_plane + o] = jy;
+        rc[3 * A.rec_plane + o] = psB;
+    }
+    if (MODE == MODE_STEP_REDUCE || MODE == MODE_MACROS) {
         acc.m += rho_d;
         acc.x += (double)rho * (double)ux;
         acc.y += (double)rho * (double)uy;

@@ -32,6 +32,7 @@
 #include <new>
 
 #include "lbm.h"
+#include "lbm_ctx.h"
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(256) LBM_OCCUPANCY_HINT void k_step(StepArgs A)
         march_row<T, MODE>(A, V, L, r + 3, y0, y1, R2, R3, R1, d2, d3, psA, psB, acc);
     }
     }
-    if (MODE != MODE_STEP) {
+    if (MODE == MODE_STEP_REDUCE || MODE == MODE_MACROS) {
         acc.m = wave_sum(acc.m);
         acc.x = wave_sum(acc.x);
         acc.y = wave_sum(acc.y);
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
                        sps[k][L.lane + 1], sps[k + 1][L.lane - 1], sps[k + 1][L.lane], sps[k + 1][L.lane + 1], Ftx, Fty);
         update_node<T, MODE>(A, L, r, R, dr, ps, Ftx, Fty, acc);
     }
-    if (MODE != MODE_STEP) {
+    if (MODE == MODE_STEP_REDUCE || MODE == MODE_MACROS) {
         acc.m = wave_sum(acc.m);
         acc.x = wave_sum(acc.x);
         acc.y = wave_sum(acc.y);
@@ -307,26 +308,7 @@ __global__ void k_populations(StepArgs A, double* out)
 }  // namespace
 
 // ===================================================================== host side
-struct lbm_ctx {
-    lbm_params P;
-    StepArgs args;
-    int ld;
-    size_t plane, pop_bytes;
-    void* buf[2];
-    int cur;
-    int64_t step;
-    char* ws;
-    size_t ws_bytes;
-    unsigned* err;
-    double* partials;
-    double* redblk;
-    double* hist;
-    double* red;
-    int64_t hist_count;
-    int grid;
-};
-
-namespace {
+namespace lbmk {
 
 bool hip_ok(hipError_t e, const char* what)
 {
@@ -422,6 +404,34 @@ bool launch_reduce(lbm_ctx* c, double* out, long long step, int with_step, hipSt
     return hip_ok(hipGetLastError(), "reduction launch");
 }
 
+// one forward step of the row-block kernel that also records (drho, j, psi) per node
+bool launch_record_step(lbm_ctx* c, void* rec, hipStream_t s)
+{
+    StepArgs A = c->args;
+    A.src = c->buf[c->cur];
+    A.dst = c->buf[c->cur ^ 1];
+    A.step = c->step;
+    A.rec = rec;
+    A.rec_plane = (size_t)c->P.nx * c->P.ny;
+    if (!A.blk) {
+        // recording always uses the row-block decomposition (same node arithmetic)
+        int strips, seg_h, nseg, blk;
+        lbm_params q = c->P;
+        q.kernel_variant = LBM_VARIANT_BLOCK;
+        A.nwork = decompose(q, &strips, &seg_h, &nseg, &blk);
+        A.strips = strips;
+        A.seg_h = seg_h;
+        A.nseg = nseg;
+        A.blk = 1;
+    }
+    const int grid = ((A.nwork / kBlkWaves) + 7) & ~7;
+    if (c->P.prec == LBM_FP32_SHIFTED)
+        hipLaunchKernelGGL((k_step_blk<float, MODE_RECORD>), dim3(grid), dim3(64 * kBlkWaves), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_step_blk<double, MODE_RECORD>), dim3(grid), dim3(64 * kBlkWaves), 0, s, A);
+    return hip_ok(hipGetLastError(), "k_step_blk(record) launch");
+}
+
 template <typename T>
 bool launch_step(lbm_ctx* c, int mode, hipStream_t s)
 {
@@ -439,7 +449,7 @@ bool launch_step(lbm_ctx* c, int mode, hipStream_t s)
     return hip_ok(hipGetLastError(), "k_step launch");
 }
 
-}  // namespace
+}  // namespace lbmk
 
 extern "C" {
 
@@ -562,6 +572,17 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
     hipStream_t s = (hipStream_t)stream;
     const bool f32 = c->P.prec == LBM_FP32_SHIFTED;
     for (int64_t k = 0; k < nsteps; ++k) {
+        if (c->ckpt_K > 0 && c->step % c->ckpt_K == 0) {
+            const int64_t slot = c->step / c->ckpt_K;
+            if (slot >= c->ckpt_slots) {
+                lbm_set_error("lbm_step: checkpoint buffer full (more steps than slots * K)");
+                return LBM_ESTATE;
+            }
+            if (!hip_ok(hipMemcpyAsync((char*)c->ckpt + slot * c->pop_bytes, c->buf[c->cur], c->pop_bytes,
+                                       hipMemcpyDeviceToDevice, s),
+                        "checkpoint copy"))
+                return LBM_EHIP;
+        }
         const bool red = c->P.reduce_every > 0 && (c->step % c->P.reduce_every) == 0;
         const int mode = red ? MODE_STEP_REDUCE : MODE_STEP;
         if (!(f32 ? launch_step<float>(c, mode, s) : launch_step<double>(c, mode, s))) return LBM_EHIP;

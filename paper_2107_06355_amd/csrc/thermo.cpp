@@ -11,6 +11,7 @@
 // 8-point Gauss-Legendre quadrature in ln(rho) for integrals over the
 // shaped loop.
 #include <cmath>
+#include <complex>
 #include <cstring>
 
 #include "lbm.h"
@@ -176,22 +177,21 @@ double gl_log(F g, double lo, double hi, int panels = 768)
 }
 
 // ----------------------------------------------------------------- shaped loop
-void fill_region1(lbm_eos& e)
+// ellipse coefficients (a^2, b) of a region joining the saturated knot
+// (rho_s, p_s), where the slope is S, to the knot (rho_k, p_k) of zero slope;
+// with D = rho_k - rho_s, dp = p_k - p_s and r = dp/(S D):
+// a^2 = D^2 (1-r)^2/(1-2r), b = |dp| (1-r)/(1-2r) (Sec. III.D, regions 1 and 3)
+template <class R>
+void ellipse_coeffs(R rho_k, R p_k, double rho_s, double p_s, double S, R* asq, R* b)
 {
-    // Sec. III.D region 1, written with r = (p_max-p_sat)/(slope_v D):
-    // a1^2 = D^2 (1-r)^2/(1-2r), b1 = (p_max-p_sat)(1-r)/(1-2r)
-    const double D = e.rho_max - e.rho_v, dp = e.p_max - e.p_sat_new;
-    const double r = dp / (e.slope_v * D);
-    e.a1sq = D * D * (1.0 - r) * (1.0 - r) / (1.0 - 2.0 * r);
-    e.b1 = dp * (1.0 - r) / (1.0 - 2.0 * r);
+    const R D = rho_k - rho_s, dp = p_k - p_s;
+    const R r = dp / (S * D);
+    *asq = D * D * (1.0 - r) * (1.0 - r) / (1.0 - 2.0 * r);
+    *b = (std::real(dp) < 0.0 ? -dp : dp) * (1.0 - r) / (1.0 - 2.0 * r);
 }
-void fill_region3(lbm_eos& e)
-{
-    const double D = e.rho_l - e.rho_min, dp = e.p_sat_new - e.p_min;
-    const double r = dp / (e.slope_l * D);
-    e.a3sq = D * D * (1.0 - r) * (1.0 - r) / (1.0 - 2.0 * r);
-    e.b3 = dp * (1.0 - r) / (1.0 - 2.0 * r);
-}
+
+void fill_region1(lbm_eos& e) { ellipse_coeffs<double>(e.rho_max, e.p_max, e.rho_v, e.p_sat_new, e.slope_v, &e.a1sq, &e.b1); }
+void fill_region3(lbm_eos& e) { ellipse_coeffs<double>(e.rho_min, e.p_min, e.rho_l, e.p_sat_new, e.slope_l, &e.a3sq, &e.b3); }
 
 double mech_residual(const lbm_eos& e, double eps, double G, bool* bad)
 {
@@ -239,6 +239,50 @@ void lbm_set_error(const char* msg)
 }
 
 extern "C" const char* lbm_last_error(void) { return g_msg; }
+
+// d(b1, a1^2)/d(rho_max, p_max) and d(b3, a3^2)/d(rho_min, p_min) by complex-step
+// differentiation of the coefficient formulas (exact to rounding)
+void lbm_knot_jacobians(const lbm_eos* ep, double J1[2][2], double J3[2][2])
+{
+    const lbm_eos& e = *ep;
+    using C = std::complex<double>;
+    const double h = 1e-30;
+    for (int k = 0; k < 2; ++k) {
+        const double sr = k == 0 ? h * std::fabs(e.rho_max) : h * std::fabs(e.p_max);
+        C a, b;
+        ellipse_coeffs<C>(C(e.rho_max, k == 0 ? sr : 0.0), C(e.p_max, k == 1 ? sr : 0.0), e.rho_v, e.p_sat_new, e.slope_v,
+                          &a, &b);
+        J1[0][k] = b.imag() / sr;
+        J1[1][k] = a.imag() / sr;
+        const double s3 = k == 0 ? h * std::fabs(e.rho_min) : h * std::fabs(e.p_min);
+        ellipse_coeffs<C>(C(e.rho_min, k == 0 ? s3 : 0.0), C(e.p_min, k == 1 ? s3 : 0.0), e.rho_l, e.p_sat_new, e.slope_l,
+                          &a, &b);
+        J3[0][k] = b.imag() / s3;
+        J3[1][k] = a.imag() / s3;
+    }
+}
+
+extern "C" int lbm_eos_set_knots(lbm_eos* ep, double rho_max, double p_max, double rho_min, double p_min)
+{
+    lbm_eos& e = *ep;
+    if (e.shape != LBM_SHAPE_SMOOTH && e.shape != LBM_SHAPE_MODSMOOTH) {
+        lbm_set_error("lbm_eos_set_knots: only the Smooth loops have four knots");
+        return LBM_EINVAL;
+    }
+    if (!(e.rho_v < rho_max && rho_max < rho_min && rho_min < e.rho_l) ||
+        !(2.0 * (p_max - e.p_sat_new) < e.slope_v * (rho_max - e.rho_v)) || !(p_max > e.p_sat_new) ||
+        !(2.0 * (e.p_sat_new - p_min) < e.slope_l * (e.rho_l - rho_min)) || !(p_min < e.p_sat_new)) {
+        lbm_set_error("lbm_eos_set_knots: knots out of order or an ellipse would not be real");
+        return LBM_EINVAL;
+    }
+    e.rho_max = rho_max;
+    e.p_max = p_max;
+    e.rho_min = rho_min;
+    e.p_min = p_min;
+    fill_region1(e);
+    fill_region3(e);
+    return LBM_OK;
+}
 
 extern "C" double lbm_eos_pressure(const lbm_eos* ep, double rho)
 {

@@ -87,6 +87,10 @@ def _signatures():
         "lbm_macros_batched": ([vp, vp, vp, vp, vp], i),
         "lbm_status_batched": ([vp, C.POINTER(C.c_int), vp], i),
         "lbm_destroy_batched": ([vp], None),
+        "lbm_adjoint_layout": ([C.POINTER(LbmParams), i, C.POINTER(sz), C.POINTER(sz)], i),
+        "lbm_set_checkpointing": ([vp, vp, sz, i], i),
+        "lbm_adjoint": ([vp, vp, vp, sz, vp, sz, dp, vp, vp], i),
+        "lbm_eos_set_knots": ([C.POINTER(LbmEos), d, d, d, d], i),
         "lbm_strerror": ([i], C.c_char_p),
         "lbm_last_error": ([], C.c_char_p),
     }
@@ -148,6 +152,23 @@ def eos_pressure(e: LbmEos, rho: float) -> float:
 
 def eos_slope(e: LbmEos, rho: float) -> float:
     return load().lbm_eos_slope(C.byref(e), float(rho))
+
+
+def eos_set_knots(e: LbmEos, rho_max: float, p_max: float, rho_min: float, p_min: float) -> LbmEos:
+    """Copy of a built Smooth / Modified Smooth EOS with the four loop knots replaced."""
+    out = LbmEos()
+    C.memmove(C.byref(out), C.byref(e), C.sizeof(LbmEos))
+    _check(load().lbm_eos_set_knots(C.byref(out), rho_max, p_max, rho_min, p_min), "lbm_eos_set_knots")
+    return out
+
+
+def adjoint_layout(P: LbmParams, K: int) -> tuple[int, int]:
+    rec, adj = C.c_size_t(0), C.c_size_t(0)
+    _check(load().lbm_adjoint_layout(C.byref(P), int(K), C.byref(rec), C.byref(adj)), "lbm_adjoint_layout")
+    return rec.value, adj.value
+
+
+GRAD_NAMES = ("rho_max", "p_max", "rho_min", "p_min", "G", "sigma")
 
 
 def make_params(nx, ny, eos: LbmEos, G=-1.0, sigma=0.0, tau=None, prec=FP64, rho_ref=None, walls=False,
@@ -283,6 +304,31 @@ class Lattice:
 
     def load_state(self, buf, step: int):
         _check(load().lbm_load(self._h, buf.data_ptr(), int(step), self._s()), "lbm_load")
+
+    def enable_checkpointing(self, K: int, max_steps: int):
+        """Keep the state every K steps (up to max_steps) for lbm_adjoint; call before stepping."""
+        t = self.torch
+        slots = max(1, -(-int(max_steps) // int(K)))
+        self._ckpt = t.empty(slots * self.pop_bytes, dtype=t.uint8, device=self.device)
+        rec, adj = adjoint_layout(self.P, K)
+        self._rec = t.empty(rec, dtype=t.uint8, device=self.device)
+        self._adj = t.empty(adj, dtype=t.uint8, device=self.device)
+        _check(load().lbm_set_checkpointing(self._h, self._ckpt.data_ptr(), self._ckpt.numel(), int(K)),
+               "lbm_set_checkpointing")
+
+    def adjoint(self, dL_drho, want_rho0: bool = False):
+        """Gradient of a loss L(rho(T)) given dL/drho(T) [ny][nx]: dict of GRAD_NAMES (+ 'rho0' field)."""
+        t = self.torch
+        g = self._dev(dL_drho, (self.ny, self.nx))
+        out = (C.c_double * 6)()
+        r0 = t.empty((self.ny, self.nx), dtype=t.float64, device=self.device) if want_rho0 else None
+        _check(load().lbm_adjoint(self._h, g.data_ptr(), self._rec.data_ptr(), self._rec.numel(), self._adj.data_ptr(),
+                                  self._adj.numel(), out, r0.data_ptr() if r0 is not None else None, self._s()),
+               "lbm_adjoint")
+        res = dict(zip(GRAD_NAMES, list(out)))
+        if r0 is not None:
+            res["rho0"] = r0
+        return res
 
 
 # ---------------------------------------------------------------------------- batched lattices

@@ -1,0 +1,149 @@
+"""Discrete adjoint (checkpoint + recompute) against central finite differences of the FP64 oracle.
+
+The loss is L = sum_x w(x) rho(x, T) with a seeded weight field w, so dL/drho(T) = w.
+The parameters are the four Smooth-loop knots (Sec. III.D), G and the Eq. LiFS sigma.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from lbm_inputs import droplet_density, droplet_on_film
+
+pytestmark = pytest.mark.gpu
+
+SMOOTH = dict(Tr=0.6, a=0.387, shape=1, alpha=0.834, k_vap=2 / 0.387)
+TAU = [1.0, 1.1, 1.2, 1.0, 1.1, 1.0, 1.1, 0.8, 0.8]
+NAMES = ("rho_max", "p_max", "rho_min", "p_min", "G", "sigma")
+
+
+def _case(kind):
+    e, s = O.eos_build(O.make_eos(**SMOOTH))
+    if kind == "droplet":
+        nx, ny = 37, 29
+        rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=8, W=4)
+        extra = {}
+    else:
+        nx, ny = 40, 24
+        rho0, _, _ = droplet_on_film(nx, ny, e.rho_v, e.rho_l, R=6, h=5, gap=3, V=0.0, W=4)
+        extra = dict(walls=True, rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v)
+    w = np.random.default_rng(11).standard_normal((ny, nx))
+    return e, s, nx, ny, rho0, w, extra
+
+
+def _oracle_loss(e, s, nx, ny, rho0, w, extra, steps, G=-1.0, knots=None, sigma=None):
+    ee = O.eos_set_knots(e, *knots) if knots is not None else e
+    P = O.make_params(nx, ny, ee, G=G, sigma=s if sigma is None else sigma, tau=TAU, **extra)
+    L = O.Lattice(P)
+    L.init_eq(rho0)
+    L.run(steps)
+    return float((w * L.macros()["rho"]).sum())
+
+
+def _fd(e, s, nx, ny, rho0, w, extra, steps):
+    k = [e.rho_max, e.p_max, e.rho_min, e.p_min]
+    g = []
+    for j in range(4):
+        h = 1e-5 * abs(k[j])
+        kp, km = list(k), list(k)
+        kp[j] += h
+        km[j] -= h
+        g.append((_oracle_loss(e, s, nx, ny, rho0, w, extra, steps, knots=kp)
+                  - _oracle_loss(e, s, nx, ny, rho0, w, extra, steps, knots=km)) / (2 * h))
+    h = 1e-5
+    g.append((_oracle_loss(e, s, nx, ny, rho0, w, extra, steps, G=-1 + h)
+              - _oracle_loss(e, s, nx, ny, rho0, w, extra, steps, G=-1 - h)) / (2 * h))
+    h = 1e-5 * s
+    g.append((_oracle_loss(e, s, nx, ny, rho0, w, extra, steps, sigma=s + h)
+              - _oracle_loss(e, s, nx, ny, rho0, w, extra, steps, sigma=s - h)) / (2 * h))
+    return np.array(g)
+
+
+def _gpu(lbm, kind, prec, steps, K, want_rho0=False):
+    e, s, nx, ny, rho0, w, extra = _case(kind)
+    el, sl = lbm.eos_build(lbm.make_eos(**SMOOTH))
+    kw = dict(extra)
+    P = lbm.make_params(nx, ny, el, sigma=sl, tau=TAU, prec=prec, **kw)
+    lat = lbm.Lattice(P, rho0, device="cuda:0")
+    lat.enable_checkpointing(K, steps)
+    lat.step(steps)
+    lat.check()
+    before = lat.macros()["rho"].cpu().numpy()
+    g = lat.adjoint(w, want_rho0=want_rho0)
+    after = lat.macros()["rho"].cpu().numpy()
+    assert np.array_equal(before, after), "adjoint must restore the forward state at T"
+    return g, (e, s, nx, ny, rho0, w, extra)
+
+
+@pytest.mark.parametrize("kind", ["droplet", "walls"])
+def test_adjoint_fp64_matches_oracle_finite_differences(gpu_lib, kind):
+    lbm = gpu_lib
+    steps, K = 20, 7  # segments of 7, 7 and 6 steps
+    g, case = _gpu(lbm, kind, lbm.FP64, steps, K)
+    fd = _fd(*case, steps)
+    got = np.array([g[n] for n in NAMES])
+    for n, a, b in zip(NAMES, got, fd):
+        assert abs(a - b) <= 1e-4 * abs(b) + 1e-9 * np.abs(fd).max(), (kind, n, a, b)
+
+
+def test_adjoint_G_sigma_scaling_identity(gpu_lib):
+    """psi ~ G^-1/2 makes F independent of G and the Eq. LiFS term depend on sigma*G only,
+    so G dL/dG = sigma dL/dsigma for any loss on rho."""
+    lbm = gpu_lib
+    g, (e, s, *_rest) = _gpu(lbm, "droplet", lbm.FP64, 30, 10)
+    assert abs(-1.0 * g["G"] - s * g["sigma"]) <= 1e-10 * abs(s * g["sigma"]) + 1e-14
+
+
+def test_adjoint_initial_density_gradient(gpu_lib):
+    lbm = gpu_lib
+    steps = 12
+    g, (e, s, nx, ny, rho0, w, extra) = _gpu(lbm, "droplet", lbm.FP64, steps, 5, want_rho0=True)
+    d0 = g["rho0"].cpu().numpy()
+    rng = np.random.default_rng(5)
+    pts = [(ny // 2, nx // 2), (ny // 2, nx // 2 + 8), (0, 0)] + [tuple(rng.integers(0, (ny, nx))) for _ in range(3)]
+    for (y, x) in pts:
+        h = 1e-6 * rho0[y, x]
+        rp, rm = rho0.copy(), rho0.copy()
+        rp[y, x] += h
+        rm[y, x] -= h
+        fd = (_oracle_loss(e, s, nx, ny, rp, w, extra, steps) - _oracle_loss(e, s, nx, ny, rm, w, extra, steps)) / (2 * h)
+        assert abs(d0[y, x] - fd) <= 1e-5 * abs(fd) + 1e-7, (y, x, d0[y, x], fd)
+
+
+def test_adjoint_fp32_close_to_fp64(gpu_lib):
+    lbm = gpu_lib
+    g64, _ = _gpu(lbm, "droplet", lbm.FP64, 40, 16)
+    g32, _ = _gpu(lbm, "droplet", lbm.FP32_SHIFTED, 40, 16)
+    scale = max(abs(g64[n]) for n in NAMES)
+    for n in NAMES:
+        assert abs(g32[n] - g64[n]) <= 2e-3 * abs(g64[n]) + 1e-5 * scale, (n, g32[n], g64[n])
+
+
+def test_adjoint_one_segment_equals_many(gpu_lib):
+    lbm = gpu_lib
+    a, _ = _gpu(lbm, "walls", lbm.FP64, 15, 15)
+    b, _ = _gpu(lbm, "walls", lbm.FP64, 15, 4)
+    for n in NAMES:
+        assert abs(a[n] - b[n]) <= 1e-12 * max(1.0, abs(a[n])), (n, a[n], b[n])
+
+
+def test_adjoint_error_paths(gpu_lib):
+    lbm = gpu_lib
+    e, s = lbm.eos_build(lbm.make_eos(**SMOOTH))
+    rho0 = droplet_density(16, 16, e.rho_v, e.rho_l, R=4, W=3)
+    lat = lbm.Lattice(lbm.make_params(16, 16, e, sigma=s), rho0, device="cuda:0")
+    lat.step(1)
+    with pytest.raises(lbm.LbmError) as ei:
+        lat.enable_checkpointing(4, 8)  # after the first step
+    assert ei.value.code == lbm.LBM_ESTATE
+    lat2 = lbm.Lattice(lbm.make_params(16, 16, e, sigma=s), rho0, device="cuda:0")
+    lat2.enable_checkpointing(4, 8)
+    lat2.step(8)
+    with pytest.raises(lbm.LbmError) as ei:
+        lat2.step(1)  # checkpoint slots exhausted
+    assert ei.value.code == lbm.LBM_ESTATE
+    lat3 = lbm.Lattice(lbm.make_params(16, 16, e, sigma=s, var_tau=True, tau_l=0.8, tau_v=1.4), rho0, device="cuda:0")
+    lat3.enable_checkpointing(4, 8)
+    lat3.step(4)
+    with pytest.raises(lbm.LbmError) as ei:
+        lat3.adjoint(np.ones((16, 16)))
+    assert ei.value.code == lbm.LBM_EINVAL

@@ -139,9 +139,7 @@ def _smooth(c):
     return cs(c.pop("Tr"), a=c.pop("a", 0.5), shape=O.SHAPE_SMOOTH, **c)
 
 
-@pytest.mark.parametrize("case", SMOOTH_CASES)
-def test_smooth_loop_knots_and_sound_speed_continuity(case):
-    e, _ = _smooth(case)
+def _check_knot_continuity(e):
     knots = [(e.rho_v, e.p_sat_new, e.slope_v), (e.rho_max, e.p_max, 0.0),
              (e.rho_min, e.p_min, 0.0), (e.rho_l, e.p_sat_new, e.slope_l)]
     for r, pk, sk in knots:
@@ -160,6 +158,12 @@ def test_smooth_loop_knots_and_sound_speed_continuity(case):
         tol = 1e-3 * max(abs(e.slope_v), abs(e.slope_l)) + 1e-9
         assert sl == pytest.approx(sk, abs=tol)
         assert sr == pytest.approx(sk, abs=tol)
+
+
+@pytest.mark.parametrize("case", SMOOTH_CASES)
+def test_smooth_loop_knots_and_sound_speed_continuity(case):
+    e, _ = _smooth(case)
+    _check_knot_continuity(e)
     # vapor and liquid branch slopes as prescribed (Sec. III.D): vapor scaled by k_vap, liquid unchanged
     assert e.slope_v == pytest.approx(e.k_vap * O.base_dp(e, e.rho_v)[0], rel=1e-12)
     assert e.slope_l == pytest.approx(O.base_dp(e, e.rho_l)[0], rel=1e-12)
@@ -170,6 +174,21 @@ def test_smooth_loop_knots_and_sound_speed_continuity(case):
         assert O.eos_p(e, r)[0] == pytest.approx(e.k_vap * O.base_p(e, r)[0], rel=1e-12)
     for r in (1.01 * e.rho_l, 1.05 * e.rho_l):
         assert O.eos_p(e, r)[0] == pytest.approx(O.base_p(e, r)[0] + (e.k_vap - 1) * e.p_sat, rel=1e-12)
+
+
+@pytest.mark.parametrize("case", SMOOTH_CASES[5:8])
+def test_moved_knots_keep_the_loop_continuous(case):
+    """Knots treated as free parameters (finite-difference gradients): after moving each one the
+    refitted ellipses still meet the saturated branches with their slopes and the knots flat."""
+    e, _ = _smooth(case)
+    k = [e.rho_max, e.p_max, e.rho_min, e.p_min]
+    assert O.eos_set_knots(e, *k).a1sq == e.a1sq and O.eos_set_knots(e, *k).b3 == e.b3
+    for j, rel in ((0, 0.01), (1, 0.02), (2, -0.01), (3, 0.03)):
+        kk = list(k)
+        kk[j] += rel * abs(kk[j])
+        _check_knot_continuity(O.eos_set_knots(e, *kk))
+    with pytest.raises(O.OracleError):
+        O.eos_set_knots(e, e.rho_min, e.p_max, e.rho_max, e.p_min)
 
 
 @pytest.mark.parametrize("case", SMOOTH_CASES)
