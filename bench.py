@@ -101,6 +101,91 @@ def cpu_baseline(n, steps):
                       % (n, n, steps, dt)}
 
 
+def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
+    """Adjoint of the static-droplet loss (far-field vapor density + interface width): cost against the
+    plain forward, and, in FP64, agreement with central differences of the same forward (h = 1e-6)."""
+    import torch
+    from lbm_inputs import droplet_density
+    from paper_2107_06355_amd.rollout import vapor_width_loss
+
+    e, s = lbm.eos_build(lbm.make_eos(**EOS_KW))
+    rho0 = droplet_density(n, n, e.rho_v, e.rho_l, R=R, W=W0)
+
+    def loss_grad(rho):
+        r = rho.detach().clone().requires_grad_(True)
+        L = vapor_width_loss(r, e.rho_v, R, W0)
+        L.backward()
+        return float(L.detach()), r.grad
+
+    def run(prec, ckpt, ee=e, G=-1.0, sig=s):
+        P = lbm.make_params(n, n, ee, G=G, sigma=sig, tau=TAU, prec=prec, reduce_every=0)
+        lat = lbm.Lattice(P, rho0, device="cuda:0")
+        if ckpt:
+            lat.enable_checkpointing(K, steps)
+        return lat
+
+    out = {"workload": "static droplet %dx%d R=%d W0=%g, shaped PR Tr=0.5, %d steps, checkpoint every %d"
+                       % (n, n, R, W0, steps, K)}
+    for prec, name in ((lbm.FP32_SHIFTED, "fp32"), (lbm.FP64, "fp64")):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        plain = run(prec, False)
+        plain.step(50)
+        torch.cuda.synchronize()
+        ev[0].record(plain.stream)
+        plain.step(steps)
+        ev[1].record(plain.stream)
+        plain.check()
+        plain.close()
+        lat = run(prec, True)
+        ev[2].record(lat.stream)
+        lat.step(steps)
+        ev[3].record(lat.stream)
+        lat.check()
+        L0, g = loss_grad(lat.macros()["rho"])
+        ev[4].record(lat.stream)
+        grads = lat.adjoint(g)
+        ev[5].record(lat.stream)
+        torch.cuda.synchronize()
+        t_fwd, t_ck, t_adj = (ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), ev[4].elapsed_time(ev[5]))
+        out[name] = {"forward_ms": t_fwd, "forward_checkpointed_ms": t_ck, "adjoint_ms": t_adj,
+                     "adjoint_over_forward": t_adj / t_fwd, "loss": L0, "grad": grads}
+        print("# adjoint %s: forward %.1f ms (checkpointed %.1f), adjoint %.1f ms -> %.2fx" % (
+            name, t_fwd, t_ck, t_adj, t_adj / t_fwd), file=sys.stderr, flush=True)
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    if fd_check:
+        # central differences of the FP64 forward, relative step 1e-6
+        base = [e.rho_max, e.p_max, e.rho_min, e.p_min]
+
+        def L_of(knots=None, G=-1.0, sig=s):
+            ee = lbm.eos_set_knots(e, *knots) if knots is not None else e
+            lat = run(lbm.FP64, False, ee, G, sig)
+            lat.step(steps)
+            lat.check()
+            val = loss_grad(lat.macros()["rho"])[0]
+            lat.close()
+            return val
+
+        fd = {}
+        for j, nm in enumerate(("rho_max", "p_max", "rho_min", "p_min")):
+            h = 1e-6 * abs(base[j])
+            kp, km = list(base), list(base)
+            kp[j] += h
+            km[j] -= h
+            fd[nm] = (L_of(kp) - L_of(km)) / (2 * h)
+        fd["G"] = (L_of(G=-1.0 + 1e-6) - L_of(G=-1.0 - 1e-6)) / 2e-6
+        fd["sigma"] = (L_of(sig=s * (1 + 1e-6)) - L_of(sig=s * (1 - 1e-6))) / (2e-6 * s)
+        g64 = out["fp64"]["grad"]
+        out["fd_fp64"] = fd
+        out["rel_err_fp64_vs_fd"] = {k: abs(g64[k] - fd[k]) / max(abs(fd[k]), 1e-300) for k in fd}
+        g32 = out["fp32"]["grad"]
+        out["rel_err_fp32_vs_fd"] = {k: abs(g32[k] - fd[k]) / max(abs(fd[k]), 1e-300) for k in fd}
+        print("# adjoint vs FD (fp64): max rel err %.2e" % max(out["rel_err_fp64_vs_fd"].values()),
+              file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +202,10 @@ def main():
     ap.add_argument("--calib-only", action="store_true", help="only measure the plain copy bandwidth")
     ap.add_argument("--variant", type=int, default=0, help="step-kernel decomposition: 0 auto, 1 row march, 2 row block")
     ap.add_argument("--sweep-variants", default="", help="comma list of kernel variants for the sweep")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost / gradient leg")
+    ap.add_argument("--adjoint-only", action="store_true")
+    ap.add_argument("--no-adjoint-fd", action="store_true", help="skip the finite-difference check of the adjoint")
+    ap.add_argument("--adjoint-steps", type=int, default=4000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs the hot path on ONE GPU; --gpus %d is not supported" % args.gpus,
@@ -134,6 +223,9 @@ def main():
           file=sys.stderr, flush=True)
     if args.calib_only:
         print(json.dumps({"copy": calib}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_leg(lbm, steps=args.adjoint_steps, fd_check=not args.no_adjoint_fd)}), flush=True)
         return
     n = args.n
     res = {}
@@ -210,6 +302,8 @@ def main():
         "sweep": sweep,
         "copy_calibration": calib,
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(lbm, steps=args.adjoint_steps, fd_check=not args.no_adjoint_fd)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -6,16 +6,18 @@
 // adjoint walks the segments backwards: it restores a checkpoint, re-runs the
 // segment with a recording step that keeps (rho - rho_ref, j, psi) per node and
 // step, and then applies the transpose of each step in reverse.  One adjoint
-// step is two kernels:
-//   pass A  per node: lambda^{t+1} pulled from the downstream nodes (bounce-back
-//           at walls), transposed moment transform and MRT relaxation, Eq. LiFS
-//           and Eq. EquilibriumDistribution derivatives -> dL/dF~(x) and the
-//           local dL/dpsi(x); dL/dsigma and the F~ part of dL/dG.
-//   pass B  per node: the same local adjoint, plus dL/dpsi(x) gathered from the
-//           neighbours' dL/dF~ (transpose of Eq. ShanChenForce), through
-//           psi'(rho) (Eq. InteractionPotential) into lambda^t; dL/dp(rho(x))
-//           accumulates the derivatives with respect to the loop coefficients
-//           and the psi part of dL/dG.
+// step is one kernel (row block of 12 waves, one lattice row per wave, 62 output
+// columns per wave plus one halo column each side; the first and last waves are
+// halo rows):
+//   every lane  lambda^{t+1} pulled from the downstream nodes (bounce-back at
+//               walls), transposed moment transform and MRT relaxation, Eq. LiFS
+//               and Eq. EquilibriumDistribution derivatives -> dL/dF~ (to LDS)
+//               and the local dL/dpsi;
+//   interior    dL/dpsi(x) gathered from the neighbours' dL/dF~ (transpose of
+//               Eq. ShanChenForce), through psi'(rho) (Eq. InteractionPotential)
+//               into lambda^t; dL/dp(rho(x)) accumulates the derivatives with
+//               respect to the loop coefficients, and the F~ and psi parts of
+//               dL/dG and dL/dsigma are summed.
 // Parameter gradients are summed in FP64 per workgroup in a fixed order.
 #include <hip/hip_runtime.h>
 
@@ -40,17 +42,18 @@ struct AdjArgs {
     const void* lam_in;  // lambda^{t+1}: 9 planes [ny][ld]
     void* lam_out;       // lambda^t
     const void* rec;     // step t: drho, j_x, j_y, psi planes [ny][nx]
-    void* dft;           // dL/dF~_x, dL/dF~_y, local dL/dpsi planes [ny][nx]
     double* acc;         // [blocks][kAcc] running sums
+    int strips;          // column strips of kAdjW outputs
     size_t lplane, rplane;
     double c_e, c_q;     // 1/(tau_e - 1/2), 1/(tau_eps - 1/2) of Eq. LiFS
+    double inv_G;
 };
 
 template <typename T>
 struct LocalAdj {
     T df[9];
     T dftx, dfty, dpsi;
-    double dsig;
+    T dsig;
 };
 
 template <typename T>
@@ -62,21 +65,33 @@ __device__ __forceinline__ T ldT(const void* base, size_t i)
 // node coordinates with periodic wrap in x and y (walls handled by the callers)
 __device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
 
-// psi and F~ at (x, y) from the recorded psi planes (ghost psi at walls)
+// psi and F~ at (x, y) from the recorded psi plane (ghost psi beyond the walls)
 template <typename T>
 __device__ __forceinline__ void rec_force(const AdjArgs& A, int x, int y, T& psi, T& ftx, T& fty)
 {
     const StepArgs& S = A.S;
     const T* ps = (const T*)A.rec + 3 * A.rplane;
-    auto P = [&](int xx, int yy) -> T {
-        if (S.walls && yy < 0) return (T)S.psi_lo;
-        if (S.walls && yy >= S.ny) return (T)S.psi_hi;
-        yy = yy < 0 ? yy + S.ny : (yy >= S.ny ? yy - S.ny : yy);
-        return ps[(size_t)yy * S.nx + wrapx(xx, S.nx)];
-    };
-    psi = P(x, y);
-    force_tilde<T>(S, P(x - 1, y - 1), P(x, y - 1), P(x + 1, y - 1), P(x - 1, y), P(x + 1, y), P(x - 1, y + 1),
-                   P(x, y + 1), P(x + 1, y + 1), ftx, fty);
+    const int xm = x == 0 ? S.nx - 1 : x - 1, xp = x == S.nx - 1 ? 0 : x + 1;
+    const T* rc = ps + (size_t)y * S.nx;
+    T lm, cm, rm, ln, cn, rn;
+    if (S.walls && y == 0) {
+        lm = cm = rm = (T)S.psi_lo;
+    } else {
+        const T* r = ps + (size_t)(y == 0 ? S.ny - 1 : y - 1) * S.nx;
+        lm = r[xm];
+        cm = r[x];
+        rm = r[xp];
+    }
+    if (S.walls && y == S.ny - 1) {
+        ln = cn = rn = (T)S.psi_hi;
+    } else {
+        const T* r = ps + (size_t)(y == S.ny - 1 ? 0 : y + 1) * S.nx;
+        ln = r[xm];
+        cn = r[x];
+        rn = r[xp];
+    }
+    psi = rc[x];
+    force_tilde<T>(S, lm, cm, rm, rc[xm], rc[xp], ln, cn, rn, ftx, fty);
 }
 
 // mu_i = dL/df*_i(x) = lambda^{t+1}_i(x + c_i), or lambda^{t+1}_opp(i)(x) when x + c_i is solid
@@ -151,7 +166,7 @@ __device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T
     dFy += uy * q12 - Q6 - 2 * uy * Q7 + ux * Q8;
     const T z = 12 * ((T)A.c_e * Q1 - (T)A.c_q * Q2);  // sigma |F~|^2 enters S_e and S_eps
     T dftx = 2 * (T)S.sigma * z * ftx, dfty = 2 * (T)S.sigma * z * fty;
-    o.dsig = (double)z * ((double)ftx * (double)ftx + (double)fty * (double)fty);
+    o.dsig = z * (ftx * ftx + fty * fty);
     // u = (j + F/2)/rho (Eq. Momentum)
     djx += dux * inv;
     djy += duy * inv;
@@ -178,126 +193,120 @@ __device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T
     o.df[8] = b58 + djx + d4 - djy - d6 - d8;
 }
 
-__device__ __forceinline__ void block_accumulate(const double v[kAcc], double* acc)
+constexpr int kAdjWaves = 12;            // waves (rows) per workgroup
+constexpr int kAdjRows = kAdjWaves - 2;  // output rows per workgroup
+constexpr int kAdjW = 62;                // output columns per wave
+static_assert(kAcc <= kAdjWaves, "one wave per accumulator in the workgroup sum");
+
+template <typename T>
+__global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
 {
-    __shared__ double sh[kAcc][256];
-    const int t = threadIdx.y * blockDim.x + threadIdx.x;
-    for (int k = 0; k < kAcc; ++k) sh[k][t] = v[k];
+    __shared__ T sfx[kAdjWaves][64], sfy[kAdjWaves][64];
+    __shared__ double sred[kAcc][kAdjWaves][64];
+    const StepArgs& S = A.S;
+    const int lane = threadIdx.x & 63;
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int strip = blockIdx.x % A.strips, band = blockIdx.x / A.strips;
+    const int xs = strip * kAdjW - 1 + lane;  // unwrapped column of this lane
+    const int x = ((xs % S.nx) + S.nx) % S.nx;
+    const int y = band * kAdjRows - 1 + k;    // unwrapped row of this wave
+    const bool fluid = S.walls ? (y >= 0 && y < S.ny) : true;
+    const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y)) : ((y % S.ny) + S.ny) % S.ny;
+    const size_t o = (size_t)yw * S.nx + x;
+    // running sum of accumulator k of this workgroup, read early (updated at the end by lane 0 of wave k)
+    const double acc_prev = (k < kAcc && lane == 0) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
+
+    T mu[9];
+    pull_adjoint<T>(A, x, yw, mu);
+    T psi, ftx, fty;
+    rec_force<T>(A, x, yw, psi, ftx, fty);
+    const T dr = ldT<T>(A.rec, o);
+    LocalAdj<T> L;
+    local_adjoint<T>(A, mu, dr, ldT<T>(A.rec, A.rplane + o), ldT<T>(A.rec, 2 * A.rplane + o), psi, ftx, fty, L);
+    sfx[k][lane] = fluid ? L.dftx : (T)0;
+    sfy[k][lane] = fluid ? L.dfty : (T)0;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s)
-            for (int k = 0; k < kAcc; ++k) sh[k][t] += sh[k][t + s];
-        __syncthreads();
-    }
-    if (t == 0) {
-        double* a = acc + (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * kAcc;
-        for (int k = 0; k < kAcc; ++k) a[k] += sh[k][0];
-    }
-}
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_a(AdjArgs A)
-{
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
     double v[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (x < A.S.nx && y < A.S.ny) {
-        const size_t o = (size_t)y * A.S.nx + x;
-        T mu[9];
-        pull_adjoint<T>(A, x, y, mu);
-        T psi, ftx, fty;
-        rec_force<T>(A, x, y, psi, ftx, fty);
-        LocalAdj<T> L;
-        local_adjoint<T>(A, mu, ldT<T>(A.rec, o), ldT<T>(A.rec, A.rplane + o), ldT<T>(A.rec, 2 * A.rplane + o), psi, ftx,
-                         fty, L);
-        T* d = (T*)A.dft;
-        d[o] = L.dftx;
-        d[A.rplane + o] = L.dfty;
-        d[2 * A.rplane + o] = L.dpsi;
-        v[A_SIG] = L.dsig;
-        v[A_G] = ((double)ftx * (double)L.dftx + (double)fty * (double)L.dfty) / A.S.G;  // F~ = -G sum(...)
-    }
-    block_accumulate(v, A.acc);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_b(AdjArgs A)
-{
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y * blockDim.y + threadIdx.y;
-    double v[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (x < A.S.nx && y < A.S.ny) {
-        const StepArgs& S = A.S;
-        const size_t o = (size_t)y * S.nx + x;
-        T mu[9];
-        pull_adjoint<T>(A, x, y, mu);
-        T psi, ftx, fty;
-        rec_force<T>(A, x, y, psi, ftx, fty);
-        const T dr = ldT<T>(A.rec, o);
-        LocalAdj<T> L;
-        local_adjoint<T>(A, mu, dr, ldT<T>(A.rec, A.rplane + o), ldT<T>(A.rec, 2 * A.rplane + o), psi, ftx, fty, L);
+    const bool out = k >= 1 && k <= kAdjRows && y < S.ny && lane >= 1 && lane <= kAdjW && xs < S.nx;
+    if (out) {
+        const T G = (T)S.G, iG = (T)A.inv_G;
+        T vG = (ftx * L.dftx + fty * L.dfty) * iG;  // F~ = -G sum(...)
         // transpose of Eq. ShanChenForce: dL/dpsi(x) += sum_k (-G w_k c_k) . dL/dF~(x - c_k)
-        const T* d = (const T*)A.dft;
-        const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-        const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-        const T G = (T)S.G;
+        const T g3 = -G * (T)(1.0 / 3.0), g12 = -G * (T)(1.0 / 12.0);
+        const bool lo_ok = !S.walls || y >= 1, hi_ok = !S.walls || y + 1 < S.ny;
         T dpsi = L.dpsi;
-        double dpsi_lo = 0.0, dpsi_hi = 0.0;
-        for (int k = 1; k < 9; ++k) {
-            const T wk = (k < 5) ? (T)(1.0 / 3.0) : (T)(1.0 / 12.0);
-            const int sy = y - cy[k];
-            if (!(S.walls && (sy < 0 || sy >= S.ny))) {
-                const int yy = sy < 0 ? sy + S.ny : (sy >= S.ny ? sy - S.ny : sy);
-                const size_t q = (size_t)yy * S.nx + wrapx(x - cx[k], S.nx);
-                dpsi += -G * wk * ((T)cx[k] * d[q] + (T)cy[k] * d[A.rplane + q]);
-            }
-            // ghost solid node x + c_k (walls): its psi is psi(rho_wall), which depends on G
-            const int gy = y + cy[k];
-            if (S.walls && (gy < 0 || gy >= S.ny)) {
-                const double g = -(double)G * (double)wk *
-                                 ((double)cx[k] * (double)L.dftx + (double)cy[k] * (double)L.dfty);
-                if (gy < 0) dpsi_lo += g;
-                else dpsi_hi += g;
-            }
+        // axis neighbours: source x - c_k for c = (1,0), (-1,0), (0,1), (0,-1)
+        dpsi += g3 * (sfx[k][lane - 1] - sfx[k][lane + 1]);
+        if (lo_ok) dpsi += g3 * sfy[k - 1][lane];
+        if (hi_ok) dpsi -= g3 * sfy[k + 1][lane];
+        // diagonals: c = (1,1) from (x-1, y-1), (-1,1) from (x+1, y-1), (-1,-1) from (x+1, y+1), (1,-1) from (x-1, y+1)
+        if (lo_ok)
+            dpsi += g12 * ((sfx[k - 1][lane - 1] + sfy[k - 1][lane - 1]) + (-sfx[k - 1][lane + 1] + sfy[k - 1][lane + 1]));
+        if (hi_ok)
+            dpsi += g12 * ((-sfx[k + 1][lane + 1] - sfy[k + 1][lane + 1]) + (sfx[k + 1][lane - 1] - sfy[k + 1][lane - 1]));
+        // ghost solid neighbours x + c_k (walls): psi(rho_wall) depends on G; the x parts cancel
+        if (S.walls && (y == 0 || y == S.ny - 1)) {
+            const T half = (T)0.5;  // 1/3 + 2/12
+            if (y == 0) vG += (G * L.dfty * half) * ((T)S.psi_lo * (T)-0.5 * iG);
+            if (y == S.ny - 1) vG += (-G * L.dfty * half) * ((T)S.psi_hi * (T)-0.5 * iG);
         }
         // psi(rho) (Eq. InteractionPotential): psi' = (p' - 1/3)/(G psi), dpsi/dp = 1/(G psi)
         const double rho = S.rho_ref + (double)dr;
-        double drho_eos = 0.0;
+        const DevEos& E = S.eos;
+        T drho_eos = 0;
         if (psi > (T)0) {
-            const double inv_gpsi = 1.0 / (S.G * (double)psi);
-            const double dp = dev_eos_dp(S.eos, rho);
-            drho_eos = (dp - 1.0 / 3.0) * inv_gpsi * (double)dpsi;
-            const double P = (double)dpsi * inv_gpsi;  // dL/dp(rho(x))
-            const DevEos& E = S.eos;
-            if ((E.shape == LBM_SHAPE_SMOOTH || E.shape == LBM_SHAPE_MODSMOOTH) && rho > E.rho_v && rho < E.rho_l) {
-                if (rho <= E.rho_max) {
-                    const double dd = rho - E.rho_max, sq = sqrt(1.0 - dd * dd * E.inv_a1sq);
-                    v[A_PMAX] += P;
-                    v[A_B1] += -P * (1.0 - sq);
-                    v[A_A1] += P * E.b1 * dd * dd * E.inv_a1sq * E.inv_a1sq / (2.0 * sq);
-                    v[A_RMAX] += P * E.b1 * dd * E.inv_a1sq / sq;
-                } else if (rho < E.rho_min) {
-                    const double t = (rho - E.rho_max) * E.inv_L;
-                    const double h = t * t * (3.0 - 2.0 * t), hp = 6.0 * t * (1.0 - t);
-                    v[A_PMAX] += P * (1.0 - h);
-                    v[A_PMIN] += P * h;
-                    v[A_RMAX] += P * (E.p_min - E.p_max) * hp * (t - 1.0) * E.inv_L;
-                    v[A_RMIN] += P * (E.p_min - E.p_max) * hp * (-t) * E.inv_L;
-                } else {
-                    const double dd = rho - E.rho_min, sq = sqrt(1.0 - dd * dd * E.inv_a3sq);
-                    v[A_PMIN] += P;
-                    v[A_B3] += P * (1.0 - sq);
-                    v[A_A3] += -P * E.b3 * dd * dd * E.inv_a3sq * E.inv_a3sq / (2.0 * sq);
-                    v[A_RMIN] += -P * E.b3 * dd * E.inv_a3sq / sq;
+            vG += dpsi * (-psi * (T)0.5 * iG);
+            const bool in_loop = E.shape != LBM_SHAPE_NONE && rho > E.rho_v && rho < E.rho_l;
+            if (sizeof(T) == 4 && !in_loop && E.shape != LBM_SHAPE_NONE) {
+                // bulk branches in FP32, as in the forward
+                const float r = (float)rho, dpb = dev_base_dpf(E, r);
+                const float dp = rho <= E.rho_v ? (float)E.k_vap * dpb : dpb;
+                drho_eos = (T)((dp - (1.0f / 3.0f)) * (float)dpsi / ((float)G * (float)psi));
+            } else {
+                const double inv_gpsi = A.inv_G / (double)psi;
+                drho_eos = (T)((dev_eos_dp(E, rho) - 1.0 / 3.0) * inv_gpsi * (double)dpsi);
+                const double P = (double)dpsi * inv_gpsi;  // dL/dp(rho(x))
+                if (in_loop && (E.shape == LBM_SHAPE_SMOOTH || E.shape == LBM_SHAPE_MODSMOOTH)) {
+                    if (rho <= E.rho_max) {
+                        const double dd = rho - E.rho_max, sq = sqrt(1.0 - dd * dd * E.inv_a1sq);
+                        v[A_PMAX] = P;
+                        v[A_B1] = -P * (1.0 - sq);
+                        v[A_A1] = P * E.b1 * dd * dd * E.inv_a1sq * E.inv_a1sq / (2.0 * sq);
+                        v[A_RMAX] = P * E.b1 * dd * E.inv_a1sq / sq;
+                    } else if (rho < E.rho_min) {
+                        const double tt = (rho - E.rho_max) * E.inv_L;
+                        const double h = tt * tt * (3.0 - 2.0 * tt), hp = 6.0 * tt * (1.0 - tt);
+                        v[A_PMAX] = P * (1.0 - h);
+                        v[A_PMIN] = P * h;
+                        v[A_RMAX] = P * (E.p_min - E.p_max) * hp * (tt - 1.0) * E.inv_L;
+                        v[A_RMIN] = P * (E.p_min - E.p_max) * hp * (-tt) * E.inv_L;
+                    } else {
+                        const double dd = rho - E.rho_min, sq = sqrt(1.0 - dd * dd * E.inv_a3sq);
+                        v[A_PMIN] = P;
+                        v[A_B3] = P * (1.0 - sq);
+                        v[A_A3] = -P * E.b3 * dd * dd * E.inv_a3sq * E.inv_a3sq / (2.0 * sq);
+                        v[A_RMIN] = -P * E.b3 * dd * E.inv_a3sq / sq;
+                    }
                 }
             }
-            v[A_G] += (double)dpsi * (-(double)psi / (2.0 * S.G));
         }
-        v[A_G] += dpsi_lo * (-S.psi_lo / (2.0 * S.G)) + dpsi_hi * (-S.psi_hi / (2.0 * S.G));
+        v[A_G] = (double)vG;
+        v[A_SIG] = (double)L.dsig;
         T* Lo = (T*)A.lam_out;
         const size_t li = (size_t)y * S.ld + x;
-        const T de = (T)drho_eos;
-        for (int i = 0; i < 9; ++i) Lo[i * A.lplane + li] = L.df[i] + de;
+        for (int i = 0; i < 9; ++i) Lo[i * A.lplane + li] = L.df[i] + drho_eos;
     }
-    block_accumulate(v, A.acc);
+    // fixed-order workgroup sum: each (accumulator, lane) column over the waves in
+    // order, then one wave per accumulator sums its 64 columns
+    for (int i = 0; i < kAcc; ++i) sred[i][k][lane] = v[i];
+    __syncthreads();
+    if (k < kAcc) {
+        double s = 0.0;
+        for (int w = 0; w < kAdjWaves; ++w) s += sred[k][w][lane];
+        s = wave_sum(s);
+        if (lane == 0) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
+    }
 }
 
 template <typename T>
@@ -329,8 +338,8 @@ __global__ void k_zero(double* p, size_t n)
 }
 
 struct AdjLayout {
-    size_t tsz, rec_bytes, off_fT, off_lam0, off_lam1, off_dft, off_acc, total;
-    int bx, by;
+    size_t tsz, rec_bytes, off_fT, off_lam0, off_lam1, off_acc, total;
+    int strips, blocks;
 };
 
 AdjLayout adj_layout(const lbm_params& p, int ld, size_t pop_bytes, int K)
@@ -340,8 +349,8 @@ AdjLayout adj_layout(const lbm_params& p, int ld, size_t pop_bytes, int K)
     const size_t nn = (size_t)p.nx * p.ny, lp = (size_t)ld * p.ny;
     L.rec_bytes = (size_t)K * 4 * nn * L.tsz;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    L.bx = (p.nx + 63) / 64;
-    L.by = (p.ny + 3) / 4;
+    L.strips = (p.nx + kAdjW - 1) / kAdjW;
+    L.blocks = L.strips * ((p.ny + kAdjRows - 1) / kAdjRows);
     size_t o = 0;
     L.off_fT = o;
     o += al(pop_bytes);
@@ -349,20 +358,10 @@ AdjLayout adj_layout(const lbm_params& p, int ld, size_t pop_bytes, int K)
     o += al(9 * lp * L.tsz);
     L.off_lam1 = o;
     o += al(9 * lp * L.tsz);
-    L.off_dft = o;
-    o += al(3 * nn * L.tsz);
     L.off_acc = o;
-    o += al((size_t)L.bx * L.by * kAcc * sizeof(double));
+    o += al((size_t)L.blocks * kAcc * sizeof(double));
     L.total = o;
     return L;
-}
-
-template <typename T>
-void launch_adj(lbm_ctx* c, AdjArgs& A, const AdjLayout& L, hipStream_t s, bool pass_b)
-{
-    const dim3 g(L.bx, L.by), b(64, 4);
-    if (pass_b) hipLaunchKernelGGL(k_adj_b<T>, g, b, 0, s, A);
-    else hipLaunchKernelGGL(k_adj_a<T>, g, b, 0, s, A);
 }
 
 }  // namespace
@@ -433,7 +432,7 @@ int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_b
         return LBM_EHIP;
     void* lam[2] = {ab + L.off_lam0, ab + L.off_lam1};
     double* acc = (double*)(ab + L.off_acc);
-    const size_t nacc = (size_t)L.bx * L.by * kAcc;
+    const size_t nacc = (size_t)L.blocks * kAcc;
     hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, acc, nacc);
     dim3 g1((P.nx + 127) / 128, P.ny);
     if (f32) hipLaunchKernelGGL(k_adj_seed<float>, g1, dim3(128), 0, s, P.nx, P.ny, c->ld, lp, dL_drho_T, lam[0]);
@@ -443,12 +442,13 @@ int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_b
     AdjArgs A;
     std::memset(&A, 0, sizeof(A));
     A.S = c->args;
-    A.dft = ab + L.off_dft;
     A.acc = acc;
+    A.strips = L.strips;
     A.lplane = lp;
     A.rplane = nn;
     A.c_e = 1.0 / (P.tau[1] - 0.5);
     A.c_q = 1.0 / (P.tau[2] - 0.5);
+    A.inv_G = 1.0 / P.G;
     int li = 0;
     for (int64_t k = S - 1; k >= 0; --k) {
         const int64_t t0 = k * K;
@@ -467,13 +467,8 @@ int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_b
             A.rec = (const char*)rec_buf + (size_t)j * 4 * nn * L.tsz;
             A.lam_in = lam[li];
             A.lam_out = lam[li ^ 1];
-            if (f32) {
-                launch_adj<float>(c, A, L, s, false);
-                launch_adj<float>(c, A, L, s, true);
-            } else {
-                launch_adj<double>(c, A, L, s, false);
-                launch_adj<double>(c, A, L, s, true);
-            }
+            if (f32) hipLaunchKernelGGL(k_adj_blk<float>, dim3(L.blocks), dim3(64 * kAdjWaves), 0, s, A);
+            else hipLaunchKernelGGL(k_adj_blk<double>, dim3(L.blocks), dim3(64 * kAdjWaves), 0, s, A);
             if (!hip_ok(hipGetLastError(), "adjoint step launch")) return LBM_EHIP;
             li ^= 1;
         }
@@ -491,7 +486,7 @@ int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_b
         !hip_ok(hipStreamSynchronize(s), "adjoint sync"))
         return LBM_EHIP;
     double a[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (size_t b = 0; b < (size_t)L.bx * L.by; ++b)
+    for (size_t b = 0; b < (size_t)L.blocks; ++b)
         for (int k = 0; k < kAcc; ++k) a[k] += h[b * kAcc + k];
     // chain the loop coefficients (b1, a1^2), (b3, a3^2) back to the four knots
     double gk[4] = {0, 0, 0, 0};

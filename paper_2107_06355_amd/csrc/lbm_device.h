@@ -241,6 +241,18 @@ __device__ __forceinline__ float dev_base_pf(const DevEos& E, float r)
     return (float)E.scale * ((float)E.RT * r / (1.0f - br) - (float)E.aal * r * r / (1.0f + br * (2.0f - br)));
 }
 
+__device__ __forceinline__ float dev_base_dpf(const DevEos& E, float r)
+{
+    if (E.base == LBM_BASE_CS) {
+        const float n = 0.25f * (float)E.b * r, m = 1.0f - n;
+        const float m2 = m * m;
+        return (float)E.scale *
+               ((float)E.RT * (1.0f + n * (4.0f + n * (4.0f + n * (-4.0f + n)))) / (m2 * m2) - 2.0f * (float)E.aal * r);
+    }
+    const float br = (float)E.b * r, m = 1.0f - br, D = 1.0f + br * (2.0f - br);
+    return (float)E.scale * ((float)E.RT / (m * m) - 2.0f * (float)E.aal * r * (1.0f + br) / (D * D));
+}
+
 // psi (Eq. InteractionPotential, c = 1) of a node with density rho_ref + drho.
 // FP64 path: everything in FP64.  FP32 path: the bulk vapor/liquid branches in
 // FP32, the shaped loop between rho_v and rho_l (the branch junctions) in FP64.

@@ -1,0 +1,104 @@
+"""torch.autograd front end of lbm_adjoint.
+
+``LbmRollout.apply(knots, G, sigma, rho0, spec)`` runs ``spec.steps`` fused steps from
+f^eq(rho0, u = 0) and returns rho(T) as a float64 tensor on the lattice's device; its backward
+calls lbm_adjoint (checkpoint every ``spec.K`` steps, recompute per segment) and returns
+dL/d(knots), dL/dG, dL/dsigma and dL/drho0.  knots = (rho_max, p_max, rho_min, p_min) are the
+four interior points of the Smooth loop (Sec. III.D), treated as free parameters with the
+ellipse coefficients refitted to them; sigma is the Eq. LiFS coefficient, independent of G.
+All arithmetic runs in liblbm; this module only marshals tensors.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import lbm
+
+
+@dataclass
+class RolloutSpec:
+    eos: lbm.LbmEos                      # a built Smooth / Modified Smooth EOS (lbm.eos_build)
+    nx: int
+    ny: int
+    steps: int
+    K: int = 200
+    prec: int = lbm.FP32_SHIFTED
+    params: dict = field(default_factory=dict)   # extra lbm.make_params keywords (tau, walls, ...)
+    device: str = "cuda:0"
+
+
+def _f(x) -> float:
+    return float(x.detach().cpu().item()) if hasattr(x, "detach") else float(x)
+
+
+def _autograd_function():
+    import torch
+
+    class LbmRollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, knots, G, sigma, rho0, spec: RolloutSpec):
+            k = [float(v) for v in knots.detach().cpu().double().tolist()]
+            e = lbm.eos_set_knots(spec.eos, *k)
+            P = lbm.make_params(spec.nx, spec.ny, e, G=_f(G), sigma=_f(sigma), prec=spec.prec, **spec.params)
+            lat = lbm.Lattice(P, rho0.detach(), device=spec.device)
+            lat.enable_checkpointing(spec.K, spec.steps)
+            lat.step(spec.steps)
+            lat.check()
+            rho = lat.macros()["rho"]
+            ctx.lat = lat
+            ctx.meta = (knots.dtype, knots.device, rho0.dtype, rho0.device)
+            return rho
+
+        @staticmethod
+        def backward(ctx, grad_rho):
+            lat = ctx.lat
+            kd, kdev, rd, rdev = ctx.meta
+            g = lat.adjoint(grad_rho.detach().to(torch.float64).contiguous(), want_rho0=ctx.needs_input_grad[3])
+            ctx.lat = None
+            lat.close()
+            gk = torch.tensor([g[n] for n in lbm.GRAD_NAMES[:4]], dtype=kd, device=kdev)
+            gG = torch.tensor(g["G"], dtype=torch.float64)
+            gs = torch.tensor(g["sigma"], dtype=torch.float64)
+            gr = g["rho0"].to(dtype=rd, device=rdev) if "rho0" in g else None
+            return gk, gG, gs, gr, None
+
+    return LbmRollout
+
+
+_FN = None
+
+
+def rollout(knots, G, sigma, rho0, spec: RolloutSpec):
+    """rho(T) with gradients flowing to knots, G, sigma and rho0 (torch tensors)."""
+    global _FN
+    if _FN is None:
+        _FN = _autograd_function()
+    return _FN.apply(knots, G, sigma, rho0, spec)
+
+
+def knots_of(e: lbm.LbmEos) -> np.ndarray:
+    return np.array([e.rho_max, e.p_max, e.rho_min, e.p_min])
+
+
+def vapor_width_loss(rho, rho_v_ref: float, R0: float, W0: float, center=None, lam_w: float = 0.01):
+    """Squared relative error of the mean far-field vapor density plus an interface-width penalty.
+
+    rho_bar_v averages rho over |x - x_c| > R0 + 2 W0.  W_eff = 4.6 drho^2 2 pi R0 / (3 sum |grad rho|^2)
+    is the width of a tanh profile of the droplet-initialisation form with the same gradient energy
+    (central differences, periodic), drho = rho_l - rho_v taken from the field's max and the vapor mean.
+    """
+    import torch
+
+    ny, nx = rho.shape
+    cy, cx = (ny / 2, nx / 2) if center is None else center
+    yy, xx = torch.meshgrid(torch.arange(ny, dtype=rho.dtype, device=rho.device),
+                            torch.arange(nx, dtype=rho.dtype, device=rho.device), indexing="ij")
+    far = ((xx - cx) ** 2 + (yy - cy) ** 2).sqrt() > R0 + 2 * W0
+    rv = rho[far].mean()
+    gx = 0.5 * (torch.roll(rho, -1, 1) - torch.roll(rho, 1, 1))
+    gy = 0.5 * (torch.roll(rho, -1, 0) - torch.roll(rho, 1, 0))
+    drho = rho.max() - rv
+    w_eff = 4.6 * drho ** 2 * 2 * np.pi * R0 / (3 * (gx ** 2 + gy ** 2).sum())
+    return ((rv - rho_v_ref) / rho_v_ref) ** 2 + lam_w * ((w_eff - W0) / W0) ** 2

@@ -147,3 +147,24 @@ def test_adjoint_error_paths(gpu_lib):
     with pytest.raises(lbm.LbmError) as ei:
         lat3.adjoint(np.ones((16, 16)))
     assert ei.value.code == lbm.LBM_EINVAL
+
+
+def test_rollout_autograd_matches_direct_adjoint(gpu_lib):
+    import torch
+
+    from paper_2107_06355_amd.rollout import RolloutSpec, knots_of, rollout
+
+    lbm = gpu_lib
+    e, s, nx, ny, rho0, w, extra = _case("droplet")
+    el, sl = lbm.eos_build(lbm.make_eos(**SMOOTH))
+    spec = RolloutSpec(eos=el, nx=nx, ny=ny, steps=16, K=6, prec=lbm.FP64, params=dict(tau=TAU))
+    knots = torch.tensor(knots_of(el), dtype=torch.float64, requires_grad=True)
+    G = torch.tensor(-1.0, dtype=torch.float64, requires_grad=True)
+    sig = torch.tensor(sl, dtype=torch.float64, requires_grad=True)
+    r0 = torch.tensor(rho0, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    rho = rollout(knots, G, sig, r0, spec)
+    (torch.as_tensor(w, device=rho.device) * rho).sum().backward()
+    g, _ = _gpu(lbm, "droplet", lbm.FP64, 16, 6, want_rho0=True)
+    np.testing.assert_array_equal(knots.grad.numpy(), [g[n] for n in NAMES[:4]])
+    assert G.grad.item() == g["G"] and sig.grad.item() == g["sigma"]
+    np.testing.assert_array_equal(r0.grad.cpu().numpy(), g["rho0"].cpu().numpy())
