@@ -1,11 +1,16 @@
 """Throughput of the fused shaped-EOS pseudopotential D2Q9 step on one MI355X.
 
-Default workload (the quoted configuration): static droplet on a 512x512 periodic lattice,
+Default workload: static droplet (R=80, tanh rim of width 20) on a 512x512 periodic lattice,
 shaped Peng-Robinson EOS (a=2/49, b=2/21, omega=0.344) at Tr=0.5 with the Smooth vdW-loop
 replacement (alpha=0.3), raised vapor sound speed (k_vap=4), EOS scale 0.25, MRT with
 tau_nu=0.7 and Li forcing with sigma from eps; FP32-shifted storage (rho_ref = rho_v) with
-FP64 mass/momentum reductions every 100 steps.  One "step" is one time step of the whole
-hot path.  Inputs are resident in HBM before the timed region starts.
+FP64 mass/momentum reductions every 100 steps, 50k steps; the same in FP64.  One "step" is
+one time step of the whole hot path.  Inputs are resident in HBM before the timed region
+starts.  The roofline figure times the step kernel alone on the stream it is launched on.
+
+Further legs (in the same JSON line): an HBM sweep of larger lattices, the adjoint of the
+droplet loss (cost against the forward, agreement with central differences), a plain
+device-copy calibration and the FP64 CPU oracle on a bounded sample.
 
 Prints ONE JSON line (rank 0).  --gpus N with N > 1 exits: this build runs on one GPU.
 """
@@ -36,6 +41,7 @@ def workload_name(n, R):
 
 
 def make_lattice(lbm, n, prec, R=None, reduce_every=100, band_rows=0, variant=0):
+    """Static droplet on an n x n periodic lattice; R defaults to n/6 (the roofline sweep)."""
     from lbm_inputs import droplet_density
 
     e, s = lbm.eos_build(lbm.make_eos(**EOS_KW))
@@ -84,13 +90,41 @@ def copy_bandwidth(nbytes=1 << 31, reps=20):
     return {"bytes_moved": 2 * nbytes, "GB/s": 2 * nbytes / sec / 1e9, "us": sec * 1e6}
 
 
-def cpu_baseline(n, steps):
+def sources_digest() -> str:
+    """SHA-256 over the sources of the step kernels (a PMC summary is valid only for these)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("lbm_device.h", "lbm_step.hip"):
+        with open(os.path.join(ROOT, "paper_2107_06355_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, n, prec):
+    """HBM bytes per launch of `kernel` at n x n from the committed PMC summary, or None when there is
+    none for this kernel/size or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_step_droplet_pmc_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    want = "%s n=%d %s" % (kernel, n, prec)
+    digest = sources_digest()
+    for line in open(path):
+        if line.startswith("| traffic |"):
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            # | traffic | kernel n=.. prec | bytes/launch | sources sha256 |
+            if len(cells) >= 4 and cells[1] == want and cells[3] == digest:
+                return float(cells[2])
+    return None
+
+
+def cpu_baseline(n, steps, R):
     """The FP64 oracle on a bounded sample of the same workload (single thread)."""
     import oracle as O
     from lbm_inputs import droplet_density
 
     eo, so = O.eos_build(O.make_eos(**EOS_KW))
-    rho0 = droplet_density(n, n, eo.rho_v, eo.rho_l, R=n // 6, W=20)
+    rho0 = droplet_density(n, n, eo.rho_v, eo.rho_l, R=R, W=20)
     L = O.Lattice(O.make_params(n, n, eo, sigma=so, tau=TAU))
     L.init_eq(rho0)
     t0 = time.perf_counter()
@@ -189,12 +223,13 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=50000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--n", type=int, default=512, help="lattice side of the timed workload")
+    ap.add_argument("--radius", type=int, default=80, help="droplet radius of the timed workload")
     ap.add_argument("--sweep", default="2048,4096,8192", help="extra lattice sides for the HBM roofline ('' = none)")
     ap.add_argument("--sweep-steps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="", help="fp32 | fp64: time just one precision of the main workload")
     ap.add_argument("--band-rows", type=int, default=0, help="rows per wave band (0 = the library's choice)")
@@ -232,21 +267,31 @@ def main():
     for prec in ("fp32", "fp64"):
         if args.only and prec != args.only:
             continue
-        L, e, s, _ = make_lattice(lbm, n, prec, band_rows=args.band_rows, variant=args.variant)
+        # the metric: the whole hot path, FP64 mass/momentum reductions every 100 steps
+        L, e, s, _ = make_lattice(lbm, n, prec, R=args.radius, band_rows=args.band_rows, variant=args.variant)
         var, rows, waves = lbm.describe(L.P)
         sec, wall = time_steps(L, args.steps, args.warmup)
         L.check()
+        L.close()
+        del L
+        # the roofline: the step kernel alone (no reduction launches in the timed region)
+        L, e, s, _ = make_lattice(lbm, n, prec, R=args.radius, reduce_every=0, band_rows=args.band_rows,
+                                  variant=args.variant)
+        ksec, _ = time_steps(L, args.steps, args.warmup)
+        L.check()
         cells = n * n
         mlups = cells * args.steps / sec / 1e6
-        gbs = BYTES[prec] * cells * args.steps / sec / 1e9
-        res[prec] = {"MLUPS": mlups, "GB/s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+        kgbs = BYTES[prec] * cells * args.steps / ksec / 1e9
+        res[prec] = {"MLUPS": mlups, "GB/s_step": BYTES[prec] * cells * args.steps / sec / 1e9,
                      "ms_per_step": sec * 1e3 / args.steps, "wall_s": wall,
-                     "avg_launch_us": sec * 1e6 / args.steps,
-                     "kernel": ("k_step_blk<%s>" if var == lbm.VARIANT_BLOCK else "k_step<%s>")
+                     "kernel_GB/s": kgbs, "frac_hbm_peak": kgbs / HBM_PEAK_GBS,
+                     "avg_launch_us": ksec * 1e6 / args.steps,
+                     "kernel": ("k_step_blk<%s, 0>" if var == lbm.VARIANT_BLOCK else "k_step<%s, 0>")
                                % ("float" if prec == "fp32" else "double"),
                      "rows_per_block": rows, "waves": waves}
-        print("# %s %dx%d: %.1f MLUPS, %.1f GB/s algorithmic (%.1f%% of 8 TB/s), %.2f us/step"
-              % (prec, n, n, mlups, gbs, 100 * gbs / HBM_PEAK_GBS, sec * 1e6 / args.steps), file=sys.stderr, flush=True)
+        print("# %s %dx%d: %.1f MLUPS (%.2f us/step with reductions); step kernel %.2f us = %.1f GB/s "
+              "algorithmic (%.1f%% of 8 TB/s)" % (prec, n, n, mlups, sec * 1e6 / args.steps, ksec * 1e6 / args.steps,
+                                                   kgbs, 100 * kgbs / HBM_PEAK_GBS), file=sys.stderr, flush=True)
         L.close()
         del L
         torch.cuda.empty_cache()
@@ -291,12 +336,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if main_prec == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": workload_name(n, n // 6), "lattice": [n, n], "storage": main_prec,
+        "config": {"workload": workload_name(n, args.radius), "lattice": [n, n], "storage": main_prec,
                    "reduce_every": 100},
-        "roofline": {"bound": "hbm", "achieved": r["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["GB/s"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": r["kernel"], "bytes_per_cell": BYTES[main_prec],
-                     "avg_launch_us": r["avg_launch_us"]},
+        "roofline": {"bound": "hbm", "achieved": r["kernel_GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r["kernel_GB/s"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(r["kernel"], n, main_prec),
+                     "kernel": r["kernel"], "bytes_per_cell": BYTES[main_prec], "cells_per_launch": n * n,
+                     "avg_launch_us": r["avg_launch_us"],
+                     "copy_ceiling_frac": r["kernel_GB/s"] / calib["GB/s"]},
         "fp64": res.get("fp64"),
         "fp32": res.get("fp32"),
         "sweep": sweep,
@@ -305,7 +352,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(lbm, steps=args.adjoint_steps, fd_check=not args.no_adjoint_fd)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, args.radius)
     print(json.dumps(out), flush=True)
 
 
