@@ -550,11 +550,14 @@ int or_eos_build(or_eos* e, double G, double* sigma_out)
         double lo = e->p_sat_new;
         double span = hi - lo;
         int ok = 1;
+        /* p_max -> p_sat_new flattens ellipse 1 onto its chord: a1^2 -> D^2 with a margin of
+         * order (dp/(S_v D))^2, so the lower end stays 1e-6 of the span inside to keep the
+         * ellipse real in FP64 */
         if (e->shape == OR_SHAPE_SMOOTH) {
-            e->p_max = bisect(smooth_maxwell_of_pmax, e, lo + span * 1e-9, hi - span * 1e-9, &ok);
+            e->p_max = bisect(smooth_maxwell_of_pmax, e, lo + span * 1e-6, hi - span * 1e-9, &ok);
         } else {
             modctx m = {e, G};
-            e->p_max = bisect(smooth_mech_of_pmax, &m, lo + span * 1e-9, hi - span * 1e-9, &ok);
+            e->p_max = bisect(smooth_mech_of_pmax, &m, lo + span * 1e-6, hi - span * 1e-9, &ok);
         }
         if (!ok) return OR_ENOROOT;
         region1_coeffs(e);

@@ -35,7 +35,8 @@ def test_no_torch_in_the_abi():
 CASES = [dict(Tr=0.7), dict(Tr=0.35), dict(Tr=0.5, shape=1, alpha=0.61), dict(Tr=0.5, shape=1, alpha=0.207, k_vap=4.0),
          dict(Tr=0.6, a=0.387, shape=3, r_theta=0.45), dict(Tr=0.6, a=0.387, shape=2, alpha=0.446, k_vap=2 / 0.387),
          dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0),
-         dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.8)]
+         dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.8),
+         dict(Tr=0.35, shape=1, alpha=0.3, k_vap=4.0)]  # deep loop: ellipse 1 nearly flat near p_sat
 
 
 @pytest.mark.parametrize("kw", CASES)
