@@ -1,0 +1,72 @@
+"""Droplet impact on a liquid film (Sec. IV) at 2048x1024 with walls: full-size parity and invariants.
+
+Setup: periodic in x, half-way bounce-back walls top and bottom with ghost densities rho_l
+(bottom) and rho_v (top), film of height 0.2 D = 40, droplet R = 100 moving at V = 0.072
+(Re = V D / nu_l = 300 with tau_l = 0.644, We ~ 100), relaxation matrix
+diag(1, ..., 1, 1/tau, 1/tau) with Eq. RelaxationTime.  EOS: Smooth C-S at Tr = 0.35
+(density ratio 7.9e4), the paper's EOS for its stability study.
+
+At this size the oracle cannot run the whole impact, so the checks are
+  * one full-size step from the GPU state after a few hundred steps, against the oracle's
+    step from the same populations (FP64: 1e-12; FP32-shifted: the one-step rounding bound),
+  * a long FP32-shifted run: no unstable node, FP64 mass drift <= 1e-10 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from lbm_inputs import droplet_on_film
+
+pytestmark = pytest.mark.gpu
+
+NX, NY = 2048, 1024
+EOS_KW = dict(base=0, a=0.5, b=4.0, R=1.0, Tr=0.35, shape=1, alpha=0.3, k_vap=4.0)
+V, TAU_L = 0.072, 0.644
+
+
+def _setup(lbm, prec, vr):
+    e, s = lbm.eos_build(lbm.make_eos(**EOS_KW))
+    tau_v = 0.5 + vr * (TAU_L - 0.5)
+    rho, ux, uy = droplet_on_film(NX, NY, e.rho_v, e.rho_l, R=100, h=40, gap=4, V=V, W=8)
+    kw = dict(walls=True, rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v, var_tau=vr != 1.0, tau_l=TAU_L, tau_v=tau_v)
+    P = lbm.make_params(NX, NY, e, sigma=s, tau=[1] * 7 + [TAU_L] * 2, prec=prec, reduce_every=1000, **kw)
+    return lbm.Lattice(P, rho, ux, uy, device="cuda:0"), e, kw
+
+
+@pytest.mark.parametrize("prec_name,vr", [("fp64", 5.0), ("fp32", 5.0), ("fp64", 1.0)])
+def test_drop_impact_one_full_size_step_matches_oracle(gpu_lib, prec_name, vr):
+    lbm = gpu_lib
+    prec = lbm.FP64 if prec_name == "fp64" else lbm.FP32_SHIFTED
+    L, e, kw = _setup(lbm, prec, vr)
+    L.step(400)  # the droplet has started to deform the film
+    L.check()
+    f_t = L.populations().cpu().numpy()
+    L.step(1)
+    f_g = L.populations().cpu().numpy()
+    eo, so = O.eos_build(O.make_eos(**EOS_KW))
+    OL = O.Lattice(O.make_params(NX, NY, eo, sigma=so, tau=[1] * 7 + [TAU_L] * 2, **kw))
+    OL.set_f(f_t)
+    OL.run(1)
+    f_o = OL.get_f()
+    if prec == lbm.FP64:
+        assert np.abs(f_g - f_o).max() <= 1e-12 * np.abs(f_o).max()
+    else:
+        w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+        dev = np.abs(f_o - w * e.rho_v).max()
+        assert np.abs(f_g - f_o).max() <= 2e-6 * dev
+
+
+def test_drop_impact_long_run_is_stable_and_conserves_mass(gpu_lib):
+    lbm = gpu_lib
+    L, e, _ = _setup(lbm, lbm.FP32_SHIFTED, 1.0)
+    L.step(30001)
+    L.check()
+    h = L.history()
+    assert h.shape[0] == 31
+    mass = h[:, 1]
+    assert np.abs(mass / mass[0] - 1).max() <= 1e-10
+    m = L.macros()
+    rho = m["rho"].cpu().numpy()
+    assert np.isfinite(rho).all() and rho.min() > 0
+    # the droplet has merged with the film: no liquid left above the splash region's top
+    assert rho[NY - 50:, :].max() < 0.5 * (e.rho_v + e.rho_l)
