@@ -220,6 +220,46 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
     return out
 
 
+def batched_leg(lbm, steps=20000, n_lattices=64, seed=0):
+    """Uneven batched planar sweep: 64 lattices 4 x L_b (L_b = 4 U{32..512}), Tr ~ U(0.35, 0.95), shaped PR,
+    FP32-shifted, one persistent launch per call; aggregate MLUPS and coexistence error against Maxwell."""
+    import torch
+    from lbm_inputs import batched_planar_recipe, planar_density
+
+    lengths, trs = batched_planar_recipe(n_lattices=n_lattices, seed=seed)
+    P, rhos, eos = [], [], []
+    for L, Tr in zip(lengths, trs):
+        e, s = lbm.eos_build(lbm.make_eos(**dict(EOS_KW, Tr=Tr)))
+        P.append(lbm.make_params(L, 4, e, sigma=s, tau=[1.0] * 9, prec=lbm.FP32_SHIFTED))
+        rhos.append(planar_density(L, 4, e.rho_v, e.rho_l, W=20, axis=0))
+        eos.append(e)
+    B = lbm.Batch(P, rhos, device="cuda:0")
+    B.step(100)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(B.stream)
+    B.step(steps)
+    ev[1].record(B.stream)
+    torch.cuda.synchronize()
+    B.check()
+    sec = ev[0].elapsed_time(ev[1]) / 1e3
+    cells = sum(4 * L for L in lengths)
+    got = B.macros()
+    ev_v = [abs(got[b]["rho"][0, 0] - eos[b].rho_v) / eos[b].rho_v for b in range(n_lattices)]
+    ev_l = [abs(got[b]["rho"][0, lengths[b] // 2] - eos[b].rho_l) / eos[b].rho_l for b in range(n_lattices)]
+    B.close()
+    out = {"workload": "%d planar lattices 4 x L, L in [%d, %d], Tr in [%.2f, %.2f], shaped PR, FP32-shifted, %d steps"
+                       % (n_lattices, min(lengths), max(lengths), min(trs), max(trs), steps + 100),
+           "cells": cells, "steps": steps, "seconds": sec, "MLUPS": cells * steps / sec / 1e6,
+           "us_per_step": sec * 1e6 / steps,
+           "vapor_rel_err_vs_maxwell": {"max": max(ev_v), "mean": sum(ev_v) / n_lattices},
+           "liquid_rel_err_vs_maxwell": {"max": max(ev_l), "mean": sum(ev_l) / n_lattices}}
+    print("# batched %d lattices (%d cells): %.1f us/step, %.0f MLUPS; vapor error vs Maxwell max %.2f%% mean %.2f%%"
+          % (n_lattices, cells, out["us_per_step"], out["MLUPS"], 100 * max(ev_v), 100 * sum(ev_v) / n_lattices),
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,6 +281,8 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true")
     ap.add_argument("--no-adjoint-fd", action="store_true", help="skip the finite-difference check of the adjoint")
     ap.add_argument("--adjoint-steps", type=int, default=4000)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-lattice sweep leg")
+    ap.add_argument("--batched-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs the hot path on ONE GPU; --gpus %d is not supported" % args.gpus,
@@ -258,6 +300,9 @@ def main():
           file=sys.stderr, flush=True)
     if args.calib_only:
         print(json.dumps({"copy": calib}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched_leg(lbm)}), flush=True)
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_leg(lbm, steps=args.adjoint_steps, fd_check=not args.no_adjoint_fd)}), flush=True)
@@ -349,6 +394,8 @@ def main():
         "sweep": sweep,
         "copy_calibration": calib,
     }
+    if not args.no_batched:
+        out["batched"] = batched_leg(lbm)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(lbm, steps=args.adjoint_steps, fd_check=not args.no_adjoint_fd)
     if not args.no_cpu:

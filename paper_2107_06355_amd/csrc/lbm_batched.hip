@@ -237,6 +237,7 @@ int lbm_init_batched(lbm_batch** out, int B, const lbm_params* p, void* f_a, voi
         A.G = P.G;
         A.sigma = P.sigma;
         for (int k = 0; k < 9; ++k) A.s[k] = 1.0 / P.tau[k];
+        fill_coef(A, P.tau, P.G, P.sigma);
         A.tau_v = P.tau_v;
         A.rho_v_tau = P.rho_v_tau;
         A.dtau_drho = P.var_tau ? (P.tau_l - P.tau_v) / (P.rho_l_tau - P.rho_v_tau) : 0.0;

@@ -19,7 +19,9 @@ namespace lbmk {
 #ifndef LBM_WAVES_PER_EU
 #define LBM_WAVES_PER_EU 0
 #endif
-#if LBM_WAVES_PER_EU > 0
+#if LBM_WAVES_PER_EU > 0 && defined(LBM_WAVES_PER_EU_MAX)
+#define LBM_OCCUPANCY_HINT __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU, LBM_WAVES_PER_EU_MAX)))
+#elif LBM_WAVES_PER_EU > 0
 #define LBM_OCCUPANCY_HINT __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
 #else
 #define LBM_OCCUPANCY_HINT
@@ -97,6 +99,16 @@ __device__ __forceinline__ double dev_eos_dp(const DevEos& E, double r)
 }
 
 // ----------------------------------------------------------------- kernel arguments
+// Per-lattice constants of the node update, precomputed on the host in the
+// arithmetic type of the path (no per-node conversions or divisions).
+template <typename T>
+struct Coef {
+    T se, sq, sqx, sqy, snu;   // rates 1/tau of e, eps, q_x, q_y and the shear moments (Eq. RelaxationMatrix)
+    T he, hq, hqx, hqy, hnu;   // 1 - s/2 (the (I - Lambda/2) factor of the source)
+    T le, lq;                  // Eq. LiFS: 12 sigma (1 - s/2) / (tau - 1/2) for e and eps
+    T G, two_inv_G;            // Eq. ShanChenForce and Eq. InteractionPotential
+};
+
 struct StepArgs {
     const void* src;
     void* dst;
@@ -109,6 +121,8 @@ struct StepArgs {
     double tau_v, dtau_drho, tau_lo, tau_hi, rho_v_tau;
     double rho_ref;
     double psi_lo, psi_hi;
+    Coef<double> cd;
+    Coef<float> cf;
     DevEos eos;
     double* partials;        // [nwork][3] FP64 per-wave sums
     unsigned* err;           // [0] flag, [1] first failing step
@@ -121,6 +135,17 @@ struct StepArgs {
 };
 
 enum { MODE_STEP = 0, MODE_STEP_REDUCE = 1, MODE_MACROS = 2, MODE_RECORD = 3 };
+
+template <typename T>
+__device__ __forceinline__ const Coef<T>& coef(const StepArgs& A);
+template <>
+__device__ __forceinline__ const Coef<double>& coef<double>(const StepArgs& A) { return A.cd; }
+template <>
+__device__ __forceinline__ const Coef<float>& coef<float>(const StepArgs& A) { return A.cf; }
+
+// reciprocal: hardware v_rcp_f32 (1 ulp) on the FP32 path, IEEE division on the FP64 path
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 
 __constant__ double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
@@ -235,10 +260,12 @@ __device__ __forceinline__ float dev_base_pf(const DevEos& E, float r)
 {
     if (E.base == LBM_BASE_CS) {
         const float n = 0.25f * (float)E.b * r, m = 1.0f - n;
-        return (float)E.scale * ((float)E.RT * r * (1.0f + n * (1.0f + n * (1.0f - n))) / (m * m * m) - (float)E.aal * r * r);
+        return (float)E.scale *
+               ((float)E.RT * r * (1.0f + n * (1.0f + n * (1.0f - n))) * __builtin_amdgcn_rcpf(m * m * m) - (float)E.aal * r * r);
     }
     const float br = (float)E.b * r;
-    return (float)E.scale * ((float)E.RT * r / (1.0f - br) - (float)E.aal * r * r / (1.0f + br * (2.0f - br)));
+    return (float)E.scale * ((float)E.RT * r * __builtin_amdgcn_rcpf(1.0f - br) -
+                             (float)E.aal * r * r * __builtin_amdgcn_rcpf(1.0f + br * (2.0f - br)));
 }
 
 __device__ __forceinline__ float dev_base_dpf(const DevEos& E, float r)
@@ -265,12 +292,12 @@ __device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check
         const float r = (float)rho;
         const float pb = dev_base_pf(E, r);
         const float p = rho <= E.rho_v ? (float)E.k_vap * pb : pb + (float)E.dP;
-        const float q = 2.0f * (p - r * (1.0f / 3.0f)) / (float)A.G;
+        const float q = (p - r * (1.0f / 3.0f)) * A.cf.two_inv_G;
         if (check && !(q >= 0.0f && r > 0.0f)) flag_unstable(A);
         return (T)(q > 0.0f ? sqrtf(q) : 0.0f);
     }
     const double p = dev_eos_p(E, rho);
-    const double q = 2.0 * (p - rho * (1.0 / 3.0)) / A.G;
+    const double q = (p - rho * (1.0 / 3.0)) * A.cd.two_inv_G;
     if (check && !(q >= 0.0 && rho > 0.0)) flag_unstable(A);
     if (sizeof(T) == 4) return (T)(q > 0.0 ? sqrtf((float)q) : 0.0f);
     return (T)(q > 0.0 ? sqrt(q) : 0.0);
@@ -331,7 +358,7 @@ __device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, in
     const T mxx = (gp[1] - gp[2]) + (gp[3] - gp[4]);
     const T mxy = (gp[5] - gp[6]) + (gp[7] - gp[8]);
     // forced velocity (Eq. Momentum)
-    const T inv_rho = (T)1 / rho;
+    const T inv_rho = rcp(rho);
     const T ux = (jx + (T)0.5 * Fx) * inv_rho, uy = (jy + (T)0.5 * Fy) * inv_rho;
 
     if (MODE == MODE_MACROS) {
@@ -360,12 +387,14 @@ __device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, in
     }
     if (MODE == MODE_MACROS) return;
     // rates (Eq. RelaxationMatrix; Eq. RelaxationTime on the shear moments)
-    const T se = (T)A.s[1], sq = (T)A.s[2], sqx = (T)A.s[4], sqy = (T)A.s[6];
-    T snu = (T)A.s[7];
+    const Coef<T>& K = coef<T>(A);
+    const T se = K.se, sq = K.sq, sqx = K.sqx, sqy = K.sqy;
+    T snu = K.snu, hnu = K.hnu;
     if (A.var_tau) {
         double tau = A.tau_v + A.dtau_drho * (rho_d - A.rho_v_tau);
         tau = fmin(fmax(tau, A.tau_lo), A.tau_hi);
         snu = (T)(1.0 / tau);
+        hnu = (T)1 - (T)0.5 * snu;
     }
     const T u2 = ux * ux + uy * uy;
     const T uF = ux * Fx + uy * Fy;
@@ -376,16 +405,15 @@ __device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, in
     const T eqxx = rho * (ux * ux - uy * uy);
     const T eqxy = rho * ux * uy;
     // Eq. LiFS source, multiplied by (I - Lambda/2)
-    const T sig12 = (T)(12.0 * A.sigma) * F2;
-    const T Se = ((T)6 * uF + sig12 / ((T)1 / se - (T)0.5)) * ((T)1 - (T)0.5 * se);
-    const T Sq = (-(T)6 * uF - sig12 / ((T)1 / sq - (T)0.5)) * ((T)1 - (T)0.5 * sq);
+    const T Se = (T)6 * uF * K.he + K.le * F2;
+    const T Sq = -(T)6 * uF * K.hq - K.lq * F2;
     // relaxed moments m* = m - Lambda (m - m^eq) + (I - Lambda/2) S
     const T ne = (me - se * (me - eqe) + Se) * (T)(1.0 / 36.0);
     const T nq = (mq - sq * (mq - eqq) + Sq) * (T)(1.0 / 36.0);
-    const T nqx = (mqx - sqx * (mqx + rho * ux) - ((T)1 - (T)0.5 * sqx) * Fx) * (T)(1.0 / 12.0);
-    const T nqy = (mqy - sqy * (mqy + rho * uy) - ((T)1 - (T)0.5 * sqy) * Fy) * (T)(1.0 / 12.0);
-    const T nxx = (mxx - snu * (mxx - eqxx) + ((T)1 - (T)0.5 * snu) * (T)2 * (ux * Fx - uy * Fy)) * (T)0.25;
-    const T nxy = (mxy - snu * (mxy - eqxy) + ((T)1 - (T)0.5 * snu) * (ux * Fy + uy * Fx)) * (T)0.25;
+    const T nqx = (mqx - sqx * (mqx + rho * ux) - K.hqx * Fx) * (T)(1.0 / 12.0);
+    const T nqy = (mqy - sqy * (mqy + rho * uy) - K.hqy * Fy) * (T)(1.0 / 12.0);
+    const T nxx = (mxx - snu * (mxx - eqxx) + hnu * (T)2 * (ux * Fx - uy * Fy)) * (T)0.25;
+    const T nxy = (mxy - snu * (mxy - eqxy) + hnu * (ux * Fy + uy * Fx)) * (T)0.25;
     const T n0 = dr * (T)(1.0 / 9.0);
     const T njx = (jx + Fx) * (T)(1.0 / 6.0);
     const T njy = (jy + Fy) * (T)(1.0 / 6.0);
@@ -417,7 +445,7 @@ template <typename T>
 __device__ __forceinline__ void force_tilde(const StepArgs& A, T lm, T cm, T rm_, T lc, T rc, T ln, T cn, T rn_,
                                             T& Ftx, T& Fty)
 {
-    const T G = (T)A.G;
+    const T G = coef<T>(A).G;
     const T third = (T)(1.0 / 3.0), twelfth = (T)(1.0 / 12.0);
     Ftx = -G * ((rc - lc) * third + ((rn_ - ln) + (rm_ - lm)) * twelfth);
     Fty = -G * ((cn - cm) * third + ((rn_ + ln) - (rm_ + lm)) * twelfth);
@@ -472,6 +500,33 @@ inline DevEos dev_eos(const lbm_eos& e)
     E.rho_m = e.rho_m;
     E.theta = e.theta;
     return E;
+}
+
+// Node-update constants of a lattice from its relaxation times (Eq. RelaxationMatrix),
+// G and the Eq. LiFS sigma, in both arithmetic types.
+inline void fill_coef(StepArgs& A, const double tau[9], double G, double sigma)
+{
+    Coef<double> c;
+    const double s[9] = {1 / tau[0], 1 / tau[1], 1 / tau[2], 1 / tau[3], 1 / tau[4],
+                         1 / tau[5], 1 / tau[6], 1 / tau[7], 1 / tau[8]};
+    c.se = s[1];
+    c.sq = s[2];
+    c.sqx = s[4];
+    c.sqy = s[6];
+    c.snu = s[7];
+    c.he = 1 - 0.5 * s[1];
+    c.hq = 1 - 0.5 * s[2];
+    c.hqx = 1 - 0.5 * s[4];
+    c.hqy = 1 - 0.5 * s[6];
+    c.hnu = 1 - 0.5 * s[7];
+    c.le = 12.0 * sigma * c.he / (tau[1] - 0.5);
+    c.lq = 12.0 * sigma * c.hq / (tau[2] - 0.5);
+    c.G = G;
+    c.two_inv_G = 2.0 / G;
+    A.cd = c;
+    A.cf = Coef<float>{(float)c.se, (float)c.sq, (float)c.sqx, (float)c.sqy, (float)c.snu,
+                       (float)c.he, (float)c.hq, (float)c.hqx, (float)c.hqy, (float)c.hnu,
+                       (float)c.le, (float)c.lq, (float)c.G, (float)c.two_inv_G};
 }
 
 inline int validate(const lbm_params* p)
