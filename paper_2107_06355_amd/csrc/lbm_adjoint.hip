@@ -47,7 +47,26 @@ struct AdjArgs {
     size_t lplane, rplane;
     double c_e, c_q;     // 1/(tau_e - 1/2), 1/(tau_eps - 1/2) of Eq. LiFS
     double inv_G;
+    // the same constants in the arithmetic type of the path
+    struct K { double c_e, c_q, two_sigma, inv_G; } kd;
+    struct KF { float c_e, c_q, two_sigma, inv_G; } kf;
 };
+
+template <typename T>
+struct AdjK;
+template <>
+struct AdjK<double> {
+    __device__ static const AdjArgs::K& get(const AdjArgs& A) { return A.kd; }
+};
+template <>
+struct AdjK<float> {
+    __device__ static const AdjArgs::KF& get(const AdjArgs& A) { return A.kf; }
+};
+template <typename T>
+__device__ __forceinline__ auto adj_coef(const AdjArgs& A) -> decltype(AdjK<T>::get(A))
+{
+    return AdjK<T>::get(A);
+}
 
 template <typename T>
 struct LocalAdj {
@@ -124,9 +143,10 @@ __device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T
                                               LocalAdj<T>& o)
 {
     const StepArgs& S = A.S;
+    const Coef<T>& K = coef<T>(S);
     const T rho = (T)(S.rho_ref + (double)dr);
     const T Fx = psi * ftx, Fy = psi * fty;
-    const T inv = (T)1 / rho;
+    const T inv = rcp(rho);
     const T ux = (jx + (T)0.5 * Fx) * inv, uy = (jy + (T)0.5 * Fy) * inv;
     // nu = D^-1 M mu  (adjoint of f* = M^T D^-1 m*)
     const T m14 = (mu[1] + mu[2]) + (mu[3] + mu[4]);
@@ -143,14 +163,13 @@ __device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T
     const T n6 = (-2 * a24 + a5678y) * (T)(1.0 / 12.0);
     const T n7 = ((mu[1] - mu[2]) + (mu[3] - mu[4])) * (T)0.25;
     const T n8 = ((mu[5] - mu[6]) + (mu[7] - mu[8])) * (T)0.25;
-    const T se = (T)S.s[1], sq = (T)S.s[2], sqx = (T)S.s[4], sqy = (T)S.s[6], snu = (T)S.s[7];
     // m*_k = m_k - s_k (m_k - m^eq_k) + (1 - s_k/2) S_k: direct, equilibrium and source adjoints
-    const T d1 = n1 * ((T)1 - se), E1 = n1 * se, Q1 = n1 * ((T)1 - (T)0.5 * se);
-    const T d2 = n2 * ((T)1 - sq), E2 = n2 * sq, Q2 = n2 * ((T)1 - (T)0.5 * sq);
-    const T d4 = n4 * ((T)1 - sqx), E4 = n4 * sqx, Q4 = n4 * ((T)1 - (T)0.5 * sqx);
-    const T d6 = n6 * ((T)1 - sqy), E6 = n6 * sqy, Q6 = n6 * ((T)1 - (T)0.5 * sqy);
-    const T d7 = n7 * ((T)1 - snu), E7 = n7 * snu, Q7 = n7 * ((T)1 - (T)0.5 * snu);
-    const T d8 = n8 * ((T)1 - snu), E8 = n8 * snu, Q8 = n8 * ((T)1 - (T)0.5 * snu);
+    const T d1 = n1 * ((T)1 - K.se), E1 = n1 * K.se, Q1 = n1 * K.he;
+    const T d2 = n2 * ((T)1 - K.sq), E2 = n2 * K.sq, Q2 = n2 * K.hq;
+    const T d4 = n4 * ((T)1 - K.sqx), E4 = n4 * K.sqx, Q4 = n4 * K.hqx;
+    const T d6 = n6 * ((T)1 - K.sqy), E6 = n6 * K.sqy, Q6 = n6 * K.hqy;
+    const T d7 = n7 * ((T)1 - K.snu), E7 = n7 * K.snu, Q7 = n7 * K.hnu;
+    const T d8 = n8 * ((T)1 - K.snu), E8 = n8 * K.snu, Q8 = n8 * K.hnu;
     // conserved moments: m*_0 = rho, m*_3 = j_x + F_x, m*_5 = j_y + F_y
     T drho = n0, djx = n3, djy = n5, dFx = n3, dFy = n5;
     // equilibrium moments (Eq. EquilibriumDistribution in the moment basis)
@@ -164,8 +183,9 @@ __device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T
     duy += Fy * q12 - 2 * Fy * Q7 + Fx * Q8;
     dFx += ux * q12 - Q4 + 2 * ux * Q7 + uy * Q8;
     dFy += uy * q12 - Q6 - 2 * uy * Q7 + ux * Q8;
-    const T z = 12 * ((T)A.c_e * Q1 - (T)A.c_q * Q2);  // sigma |F~|^2 enters S_e and S_eps
-    T dftx = 2 * (T)S.sigma * z * ftx, dfty = 2 * (T)S.sigma * z * fty;
+    // sigma |F~|^2 enters S_e and S_eps with 12/(tau - 1/2); z = dL/d(sigma |F~|^2)
+    const T z = (T)12 * (adj_coef<T>(A).c_e * Q1 - adj_coef<T>(A).c_q * Q2);
+    T dftx = adj_coef<T>(A).two_sigma * z * ftx, dfty = adj_coef<T>(A).two_sigma * z * fty;
     o.dsig = z * (ftx * ftx + fty * fty);
     // u = (j + F/2)/rho (Eq. Momentum)
     djx += dux * inv;
@@ -230,7 +250,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
     double v[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const bool out = k >= 1 && k <= kAdjRows && y < S.ny && lane >= 1 && lane <= kAdjW && xs < S.nx;
     if (out) {
-        const T G = (T)S.G, iG = (T)A.inv_G;
+        const T G = coef<T>(S).G, iG = adj_coef<T>(A).inv_G;
         T vG = (ftx * L.dftx + fty * L.dfty) * iG;  // F~ = -G sum(...)
         // transpose of Eq. ShanChenForce: dL/dpsi(x) += sum_k (-G w_k c_k) . dL/dF~(x - c_k)
         const T g3 = -G * (T)(1.0 / 3.0), g12 = -G * (T)(1.0 / 12.0);
@@ -262,7 +282,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
                 // bulk branches in FP32, as in the forward
                 const float r = (float)rho, dpb = dev_base_dpf(E, r);
                 const float dp = rho <= E.rho_v ? (float)E.k_vap * dpb : dpb;
-                drho_eos = (T)((dp - (1.0f / 3.0f)) * (float)dpsi / ((float)G * (float)psi));
+                drho_eos = (T)((dp - (1.0f / 3.0f)) * (float)dpsi * rcp((float)G * (float)psi));
             } else {
                 const double inv_gpsi = A.inv_G / (double)psi;
                 drho_eos = (T)((dev_eos_dp(E, rho) - 1.0 / 3.0) * inv_gpsi * (double)dpsi);
@@ -449,6 +469,8 @@ int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_b
     A.c_e = 1.0 / (P.tau[1] - 0.5);
     A.c_q = 1.0 / (P.tau[2] - 0.5);
     A.inv_G = 1.0 / P.G;
+    A.kd = {A.c_e, A.c_q, 2.0 * P.sigma, A.inv_G};
+    A.kf = {(float)A.c_e, (float)A.c_q, (float)(2.0 * P.sigma), (float)A.inv_G};
     int li = 0;
     for (int64_t k = S - 1; k >= 0; --k) {
         const int64_t t0 = k * K;

@@ -273,11 +273,13 @@ __device__ __forceinline__ float dev_base_dpf(const DevEos& E, float r)
     if (E.base == LBM_BASE_CS) {
         const float n = 0.25f * (float)E.b * r, m = 1.0f - n;
         const float m2 = m * m;
-        return (float)E.scale *
-               ((float)E.RT * (1.0f + n * (4.0f + n * (4.0f + n * (-4.0f + n)))) / (m2 * m2) - 2.0f * (float)E.aal * r);
+        return (float)E.scale * ((float)E.RT * (1.0f + n * (4.0f + n * (4.0f + n * (-4.0f + n)))) *
+                                     __builtin_amdgcn_rcpf(m2 * m2) -
+                                 2.0f * (float)E.aal * r);
     }
     const float br = (float)E.b * r, m = 1.0f - br, D = 1.0f + br * (2.0f - br);
-    return (float)E.scale * ((float)E.RT / (m * m) - 2.0f * (float)E.aal * r * (1.0f + br) / (D * D));
+    return (float)E.scale * ((float)E.RT * __builtin_amdgcn_rcpf(m * m) -
+                             2.0f * (float)E.aal * r * (1.0f + br) * __builtin_amdgcn_rcpf(D * D));
 }
 
 // psi (Eq. InteractionPotential, c = 1) of a node with density rho_ref + drho.
