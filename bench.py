@@ -260,6 +260,31 @@ def batched_leg(lbm, steps=20000, n_lattices=64, seed=0):
     return out
 
 
+def stability_leg(lbm, steps=3000):
+    """Sec. IV stability map: width calibration (batched planar lattices) and 3 EOS x 9 Tr x 12 v_r
+    droplet impacts (600 x 250, FP32-shifted); the largest stable simulated density ratio per EOS."""
+    import torch
+    from paper_2107_06355_amd import stability as S
+
+    t0 = time.perf_counter()
+    table = S.calibrate()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    smap, best = S.stability_map(table, steps=steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    runs = sum(len(v) for v in smap.values())
+    out = {"calibration_s": t1 - t0, "map_s": t2 - t1, "impact_runs": runs, "steps_per_run": steps,
+           "best": {k: (None if v is None else {"ratio": v[0], "Tr": v[1], "vr": v[2]}) for k, v in best.items()},
+           "map": {k: {"%.2f" % Tr: "".join("S" if m[(Tr, vr)] else "." for vr in S.VRS) for Tr in S.TRS}
+                   for k, m in smap.items()},
+           "vr": list(S.VRS)}
+    print("# stability map: calibration %.1f s, %d impacts in %.1f s; best ratio %s" % (
+        t1 - t0, runs, t2 - t1, {k: (None if v is None else round(v[0])) for k, v in best.items()}),
+        file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +308,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=4000)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-lattice sweep leg")
     ap.add_argument("--batched-only", action="store_true")
+    ap.add_argument("--stability-map", action="store_true", help="add the Sec. IV stability-map leg (~1 min)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs the hot path on ONE GPU; --gpus %d is not supported" % args.gpus,
@@ -396,6 +422,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_leg(lbm)
+    if args.stability_map:
+        out["stability"] = stability_leg(lbm)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(lbm, steps=args.adjoint_steps, fd_check=not args.no_adjoint_fd)
     if not args.no_cpu:

@@ -293,3 +293,16 @@ def test_modified_smooth_point():
     r = O.run_planar(e, forcing=O.FORCING_GUO, sigma=0.0)
     assert r["width"] == c["w"]
     assert r["gamma"] == pytest.approx(c["gamma"], rel=0.03)
+
+
+# ---------------------------------------------------------------- stability study (Sec. IV)
+@pytest.mark.slow
+def test_cs_density_ratio_at_tr035():
+    """C-S a = 0.363 at Tr = 0.35 (planar, Li forcing with sigma from eps): the simulated density
+    ratio the paper quotes for its stability study."""
+    with open(os.path.join(GOLD, "stability.json")) as fh:
+        g = json.load(fh)
+    e, s = cs_eos(0.35, a=0.363)
+    r = O.run_planar(e, sigma=s)
+    assert r["residual"] < 1e-6
+    assert r["rho_l"] / r["rho_v"] == pytest.approx(g["cs_Tr035_ratio"], rel=2e-3)
