@@ -232,6 +232,50 @@ def test_shear_wave_decay_rate():
     assert amp / 1e-6 == pytest.approx(math.exp(-nu * k * k * T), rel=2e-3)
 
 
+@pytest.mark.parametrize("where", ["vapor", "liquid", "metastable vapor", "compressed liquid"])
+def test_relaxation_time_of_density_shear_decay(where):
+    """Eq. RelaxationTime: at uniform density the fluid is single phase, so a shear wave decays at
+    nu = (tau(rho) - 1/2)/3 with tau interpolated between tau_v at rho_v and tau_l at rho_l, and
+    held at the end value outside [rho_v, rho_l] (reading R8)."""
+    e, s = cs_eos(0.7)
+    rho0 = {"vapor": e.rho_v, "liquid": e.rho_l, "metastable vapor": e.rho_v + 0.02 * (e.rho_l - e.rho_v),
+            "compressed liquid": 1.05 * e.rho_l}[where]
+    tau_l, tau_v = 0.8, 1.4
+    expect = {"vapor": tau_v, "liquid": tau_l, "metastable vapor": 0.98 * tau_v + 0.02 * tau_l,
+              "compressed liquid": tau_l}[where]
+    nx, ny, T = 4, 64, 400
+    rho, ux, uy = shear_wave(nx, ny, rho0, 1e-6)
+    L = O.Lattice(O.make_params(nx, ny, e, sigma=s, tau=[1] * 9, var_tau=True, tau_l=tau_l, tau_v=tau_v))
+    L.init_eq(rho, ux, uy)
+    L.run(T)
+    u = L.macros()["ux"][:, 0]
+    k = 2 * np.pi / ny
+    amp = 2 * (u * np.sin(k * np.arange(ny))).sum() / ny
+    assert amp / 1e-6 == pytest.approx(math.exp(-(expect - 0.5) / 3 * k * k * T), rel=3e-3)
+
+
+@pytest.mark.parametrize("tau_nu", [0.8, 1.0, 1.5])
+def test_halfway_walls_shear_mode_decay(tau_nu):
+    """Half-way bounce-back (Sec. IV) puts the no-slip walls half a node outside the first and last
+    fluid rows: u_x = sin(pi (y + 1/2)/ny) decays at nu (pi/ny)^2 (a wall on the rows themselves
+    would give (pi/(ny-1))^2, 6.6% faster at ny = 32)."""
+    e, s = cs_eos(0.7)
+    nx, ny, T, A = 4, 32, 1500, 1e-6
+    y = np.arange(ny)
+    mode = np.sin(np.pi * (y + 0.5) / ny)
+    ux = np.repeat((A * mode)[:, None], nx, axis=1)
+    rho = np.full((ny, nx), e.rho_l)
+    P = O.make_params(nx, ny, e, sigma=s, tau=[1] * 7 + [tau_nu] * 2, walls=True, rho_wall_lo=e.rho_l,
+                      rho_wall_hi=e.rho_l)
+    L = O.Lattice(P)
+    L.init_eq(rho, ux, np.zeros_like(ux))
+    L.run(T)
+    u = L.macros()["ux"][:, 0]
+    amp = (u * mode).sum() / (mode * mode).sum()
+    rate = math.log(amp / A) / -T
+    assert rate == pytest.approx((tau_nu - 0.5) / 3 * (np.pi / ny) ** 2, rel=5e-3)
+
+
 def test_G_invariance():
     """Eq. InteractionPotential makes G cancel; with Li forcing only sigma G matters."""
     e, s = cs_eos(0.6)
