@@ -260,6 +260,36 @@ def batched_leg(lbm, steps=20000, n_lattices=64, seed=0):
     return out
 
 
+def fd_leg(lbm, n=512, steps=2000, dt=0.2):
+    """Finite-difference reference solver (MacCormack, FP64) on an n x n periodic droplet: C-S a=0.387 at
+    Tr=0.6 with eps of the Li scheme (the paper's FD case), h = 1.  Algorithmic bytes per node and step:
+    psi/p from rho twice (8 B in, 16 B out each), predictor (40 B in, 24 B out), corrector (64 B in,
+    24 B out) = 200 B."""
+    import torch
+    from lbm_inputs import droplet_density
+
+    e, s = lbm.eos_build(lbm.make_eos(base=0, a=0.387, b=4.0, R=1.0, Tr=0.6))
+    F = lbm.FdSolver(lbm.make_fd_params(n, n, e, h=1.0, dt=dt, eps=e.eps),
+                     droplet_density(n, n, e.rho_v, e.rho_l, R=n // 6, W=8), device="cuda:0")
+    F.step(100)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(F.stream)
+    F.step(steps)
+    ev[1].record(F.stream)
+    torch.cuda.synchronize()
+    F.check()
+    sec = ev[0].elapsed_time(ev[1]) / 1e3
+    F.close()
+    gbs = 200.0 * n * n * steps / sec / 1e9
+    out = {"workload": "FD MacCormack %dx%d periodic droplet, C-S a=0.387 Tr=0.6, h=1, dt=%g, FP64" % (n, n, dt),
+           "us_per_step": sec * 1e6 / steps, "Mnode_steps_per_s": n * n * steps / sec / 1e6, "GB/s": gbs,
+           "frac_hbm_peak": gbs / HBM_PEAK_GBS, "bytes_per_node_step": 200, "launches_per_step": 4}
+    print("# FD solver %dx%d: %.2f us/step, %.0f Mnode-steps/s, %.0f GB/s algorithmic" % (
+        n, n, out["us_per_step"], out["Mnode_steps_per_s"], gbs), file=sys.stderr, flush=True)
+    return out
+
+
 def stability_leg(lbm, steps=3000):
     """Sec. IV stability map: width calibration (batched planar lattices) and 3 EOS x 9 Tr x 12 v_r
     droplet impacts (600 x 250, FP32-shifted); the largest stable simulated density ratio per EOS."""
@@ -309,6 +339,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-lattice sweep leg")
     ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--stability-map", action="store_true", help="add the Sec. IV stability-map leg (~1 min)")
+    ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference reference-solver leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs the hot path on ONE GPU; --gpus %d is not supported" % args.gpus,
@@ -424,6 +455,9 @@ def main():
         out["batched"] = batched_leg(lbm)
     if args.stability_map:
         out["stability"] = stability_leg(lbm)
+    if not args.no_fd:
+        out["fd"] = fd_leg(lbm)
+        out["fd_4096"] = fd_leg(lbm, n=4096, steps=50)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(lbm, steps=args.adjoint_steps, fd_check=not args.no_adjoint_fd)
     if not args.no_cpu:

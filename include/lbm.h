@@ -222,6 +222,43 @@ int lbm_macros_batched(lbm_batch* ctx, double* rho, double* ux, double* uy, void
 /* LBM_EUNSTABLE if any lattice met psi^2 < 0; first_bad_out = its index or -1. */
 int lbm_status_batched(lbm_batch* ctx, int* first_bad_out, void* stream);
 void lbm_destroy_batched(lbm_batch* ctx);
+
+/* ------------------------------------------------------------------------
+ * Finite-difference reference solver (appendix "Finite Difference Method"):
+ * the mass equation and Eq. FDmomentum for rho, u, v on a doubly periodic
+ * mesh of spacing h (LBM units, c = 1, c_s^2 = 1/3), viscous stress of
+ * Eq. StressTensor with Eq. DynamicViscosity (tau_nu(rho) of
+ * Eq. RelaxationTime when var_tau), pseudopotential pressure tensor through
+ * Eq. FDforce, MacCormack predictor (forward one-sided first derivatives) and
+ * corrector (backward), central second and higher derivatives.  FP64.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int nx, ny;           /* mesh nodes (>= 3 each), periodic in x and y */
+    int var_tau;          /* 1: tau_nu from Eq. RelaxationTime (tau_l, tau_v, rho_*_tau) */
+    int pad_;
+    double h, dt;         /* mesh spacing and time step (LBM units) */
+    double G, eps;        /* interaction constant (< 0); eps of the pressure tensor (Li: -16 G sigma, Guo: 0) */
+    double tau_e, tau_nu; /* relaxation times of Eq. DynamicViscosity */
+    double tau_l, tau_v, rho_v_tau, rho_l_tau;
+    lbm_eos eos;          /* built by lbm_eos_build */
+} lbm_fd_params;
+typedef struct lbm_fd_ctx lbm_fd_ctx;
+
+/* Bytes of the caller-owned device buffer (an error word and 8 float64 fields
+ * [ny][nx]); LBM_EINVAL for bad sizes, h, dt or G. */
+int lbm_fd_layout(const lbm_fd_params* p, size_t* bytes);
+/* Initial state: rho0, u0, v0 device float64 [ny][nx] (u0, v0 may be NULL for
+ * rest).  The buffer holds all solver state; the context holds only pointers. */
+int lbm_fd_init(lbm_fd_ctx** ctx, const lbm_fd_params* p, void* buf, size_t buf_bytes, const double* rho0,
+                const double* u0, const double* v0, void* stream);
+/* nsteps predictor-corrector steps (asynchronous, four launches each). */
+int lbm_fd_step(lbm_fd_ctx* ctx, int64_t nsteps, void* stream);
+/* Copy rho, u, v (device float64 [ny][nx], any may be NULL); asynchronous. */
+int lbm_fd_fields(lbm_fd_ctx* ctx, double* rho, double* u, double* v, void* stream);
+/* LBM_EUNSTABLE once a node met psi^2 < 0 or rho <= 0; synchronises. */
+int lbm_fd_status(lbm_fd_ctx* ctx, void* stream);
+void lbm_fd_destroy(lbm_fd_ctx* ctx);
+
 const char* lbm_strerror(int code);
 const char* lbm_last_error(void);
 

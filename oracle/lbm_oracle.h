@@ -104,6 +104,24 @@ void   or_force_tilde_field(int nx, int ny, const double* psi, int walls, double
 void   or_feq(double rho, double ux, double uy, double* feq);
 void   or_matrix(double* M, double* Minv);
 
+/* Finite-difference reference solver (Appendix "Finite Difference Method"), fd_oracle.c */
+typedef struct {
+    int nx, ny;           /* doubly periodic mesh */
+    int var_tau;          /* 1: tau_nu from Eq. RelaxationTime */
+    int pad_;
+    double h, dt;         /* mesh spacing and time step, LBM units */
+    double G, eps;        /* interaction constant; eps of the pressure tensor (Li: -16 G sigma; Guo: 0) */
+    double tau_e, tau_nu; /* Eq. DynamicViscosity */
+    double tau_l, tau_v, rho_v_tau, rho_l_tau;
+    or_eos eos;
+} or_fd_params;
+typedef struct or_fd or_fd;
+or_fd* or_fd_new(const or_fd_params* p);
+void   or_fd_free(or_fd* f);
+void   or_fd_set(or_fd* f, const double* rho, const double* u, const double* v);
+void   or_fd_get(const or_fd* f, double* rho, double* u, double* v);
+int    or_fd_run(or_fd* f, long long nsteps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
+_SRC_FD = os.path.join(_HERE, "fd_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -61,15 +62,25 @@ class OrParams(C.Structure):
     ]
 
 
+class OrFdParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("var_tau", C.c_int), ("pad_", C.c_int),
+        ("h", C.c_double), ("dt", C.c_double), ("G", C.c_double), ("eps", C.c_double),
+        ("tau_e", C.c_double), ("tau_nu", C.c_double),
+        ("tau_l", C.c_double), ("tau_v", C.c_double), ("rho_v_tau", C.c_double), ("rho_l_tau", C.c_double),
+        ("eos", OrEos),
+    ]
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no vector intrinsics)."""
     with _lock:
         if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
-            os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "lbm_oracle.h"))
+            os.path.getmtime(_SRC), os.path.getmtime(_SRC_FD), os.path.getmtime(os.path.join(_HERE, "lbm_oracle.h"))
         ):
             tmp = _LIB + ".tmp%d" % os.getpid()
             subprocess.check_call(
-                ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+                ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, _SRC_FD, "-lm"]
             )
             os.replace(tmp, _LIB)
     return _LIB
@@ -94,6 +105,13 @@ def lib():
         L.or_maxwell_residual.restype = d
         L.or_mech_residual.argtypes = [C.POINTER(OrEos), d, d]
         L.or_mech_residual.restype = d
+        L.or_fd_new.argtypes = [C.POINTER(OrFdParams)]
+        L.or_fd_new.restype = p
+        L.or_fd_free.argtypes = [p]
+        L.or_fd_set.argtypes = [p, dp, dp, dp]
+        L.or_fd_get.argtypes = [p, dp, dp, dp]
+        L.or_fd_run.argtypes = [p, C.c_longlong]
+        L.or_fd_run.restype = i
         L.or_lattice_new.argtypes = [C.POINTER(OrParams)]
         L.or_lattice_new.restype = p
         L.or_lattice_free.argtypes = [p]
@@ -210,6 +228,51 @@ def make_params(nx, ny, eos: OrEos, G=-1.0, sigma=0.0, forcing=FORCING_LI, tau=N
     P.rho_l_tau = eos.rho_l if rho_l_tau is None else rho_l_tau
     P.eos = eos
     return P
+
+
+def make_fd_params(nx, ny, eos: OrEos, h=1.0, dt=0.2, G=-1.0, eps=0.0, tau_e=1.0, tau_nu=1.0, var_tau=False,
+                   tau_l=1.0, tau_v=1.0, rho_v_tau=None, rho_l_tau=None) -> OrFdParams:
+    P = OrFdParams()
+    P.nx, P.ny, P.var_tau = nx, ny, int(var_tau)
+    P.h, P.dt, P.G, P.eps, P.tau_e, P.tau_nu = h, dt, G, eps, tau_e, tau_nu
+    P.tau_l, P.tau_v = tau_l, tau_v
+    P.rho_v_tau = eos.rho_v if rho_v_tau is None else rho_v_tau
+    P.rho_l_tau = eos.rho_l if rho_l_tau is None else rho_l_tau
+    P.eos = eos
+    return P
+
+
+class FdSolver:
+    """Finite-difference reference solver (MacCormack) on a doubly periodic mesh."""
+
+    def __init__(self, P: OrFdParams):
+        self.P = P
+        self._h = lib().or_fd_new(C.byref(P))
+        if not self._h:
+            raise OracleError("or_fd_new rejected the parameters")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().or_fd_free(self._h)
+            self._h = None
+
+    def set(self, rho, u=None, v=None):
+        shp = (self.P.ny, self.P.nx)
+        r = np.ascontiguousarray(rho, dtype=np.float64).reshape(shp)
+        uu = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(shp)
+        vv = None if v is None else np.ascontiguousarray(v, dtype=np.float64).reshape(shp)
+        lib().or_fd_set(self._h, _ptr(r), _ptr(uu), _ptr(vv))
+
+    def get(self):
+        shp = (self.P.ny, self.P.nx)
+        r, u, v = np.empty(shp), np.empty(shp), np.empty(shp)
+        lib().or_fd_get(self._h, _ptr(r), _ptr(u), _ptr(v))
+        return r, u, v
+
+    def run(self, n: int):
+        st = lib().or_fd_run(self._h, int(n))
+        if st != OR_OK:
+            raise OracleError("FD solver unstable (psi^2 < 0 or non-positive density)")
 
 
 class Lattice:

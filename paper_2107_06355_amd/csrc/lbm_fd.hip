@@ -1,0 +1,326 @@
+// liblbm.so: the finite-difference reference solver of the paper's appendix
+// ("Finite Difference Method"), doubly periodic, FP64.
+//
+// State: rho, u, v on an nx x ny mesh of spacing h (LBM units, c = 1,
+// c_s^2 = 1/3).  One time step is the MacCormack predictor-corrector
+//   Q* = Q^n + dt R+(Q^n),   Q^{n+1} = (Q^n + Q* + dt R-(Q*)) / 2
+// with R the right-hand sides of the mass equation and Eq. FDmomentum: first
+// derivatives of the convective, pressure and viscous terms are one-sided
+// (forward in R+, backward in R-), second derivatives and every derivative of
+// psi in Eq. FDforce are central; viscosities from Eq. DynamicViscosity with
+// tau_nu(rho) of Eq. RelaxationTime (Eq. FDviscosityDerivative).
+// Launches per step: psi/p of Q^n, predictor, psi/p of Q*, corrector (in place
+// over Q^n: the corrector reads Q^n only at its own node).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lbm.h"
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+struct lbm_fd_ctx {
+    lbm_fd_params P;
+    lbmk::DevEos eos;
+    size_t n;
+    double *rho, *u, *v, *rs, *us, *vs, *psi, *p;
+    unsigned* err;
+    long long step;
+};
+
+namespace {
+
+using namespace lbmk;
+
+struct FdArgs {
+    int nx, ny, var_tau;
+    double h, inv_h, inv_2h, inv_h2, inv_4h2, dt, G, two_inv_G, eps;
+    double tau_e, tau_nu, tau_v, tau_lo, tau_hi, dtau, rho_v_tau;
+    DevEos eos;
+    unsigned* err;
+    long long step;
+};
+
+__device__ __forceinline__ void fd_flag(const FdArgs& A)
+{
+    if (atomicCAS(A.err, 0u, 1u) == 0u) A.err[1] = (unsigned)A.step;
+}
+
+__global__ void k_fd_fields(FdArgs A, const double* rho, double* psi, double* p)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= A.nx || j >= A.ny) return;
+    const size_t k = (size_t)j * A.nx + i;
+    const double r = rho[k];
+    const double pe = dev_eos_p(A.eos, r);
+    const double q = (pe - r * (1.0 / 3.0)) * A.two_inv_G;
+    if (!(r > 0.0) || !(q >= 0.0)) fd_flag(A);
+    p[k] = pe;
+    psi[k] = q > 0.0 ? sqrt(q) : 0.0;
+}
+
+// periodic neighbour offsets of (i, j)
+struct Nb {
+    size_t c, xp, xm, yp, ym, xpyp, xpym, xmyp, xmym, x2p, x2m, y2p, y2m;
+};
+
+__device__ __forceinline__ Nb neighbours(const FdArgs& A, int i, int j)
+{
+    const int ip = i + 1 == A.nx ? 0 : i + 1, im = i == 0 ? A.nx - 1 : i - 1;
+    const int jp = j + 1 == A.ny ? 0 : j + 1, jm = j == 0 ? A.ny - 1 : j - 1;
+    const int ip2 = ip + 1 == A.nx ? 0 : ip + 1, im2 = im == 0 ? A.nx - 1 : im - 1;
+    const int jp2 = jp + 1 == A.ny ? 0 : jp + 1, jm2 = jm == 0 ? A.ny - 1 : jm - 1;
+    const size_t nx = (size_t)A.nx;
+    Nb b;
+    b.c = j * nx + i;
+    b.xp = j * nx + ip;
+    b.xm = j * nx + im;
+    b.yp = jp * nx + i;
+    b.ym = jm * nx + i;
+    b.xpyp = jp * nx + ip;
+    b.xpym = jm * nx + ip;
+    b.xmyp = jp * nx + im;
+    b.xmym = jm * nx + im;
+    b.x2p = j * nx + ip2;
+    b.x2m = j * nx + im2;
+    b.y2p = jp2 * nx + i;
+    b.y2m = jm2 * nx + i;
+    return b;
+}
+
+// one-sided first derivative along x or y: DIR = +1 forward, -1 backward
+template <int DIR>
+__device__ __forceinline__ double dx1(const FdArgs& A, const double* f, const Nb& b)
+{
+    return DIR > 0 ? (f[b.xp] - f[b.c]) * A.inv_h : (f[b.c] - f[b.xm]) * A.inv_h;
+}
+template <int DIR>
+__device__ __forceinline__ double dy1(const FdArgs& A, const double* f, const Nb& b)
+{
+    return DIR > 0 ? (f[b.yp] - f[b.c]) * A.inv_h : (f[b.c] - f[b.ym]) * A.inv_h;
+}
+
+// out = a * base + b * (Q + dt R_DIR(Q)) at every node
+template <int DIR>
+__global__ void k_fd_stage(FdArgs A, const double* rho, const double* u, const double* v, const double* psi,
+                           const double* p, const double* base_r, const double* base_u, const double* base_v,
+                           double wa, double wb, double* o_r, double* o_u, double* o_v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= A.nx || j >= A.ny) return;
+    const Nb b = neighbours(A, i, j);
+    const double cs2 = 1.0 / 3.0;
+    const double r = rho[b.c], ux = u[b.c], uy = v[b.c];
+    // one-sided first derivatives
+    const double rx = dx1<DIR>(A, rho, b), ry = dy1<DIR>(A, rho, b);
+    const double u_x = dx1<DIR>(A, u, b), u_y = dy1<DIR>(A, u, b);
+    const double v_x = dx1<DIR>(A, v, b), v_y = dy1<DIR>(A, v, b);
+    const double px = dx1<DIR>(A, p, b), py = dy1<DIR>(A, p, b);
+    const double div = u_x + v_y;
+    const double dr = -(r * div + ux * rx + uy * ry);
+    // Eq. DynamicViscosity, Eq. RelaxationTime and Eq. FDviscosityDerivative
+    double tn = A.tau_nu, dtn = 0.0;
+    if (A.var_tau) {
+        tn = A.tau_v + A.dtau * (r - A.rho_v_tau);
+        dtn = A.dtau;
+        if (tn <= A.tau_lo) { tn = A.tau_lo; dtn = 0.0; }
+        if (tn >= A.tau_hi) { tn = A.tau_hi; dtn = 0.0; }
+    }
+    const double mu = r * cs2 * (tn - 0.5), dmu = cs2 * (tn - 0.5) + r * cs2 * dtn;
+    const double muB = r * cs2 * (A.tau_e - tn), dmuB = cs2 * (A.tau_e - tn) - r * cs2 * dtn;
+    const double mux = dmu * rx, muy = dmu * ry, mBx = dmuB * rx, mBy = dmuB * ry;
+    // central second derivatives of the velocity
+    const double uc = u[b.c], vc = v[b.c];
+    const double u_xx = (u[b.xp] - 2.0 * uc + u[b.xm]) * A.inv_h2, u_yy = (u[b.yp] - 2.0 * uc + u[b.ym]) * A.inv_h2;
+    const double v_xx = (v[b.xp] - 2.0 * vc + v[b.xm]) * A.inv_h2, v_yy = (v[b.yp] - 2.0 * vc + v[b.ym]) * A.inv_h2;
+    const double u_xy = (u[b.xpyp] - u[b.xpym] - u[b.xmyp] + u[b.xmym]) * A.inv_4h2;
+    const double v_xy = (v[b.xpyp] - v[b.xpym] - v[b.xmyp] + v[b.xmym]) * A.inv_4h2;
+    // divergence of the viscous stress (Eq. FDstressTensor)
+    const double Sx = mux * (2.0 * u_x) + muy * (v_x + u_y) + mu * (2.0 * u_xx + u_yy + v_xy) + mBx * div +
+                      muB * (u_xx + v_xy);
+    const double Sy = mux * (u_y + v_x) + muy * (2.0 * v_y) + mu * (v_xx + 2.0 * v_yy + u_xy) + mBy * div +
+                      muB * (u_xy + v_yy);
+    // Eq. FDforce, central differences of psi (the Laplacian at x+-1, y+-1 reaches two nodes out)
+    const double s0 = psi[b.c], sxp = psi[b.xp], sxm = psi[b.xm], syp = psi[b.yp], sym = psi[b.ym];
+    const double sx = (sxp - sxm) * A.inv_2h, sy = (syp - sym) * A.inv_2h;
+    const double sxx = (sxp - 2.0 * s0 + sxm) * A.inv_h2, syy = (syp - 2.0 * s0 + sym) * A.inv_h2;
+    const double sxy = (psi[b.xpyp] - psi[b.xpym] - psi[b.xmyp] + psi[b.xmym]) * A.inv_4h2;
+    const double L = sxx + syy;
+    const double Lxp = (psi[b.x2p] - 2.0 * sxp + s0) * A.inv_h2 + (psi[b.xpyp] - 2.0 * sxp + psi[b.xpym]) * A.inv_h2;
+    const double Lxm = (s0 - 2.0 * sxm + psi[b.x2m]) * A.inv_h2 + (psi[b.xmyp] - 2.0 * sxm + psi[b.xmym]) * A.inv_h2;
+    const double Lyp = (psi[b.xpyp] - 2.0 * syp + psi[b.xmyp]) * A.inv_h2 + (psi[b.y2p] - 2.0 * syp + s0) * A.inv_h2;
+    const double Lym = (psi[b.xpym] - 2.0 * sym + psi[b.xmym]) * A.inv_h2 + (s0 - 2.0 * sym + psi[b.y2m]) * A.inv_h2;
+    const double Lx = (Lxp - Lxm) * A.inv_2h, Ly = (Lyp - Lym) * A.inv_2h;
+    const double gx = sx * sxx + sy * sxy, gy = sx * sxy + sy * syy;
+    const double G = A.G;
+    const double Px = -A.eps * G * 0.25 * gx + G * (1.0 / 12.0) * sx * L + G * (1.0 / 6.0) * gx + G * 0.25 * s0 * Lx;
+    const double Py = -A.eps * G * 0.25 * gy + G * (1.0 / 12.0) * sy * L + G * (1.0 / 6.0) * gy + G * 0.25 * s0 * Ly;
+    // Eq. FDmomentum
+    const double inv_r = 1.0 / r;
+    const double du = -(ux * u_x + uy * u_y) + (Sx - px - Px) * inv_r;
+    const double dv = -(ux * v_x + uy * v_y) + (Sy - py - Py) * inv_r;
+    const double nr = r + A.dt * dr, nu = ux + A.dt * du, nv = uy + A.dt * dv;
+    if (base_r) {
+        o_r[b.c] = wa * base_r[b.c] + wb * nr;
+        o_u[b.c] = wa * base_u[b.c] + wb * nu;
+        o_v[b.c] = wa * base_v[b.c] + wb * nv;
+    } else {
+        o_r[b.c] = nr;
+        o_u[b.c] = nu;
+        o_v[b.c] = nv;
+    }
+}
+
+FdArgs fd_args(const lbm_fd_ctx* c)
+{
+    const lbm_fd_params& P = c->P;
+    FdArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.nx = P.nx;
+    A.ny = P.ny;
+    A.var_tau = P.var_tau;
+    A.h = P.h;
+    A.inv_h = 1.0 / P.h;
+    A.inv_2h = 0.5 / P.h;
+    A.inv_h2 = 1.0 / (P.h * P.h);
+    A.inv_4h2 = 0.25 / (P.h * P.h);
+    A.dt = P.dt;
+    A.G = P.G;
+    A.two_inv_G = 2.0 / P.G;
+    A.eps = P.eps;
+    A.tau_e = P.tau_e;
+    A.tau_nu = P.tau_nu;
+    A.tau_v = P.tau_v;
+    A.tau_lo = P.tau_l < P.tau_v ? P.tau_l : P.tau_v;
+    A.tau_hi = P.tau_l < P.tau_v ? P.tau_v : P.tau_l;
+    A.dtau = P.var_tau ? (P.tau_l - P.tau_v) / (P.rho_l_tau - P.rho_v_tau) : 0.0;
+    A.rho_v_tau = P.rho_v_tau;
+    A.eos = c->eos;
+    A.err = c->err;
+    A.step = c->step;
+    return A;
+}
+
+bool ok(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return true;
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+    lbm_set_error(buf);
+    return false;
+}
+
+constexpr size_t kFdArrays = 8;
+
+}  // namespace
+
+extern "C" {
+
+int lbm_fd_layout(const lbm_fd_params* p, size_t* bytes)
+{
+    if (!p || p->nx < 3 || p->ny < 3 || !(p->h > 0) || !(p->dt > 0) || !(p->G < 0)) {
+        lbm_set_error("lbm_fd_layout: need nx, ny >= 3, h > 0, dt > 0 and G < 0");
+        return LBM_EINVAL;
+    }
+    if (bytes) *bytes = 256 + kFdArrays * (((size_t)p->nx * p->ny * sizeof(double) + 255) & ~(size_t)255);
+    return LBM_OK;
+}
+
+int lbm_fd_init(lbm_fd_ctx** out, const lbm_fd_params* p, void* buf, size_t buf_bytes, const double* rho0,
+                const double* u0, const double* v0, void* stream)
+{
+    size_t need = 0;
+    if (!out || !buf || !rho0) return LBM_EINVAL;
+    const int st = lbm_fd_layout(p, &need);
+    if (st != LBM_OK) return st;
+    if (buf_bytes < need) {
+        lbm_set_error("lbm_fd_init: buffer smaller than lbm_fd_layout requires");
+        return LBM_EINVAL;
+    }
+    if (p->var_tau && !(p->rho_l_tau > p->rho_v_tau)) {
+        lbm_set_error("lbm_fd_init: Eq. RelaxationTime needs rho_l_tau > rho_v_tau");
+        return LBM_EINVAL;
+    }
+    lbm_fd_ctx* c = new (std::nothrow) lbm_fd_ctx();
+    if (!c) return LBM_EINVAL;
+    c->P = *p;
+    c->eos = dev_eos(p->eos);
+    c->n = (size_t)p->nx * p->ny;
+    char* b = (char*)buf;
+    c->err = (unsigned*)b;
+    b += 256;
+    const size_t arr = (c->n * sizeof(double) + 255) & ~(size_t)255;
+    double** slots[kFdArrays] = {&c->rho, &c->u, &c->v, &c->rs, &c->us, &c->vs, &c->psi, &c->p};
+    for (size_t k = 0; k < kFdArrays; ++k, b += arr) *slots[k] = (double*)b;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = c->n * sizeof(double);
+    bool good = ok(hipMemsetAsync(c->err, 0, 256, s), "fd clear") &&
+                ok(hipMemcpyAsync(c->rho, rho0, nb, hipMemcpyDeviceToDevice, s), "fd rho0");
+    good = good && (u0 ? ok(hipMemcpyAsync(c->u, u0, nb, hipMemcpyDeviceToDevice, s), "fd u0")
+                       : ok(hipMemsetAsync(c->u, 0, nb, s), "fd u0"));
+    good = good && (v0 ? ok(hipMemcpyAsync(c->v, v0, nb, hipMemcpyDeviceToDevice, s), "fd v0")
+                       : ok(hipMemsetAsync(c->v, 0, nb, s), "fd v0"));
+    if (!good) {
+        delete c;
+        return LBM_EHIP;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_fd_step(lbm_fd_ctx* c, int64_t nsteps, void* stream)
+{
+    if (!c || nsteps < 0) return LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const dim3 blk(128), grd((c->P.nx + 127) / 128, c->P.ny);
+    for (int64_t t = 0; t < nsteps; ++t) {
+        FdArgs A = fd_args(c);
+        hipLaunchKernelGGL(k_fd_fields, grd, blk, 0, s, A, (const double*)c->rho, c->psi, c->p);
+        hipLaunchKernelGGL(k_fd_stage<+1>, grd, blk, 0, s, A, (const double*)c->rho, (const double*)c->u,
+                           (const double*)c->v, (const double*)c->psi, (const double*)c->p, (const double*)nullptr,
+                           (const double*)nullptr, (const double*)nullptr, 0.0, 1.0, c->rs, c->us, c->vs);
+        hipLaunchKernelGGL(k_fd_fields, grd, blk, 0, s, A, (const double*)c->rs, c->psi, c->p);
+        hipLaunchKernelGGL(k_fd_stage<-1>, grd, blk, 0, s, A, (const double*)c->rs, (const double*)c->us,
+                           (const double*)c->vs, (const double*)c->psi, (const double*)c->p, (const double*)c->rho,
+                           (const double*)c->u, (const double*)c->v, 0.5, 0.5, c->rho, c->u, c->v);
+        if (!ok(hipGetLastError(), "fd step launch")) return LBM_EHIP;
+        c->step++;
+    }
+    return LBM_OK;
+}
+
+int lbm_fd_fields(lbm_fd_ctx* c, double* rho, double* u, double* v, void* stream)
+{
+    if (!c) return LBM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = c->n * sizeof(double);
+    bool good = true;
+    if (rho) good = good && ok(hipMemcpyAsync(rho, c->rho, nb, hipMemcpyDeviceToDevice, s), "fd rho out");
+    if (u) good = good && ok(hipMemcpyAsync(u, c->u, nb, hipMemcpyDeviceToDevice, s), "fd u out");
+    if (v) good = good && ok(hipMemcpyAsync(v, c->v, nb, hipMemcpyDeviceToDevice, s), "fd v out");
+    return good ? LBM_OK : LBM_EHIP;
+}
+
+int lbm_fd_status(lbm_fd_ctx* c, void* stream)
+{
+    if (!c) return LBM_EINVAL;
+    unsigned h[2];
+    hipStream_t s = (hipStream_t)stream;
+    if (!ok(hipMemcpyAsync(h, c->err, sizeof(h), hipMemcpyDeviceToHost, s), "fd status") ||
+        !ok(hipStreamSynchronize(s), "fd status sync"))
+        return LBM_EHIP;
+    if (h[0]) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "lbm_fd: psi^2 < 0 or non-positive density at step %u", h[1]);
+        lbm_set_error(buf);
+        return LBM_EUNSTABLE;
+    }
+    return LBM_OK;
+}
+
+void lbm_fd_destroy(lbm_fd_ctx* c) { delete c; }
+
+}  // extern "C"

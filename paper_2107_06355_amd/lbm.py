@@ -54,6 +54,16 @@ class LbmParams(C.Structure):
     ]
 
 
+class LbmFdParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("var_tau", C.c_int), ("pad_", C.c_int),
+        ("h", C.c_double), ("dt", C.c_double), ("G", C.c_double), ("eps", C.c_double),
+        ("tau_e", C.c_double), ("tau_nu", C.c_double),
+        ("tau_l", C.c_double), ("tau_v", C.c_double), ("rho_v_tau", C.c_double), ("rho_l_tau", C.c_double),
+        ("eos", LbmEos),
+    ]
+
+
 class LbmError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -91,6 +101,12 @@ def _signatures():
         "lbm_set_checkpointing": ([vp, vp, sz, i], i),
         "lbm_adjoint": ([vp, vp, vp, sz, vp, sz, dp, vp, vp], i),
         "lbm_eos_set_knots": ([C.POINTER(LbmEos), d, d, d, d], i),
+        "lbm_fd_layout": ([C.POINTER(LbmFdParams), C.POINTER(sz)], i),
+        "lbm_fd_init": ([C.POINTER(vp), C.POINTER(LbmFdParams), vp, sz, vp, vp, vp, vp], i),
+        "lbm_fd_step": ([vp, C.c_int64, vp], i),
+        "lbm_fd_fields": ([vp, vp, vp, vp, vp], i),
+        "lbm_fd_status": ([vp, vp], i),
+        "lbm_fd_destroy": ([vp], None),
         "lbm_strerror": ([i], C.c_char_p),
         "lbm_last_error": ([], C.c_char_p),
     }
@@ -383,6 +399,71 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             load().lbm_destroy_batched(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------- finite-difference reference solver
+def make_fd_params(nx, ny, eos: LbmEos, h=1.0, dt=0.2, G=-1.0, eps=0.0, tau_e=1.0, tau_nu=1.0, var_tau=False,
+                   tau_l=1.0, tau_v=1.0, rho_v_tau=None, rho_l_tau=None) -> LbmFdParams:
+    P = LbmFdParams()
+    P.nx, P.ny, P.var_tau = nx, ny, int(var_tau)
+    P.h, P.dt, P.G, P.eps, P.tau_e, P.tau_nu = h, dt, G, eps, tau_e, tau_nu
+    P.tau_l, P.tau_v = tau_l, tau_v
+    P.rho_v_tau = eos.rho_v if rho_v_tau is None else rho_v_tau
+    P.rho_l_tau = eos.rho_l if rho_l_tau is None else rho_l_tau
+    P.eos = eos
+    return P
+
+
+class FdSolver:
+    """MacCormack finite-difference reference solver (lbm_fd_*) with state in one torch device buffer."""
+
+    def __init__(self, P: LbmFdParams, rho0, u0=None, v0=None, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.P = P
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nb = C.c_size_t(0)
+        _check(load().lbm_fd_layout(C.byref(P), C.byref(nb)), "lbm_fd_layout")
+        self.buf = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        shp = (P.ny, P.nx)
+        f = [None if a is None else torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(shp),
+                                                     device=self.device) for a in (rho0, u0, v0)]
+        h = C.c_void_p(0)
+        _check(load().lbm_fd_init(C.byref(h), C.byref(P), self.buf.data_ptr(), nb.value, f[0].data_ptr(),
+                                  f[1].data_ptr() if f[1] is not None else None,
+                                  f[2].data_ptr() if f[2] is not None else None, self._s()), "lbm_fd_init")
+        self.torch.cuda.synchronize(self.device)
+        self._h = h
+
+    def _s(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def step(self, n: int):
+        _check(load().lbm_fd_step(self._h, int(n), self._s()), "lbm_fd_step")
+
+    def check(self):
+        _check(load().lbm_fd_status(self._h, self._s()), "lbm_fd_status")
+
+    def fields(self):
+        t = self.torch
+        shp = (self.P.ny, self.P.nx)
+        out = [t.empty(shp, dtype=t.float64, device=self.device) for _ in range(3)]
+        _check(load().lbm_fd_fields(self._h, *[o.data_ptr() for o in out], self._s()), "lbm_fd_fields")
+        self.torch.cuda.synchronize(self.device)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lbm_fd_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -350,3 +350,39 @@ def test_cs_density_ratio_at_tr035():
     r = O.run_planar(e, sigma=s)
     assert r["residual"] < 1e-6
     assert r["rho_l"] / r["rho_v"] == pytest.approx(g["cs_Tr035_ratio"], rel=2e-3)
+
+
+# ---------------------------------------------------------------- finite-difference reference solver
+def test_fd_oracle_shear_wave_exact_discrete_decay():
+    """Uniform density: u = A sin(k y) decays by g = 1 - l dt + (l dt)^2 / 2 per MacCormack step with
+    l = nu (2 sin(k h/2)/h)^2 and nu = (tau_nu - 1/2)/3 (Eq. DynamicViscosity); density and v stay put."""
+    e, _ = cs_eos(0.7)
+    nx, ny, h, dt, tau, n, A = 4, 32, 1.0, 0.2, 0.8, 500, 1e-4
+    y = np.arange(ny) * h
+    k = 2 * np.pi / (ny * h)
+    F = O.FdSolver(O.make_fd_params(nx, ny, e, h=h, dt=dt, tau_nu=tau))
+    F.set(np.full((ny, nx), e.rho_l), np.repeat((A * np.sin(k * y))[:, None], nx, axis=1))
+    F.run(n)
+    r, u, v = F.get()
+    amp = 2 * (u[:, 0] * np.sin(k * y)).sum() / ny
+    lam = (tau - 0.5) / 3 * (2 / h * math.sin(k * h / 2)) ** 2
+    assert amp / A == pytest.approx((1 - lam * dt + (lam * dt) ** 2 / 2) ** n, rel=1e-12)
+    assert np.abs(r - e.rho_l).max() == 0.0 and np.abs(v).max() < 1e-18
+
+
+@pytest.mark.slow
+def test_fd_oracle_planar_second_order_toward_maxwell():
+    """With eps from Eq. VaporLiqEq the continuum equilibrium of the FD equations has the Maxwell
+    densities: halving h (fixed length 100) cuts the vapor error about four-fold."""
+    e, _ = cs_eos(0.8)
+    E = []
+    for h in (1.0, 0.5):
+        ny = int(round(100 / h))
+        dt = 0.2 * h * h
+        F = O.FdSolver(O.make_fd_params(3, ny, e, h=h, dt=dt, eps=e.eps))
+        F.set(planar_density(3, ny, e.rho_v, e.rho_l, W=10 / h, axis=1))
+        F.run(int(round(2000 / dt)))
+        r, _, _ = F.get()
+        E.append((r[0, 0] - e.rho_v) / e.rho_v)
+    assert -0.03 < E[0] < -0.015
+    assert 3.6 < E[0] / E[1] < 4.6
