@@ -244,14 +244,14 @@ typedef struct {
 } lbm_fd_params;
 typedef struct lbm_fd_ctx lbm_fd_ctx;
 
-/* Bytes of the caller-owned device buffer (an error word and 8 float64 fields
- * [ny][nx]); LBM_EINVAL for bad sizes, h, dt or G. */
+/* Bytes of the caller-owned device buffer (an error word and 6 float64 fields
+ * [ny][nx]: the state and the predicted state); LBM_EINVAL for bad sizes, h, dt or G. */
 int lbm_fd_layout(const lbm_fd_params* p, size_t* bytes);
 /* Initial state: rho0, u0, v0 device float64 [ny][nx] (u0, v0 may be NULL for
  * rest).  The buffer holds all solver state; the context holds only pointers. */
 int lbm_fd_init(lbm_fd_ctx** ctx, const lbm_fd_params* p, void* buf, size_t buf_bytes, const double* rho0,
                 const double* u0, const double* v0, void* stream);
-/* nsteps predictor-corrector steps (asynchronous, four launches each). */
+/* nsteps predictor-corrector steps (asynchronous, two launches each). */
 int lbm_fd_step(lbm_fd_ctx* ctx, int64_t nsteps, void* stream);
 /* Copy rho, u, v (device float64 [ny][nx], any may be NULL); asynchronous. */
 int lbm_fd_fields(lbm_fd_ctx* ctx, double* rho, double* u, double* v, void* stream);

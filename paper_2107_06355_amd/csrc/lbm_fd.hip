@@ -9,8 +9,11 @@
 // (forward in R+, backward in R-), second derivatives and every derivative of
 // psi in Eq. FDforce are central; viscosities from Eq. DynamicViscosity with
 // tau_nu(rho) of Eq. RelaxationTime (Eq. FDviscosityDerivative).
-// Launches per step: psi/p of Q^n, predictor, psi/p of Q*, corrector (in place
-// over Q^n: the corrector reads Q^n only at its own node).
+// Two launches per step (predictor, corrector in place over Q^n: the corrector
+// reads Q^n only at its own node).  Each workgroup owns a 32 x 8 tile and first
+// evaluates p_EOS and psi of its tile plus a two-node halo into LDS (Eq. FDforce
+// reaches two nodes out through the Laplacian of psi), then every thread forms
+// its node's right-hand side from LDS (psi, p) and the state (radius one).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,7 +29,7 @@ struct lbm_fd_ctx {
     lbm_fd_params P;
     lbmk::DevEos eos;
     size_t n;
-    double *rho, *u, *v, *rs, *us, *vs, *psi, *p;
+    double *rho, *u, *v, *rs, *us, *vs;
     unsigned* err;
     long long step;
 };
@@ -49,30 +52,15 @@ __device__ __forceinline__ void fd_flag(const FdArgs& A)
     if (atomicCAS(A.err, 0u, 1u) == 0u) A.err[1] = (unsigned)A.step;
 }
 
-__global__ void k_fd_fields(FdArgs A, const double* rho, double* psi, double* p)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
-    if (i >= A.nx || j >= A.ny) return;
-    const size_t k = (size_t)j * A.nx + i;
-    const double r = rho[k];
-    const double pe = dev_eos_p(A.eos, r);
-    const double q = (pe - r * (1.0 / 3.0)) * A.two_inv_G;
-    if (!(r > 0.0) || !(q >= 0.0)) fd_flag(A);
-    p[k] = pe;
-    psi[k] = q > 0.0 ? sqrt(q) : 0.0;
-}
-
 // periodic neighbour offsets of (i, j)
 struct Nb {
-    size_t c, xp, xm, yp, ym, xpyp, xpym, xmyp, xmym, x2p, x2m, y2p, y2m;
+    size_t c, xp, xm, yp, ym, xpyp, xpym, xmyp, xmym;
 };
 
 __device__ __forceinline__ Nb neighbours(const FdArgs& A, int i, int j)
 {
     const int ip = i + 1 == A.nx ? 0 : i + 1, im = i == 0 ? A.nx - 1 : i - 1;
     const int jp = j + 1 == A.ny ? 0 : j + 1, jm = j == 0 ? A.ny - 1 : j - 1;
-    const int ip2 = ip + 1 == A.nx ? 0 : ip + 1, im2 = im == 0 ? A.nx - 1 : im - 1;
-    const int jp2 = jp + 1 == A.ny ? 0 : jp + 1, jm2 = jm == 0 ? A.ny - 1 : jm - 1;
     const size_t nx = (size_t)A.nx;
     Nb b;
     b.c = j * nx + i;
@@ -84,10 +72,6 @@ __device__ __forceinline__ Nb neighbours(const FdArgs& A, int i, int j)
     b.xpym = jm * nx + ip;
     b.xmyp = jp * nx + im;
     b.xmym = jm * nx + im;
-    b.x2p = j * nx + ip2;
-    b.x2m = j * nx + im2;
-    b.y2p = jp2 * nx + i;
-    b.y2m = jm2 * nx + i;
     return b;
 }
 
@@ -103,22 +87,45 @@ __device__ __forceinline__ double dy1(const FdArgs& A, const double* f, const Nb
     return DIR > 0 ? (f[b.yp] - f[b.c]) * A.inv_h : (f[b.c] - f[b.ym]) * A.inv_h;
 }
 
+constexpr int kTx = 32, kTy = 8, kHalo = 2;
+constexpr int kLx = kTx + 2 * kHalo, kLy = kTy + 2 * kHalo;
+
 // out = a * base + b * (Q + dt R_DIR(Q)) at every node
 template <int DIR>
-__global__ void k_fd_stage(FdArgs A, const double* rho, const double* u, const double* v, const double* psi,
-                           const double* p, const double* base_r, const double* base_u, const double* base_v,
-                           double wa, double wb, double* o_r, double* o_u, double* o_v)
+__global__ __launch_bounds__(kTx * kTy) void k_fd_stage(FdArgs A, const double* rho, const double* u, const double* v,
+                                                        const double* base_r, const double* base_u,
+                                                        const double* base_v, double wa, double wb, double* o_r,
+                                                        double* o_u, double* o_v)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    __shared__ double spsi[kLy][kLx], spe[kLy][kLx];
+    const int tid = threadIdx.y * kTx + threadIdx.x;
+    const int i0 = blockIdx.x * kTx, j0 = blockIdx.y * kTy;
+    // p_EOS and psi (Eq. InteractionPotential) of the tile and its halo
+    for (int q = tid; q < kLx * kLy; q += kTx * kTy) {
+        const int ti = q % kLx, tj = q / kLx;
+        int gi = (i0 + ti - kHalo) % A.nx, gj = (j0 + tj - kHalo) % A.ny;
+        gi = gi < 0 ? gi + A.nx : gi;
+        gj = gj < 0 ? gj + A.ny : gj;
+        const double r = rho[(size_t)gj * A.nx + gi];
+        const double pe = dev_eos_p(A.eos, r);
+        const double qq = (pe - r * (1.0 / 3.0)) * A.two_inv_G;
+        if (!(r > 0.0) || !(qq >= 0.0)) fd_flag(A);
+        spe[tj][ti] = pe;
+        spsi[tj][ti] = qq > 0.0 ? sqrt(qq) : 0.0;
+    }
+    __syncthreads();
+    const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
     if (i >= A.nx || j >= A.ny) return;
     const Nb b = neighbours(A, i, j);
+    const int li = threadIdx.x + kHalo, lj = threadIdx.y + kHalo;
     const double cs2 = 1.0 / 3.0;
     const double r = rho[b.c], ux = u[b.c], uy = v[b.c];
     // one-sided first derivatives
     const double rx = dx1<DIR>(A, rho, b), ry = dy1<DIR>(A, rho, b);
     const double u_x = dx1<DIR>(A, u, b), u_y = dy1<DIR>(A, u, b);
     const double v_x = dx1<DIR>(A, v, b), v_y = dy1<DIR>(A, v, b);
-    const double px = dx1<DIR>(A, p, b), py = dy1<DIR>(A, p, b);
+    const double px = (DIR > 0 ? spe[lj][li + 1] - spe[lj][li] : spe[lj][li] - spe[lj][li - 1]) * A.inv_h;
+    const double py = (DIR > 0 ? spe[lj + 1][li] - spe[lj][li] : spe[lj][li] - spe[lj - 1][li]) * A.inv_h;
     const double div = u_x + v_y;
     const double dr = -(r * div + ux * rx + uy * ry);
     // Eq. DynamicViscosity, Eq. RelaxationTime and Eq. FDviscosityDerivative
@@ -144,15 +151,18 @@ __global__ void k_fd_stage(FdArgs A, const double* rho, const double* u, const d
     const double Sy = mux * (u_y + v_x) + muy * (2.0 * v_y) + mu * (v_xx + 2.0 * v_yy + u_xy) + mBy * div +
                       muB * (u_xy + v_yy);
     // Eq. FDforce, central differences of psi (the Laplacian at x+-1, y+-1 reaches two nodes out)
-    const double s0 = psi[b.c], sxp = psi[b.xp], sxm = psi[b.xm], syp = psi[b.yp], sym = psi[b.ym];
+    const double s0 = spsi[lj][li], sxp = spsi[lj][li + 1], sxm = spsi[lj][li - 1];
+    const double syp = spsi[lj + 1][li], sym = spsi[lj - 1][li];
+    const double spp = spsi[lj + 1][li + 1], spm = spsi[lj - 1][li + 1], smp = spsi[lj + 1][li - 1];
+    const double smm = spsi[lj - 1][li - 1];
     const double sx = (sxp - sxm) * A.inv_2h, sy = (syp - sym) * A.inv_2h;
     const double sxx = (sxp - 2.0 * s0 + sxm) * A.inv_h2, syy = (syp - 2.0 * s0 + sym) * A.inv_h2;
-    const double sxy = (psi[b.xpyp] - psi[b.xpym] - psi[b.xmyp] + psi[b.xmym]) * A.inv_4h2;
+    const double sxy = (spp - spm - smp + smm) * A.inv_4h2;
     const double L = sxx + syy;
-    const double Lxp = (psi[b.x2p] - 2.0 * sxp + s0) * A.inv_h2 + (psi[b.xpyp] - 2.0 * sxp + psi[b.xpym]) * A.inv_h2;
-    const double Lxm = (s0 - 2.0 * sxm + psi[b.x2m]) * A.inv_h2 + (psi[b.xmyp] - 2.0 * sxm + psi[b.xmym]) * A.inv_h2;
-    const double Lyp = (psi[b.xpyp] - 2.0 * syp + psi[b.xmyp]) * A.inv_h2 + (psi[b.y2p] - 2.0 * syp + s0) * A.inv_h2;
-    const double Lym = (psi[b.xpym] - 2.0 * sym + psi[b.xmym]) * A.inv_h2 + (s0 - 2.0 * sym + psi[b.y2m]) * A.inv_h2;
+    const double Lxp = (spsi[lj][li + 2] - 2.0 * sxp + s0) * A.inv_h2 + (spp - 2.0 * sxp + spm) * A.inv_h2;
+    const double Lxm = (s0 - 2.0 * sxm + spsi[lj][li - 2]) * A.inv_h2 + (smp - 2.0 * sxm + smm) * A.inv_h2;
+    const double Lyp = (spp - 2.0 * syp + smp) * A.inv_h2 + (spsi[lj + 2][li] - 2.0 * syp + s0) * A.inv_h2;
+    const double Lym = (spm - 2.0 * sym + smm) * A.inv_h2 + (s0 - 2.0 * sym + spsi[lj - 2][li]) * A.inv_h2;
     const double Lx = (Lxp - Lxm) * A.inv_2h, Ly = (Lyp - Lym) * A.inv_2h;
     const double gx = sx * sxx + sy * sxy, gy = sx * sxy + sy * syy;
     const double G = A.G;
@@ -213,7 +223,7 @@ bool ok(hipError_t e, const char* what)
     return false;
 }
 
-constexpr size_t kFdArrays = 8;
+constexpr size_t kFdArrays = 6;
 
 }  // namespace
 
@@ -253,7 +263,7 @@ int lbm_fd_init(lbm_fd_ctx** out, const lbm_fd_params* p, void* buf, size_t buf_
     c->err = (unsigned*)b;
     b += 256;
     const size_t arr = (c->n * sizeof(double) + 255) & ~(size_t)255;
-    double** slots[kFdArrays] = {&c->rho, &c->u, &c->v, &c->rs, &c->us, &c->vs, &c->psi, &c->p};
+    double** slots[kFdArrays] = {&c->rho, &c->u, &c->v, &c->rs, &c->us, &c->vs};
     for (size_t k = 0; k < kFdArrays; ++k, b += arr) *slots[k] = (double*)b;
     hipStream_t s = (hipStream_t)stream;
     const size_t nb = c->n * sizeof(double);
@@ -275,17 +285,15 @@ int lbm_fd_step(lbm_fd_ctx* c, int64_t nsteps, void* stream)
 {
     if (!c || nsteps < 0) return LBM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const dim3 blk(128), grd((c->P.nx + 127) / 128, c->P.ny);
+    const dim3 blk(kTx, kTy), grd((c->P.nx + kTx - 1) / kTx, (c->P.ny + kTy - 1) / kTy);
     for (int64_t t = 0; t < nsteps; ++t) {
         FdArgs A = fd_args(c);
-        hipLaunchKernelGGL(k_fd_fields, grd, blk, 0, s, A, (const double*)c->rho, c->psi, c->p);
         hipLaunchKernelGGL(k_fd_stage<+1>, grd, blk, 0, s, A, (const double*)c->rho, (const double*)c->u,
-                           (const double*)c->v, (const double*)c->psi, (const double*)c->p, (const double*)nullptr,
-                           (const double*)nullptr, (const double*)nullptr, 0.0, 1.0, c->rs, c->us, c->vs);
-        hipLaunchKernelGGL(k_fd_fields, grd, blk, 0, s, A, (const double*)c->rs, c->psi, c->p);
+                           (const double*)c->v, (const double*)nullptr, (const double*)nullptr,
+                           (const double*)nullptr, 0.0, 1.0, c->rs, c->us, c->vs);
         hipLaunchKernelGGL(k_fd_stage<-1>, grd, blk, 0, s, A, (const double*)c->rs, (const double*)c->us,
-                           (const double*)c->vs, (const double*)c->psi, (const double*)c->p, (const double*)c->rho,
-                           (const double*)c->u, (const double*)c->v, 0.5, 0.5, c->rho, c->u, c->v);
+                           (const double*)c->vs, (const double*)c->rho, (const double*)c->u, (const double*)c->v,
+                           0.5, 0.5, c->rho, c->u, c->v);
         if (!ok(hipGetLastError(), "fd step launch")) return LBM_EHIP;
         c->step++;
     }
