@@ -322,7 +322,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--n", type=int, default=512, help="lattice side of the timed workload")
     ap.add_argument("--radius", type=int, default=80, help="droplet radius of the timed workload")
-    ap.add_argument("--sweep", default="2048,4096,8192", help="extra lattice sides for the HBM roofline ('' = none)")
+    ap.add_argument("--sweep", default="2048,4096,8192,16384",
+                    help="extra lattice sides for the HBM roofline ('' = none)")
     ap.add_argument("--sweep-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")

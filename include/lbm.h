@@ -115,7 +115,9 @@ typedef struct {
 typedef struct lbm_ctx lbm_ctx;
 
 /* Layout query: row pitch, bytes of ONE population buffer (the caller
- * allocates two), and bytes of the workspace. */
+ * allocates two), and bytes of the workspace.  LBM_EINVAL when a population
+ * plane (64-aligned row pitch x ny x 8 bytes) would reach 4 GiB: offsets
+ * inside a plane are 32-bit (the largest square lattice is 23168^2). */
 int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* ws_bytes_out);
 
 /* Which step-kernel decomposition the parameters select (the automatic

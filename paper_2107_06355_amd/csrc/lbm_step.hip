@@ -477,6 +477,10 @@ int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* 
         return LBM_EINVAL;
     }
     const int ld = (p->nx + 63) & ~63;
+    if ((long long)ld * p->ny * 8 >= (1LL << 32)) {
+        lbm_set_error("lbm_layout: one population plane must stay below 4 GiB (lattice too large)");
+        return LBM_EINVAL;
+    }
     const size_t plane = (size_t)ld * p->ny;
     const size_t bytes = p->prec == LBM_FP32_SHIFTED ? plane * (8 * sizeof(float) + sizeof(double)) : plane * 9 * sizeof(double);
     int strips, seg_h, nseg, blk;

@@ -70,13 +70,14 @@ def _samples(n, rng):
     return sorted(set(pts))
 
 
-@pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
-def test_8192_droplet_sampled_nodes_one_step(gpu_lib, prec_name):
+@pytest.mark.parametrize("n,prec_name", [(8192, "fp32"), (8192, "fp64"), (16384, "fp32")])
+def test_large_droplet_sampled_nodes_one_step(gpu_lib, n, prec_name):
+    """8192^2 (the HBM sweep) and 16384^2 (the largest size of the roofline sweep: 21 GB of
+    FP32 populations, 64-bit plane offsets with 32-bit in-plane offsets)."""
     import torch
 
     lbm = gpu_lib
     prec = lbm.FP64 if prec_name == "fp64" else lbm.FP32_SHIFTED
-    n = 8192
     L, e = _lattice(lbm, n, n // 6, prec, 20)
     assert lbm.describe(L.P)[0] == lbm.VARIANT_MARCH  # the kernel bench.py times at this size
     pts = _samples(n, np.random.default_rng(7))

@@ -61,3 +61,14 @@ def test_host_thermo_rejects_bad_inputs():
     assert ei.value.code == lbm.LBM_EINVAL
     with pytest.raises(lbm.LbmError):
         lbm.eos_build(lbm.make_eos(Tr=0.5), G=1.0)
+
+
+def test_layout_rejects_a_plane_above_4_gib():
+    """Per-lane offsets inside a population plane are 32-bit: the largest lattice is the one whose
+    64-aligned row pitch times ny times 8 bytes stays below 4 GiB."""
+    e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
+    ld, pop, _ = lbm.layout(lbm.make_params(23168, 23168, e, sigma=s))
+    assert ld == 23168 and pop == 23168 * 23168 * 72
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.layout(lbm.make_params(23232, 23168, e, sigma=s))
+    assert ei.value.code == lbm.LBM_EINVAL
