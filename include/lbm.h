@@ -233,11 +233,16 @@ void lbm_destroy_batched(lbm_batch* ctx);
  * Eq. RelaxationTime when var_tau), pseudopotential pressure tensor through
  * Eq. FDforce, MacCormack predictor (forward one-sided first derivatives) and
  * corrector (backward), central second and higher derivatives.  FP64.
+ * Walls (appendix "Grid-Dependency Study"): the layer b1 one node below row 0
+ * lies on the bottom wall (u = v = 0, rho and psi extrapolated from rows 0 and
+ * 1), b2 below it holds psi of Eq. B2 with psi_l = psi(eos.rho_l); row ny-1 lies
+ * on the top wall and the layers above mirror rows ny-2 and ny-3 with the
+ * velocity reversed.
  * ------------------------------------------------------------------------ */
 typedef struct {
-    int nx, ny;           /* mesh nodes (>= 3 each), periodic in x and y */
+    int nx, ny;           /* mesh nodes (>= 3 each), periodic in x */
     int var_tau;          /* 1: tau_nu from Eq. RelaxationTime (tau_l, tau_v, rho_*_tau) */
-    int pad_;
+    int walls;            /* 0: periodic in y; 1: the wall layers above */
     double h, dt;         /* mesh spacing and time step (LBM units) */
     double G, eps;        /* interaction constant (< 0); eps of the pressure tensor (Li: -16 G sigma, Guo: 0) */
     double tau_e, tau_nu; /* relaxation times of Eq. DynamicViscosity */

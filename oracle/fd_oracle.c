@@ -12,8 +12,12 @@
  * where R+ uses first-order forward differences for the first derivatives of
  * the convective, pressure and viscous terms, R- backward differences, and all
  * second and third derivatives (and every derivative inside Eq. FDforce) are
- * second-order central differences.  Doubly periodic mesh of spacing h (LBM
- * units, c = 1, c_s^2 = 1/3); written node by node for checkability.
+ * second-order central differences.  Mesh of spacing h (LBM units, c = 1,
+ * c_s^2 = 1/3), periodic in x; in y periodic, or walls as in the appendix's
+ * grid study: below row 0 the layer b1 on the wall (rho and psi extrapolated
+ * from rows 0 and 1, u = v = 0) and the solid layer b2 (Eq. B2, psi only);
+ * row ny-1 lies on the top wall and the layers above mirror rows ny-2 and
+ * ny-3 (velocities reversed).  Written node by node for checkability.
  */
 #include "lbm_oracle.h"
 
@@ -35,6 +39,28 @@ static int idx(const or_fd* F, int i, int j)
     i = ((i % nx) + nx) % nx;
     j = ((j % ny) + ny) % ny;
     return j * nx + i;
+}
+
+enum { FD_RHO, FD_U, FD_V, FD_PSI, FD_P };
+
+/* value of a field at (i, j), including the wall layers j = -2, -1, ny, ny + 1 */
+static double val(const or_fd* F, int kind, const double* f, const double* rho, int i, int j)
+{
+    const int ny = F->P.ny;
+    if (!F->P.walls || (j >= 0 && j < ny)) return f[idx(F, i, j)];
+    if (j >= ny) {
+        /* reflexive top: t1 mirrors ny-2, t2 mirrors ny-3 (velocities reversed) */
+        const int m = 2 * (ny - 1) - j;
+        const double s = (kind == FD_U || kind == FD_V) ? -1.0 : 1.0;
+        return s * f[idx(F, i, m)];
+    }
+    /* bottom: b1 (j = -1) on the wall, b2 (j = -2) inside it */
+    if (kind == FD_U || kind == FD_V) return 0.0;
+    if (kind == FD_RHO) return 2.0 * f[idx(F, i, 0)] - f[idx(F, i, 1)];
+    if (kind == FD_P) return or_eos_p(&F->P.eos, 2.0 * rho[idx(F, i, 0)] - rho[idx(F, i, 1)]);
+    const double b1 = 2.0 * f[idx(F, i, 0)] - f[idx(F, i, 1)];
+    if (j == -1) return b1;
+    return b1 + 2.0 * F->P.h * (F->P.psi_wall - b1); /* Eq. B2 */
 }
 
 or_fd* or_fd_new(const or_fd_params* P)
@@ -109,30 +135,31 @@ static int fields(or_fd* F, const double* rho)
 }
 
 /* first derivative along axis (0 = x, 1 = y): dir +1 forward, -1 backward, 0 central */
-static double d1(const or_fd* F, const double* f, int i, int j, int axis, int dir)
+static double d1(const or_fd* F, int kind, const double* f, const double* rho, int i, int j, int axis, int dir)
 {
     const double h = F->P.h;
     const int di = axis == 0, dj = axis == 1;
-    if (dir > 0) return (f[idx(F, i + di, j + dj)] - f[idx(F, i, j)]) / h;
-    if (dir < 0) return (f[idx(F, i, j)] - f[idx(F, i - di, j - dj)]) / h;
-    return (f[idx(F, i + di, j + dj)] - f[idx(F, i - di, j - dj)]) / (2.0 * h);
+    if (dir > 0) return (val(F, kind, f, rho, i + di, j + dj) - val(F, kind, f, rho, i, j)) / h;
+    if (dir < 0) return (val(F, kind, f, rho, i, j) - val(F, kind, f, rho, i - di, j - dj)) / h;
+    return (val(F, kind, f, rho, i + di, j + dj) - val(F, kind, f, rho, i - di, j - dj)) / (2.0 * h);
 }
 
 /* central second derivatives d^2 f / dx_a dx_b */
-static double d2(const or_fd* F, const double* f, int i, int j, int a, int b)
+static double d2(const or_fd* F, int kind, const double* f, const double* rho, int i, int j, int a, int b)
 {
     const double h = F->P.h;
     if (a == b) {
         const int di = a == 0, dj = a == 1;
-        return (f[idx(F, i + di, j + dj)] - 2.0 * f[idx(F, i, j)] + f[idx(F, i - di, j - dj)]) / (h * h);
+        return (val(F, kind, f, rho, i + di, j + dj) - 2.0 * val(F, kind, f, rho, i, j) +
+                val(F, kind, f, rho, i - di, j - dj)) / (h * h);
     }
-    return (f[idx(F, i + 1, j + 1)] - f[idx(F, i + 1, j - 1)] - f[idx(F, i - 1, j + 1)] + f[idx(F, i - 1, j - 1)]) /
-           (4.0 * h * h);
+    return (val(F, kind, f, rho, i + 1, j + 1) - val(F, kind, f, rho, i + 1, j - 1) -
+            val(F, kind, f, rho, i - 1, j + 1) + val(F, kind, f, rho, i - 1, j - 1)) / (4.0 * h * h);
 }
 
-static double lap(const or_fd* F, const double* f, int i, int j)
+static double lap(const or_fd* F, const double* f, const double* rho, int i, int j)
 {
-    return d2(F, f, i, j, 0, 0) + d2(F, f, i, j, 1, 1);
+    return d2(F, FD_PSI, f, rho, i, j, 0, 0) + d2(F, FD_PSI, f, rho, i, j, 1, 1);
 }
 
 /* right-hand sides of the mass and momentum equations at every node */
@@ -145,10 +172,10 @@ static void rhs(or_fd* F, const double* rho, const double* u, const double* v, i
             const int k = idx(F, i, j);
             const double r = rho[k], ux = u[k], uy = v[k];
             /* first derivatives, one-sided per stage */
-            const double rx = d1(F, rho, i, j, 0, dir), ry = d1(F, rho, i, j, 1, dir);
-            const double uxx1 = d1(F, u, i, j, 0, dir), uxy1 = d1(F, u, i, j, 1, dir);
-            const double vx1 = d1(F, v, i, j, 0, dir), vy1 = d1(F, v, i, j, 1, dir);
-            const double px = d1(F, F->p, i, j, 0, dir), py = d1(F, F->p, i, j, 1, dir);
+            const double rx = d1(F, FD_RHO, rho, rho, i, j, 0, dir), ry = d1(F, FD_RHO, rho, rho, i, j, 1, dir);
+            const double uxx1 = d1(F, FD_U, u, rho, i, j, 0, dir), uxy1 = d1(F, FD_U, u, rho, i, j, 1, dir);
+            const double vx1 = d1(F, FD_V, v, rho, i, j, 0, dir), vy1 = d1(F, FD_V, v, rho, i, j, 1, dir);
+            const double px = d1(F, FD_P, F->p, rho, i, j, 0, dir), py = d1(F, FD_P, F->p, rho, i, j, 1, dir);
             const double div = uxx1 + vy1;
             /* mass */
             F->dr[k] = -(r * div + ux * rx + uy * ry);
@@ -159,8 +186,10 @@ static void rhs(or_fd* F, const double* rho, const double* u, const double* v, i
             const double muB = r * cs2 * (P->tau_e - tn), dmuB = cs2 * (P->tau_e - tn) - r * cs2 * dtn;
             const double mux = dmu * rx, muy = dmu * ry, mBx = dmuB * rx, mBy = dmuB * ry;
             /* central second derivatives of the velocity */
-            const double u_xx = d2(F, u, i, j, 0, 0), u_yy = d2(F, u, i, j, 1, 1), u_xy = d2(F, u, i, j, 0, 1);
-            const double v_xx = d2(F, v, i, j, 0, 0), v_yy = d2(F, v, i, j, 1, 1), v_xy = d2(F, v, i, j, 0, 1);
+            const double u_xx = d2(F, FD_U, u, rho, i, j, 0, 0), u_yy = d2(F, FD_U, u, rho, i, j, 1, 1);
+            const double u_xy = d2(F, FD_U, u, rho, i, j, 0, 1);
+            const double v_xx = d2(F, FD_V, v, rho, i, j, 0, 0), v_yy = d2(F, FD_V, v, rho, i, j, 1, 1);
+            const double v_xy = d2(F, FD_V, v, rho, i, j, 0, 1);
             /* divergence of the viscous stress (Eq. FDstressTensor) */
             const double Sx = mux * (2.0 * uxx1) + muy * (vx1 + uxy1) + mu * (2.0 * u_xx + u_yy + v_xy) + mBx * div +
                               muB * (u_xx + v_xy);
@@ -169,11 +198,12 @@ static void rhs(or_fd* F, const double* rho, const double* u, const double* v, i
             /* divergence of the non-ideal pressure tensor (Eq. FDforce), central differences */
             const double* s = F->psi;
             const double ps = s[k];
-            const double sx = d1(F, s, i, j, 0, 0), sy = d1(F, s, i, j, 1, 0);
-            const double sxx = d2(F, s, i, j, 0, 0), syy = d2(F, s, i, j, 1, 1), sxy = d2(F, s, i, j, 0, 1);
+            const double sx = d1(F, FD_PSI, s, rho, i, j, 0, 0), sy = d1(F, FD_PSI, s, rho, i, j, 1, 0);
+            const double sxx = d2(F, FD_PSI, s, rho, i, j, 0, 0), syy = d2(F, FD_PSI, s, rho, i, j, 1, 1);
+            const double sxy = d2(F, FD_PSI, s, rho, i, j, 0, 1);
             const double L = sxx + syy;
-            const double Lx = (lap(F, s, i + 1, j) - lap(F, s, i - 1, j)) / (2.0 * P->h);
-            const double Ly = (lap(F, s, i, j + 1) - lap(F, s, i, j - 1)) / (2.0 * P->h);
+            const double Lx = (lap(F, s, rho, i + 1, j) - lap(F, s, rho, i - 1, j)) / (2.0 * P->h);
+            const double Ly = (lap(F, s, rho, i, j + 1) - lap(F, s, rho, i, j - 1)) / (2.0 * P->h);
             const double gx = sx * sxx + sy * sxy, gy = sx * sxy + sy * syy;  /* (d_g psi)(d_a d_g psi) */
             const double Px = -eps * G / 4.0 * gx + G / 12.0 * sx * L + G / 6.0 * gx + G / 4.0 * ps * Lx;
             const double Py = -eps * G / 4.0 * gy + G / 12.0 * sy * L + G / 6.0 * gy + G / 4.0 * ps * Ly;

@@ -106,13 +106,14 @@ void   or_matrix(double* M, double* Minv);
 
 /* Finite-difference reference solver (Appendix "Finite Difference Method"), fd_oracle.c */
 typedef struct {
-    int nx, ny;           /* doubly periodic mesh */
+    int nx, ny;           /* mesh nodes; periodic in x */
     int var_tau;          /* 1: tau_nu from Eq. RelaxationTime */
-    int pad_;
+    int walls;            /* 0: periodic in y; 1: wall layers of the appendix (bottom b1/b2, top on row ny-1) */
     double h, dt;         /* mesh spacing and time step, LBM units */
     double G, eps;        /* interaction constant; eps of the pressure tensor (Li: -16 G sigma; Guo: 0) */
     double tau_e, tau_nu; /* Eq. DynamicViscosity */
     double tau_l, tau_v, rho_v_tau, rho_l_tau;
+    double psi_wall;      /* psi_l of Eq. B2 (solid layer below the bottom wall) */
     or_eos eos;
 } or_fd_params;
 typedef struct or_fd or_fd;

@@ -64,10 +64,11 @@ class OrParams(C.Structure):
 
 class OrFdParams(C.Structure):
     _fields_ = [
-        ("nx", C.c_int), ("ny", C.c_int), ("var_tau", C.c_int), ("pad_", C.c_int),
+        ("nx", C.c_int), ("ny", C.c_int), ("var_tau", C.c_int), ("walls", C.c_int),
         ("h", C.c_double), ("dt", C.c_double), ("G", C.c_double), ("eps", C.c_double),
         ("tau_e", C.c_double), ("tau_nu", C.c_double),
         ("tau_l", C.c_double), ("tau_v", C.c_double), ("rho_v_tau", C.c_double), ("rho_l_tau", C.c_double),
+        ("psi_wall", C.c_double),
         ("eos", OrEos),
     ]
 
@@ -231,9 +232,13 @@ def make_params(nx, ny, eos: OrEos, G=-1.0, sigma=0.0, forcing=FORCING_LI, tau=N
 
 
 def make_fd_params(nx, ny, eos: OrEos, h=1.0, dt=0.2, G=-1.0, eps=0.0, tau_e=1.0, tau_nu=1.0, var_tau=False,
-                   tau_l=1.0, tau_v=1.0, rho_v_tau=None, rho_l_tau=None) -> OrFdParams:
+                   tau_l=1.0, tau_v=1.0, rho_v_tau=None, rho_l_tau=None, walls=False) -> OrFdParams:
+    """walls: the appendix's wall layers in y, with psi_l = psi(rho_l) of the EOS in Eq. B2."""
     P = OrFdParams()
-    P.nx, P.ny, P.var_tau = nx, ny, int(var_tau)
+    P.nx, P.ny, P.var_tau, P.walls = nx, ny, int(var_tau), int(walls)
+    if walls:
+        q = 2.0 * (eos_p(eos, eos.rho_l)[0] - eos.rho_l / 3.0) / G
+        P.psi_wall = float(np.sqrt(q)) if q > 0 else 0.0
     P.h, P.dt, P.G, P.eps, P.tau_e, P.tau_nu = h, dt, G, eps, tau_e, tau_nu
     P.tau_l, P.tau_v = tau_l, tau_v
     P.rho_v_tau = eos.rho_v if rho_v_tau is None else rho_v_tau
@@ -243,7 +248,7 @@ def make_fd_params(nx, ny, eos: OrEos, h=1.0, dt=0.2, G=-1.0, eps=0.0, tau_e=1.0
 
 
 class FdSolver:
-    """Finite-difference reference solver (MacCormack) on a doubly periodic mesh."""
+    """Finite-difference reference solver (MacCormack): periodic in x; in y periodic or the appendix wall layers."""
 
     def __init__(self, P: OrFdParams):
         self.P = P

@@ -1,5 +1,6 @@
 // liblbm.so: the finite-difference reference solver of the paper's appendix
-// ("Finite Difference Method"), doubly periodic, FP64.
+// ("Finite Difference Method"), FP64; periodic in x, in y periodic or with the
+// wall layers of the appendix's grid study.
 //
 // State: rho, u, v on an nx x ny mesh of spacing h (LBM units, c = 1,
 // c_s^2 = 1/3).  One time step is the MacCormack predictor-corrector
@@ -28,6 +29,7 @@
 struct lbm_fd_ctx {
     lbm_fd_params P;
     lbmk::DevEos eos;
+    double psi_wall;
     size_t n;
     double *rho, *u, *v, *rs, *us, *vs;
     unsigned* err;
@@ -39,7 +41,8 @@ namespace {
 using namespace lbmk;
 
 struct FdArgs {
-    int nx, ny, var_tau;
+    int nx, ny, var_tau, walls;
+    double psi_wall;      // psi_l of Eq. B2
     double h, inv_h, inv_2h, inv_h2, inv_4h2, dt, G, two_inv_G, eps;
     double tau_e, tau_nu, tau_v, tau_lo, tau_hi, dtau, rho_v_tau;
     DevEos eos;
@@ -52,39 +55,10 @@ __device__ __forceinline__ void fd_flag(const FdArgs& A)
     if (atomicCAS(A.err, 0u, 1u) == 0u) A.err[1] = (unsigned)A.step;
 }
 
-// periodic neighbour offsets of (i, j)
-struct Nb {
-    size_t c, xp, xm, yp, ym, xpyp, xpym, xmyp, xmym;
-};
-
-__device__ __forceinline__ Nb neighbours(const FdArgs& A, int i, int j)
+__device__ __forceinline__ double fd_psi(const FdArgs& A, double r)
 {
-    const int ip = i + 1 == A.nx ? 0 : i + 1, im = i == 0 ? A.nx - 1 : i - 1;
-    const int jp = j + 1 == A.ny ? 0 : j + 1, jm = j == 0 ? A.ny - 1 : j - 1;
-    const size_t nx = (size_t)A.nx;
-    Nb b;
-    b.c = j * nx + i;
-    b.xp = j * nx + ip;
-    b.xm = j * nx + im;
-    b.yp = jp * nx + i;
-    b.ym = jm * nx + i;
-    b.xpyp = jp * nx + ip;
-    b.xpym = jm * nx + ip;
-    b.xmyp = jp * nx + im;
-    b.xmym = jm * nx + im;
-    return b;
-}
-
-// one-sided first derivative along x or y: DIR = +1 forward, -1 backward
-template <int DIR>
-__device__ __forceinline__ double dx1(const FdArgs& A, const double* f, const Nb& b)
-{
-    return DIR > 0 ? (f[b.xp] - f[b.c]) * A.inv_h : (f[b.c] - f[b.xm]) * A.inv_h;
-}
-template <int DIR>
-__device__ __forceinline__ double dy1(const FdArgs& A, const double* f, const Nb& b)
-{
-    return DIR > 0 ? (f[b.yp] - f[b.c]) * A.inv_h : (f[b.c] - f[b.ym]) * A.inv_h;
+    const double q = (dev_eos_p(A.eos, r) - r * (1.0 / 3.0)) * A.two_inv_G;
+    return q > 0.0 ? sqrt(q) : 0.0;
 }
 
 constexpr int kTx = 32, kTy = 8, kHalo = 2;
@@ -103,27 +77,50 @@ __global__ __launch_bounds__(kTx * kTy) void k_fd_stage(FdArgs A, const double* 
     // p_EOS and psi (Eq. InteractionPotential) of the tile and its halo
     for (int q = tid; q < kLx * kLy; q += kTx * kTy) {
         const int ti = q % kLx, tj = q / kLx;
-        int gi = (i0 + ti - kHalo) % A.nx, gj = (j0 + tj - kHalo) % A.ny;
+        int gi = (i0 + ti - kHalo) % A.nx;
         gi = gi < 0 ? gi + A.nx : gi;
+        int gj = j0 + tj - kHalo;
+        if (A.walls && gj < 0) {
+            // b1 on the bottom wall (psi, rho extrapolated from rows 0 and 1), b2 inside it (Eq. B2)
+            const double r0 = rho[gi], r1 = rho[(size_t)A.nx + gi];
+            const double b1 = 2.0 * fd_psi(A, r0) - fd_psi(A, r1);
+            spe[tj][ti] = dev_eos_p(A.eos, 2.0 * r0 - r1);
+            spsi[tj][ti] = gj == -1 ? b1 : b1 + 2.0 * A.h * (A.psi_wall - b1);
+            continue;
+        }
+        if (A.walls && gj >= A.ny) gj = max(2 * (A.ny - 1) - gj, 0);  // reflexive top layers
+        gj %= A.ny;
         gj = gj < 0 ? gj + A.ny : gj;
         const double r = rho[(size_t)gj * A.nx + gi];
         const double pe = dev_eos_p(A.eos, r);
         const double qq = (pe - r * (1.0 / 3.0)) * A.two_inv_G;
-        if (!(r > 0.0) || !(qq >= 0.0)) fd_flag(A);
+        const int rj = j0 + tj - kHalo;
+        if ((!A.walls || (rj >= 0 && rj < A.ny)) && (!(r > 0.0) || !(qq >= 0.0))) fd_flag(A);
         spe[tj][ti] = pe;
         spsi[tj][ti] = qq > 0.0 ? sqrt(qq) : 0.0;
     }
     __syncthreads();
     const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
     if (i >= A.nx || j >= A.ny) return;
-    const Nb b = neighbours(A, i, j);
     const int li = threadIdx.x + kHalo, lj = threadIdx.y + kHalo;
+    // neighbours: periodic in x; in y periodic or the wall layers (b1 below row 0: u = v = 0 and rho
+    // extrapolated; above row ny-1 the mirror of row ny-2 with u, v reversed)
+    const bool wbot = A.walls && j == 0, wtop = A.walls && j == A.ny - 1;
+    const int ip = i + 1 == A.nx ? 0 : i + 1, im = i == 0 ? A.nx - 1 : i - 1;
+    const int jp = wtop ? A.ny - 2 : (j + 1 == A.ny ? 0 : j + 1), jm = wbot ? 0 : (j == 0 ? A.ny - 1 : j - 1);
+    const double fm = wbot ? 0.0 : 1.0, fp = wtop ? -1.0 : 1.0;
+    const size_t nxs = (size_t)A.nx;
+    const size_t c = j * nxs + i, xp = j * nxs + ip, xm = j * nxs + im, yp = jp * nxs + i, ym = jm * nxs + i;
+    const size_t pp = jp * nxs + ip, pm = jm * nxs + ip, mp = jp * nxs + im, mm = jm * nxs + im;
     const double cs2 = 1.0 / 3.0;
-    const double r = rho[b.c], ux = u[b.c], uy = v[b.c];
+    const double r = rho[c], ux = u[c], uy = v[c];
+    const double r_yp = rho[yp], r_ym = wbot ? 2.0 * r - rho[nxs + i] : rho[ym];
+    const double u_yp = fp * u[yp], u_ym = fm * u[ym], v_yp = fp * v[yp], v_ym = fm * v[ym];
     // one-sided first derivatives
-    const double rx = dx1<DIR>(A, rho, b), ry = dy1<DIR>(A, rho, b);
-    const double u_x = dx1<DIR>(A, u, b), u_y = dy1<DIR>(A, u, b);
-    const double v_x = dx1<DIR>(A, v, b), v_y = dy1<DIR>(A, v, b);
+    const double rx = (DIR > 0 ? rho[xp] - r : r - rho[xm]) * A.inv_h;
+    const double ry = (DIR > 0 ? r_yp - r : r - r_ym) * A.inv_h;
+    const double u_x = (DIR > 0 ? u[xp] - ux : ux - u[xm]) * A.inv_h, u_y = (DIR > 0 ? u_yp - ux : ux - u_ym) * A.inv_h;
+    const double v_x = (DIR > 0 ? v[xp] - uy : uy - v[xm]) * A.inv_h, v_y = (DIR > 0 ? v_yp - uy : uy - v_ym) * A.inv_h;
     const double px = (DIR > 0 ? spe[lj][li + 1] - spe[lj][li] : spe[lj][li] - spe[lj][li - 1]) * A.inv_h;
     const double py = (DIR > 0 ? spe[lj + 1][li] - spe[lj][li] : spe[lj][li] - spe[lj - 1][li]) * A.inv_h;
     const double div = u_x + v_y;
@@ -140,11 +137,10 @@ __global__ __launch_bounds__(kTx * kTy) void k_fd_stage(FdArgs A, const double* 
     const double muB = r * cs2 * (A.tau_e - tn), dmuB = cs2 * (A.tau_e - tn) - r * cs2 * dtn;
     const double mux = dmu * rx, muy = dmu * ry, mBx = dmuB * rx, mBy = dmuB * ry;
     // central second derivatives of the velocity
-    const double uc = u[b.c], vc = v[b.c];
-    const double u_xx = (u[b.xp] - 2.0 * uc + u[b.xm]) * A.inv_h2, u_yy = (u[b.yp] - 2.0 * uc + u[b.ym]) * A.inv_h2;
-    const double v_xx = (v[b.xp] - 2.0 * vc + v[b.xm]) * A.inv_h2, v_yy = (v[b.yp] - 2.0 * vc + v[b.ym]) * A.inv_h2;
-    const double u_xy = (u[b.xpyp] - u[b.xpym] - u[b.xmyp] + u[b.xmym]) * A.inv_4h2;
-    const double v_xy = (v[b.xpyp] - v[b.xpym] - v[b.xmyp] + v[b.xmym]) * A.inv_4h2;
+    const double u_xx = (u[xp] - 2.0 * ux + u[xm]) * A.inv_h2, u_yy = (u_yp - 2.0 * ux + u_ym) * A.inv_h2;
+    const double v_xx = (v[xp] - 2.0 * uy + v[xm]) * A.inv_h2, v_yy = (v_yp - 2.0 * uy + v_ym) * A.inv_h2;
+    const double u_xy = (fp * u[pp] - fm * u[pm] - fp * u[mp] + fm * u[mm]) * A.inv_4h2;
+    const double v_xy = (fp * v[pp] - fm * v[pm] - fp * v[mp] + fm * v[mm]) * A.inv_4h2;
     // divergence of the viscous stress (Eq. FDstressTensor)
     const double Sx = mux * (2.0 * u_x) + muy * (v_x + u_y) + mu * (2.0 * u_xx + u_yy + v_xy) + mBx * div +
                       muB * (u_xx + v_xy);
@@ -174,13 +170,13 @@ __global__ __launch_bounds__(kTx * kTy) void k_fd_stage(FdArgs A, const double* 
     const double dv = -(ux * v_x + uy * v_y) + (Sy - py - Py) * inv_r;
     const double nr = r + A.dt * dr, nu = ux + A.dt * du, nv = uy + A.dt * dv;
     if (base_r) {
-        o_r[b.c] = wa * base_r[b.c] + wb * nr;
-        o_u[b.c] = wa * base_u[b.c] + wb * nu;
-        o_v[b.c] = wa * base_v[b.c] + wb * nv;
+        o_r[c] = wa * base_r[c] + wb * nr;
+        o_u[c] = wa * base_u[c] + wb * nu;
+        o_v[c] = wa * base_v[c] + wb * nv;
     } else {
-        o_r[b.c] = nr;
-        o_u[b.c] = nu;
-        o_v[b.c] = nv;
+        o_r[c] = nr;
+        o_u[c] = nu;
+        o_v[c] = nv;
     }
 }
 
@@ -192,6 +188,8 @@ FdArgs fd_args(const lbm_fd_ctx* c)
     A.nx = P.nx;
     A.ny = P.ny;
     A.var_tau = P.var_tau;
+    A.walls = P.walls;
+    A.psi_wall = c->psi_wall;
     A.h = P.h;
     A.inv_h = 1.0 / P.h;
     A.inv_2h = 0.5 / P.h;
@@ -258,6 +256,10 @@ int lbm_fd_init(lbm_fd_ctx** out, const lbm_fd_params* p, void* buf, size_t buf_
     if (!c) return LBM_EINVAL;
     c->P = *p;
     c->eos = dev_eos(p->eos);
+    {
+        const double q = 2.0 * (lbm_eos_pressure(&p->eos, p->eos.rho_l) - p->eos.rho_l / 3.0) / p->G;
+        c->psi_wall = q > 0.0 ? std::sqrt(q) : 0.0;  // psi_l of Eq. B2
+    }
     c->n = (size_t)p->nx * p->ny;
     char* b = (char*)buf;
     c->err = (unsigned*)b;

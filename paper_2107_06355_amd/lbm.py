@@ -56,7 +56,7 @@ class LbmParams(C.Structure):
 
 class LbmFdParams(C.Structure):
     _fields_ = [
-        ("nx", C.c_int), ("ny", C.c_int), ("var_tau", C.c_int), ("pad_", C.c_int),
+        ("nx", C.c_int), ("ny", C.c_int), ("var_tau", C.c_int), ("walls", C.c_int),
         ("h", C.c_double), ("dt", C.c_double), ("G", C.c_double), ("eps", C.c_double),
         ("tau_e", C.c_double), ("tau_nu", C.c_double),
         ("tau_l", C.c_double), ("tau_v", C.c_double), ("rho_v_tau", C.c_double), ("rho_l_tau", C.c_double),
@@ -410,9 +410,9 @@ class Batch:
 
 # ---------------------------------------------------------------------------- finite-difference reference solver
 def make_fd_params(nx, ny, eos: LbmEos, h=1.0, dt=0.2, G=-1.0, eps=0.0, tau_e=1.0, tau_nu=1.0, var_tau=False,
-                   tau_l=1.0, tau_v=1.0, rho_v_tau=None, rho_l_tau=None) -> LbmFdParams:
+                   tau_l=1.0, tau_v=1.0, rho_v_tau=None, rho_l_tau=None, walls=False) -> LbmFdParams:
     P = LbmFdParams()
-    P.nx, P.ny, P.var_tau = nx, ny, int(var_tau)
+    P.nx, P.ny, P.var_tau, P.walls = nx, ny, int(var_tau), int(walls)
     P.h, P.dt, P.G, P.eps, P.tau_e, P.tau_nu = h, dt, G, eps, tau_e, tau_nu
     P.tau_l, P.tau_v = tau_l, tau_v
     P.rho_v_tau = eos.rho_v if rho_v_tau is None else rho_v_tau

@@ -386,3 +386,54 @@ def test_fd_oracle_planar_second_order_toward_maxwell():
         E.append((r[0, 0] - e.rho_v) / e.rho_v)
     assert -0.03 < E[0] < -0.015
     assert 3.6 < E[0] / E[1] < 4.6
+
+
+def test_fd_oracle_wall_layers_shear_mode_exact_decay():
+    """Appendix wall layers: u = 0 on b1 (one node below row 0) and the reflexive top about row
+    ny-1 make sin(pi (j+1)/ny) an exact discrete eigenmode of the central second difference, so it
+    decays by (1 - l dt + (l dt)^2/2)^n with l = nu (2 sin(k h/2)/h)^2, k = pi/(ny h)."""
+    e, _ = cs_eos(0.7)
+    nx, ny, h, dt, tau, n, A = 4, 32, 1.0, 0.2, 0.8, 600, 1e-4
+    j = np.arange(ny)
+    mode = np.sin(np.pi * (j + 1) / ny)
+    F = O.FdSolver(O.make_fd_params(nx, ny, e, h=h, dt=dt, tau_nu=tau, walls=True))
+    F.set(np.full((ny, nx), e.rho_l), np.repeat((A * mode)[:, None], nx, axis=1))
+    F.run(n)
+    r, u, v = F.get()
+    amp = (u[:, 0] * mode).sum() / (mode * mode).sum()
+    k = np.pi / (ny * h)
+    lam = (tau - 0.5) / 3 * (2 / h * math.sin(k * h / 2)) ** 2
+    assert amp / A == pytest.approx((1 - lam * dt + (lam * dt) ** 2 / 2) ** n, rel=1e-11)
+    assert np.abs(r - e.rho_l).max() < 1e-15 and np.abs(v).max() < 1e-18
+
+
+def test_fd_oracle_wall_solid_layer_one_step_closed_form():
+    """Uniform vapor at rest between the wall layers, psi_l = psi(rho_l) in Eq. B2: only the b2 layer
+    differs from psi_v, so at t = 0 the one nonzero right-hand side is Eq. FDforce at row 0,
+    P_y = (G/4) psi_v d_y(lap psi) = -G psi_v (psi_l - psi_v) / (4 h^2).  The predictor then gives
+    v* = w = -dt P_y / rho_v on row 0; the corrector (backward first differences, v = 0 on b1, central
+    v_yy) moves mass between rows 0 and 1 and diffuses w.  Worked out by hand for one step."""
+    e, _ = cs_eos(0.7)
+    nx, ny, h, dt, te, tn, G = 5, 12, 1.0, 0.1, 1.1, 0.8, -1.0
+    F = O.FdSolver(O.make_fd_params(nx, ny, e, h=h, dt=dt, G=G, tau_e=te, tau_nu=tn, walls=True))
+    rv = e.rho_v
+    F.set(np.full((ny, nx), rv))
+    F.run(1)
+    r, u, v = F.get()
+    psi = lambda x: math.sqrt(2 * (O.eos_p(e, x)[0] - x / 3) / G)
+    ps_v, ps_l = psi(rv), psi(e.rho_l)
+    Py = -G * ps_v * (ps_l - ps_v) / (4 * h * h)
+    w = -dt * Py / rv
+    mu, muB = rv / 3 * (tn - 0.5), rv / 3 * (te - tn)
+    Sy0 = (2 * mu + muB) * (-2 * w / h**2)
+    Sy1 = (2 * mu + muB) * (w / h**2)
+    r_want = np.full(ny, rv)
+    r_want[0] = rv - dt * rv * w / (2 * h)
+    r_want[1] = rv + dt * rv * w / (2 * h)
+    v_want = np.zeros(ny)
+    v_want[0] = (w + dt * (-w * w / h + (Sy0 - Py) / rv)) / 2
+    v_want[1] = dt * Sy1 / rv / 2
+    assert w < 0  # with G < 0 a solid of psi_l > psi_v attracts the vapor (v points into the wall)
+    np.testing.assert_allclose(r, np.repeat(r_want[:, None], nx, axis=1), rtol=1e-14, atol=0)
+    np.testing.assert_allclose(v, np.repeat(v_want[:, None], nx, axis=1), rtol=1e-12, atol=1e-20)
+    assert np.abs(u).max() == 0.0
