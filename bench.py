@@ -30,6 +30,8 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + HBM GB/s (%roofline), FP32-shifted vs FP64 D2Q9; adjoint/fwd time"
 # algorithmic bytes per cell update: 8 moving populations read + written, rest population FP64 read + written
 BYTES = {"fp32": 8 * 4 * 2 + 8 * 2, "fp64": 9 * 8 * 2}
+# step kernel of each decomposition (lbm_variant): row march, row block, two-step block
+KERNEL_NAME = {1: "k_step<%s, 0>", 2: "k_step_blk<%s, 0>", 3: "k_step2_blk<%s>"}
 
 EOS_KW = dict(base=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
 TAU = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]
@@ -383,14 +385,14 @@ def main():
         ksec, _ = time_steps(L, args.steps, args.warmup)
         L.check()
         cells = n * n
+        spl = 2 if var == lbm.VARIANT_BLOCK2 else 1  # time steps per launch of the step kernel
         mlups = cells * args.steps / sec / 1e6
         kgbs = BYTES[prec] * cells * args.steps / ksec / 1e9
         res[prec] = {"MLUPS": mlups, "GB/s_step": BYTES[prec] * cells * args.steps / sec / 1e9,
                      "ms_per_step": sec * 1e3 / args.steps, "wall_s": wall,
                      "kernel_GB/s": kgbs, "frac_hbm_peak": kgbs / HBM_PEAK_GBS,
-                     "avg_launch_us": ksec * 1e6 / args.steps,
-                     "kernel": ("k_step_blk<%s, 0>" if var == lbm.VARIANT_BLOCK else "k_step<%s, 0>")
-                               % ("float" if prec == "fp32" else "double"),
+                     "avg_launch_us": ksec * 1e6 / (args.steps / spl), "steps_per_launch": spl,
+                     "kernel": KERNEL_NAME[var] % ("float" if prec == "fp32" else "double"),
                      "rows_per_block": rows, "waves": waves}
         print("# %s %dx%d: %.1f MLUPS (%.2f us/step with reductions); step kernel %.2f us = %.1f GB/s "
               "algorithmic (%.1f%% of 8 TB/s)" % (prec, n, n, mlups, sec * 1e6 / args.steps, ksec * 1e6 / args.steps,
@@ -444,8 +446,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": r["kernel_GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["kernel_GB/s"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic(r["kernel"], n, main_prec),
-                     "kernel": r["kernel"], "bytes_per_cell": BYTES[main_prec], "cells_per_launch": n * n,
-                     "avg_launch_us": r["avg_launch_us"],
+                     "kernel": r["kernel"], "bytes_per_cell": BYTES[main_prec],
+                     "cell_updates_per_launch": n * n * r["steps_per_launch"],
+                     "steps_per_launch": r["steps_per_launch"], "avg_launch_us": r["avg_launch_us"],
                      "copy_ceiling_frac": r["kernel_GB/s"] / calib["GB/s"]},
         "fp64": res.get("fp64"),
         "fp32": res.get("fp32"),

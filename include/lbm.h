@@ -48,11 +48,20 @@ typedef enum {
 } lbm_status;
 
 typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_prec;
-/* Step-kernel decompositions (identical results up to FP rounding order):
- * ROW_MARCH: one wavefront marches up a band of rows of a 62-column strip
- * with two rows of loads in flight; ROW_BLOCK: a 16-wavefront workgroup loads
- * 16 rows of a strip, one per wavefront, and shares psi through LDS. */
-typedef enum { LBM_VARIANT_AUTO = 0, LBM_VARIANT_MARCH = 1, LBM_VARIANT_BLOCK = 2 } lbm_variant;
+/* Step-kernel decompositions (identical node arithmetic; results agree up to
+ * the compiler's FMA contraction choices):
+ * MARCH: one wavefront marches up a band of rows of a 62-column strip with
+ * two rows of loads in flight; BLOCK: a 12-wavefront workgroup loads 12 rows
+ * of a strip, one per wavefront, and shares psi through LDS; BLOCK2 (periodic
+ * lattices only): a 16-wavefront workgroup advances a 58 x 10 tile by two
+ * time steps per launch and keeps the intermediate populations in LDS
+ * (temporal blocking; a step that reduces or checkpoints runs alone). */
+typedef enum {
+    LBM_VARIANT_AUTO = 0,
+    LBM_VARIANT_MARCH = 1,
+    LBM_VARIANT_BLOCK = 2,
+    LBM_VARIANT_BLOCK2 = 3
+} lbm_variant;
 typedef enum { LBM_BASE_CS = 0, LBM_BASE_PR = 1 } lbm_base;
 typedef enum {
     LBM_SHAPE_NONE = 0,      /* the base EOS itself */

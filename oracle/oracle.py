@@ -121,6 +121,8 @@ def lib():
         L.or_get_f.argtypes = [p, dp]
         L.or_run.argtypes = [p, C.c_longlong]
         L.or_run.restype = i
+        L.or_run_window.argtypes = [p, C.c_longlong]
+        L.or_run_window.restype = i
         L.or_fail_step.argtypes = [p]
         L.or_fail_step.restype = C.c_longlong
         L.or_macros.argtypes = [p, dp, dp, dp, dp, dp, dp, dp]
@@ -317,6 +319,12 @@ class Lattice:
         st = lib().or_run(self._h, int(nsteps))
         if st != OR_OK:
             raise OracleError("oracle run unstable at step %d" % lib().or_fail_step(self._h))
+        self.step += int(nsteps)
+
+    def run_window(self, nsteps: int) -> None:
+        """Steps of a periodic window cut from a larger lattice: nodes the cut makes unphysical
+        get NaN psi instead of stopping the run; NaN then spreads two nodes per step at most."""
+        lib().or_run_window(self._h, int(nsteps))
         self.step += int(nsteps)
 
     def macros(self) -> dict:

@@ -20,6 +20,7 @@ struct lbm_ctx {
     double* red;
     int64_t hist_count;
     int grid;
+    int blk2, grid2;  // LBM_VARIANT_BLOCK2: two-step launches and their grid
     // checkpoints for the adjoint: the state f*(t) at every t = K*slot
     void* ckpt;
     int64_t ckpt_slots;
@@ -32,4 +33,5 @@ bool hip_ok(hipError_t e, const char* what);
 bool launch_reduce(lbm_ctx* c, double* out, long long step, int with_step, hipStream_t s);
 bool launch_record_step(lbm_ctx* c, void* rec, hipStream_t s);
 int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk);
+int resolve_variant(const lbm_params& p);
 }  // namespace lbmk

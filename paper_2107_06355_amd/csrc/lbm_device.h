@@ -249,10 +249,10 @@ __device__ __forceinline__ double node_drho(double g0, const T g[9])
            (((double)g[5] + (double)g[6]) + ((double)g[7] + (double)g[8]));
 }
 
-__device__ __forceinline__ void flag_unstable(const StepArgs& A)
+__device__ __forceinline__ void flag_unstable(const StepArgs& A, int dstep = 0)
 {
     atomicOr(A.err, 1u);
-    atomicMin(A.err + 1, (unsigned)A.step);
+    atomicMin(A.err + 1, (unsigned)(A.step + dstep));
 }
 
 // base EOS in FP32 (bulk branches of the FP32 path)
@@ -286,7 +286,7 @@ __device__ __forceinline__ float dev_base_dpf(const DevEos& E, float r)
 // FP64 path: everything in FP64.  FP32 path: the bulk vapor/liquid branches in
 // FP32, the shaped loop between rho_v and rho_l (the branch junctions) in FP64.
 template <typename T>
-__device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check)
+__device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check, int dstep = 0)
 {
     const double rho = A.rho_ref + drho;
     const DevEos& E = A.eos;
@@ -295,12 +295,12 @@ __device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check
         const float pb = dev_base_pf(E, r);
         const float p = rho <= E.rho_v ? (float)E.k_vap * pb : pb + (float)E.dP;
         const float q = (p - r * (1.0f / 3.0f)) * A.cf.two_inv_G;
-        if (check && !(q >= 0.0f && r > 0.0f)) flag_unstable(A);
+        if (check && !(q >= 0.0f && r > 0.0f)) flag_unstable(A, dstep);
         return (T)(q > 0.0f ? sqrtf(q) : 0.0f);
     }
     const double p = dev_eos_p(E, rho);
     const double q = (p - rho * (1.0 / 3.0)) * A.cd.two_inv_G;
-    if (check && !(q >= 0.0 && rho > 0.0)) flag_unstable(A);
+    if (check && !(q >= 0.0 && rho > 0.0)) flag_unstable(A, dstep);
     if (sizeof(T) == 4) return (T)(q > 0.0 ? sqrtf((float)q) : 0.0f);
     return (T)(q > 0.0 ? sqrt(q) : 0.0);
 }
@@ -338,8 +338,8 @@ __device__ __forceinline__ int load_index(const StepArgs& A, int r)
 // the Eq. LiFS source, inverse transform and store (or the macroscopic outputs).
 // psB = psi(x, y); Ftx, Fty = F~ = F/psi(x) from Eq. ShanChenForce.
 template <typename T, int MODE>
-__device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, int y, const Row<T>& P, double drp,
-                                            T psB, T Ftx, T Fty, Acc& acc)
+__device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, int y, const Row<T>& P, double drp,
+                                             T psB, T Ftx, T Fty, Acc& acc, T o[9], double& o0)
 {
     const T* gp = P.g;
     const int x = L.x;
@@ -387,7 +387,7 @@ __device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, in
         acc.x += (double)rho * (double)ux;
         acc.y += (double)rho * (double)uy;
     }
-    if (MODE == MODE_MACROS) return;
+    if (MODE == MODE_MACROS) return false;
     // rates (Eq. RelaxationMatrix; Eq. RelaxationTime on the shear moments)
     const Coef<T>& K = coef<T>(A);
     const T se = K.se, sq = K.sq, sqx = K.sqx, sqy = K.sqy;
@@ -422,7 +422,6 @@ __device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, in
     // f* = M^-1 m* = M^T diag(1/9,1/36,1/36,1/6,1/12,1/6,1/12,1/4,1/4) m*
     const T a14 = n0 - ne - 2 * nq;
     const T a58 = n0 + 2 * ne + nq;
-    T o[9];
     o[1] = a14 + njx - 2 * nqx + nxx;
     o[2] = a14 + njy - 2 * nqy - nxx;
     o[3] = a14 - njx + 2 * nqx + nxx;
@@ -431,13 +430,24 @@ __device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, in
     o[6] = a58 - njx - nqx + njy + nqy - nxy;
     o[7] = a58 - njx - nqx - njy - nqy + nxy;
     o[8] = a58 + njx + nqx - njy - nqy - nxy;
+    // rest population: exact node mass in FP64 (conserved by the collision)
+    o0 = drp - ((((double)o[1] + (double)o[2]) + ((double)o[3] + (double)o[4])) +
+                (((double)o[5] + (double)o[6]) + ((double)o[7] + (double)o[8])));
+    return true;
+}
+
+// node_collide, then the store of f* at (x, y) of the destination buffer
+template <typename T, int MODE>
+__device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, int y, const Row<T>& P, double drp,
+                                            T psB, T Ftx, T Fty, Acc& acc)
+{
+    T o[9];
+    double o0;
+    if (!node_collide<T, MODE>(A, L, y, P, drp, psB, Ftx, Fty, acc, o, o0)) return;
     const WView<T> D = make_wview<T>(A.dst, A.plane);
-    const uint32_t off = (uint32_t)y * (uint32_t)A.ld + (uint32_t)x;
+    const uint32_t off = (uint32_t)y * (uint32_t)A.ld + (uint32_t)L.x;
 #pragma unroll
     for (int i = 1; i < 9; ++i) *(T*)(D.mv[i] + off * (uint32_t)sizeof(T)) = o[i];
-    // rest population: exact node mass in FP64 (conserved by the collision)
-    const double o0 = drp - ((((double)o[1] + (double)o[2]) + ((double)o[3] + (double)o[4])) +
-                             (((double)o[5] + (double)o[6]) + ((double)o[7] + (double)o[8])));
     *(double*)(D.rest + off * 8u) = o0;
 }
 
@@ -550,8 +560,12 @@ inline int validate(const lbm_params* p)
             lbm_set_error("lbm: every relaxation time must exceed 1/2");
             return LBM_EINVAL;
         }
-    if (p->kernel_variant < 0 || p->kernel_variant > LBM_VARIANT_BLOCK) {
-        lbm_set_error("lbm: kernel_variant must be 0 (automatic), 1 (row march) or 2 (row block)");
+    if (p->kernel_variant < 0 || p->kernel_variant > LBM_VARIANT_BLOCK2) {
+        lbm_set_error("lbm: kernel_variant must be 0 (automatic), 1 (row march), 2 (row block) or 3 (two-step block)");
+        return LBM_EINVAL;
+    }
+    if (p->kernel_variant == LBM_VARIANT_BLOCK2 && p->walls) {
+        lbm_set_error("lbm: the two-step block kernel covers periodic lattices only (walls = 0)");
         return LBM_EINVAL;
     }
     if (p->band_rows < 0 || p->band_rows > 4096) {

@@ -208,6 +208,110 @@ __global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
     }
 }
 
+// Two time steps per launch (temporal blocking), periodic lattices.  A
+// workgroup of 16 waves owns an output tile of 10 rows x 58 columns; wave k
+// holds row y0-3+k and lane l column x0-3+l in every phase, so the tile grown
+// by d nodes is the set of (wave, lane) pairs at distance <= d from it:
+//   1. pull step t from the source buffer on the tile grown by 3; rho, psi(t) -> LDS
+//   2. collide step t on the tile grown by 2 (psi of the 3x3 stencil from LDS);
+//      the post-collision populations go to LDS in their storage format
+//   3. pull step t+1 from LDS on the tile grown by 1; rho, psi(t+1) -> LDS
+//   4. collide step t+1 on the tile and store to the destination buffer.
+// Every node runs the arithmetic of the one-step kernels, and LDS holds the
+// intermediate state exactly as global memory would (FP32 deviations, FP64
+// rest population), so one launch equals two one-step launches.  Memory
+// traffic per output node is one population read (plus the 3-node ring) and
+// one write per two steps.
+constexpr int k2Waves = 16, k2Rows = k2Waves - 6, k2Cols = 64 - 6;
+
+// FP32: 8 waves per SIMD, two workgroups per CU (the compiler spills scalar registers
+// to vector lanes to fit).  FP64: the compiler's choice (77 VGPRs, one workgroup per
+// CU); forcing two workgroups spills vector registers to scratch and measured 25%
+// slower on MI355X at 4096^2.
+template <typename T>
+__global__ __launch_bounds__(64 * k2Waves) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4)))
+void k_step2_blk(StepArgs A)
+{
+    __shared__ T sps[k2Waves][64];
+    __shared__ T smv[8][k2Waves - 2][64];
+    __shared__ double sg0[k2Waves - 2][64];
+    const int strips = (A.nx + k2Cols - 1) / k2Cols, bands = (A.ny + k2Rows - 1) / k2Rows;
+    const int nb = gridDim.x;
+    const int logical = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);  // XCD-contiguous blocks
+    if (logical >= strips * bands) return;  // whole workgroup leaves together
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    const int strip = logical % strips, band = logical / strips;
+    const int x0 = strip * k2Cols, y0 = band * k2Rows;
+    const int W = min(k2Cols, A.nx - x0), H = min(k2Rows, A.ny - y0);
+    // distance of this lane's column and this wave's row from the output tile
+    const int dl = l < 3 ? 3 - l : (l > W + 2 ? l - (W + 2) : 0);
+    const int dk = k < 3 ? 3 - k : (k > H + 2 ? k - (H + 2) : 0);
+    const int d = max(dl, dk);
+    Lane L;
+    L.lane = l;
+    L.valid = d <= 3;
+    L.interior = d == 0;
+    int x = ((x0 - 3 + l) % A.nx + A.nx) % A.nx;
+    if (dl > 3) x = 0;
+    L.x = x;
+    L.xm = x == 0 ? A.nx - 1 : x - 1;
+    L.xp = x == A.nx - 1 ? 0 : x + 1;
+    const int r = y0 - 3 + k;  // unwrapped row; in [0, ny) on the output tile
+    const int rw = (r % A.ny + A.ny) % A.ny;
+    Acc acc = {0.0, 0.0, 0.0};
+
+    // 1. step t: pull, rho, psi
+    Row<T> R;
+    double dr = 0.0;
+    T ps = (T)0;
+    if (dk <= 3 && dl <= 3) {
+        const View<T> V = make_view<T>(A.src, A.plane);
+        pull<T>(V, A, L.x, L.xm, L.xp, rw, R.g0, R.g);
+        dr = node_drho<T>(R.g0, R.g);
+        ps = node_psi<T>(A, dr, true);
+    }
+    sps[k][l] = ps;
+    __syncthreads();
+    // 2. step t: collide on the tile grown by 2, post-collision state to LDS
+    if (dk <= 2 && dl <= 2) {
+        T Ftx, Fty;
+        force_tilde<T>(A, sps[k - 1][l - 1], sps[k - 1][l], sps[k - 1][l + 1], sps[k][l - 1], sps[k][l + 1],
+                       sps[k + 1][l - 1], sps[k + 1][l], sps[k + 1][l + 1], Ftx, Fty);
+        T o[9];
+        double o0;
+        node_collide<T, MODE_STEP>(A, L, rw, R, dr, ps, Ftx, Fty, acc, o, o0);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) smv[i - 1][k - 1][l] = o[i];
+        sg0[k - 1][l] = o0;
+    }
+    __syncthreads();
+    // 3. step t+1: pull from LDS on the tile grown by 1 (f_i(x) = f*_i(x - c_i)), psi(t+1)
+    if (dk <= 1 && dl <= 1) {
+        const int q = k - 1;  // LDS row of this wave
+        R.g0 = sg0[q][l];
+        R.g[1] = smv[0][q][l - 1];
+        R.g[3] = smv[2][q][l + 1];
+        R.g[2] = smv[1][q - 1][l];
+        R.g[5] = smv[4][q - 1][l - 1];
+        R.g[6] = smv[5][q - 1][l + 1];
+        R.g[4] = smv[3][q + 1][l];
+        R.g[7] = smv[6][q + 1][l + 1];
+        R.g[8] = smv[7][q + 1][l - 1];
+        dr = node_drho<T>(R.g0, R.g);
+        ps = node_psi<T>(A, dr, true, 1);
+        sps[k][l] = ps;
+    }
+    __syncthreads();
+    // 4. step t+1: collide on the tile and store
+    if (d == 0) {
+        T Ftx, Fty;
+        force_tilde<T>(A, sps[k - 1][l - 1], sps[k - 1][l], sps[k - 1][l + 1], sps[k][l - 1], sps[k][l + 1],
+                       sps[k + 1][l - 1], sps[k + 1][l], sps[k + 1][l + 1], Ftx, Fty);
+        update_node<T, MODE_STEP>(A, L, r, R, dr, ps, Ftx, Fty, acc);
+    }
+}
+
 // Fixed-order FP64 reduction of the per-wave partials, two passes: block b sums
 // the contiguous chunk b of the partials (thread-strided, then a tree), and one
 // block sums the block results.  The order depends only on the sizes, so the
@@ -325,18 +429,29 @@ bool hip_ok(hipError_t e, const char* what)
 // Work decomposition.  Returns the number of waves (partial-sum slots).
 // Row-march kernel: one wave per (strip, band of seg_h rows).  Row-block
 // kernel: one 16-wave workgroup per (strip, band of 14 rows).
-int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk)
+int resolve_variant(const lbm_params& p)
 {
-    *strips = (p.nx + kStripW - 1) / kStripW;
     int v = p.kernel_variant;
-    if (v == 0) {
+    if (v == 0 && !p.walls) {
+        // measured on MI355X, 512^2 .. 4096^2 in both precisions: two steps per launch
+        // beat every one-step decomposition on periodic lattices
+        v = LBM_VARIANT_BLOCK2;
+    } else if (v == 0) {
         // measured on MI355X: the row block wins while the lattice is cache-resident or
         // the step is FP64; large FP32 lattices prefer the row march (4-row bands)
         const long long cells = (long long)p.nx * p.ny;
         const long long limit = p.prec == LBM_FP32_SHIFTED ? (5LL << 20) : (40LL << 20);
         v = cells <= limit ? LBM_VARIANT_BLOCK : LBM_VARIANT_MARCH;
     }
-    *blk = v == LBM_VARIANT_BLOCK;
+    return v;
+}
+
+int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk)
+{
+    *strips = (p.nx + kStripW - 1) / kStripW;
+    const int v = resolve_variant(p);
+    // BLOCK2 runs its single steps (reductions, checkpoints, odd counts) on the row block
+    *blk = v == LBM_VARIANT_BLOCK || v == LBM_VARIANT_BLOCK2;
     if (*blk) {
         *seg_h = kBlkRows;
         *nseg = (p.ny + kBlkRows - 1) / kBlkRows;
@@ -395,6 +510,9 @@ void fill_args(lbm_ctx* c)
     A.err = c->err;
     const int blocks = A.blk ? A.nwork / kBlkWaves : (A.nwork + kWaves - 1) / kWaves;
     c->grid = (blocks + 7) & ~7;
+    c->blk2 = resolve_variant(p) == LBM_VARIANT_BLOCK2;
+    const int blocks2 = ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + k2Rows - 1) / k2Rows);
+    c->grid2 = (blocks2 + 7) & ~7;
 }
 
 bool launch_reduce(lbm_ctx* c, double* out, long long step, int with_step, hipStream_t s)
@@ -434,6 +552,18 @@ bool launch_record_step(lbm_ctx* c, void* rec, hipStream_t s)
     else
         hipLaunchKernelGGL((k_step_blk<double, MODE_RECORD>), dim3(grid), dim3(64 * kBlkWaves), 0, s, A);
     return hip_ok(hipGetLastError(), "k_step_blk(record) launch");
+}
+
+// two steps in one launch (LBM_VARIANT_BLOCK2): source buf[cur], result in buf[cur ^ 1]
+template <typename T>
+bool launch_step2(lbm_ctx* c, hipStream_t s)
+{
+    StepArgs A = c->args;
+    A.src = c->buf[c->cur];
+    A.dst = c->buf[c->cur ^ 1];
+    A.step = c->step;
+    hipLaunchKernelGGL(k_step2_blk<T>, dim3(c->grid2), dim3(64 * k2Waves), 0, s, A);
+    return hip_ok(hipGetLastError(), "k_step2_blk launch");
 }
 
 template <typename T>
@@ -501,7 +631,7 @@ int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int*
     }
     int strips, seg_h, nseg, blk;
     const int nw = decompose(*p, &strips, &seg_h, &nseg, &blk);
-    if (variant_out) *variant_out = blk ? LBM_VARIANT_BLOCK : LBM_VARIANT_MARCH;
+    if (variant_out) *variant_out = resolve_variant(*p);
     if (band_rows_out) *band_rows_out = seg_h;
     if (waves_out) *waves_out = nw;
     return LBM_OK;
@@ -579,6 +709,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
     }
     hipStream_t s = (hipStream_t)stream;
     const bool f32 = c->P.prec == LBM_FP32_SHIFTED;
+    const int re = c->P.reduce_every;
     for (int64_t k = 0; k < nsteps; ++k) {
         if (c->ckpt_K > 0 && c->step % c->ckpt_K == 0) {
             const int64_t slot = c->step / c->ckpt_K;
@@ -591,7 +722,17 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
                         "checkpoint copy"))
                 return LBM_EHIP;
         }
-        const bool red = c->P.reduce_every > 0 && (c->step % c->P.reduce_every) == 0;
+        const bool red = re > 0 && (c->step % re) == 0;
+        // two steps in one launch when neither this step nor the next reduces and no
+        // checkpoint falls between them
+        if (c->blk2 && !red && k + 1 < nsteps && !(re > 0 && (c->step + 1) % re == 0) &&
+            !(c->ckpt_K > 0 && (c->step + 1) % c->ckpt_K == 0)) {
+            if (!(f32 ? launch_step2<float>(c, s) : launch_step2<double>(c, s))) return LBM_EHIP;
+            c->cur ^= 1;
+            c->step += 2;
+            ++k;
+            continue;
+        }
         const int mode = red ? MODE_STEP_REDUCE : MODE_STEP;
         if (!(f32 ? launch_step<float>(c, mode, s) : launch_step<double>(c, mode, s))) return LBM_EHIP;
         if (red) {

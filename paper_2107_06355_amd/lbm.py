@@ -20,7 +20,7 @@ LBM_OK, LBM_EINVAL, LBM_EUNSTABLE, LBM_EHIP, LBM_ESTATE, LBM_ENOROOT = 0, -1, -2
 FP64, FP32_SHIFTED = 0, 1
 BASE_CS, BASE_PR = 0, 1
 SHAPE_NONE, SHAPE_SMOOTH, SHAPE_MODSMOOTH, SHAPE_PENG = 0, 1, 2, 3
-VARIANT_AUTO, VARIANT_MARCH, VARIANT_BLOCK = 0, 1, 2
+VARIANT_AUTO, VARIANT_MARCH, VARIANT_BLOCK, VARIANT_BLOCK2 = 0, 1, 2, 3
 
 
 class LbmEos(C.Structure):

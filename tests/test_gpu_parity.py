@@ -52,17 +52,22 @@ def rel_f_err(L, OL):
 # ---------------------------------------------------------------- FP64 elementwise parity
 VARIANTS = [(1, 0), (1, 1), (1, 3), (2, 0)]  # (kernel variant, band rows): march auto/1/3 rows, row block
 VARIANT_IDS = ["march", "march-h1", "march-h3", "block"]
+# periodic lattices also run the two-step block (58 x 10 tiles, two steps per launch)
+VARIANTS_P = VARIANTS + [(3, 0)]
+VARIANT_IDS_P = VARIANT_IDS + ["block2"]
 
 
-@pytest.mark.parametrize("variant,band", VARIANTS, ids=VARIANT_IDS)
-@pytest.mark.parametrize("nx,ny", [(130, 37), (62, 5), (63, 9), (2, 200), (256, 4), (1, 7), (5, 1), (70, 29)])
+@pytest.mark.parametrize("variant,band", VARIANTS_P, ids=VARIANT_IDS_P)
+@pytest.mark.parametrize("nx,ny", [(130, 37), (62, 5), (63, 9), (2, 200), (256, 4), (1, 7), (5, 1), (70, 29),
+                                   (117, 21)])
 def test_fp64_planar_and_ragged_shapes(gpu_lib, nx, ny, variant, band):
-    """Ragged strips (62-column waves), ragged bands / blocks, 1-wide and 1-tall lattices."""
+    """Ragged strips (62-column waves; 58-column tiles of the two-step block), ragged bands / blocks,
+    1-wide and 1-tall lattices (the two-step tiles wrap onto themselves), odd step counts."""
     kw = dict(Tr=0.7)
     e, _, _, _ = both_eos(gpu_lib, **kw)
     rho0 = planar_density(nx, ny, e.rho_v, e.rho_l, W=5, axis=1 if ny >= nx else 0)
     rho0 = rho0 * (1 + 0.01 * random_field(nx, ny, 1.0, 1.0, seed=nx * 1000 + ny))
-    for steps in (1, 40):
+    for steps in (1, 2, 41):
         L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, steps, tau=TAU_MRT, variant=variant, band_rows=band)
         assert rel_f_err(L, OL) < 1e-12, (nx, ny, steps)
 
@@ -98,7 +103,7 @@ def test_fp64_walls_variable_tau_moving_droplet(gpu_lib, variant, band):
     assert rel_f_err(L, OL) < 1e-12
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["march", "block"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["march", "block", "block2"])
 def test_fp64_macros_match_oracle(gpu_lib, variant):
     kw = dict(Tr=0.6)
     e, _, _, _ = both_eos(gpu_lib, **kw)
@@ -162,7 +167,35 @@ def test_fp32_one_step_elementwise(gpu_lib, variant):
     assert np.abs(f_g - f_o).max() <= 2e-6 * dev
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["march", "block"])
+def test_fp32_two_step_launch_elementwise(gpu_lib):
+    """One two-step launch (LDS-held intermediate state) from an FP32-representable state against
+    two FP64 oracle steps, and against two launches of the one-step block kernel."""
+    kw = dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
+    e, s, eo, so = both_eos(gpu_lib, **kw)
+    nx, ny = 128, 96
+    tau = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]
+    rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=25, W=20)
+    f = {}
+    for variant in (2, 3):
+        P = gpu_lib.make_params(nx, ny, e, sigma=s, tau=tau, prec=gpu_lib.FP32_SHIFTED, kernel_variant=variant)
+        L = gpu_lib.Lattice(P, rho0, device="cuda:0")
+        L.step(50)
+        f_t = L.populations().cpu().numpy()
+        L.step(2)
+        L.check()
+        f[variant] = L.populations().cpu().numpy()
+    OL = O.Lattice(O.make_params(nx, ny, eo, sigma=so, tau=tau))
+    OL.set_f(f_t)
+    OL.run(2)
+    f_o = OL.get_f()
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+    dev = np.abs(f_o - w * e.rho_v).max()
+    assert np.abs(f[3] - f_o).max() <= 4e-6 * dev
+    # same node arithmetic as the one-step kernel: at most FMA-contraction differences
+    assert np.abs(f[3] - f[2]).max() <= 1e-6 * dev
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["march", "block", "block2"])
 def test_fp32_mass_drift_droplet(gpu_lib, variant):
     """FP64 per-node rest population keeps the FP32-shifted mass exact: drift <= 1e-10 relative."""
     kw = dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
@@ -249,7 +282,8 @@ def test_unstable_state_is_reported(gpu_lib):
 def test_invalid_parameters_rejected(gpu_lib):
     e, _ = gpu_lib.eos_build(gpu_lib.make_eos(Tr=0.7))
     for bad in (dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.5, 0.5]), dict(G=1.0), dict(prec=1, rho_ref=-1.0),
-                dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.8, 0.9])):
+                dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.8, 0.9]), dict(kernel_variant=3, walls=True),
+                dict(kernel_variant=4)):
         P = gpu_lib.make_params(8, 8, e, **bad)
         with pytest.raises(gpu_lib.LbmError) as ei:
             gpu_lib.Lattice(P, np.full((8, 8), e.rho_v), device="cuda:0")

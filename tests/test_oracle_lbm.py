@@ -191,6 +191,43 @@ def test_mass_and_momentum_conservation_droplet():
     assert abs(m["Fx"].sum()) < 1e-15 * np.abs(m["Fx"]).sum() + 1e-18
 
 
+def test_window_run_matches_run_and_confines_invalid_nodes():
+    """or_run_window (used to check sampled nodes of huge lattices on small periodic windows) takes
+    the same steps as or_run; a node with psi^2 < 0 poisons only nodes within 2 per step of it."""
+    e, s = cs_eos(0.7)
+    nx, ny = 23, 21
+    rho = droplet_density(nx, ny, e.rho_v, e.rho_l, R=6, W=5)
+    P = O.make_params(nx, ny, e, sigma=s, tau=[1, 1.2, 1.1, 1, 1.1, 1, 1.1, 0.8, 0.8])
+    A, B = O.Lattice(P), O.Lattice(P)
+    A.init_eq(rho)
+    B.init_eq(rho)
+    A.run(3)
+    B.run_window(3)
+    assert np.array_equal(A.get_f(), B.get_f())
+    # near the C-S packing limit (b rho / 4 = 0.9) p - rho/3 > 0: psi^2 < 0
+    bad = rho.copy()
+    bad[4, 5] = 0.9
+    C_ = O.Lattice(P)
+    C_.init_eq(bad)
+    with pytest.raises(O.OracleError):
+        C_.run(1)
+    for steps in (1, 2, 3):
+        C_ = O.Lattice(P)
+        C_.init_eq(bad)
+        C_.run_window(steps)
+        fc = C_.get_f()
+        ref = O.Lattice(P)
+        ref.init_eq(rho)
+        ref.run(steps)
+        yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+        d = np.maximum(np.minimum(np.abs(xx - 5), nx - np.abs(xx - 5)), np.minimum(np.abs(yy - 4), ny - np.abs(yy - 4)))
+        nan = ~np.isfinite(fc).all(axis=0)
+        assert nan[4, 5] and nan.any() and not nan[d > 2 * steps].any()
+        # outside the reach of the planted node's initial neighbourhood the run is the clean one
+        far = d > 2 * steps + 2
+        assert np.array_equal(fc[:, far], ref.get_f()[:, far])
+
+
 def test_walls_conserve_mass_and_keep_uniform_state():
     e, s = cs_eos(0.7)
     P = O.make_params(6, 8, e, sigma=s, walls=True, rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_l)
