@@ -281,7 +281,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
             if (sizeof(T) == 4 && !in_loop && E.shape != LBM_SHAPE_NONE) {
                 // bulk branches in FP32, as in the forward
                 const float r = (float)rho, dpb = dev_base_dpf(E, r);
-                const float dp = rho <= E.rho_v ? (float)E.k_vap * dpb : dpb;
+                const float dp = rho <= E.rho_v ? E.fk_vap * dpb : dpb;
                 drho_eos = (T)((dp - (1.0f / 3.0f)) * (float)dpsi * rcp((float)G * (float)psi));
             } else {
                 const double inv_gpsi = A.inv_G / (double)psi;

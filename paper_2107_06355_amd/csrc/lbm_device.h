@@ -35,6 +35,7 @@ struct DevEos {
     double RT, aal, b, scale, k_vap, dP;
     double rho_v, rho_l, rho_max, rho_min;
     double p0, p_max, p_min, inv_a1sq, b1, inv_a3sq, b3, inv_L, rho_m, theta;
+    float fRT, faal, fb, fscale, fk_vap, fdP;  // the bulk-branch constants rounded to FP32 (FP32 path)
 };
 
 __device__ __forceinline__ double dev_base_p(const DevEos& E, double r)
@@ -259,32 +260,31 @@ __device__ __forceinline__ void flag_unstable(const StepArgs& A, int dstep = 0)
 __device__ __forceinline__ float dev_base_pf(const DevEos& E, float r)
 {
     if (E.base == LBM_BASE_CS) {
-        const float n = 0.25f * (float)E.b * r, m = 1.0f - n;
-        return (float)E.scale *
-               ((float)E.RT * r * (1.0f + n * (1.0f + n * (1.0f - n))) * __builtin_amdgcn_rcpf(m * m * m) - (float)E.aal * r * r);
+        const float n = 0.25f * E.fb * r, m = 1.0f - n;
+        return E.fscale *
+               (E.fRT * r * (1.0f + n * (1.0f + n * (1.0f - n))) * __builtin_amdgcn_rcpf(m * m * m) - E.faal * r * r);
     }
-    const float br = (float)E.b * r;
-    return (float)E.scale * ((float)E.RT * r * __builtin_amdgcn_rcpf(1.0f - br) -
-                             (float)E.aal * r * r * __builtin_amdgcn_rcpf(1.0f + br * (2.0f - br)));
+    const float br = E.fb * r;
+    return E.fscale * (E.fRT * r * __builtin_amdgcn_rcpf(1.0f - br) -
+                       E.faal * r * r * __builtin_amdgcn_rcpf(1.0f + br * (2.0f - br)));
 }
 
 __device__ __forceinline__ float dev_base_dpf(const DevEos& E, float r)
 {
     if (E.base == LBM_BASE_CS) {
-        const float n = 0.25f * (float)E.b * r, m = 1.0f - n;
+        const float n = 0.25f * E.fb * r, m = 1.0f - n;
         const float m2 = m * m;
-        return (float)E.scale * ((float)E.RT * (1.0f + n * (4.0f + n * (4.0f + n * (-4.0f + n)))) *
-                                     __builtin_amdgcn_rcpf(m2 * m2) -
-                                 2.0f * (float)E.aal * r);
+        return E.fscale * (E.fRT * (1.0f + n * (4.0f + n * (4.0f + n * (-4.0f + n)))) * __builtin_amdgcn_rcpf(m2 * m2) -
+                           2.0f * E.faal * r);
     }
-    const float br = (float)E.b * r, m = 1.0f - br, D = 1.0f + br * (2.0f - br);
-    return (float)E.scale * ((float)E.RT * __builtin_amdgcn_rcpf(m * m) -
-                             2.0f * (float)E.aal * r * (1.0f + br) * __builtin_amdgcn_rcpf(D * D));
+    const float br = E.fb * r, m = 1.0f - br, D = 1.0f + br * (2.0f - br);
+    return E.fscale * (E.fRT * __builtin_amdgcn_rcpf(m * m) - 2.0f * E.faal * r * (1.0f + br) * __builtin_amdgcn_rcpf(D * D));
 }
 
 // psi (Eq. InteractionPotential, c = 1) of a node with density rho_ref + drho.
 // FP64 path: everything in FP64.  FP32 path: the bulk vapor/liquid branches in
-// FP32, the shaped loop between rho_v and rho_l (the branch junctions) in FP64.
+// FP32, the shaped loop between rho_v and rho_l (the branch junctions) in FP64;
+// the square root is the hardware one (within 1 ulp, no correction sequence).
 template <typename T>
 __device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check, int dstep = 0)
 {
@@ -293,15 +293,15 @@ __device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check
     if (sizeof(T) == 4 && E.shape != LBM_SHAPE_NONE && (rho <= E.rho_v || rho >= E.rho_l)) {
         const float r = (float)rho;
         const float pb = dev_base_pf(E, r);
-        const float p = rho <= E.rho_v ? (float)E.k_vap * pb : pb + (float)E.dP;
+        const float p = rho <= E.rho_v ? E.fk_vap * pb : pb + E.fdP;
         const float q = (p - r * (1.0f / 3.0f)) * A.cf.two_inv_G;
         if (check && !(q >= 0.0f && r > 0.0f)) flag_unstable(A, dstep);
-        return (T)(q > 0.0f ? sqrtf(q) : 0.0f);
+        return (T)(q > 0.0f ? __builtin_amdgcn_sqrtf(q) : 0.0f);
     }
     const double p = dev_eos_p(E, rho);
     const double q = (p - rho * (1.0 / 3.0)) * A.cd.two_inv_G;
     if (check && !(q >= 0.0 && rho > 0.0)) flag_unstable(A, dstep);
-    if (sizeof(T) == 4) return (T)(q > 0.0 ? sqrtf((float)q) : 0.0f);
+    if (sizeof(T) == 4) return (T)(q > 0.0 ? __builtin_amdgcn_sqrtf((float)q) : 0.0f);
     return (T)(q > 0.0 ? sqrt(q) : 0.0);
 }
 
@@ -511,6 +511,12 @@ inline DevEos dev_eos(const lbm_eos& e)
     E.inv_L = e.rho_min > e.rho_max ? 1.0 / (e.rho_min - e.rho_max) : 0.0;
     E.rho_m = e.rho_m;
     E.theta = e.theta;
+    E.fRT = (float)E.RT;
+    E.faal = (float)E.aal;
+    E.fb = (float)E.b;
+    E.fscale = (float)E.scale;
+    E.fk_vap = (float)E.k_vap;
+    E.fdP = (float)E.dP;
     return E;
 }
 
