@@ -31,7 +31,7 @@ METRIC = "MLUPS + HBM GB/s (%roofline), FP32-shifted vs FP64 D2Q9; adjoint/fwd t
 # algorithmic bytes per cell update: 8 moving populations read + written, rest population FP64 read + written
 BYTES = {"fp32": 8 * 4 * 2 + 8 * 2, "fp64": 9 * 8 * 2}
 # step kernel of each decomposition (lbm_variant): row march, row block, two-step block
-KERNEL_NAME = {1: "k_step<%s, 0>", 2: "k_step_blk<%s, 0>", 3: "k_step2_blk<%s>"}
+KERNEL_NAME = {1: "k_step<%s, 0>", 2: "k_step_blk<%s, 0>", 3: "k_step2_blk<%s, 0, false>"}
 
 EOS_KW = dict(base=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
 TAU = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]
@@ -153,50 +153,66 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
         L.backward()
         return float(L.detach()), r.grad
 
-    def run(prec, ckpt, ee=e, G=-1.0, sig=s):
+    def run(prec, mode=None, ee=e, G=-1.0, sig=s):
         P = lbm.make_params(n, n, ee, G=G, sigma=sig, tau=TAU, prec=prec, reduce_every=0)
         lat = lbm.Lattice(P, rho0, device="cuda:0")
-        if ckpt:
+        if mode == "checkpoint":
             lat.enable_checkpointing(K, steps)
+        elif mode == "record":
+            lat.enable_recording(steps)
         return lat
 
-    out = {"workload": "static droplet %dx%d R=%d W0=%g, shaped PR Tr=0.5, %d steps, checkpoint every %d"
-                       % (n, n, R, W0, steps, K)}
+    out = {"workload": "static droplet %dx%d R=%d W0=%g, shaped PR Tr=0.5, %d steps; the forward records every "
+                       "step (primary) or checkpoints every %d steps and recomputes" % (n, n, R, W0, steps, K)}
     for prec, name in ((lbm.FP32_SHIFTED, "fp32"), (lbm.FP64, "fp64")):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-        plain = run(prec, False)
+        plain = run(prec)
         plain.step(50)
         torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record(plain.stream)
         plain.step(steps)
         ev[1].record(plain.stream)
         plain.check()
         plain.close()
-        lat = run(prec, True)
-        ev[2].record(lat.stream)
-        lat.step(steps)
-        ev[3].record(lat.stream)
-        lat.check()
-        L0, g = loss_grad(lat.macros()["rho"])
-        ev[4].record(lat.stream)
-        grads = lat.adjoint(g)
-        ev[5].record(lat.stream)
         torch.cuda.synchronize()
-        t_fwd, t_ck, t_adj = (ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), ev[4].elapsed_time(ev[5]))
-        out[name] = {"forward_ms": t_fwd, "forward_checkpointed_ms": t_ck, "adjoint_ms": t_adj,
-                     "adjoint_over_forward": t_adj / t_fwd, "loss": L0, "grad": grads}
-        print("# adjoint %s: forward %.1f ms (checkpointed %.1f), adjoint %.1f ms -> %.2fx" % (
-            name, t_fwd, t_ck, t_adj, t_adj / t_fwd), file=sys.stderr, flush=True)
-        lat.close()
-        del lat
-        torch.cuda.empty_cache()
+        t_fwd = ev[0].elapsed_time(ev[1])
+        res = {"forward_ms": t_fwd}
+        for mode in ("record", "checkpoint"):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            lat = run(prec, mode)
+            ev[0].record(lat.stream)
+            lat.step(steps)
+            ev[1].record(lat.stream)
+            lat.check()
+            L0, g = loss_grad(lat.macros()["rho"])
+            ev[2].record(lat.stream)
+            grads = lat.adjoint(g)
+            ev[3].record(lat.stream)
+            torch.cuda.synchronize()
+            t_f, t_adj = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+            res[mode] = {"forward_ms": t_f, "adjoint_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd,
+                         # what gradients cost on top of a plain forward, in plain forwards
+                         "extra_over_forward": (t_f - t_fwd + t_adj) / t_fwd, "grad": grads}
+            res["loss"] = L0
+            print("# adjoint %s (%s): forward %.1f ms (plain %.1f), adjoint %.1f ms -> %.2fx the plain forward, "
+                  "%.2fx extra in all" % (name, mode, t_f, t_fwd, t_adj, t_adj / t_fwd,
+                                          res[mode]["extra_over_forward"]), file=sys.stderr, flush=True)
+            lat.close()
+            del lat
+            torch.cuda.empty_cache()
+        res["grad"] = res["record"]["grad"]
+        res["adjoint_over_forward"] = res["record"]["adjoint_over_forward"]
+        res["record_vs_checkpoint_max_rel_diff"] = max(
+            abs(res["record"]["grad"][k] - res["checkpoint"]["grad"][k]) / max(abs(res["checkpoint"]["grad"][k]), 1e-300)
+            for k in res["record"]["grad"])
+        out[name] = res
     if fd_check:
         # central differences of the FP64 forward, relative step 1e-6
         base = [e.rho_max, e.p_max, e.rho_min, e.p_min]
 
         def L_of(knots=None, G=-1.0, sig=s):
             ee = lbm.eos_set_knots(e, *knots) if knots is not None else e
-            lat = run(lbm.FP64, False, ee, G, sig)
+            lat = run(lbm.FP64, None, ee, G, sig)
             lat.step(steps)
             lat.check()
             val = loss_grad(lat.macros()["rho"])[0]

@@ -52,10 +52,10 @@ typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_prec;
  * the compiler's FMA contraction choices):
  * MARCH: one wavefront marches up a band of rows of a 62-column strip with
  * two rows of loads in flight; BLOCK: a 12-wavefront workgroup loads 12 rows
- * of a strip, one per wavefront, and shares psi through LDS; BLOCK2 (periodic
- * lattices only): a 16-wavefront workgroup advances a 58 x 10 tile by two
- * time steps per launch and keeps the intermediate populations in LDS
- * (temporal blocking; a step that reduces or checkpoints runs alone). */
+ * of a strip, one per wavefront, and shares psi through LDS; BLOCK2: a
+ * 16-wavefront workgroup advances a 58 x 10 tile by two time steps per launch
+ * and keeps the intermediate populations in LDS (temporal blocking; a step
+ * that reduces or checkpoints runs alone on BLOCK). */
 typedef enum {
     LBM_VARIANT_AUTO = 0,
     LBM_VARIANT_MARCH = 1,
@@ -184,8 +184,11 @@ void lbm_destroy(lbm_ctx* ctx);
  * rho_max, p_max, rho_min, p_min, as independent parameters; the ellipse
  * coefficients follow them), the interaction constant G and the Eq. LiFS
  * sigma (held fixed while G varies).  The forward must run from step 0 with
- * checkpointing enabled; the adjoint recomputes each K-step segment from its
- * checkpoint.  Eq. RelaxationTime (var_tau) is not differentiated.
+ * recording or checkpointing enabled.  Recording keeps every step's record
+ * (drho, j, psi) in HBM and the adjoint only runs the transposed steps;
+ * checkpointing keeps the state every K steps and the adjoint recomputes each
+ * K-step segment from its checkpoint (memory O(T/K) states + K records instead
+ * of O(T) records).  Eq. RelaxationTime (var_tau) is not differentiated.
  * ------------------------------------------------------------------------ */
 
 /* Bytes of the per-segment record (K steps of drho, j, psi) and of the
@@ -195,12 +198,22 @@ int lbm_adjoint_layout(const lbm_params* p, int K, size_t* rec_bytes, size_t* ad
  * is lbm_layout's pop_bytes).  Call before the first lbm_step; K = 0 turns
  * checkpointing off.  lbm_step returns LBM_ESTATE when the slots run out. */
 int lbm_set_checkpointing(lbm_ctx* ctx, void* ckpt_buf, size_t ckpt_bytes, int K);
+/* Keep the record of every step 0 .. max_steps-1 of the forward in rec_buf
+ * (device, caller-owned, rec_bytes >= the rec_bytes lbm_adjoint_layout gives
+ * for K = max_steps: 4 planes of [ny][nx] in the storage precision per step,
+ * step after step).  Call before the first lbm_step; max_steps = 0 turns it
+ * off.  lbm_step returns LBM_ESTATE rather than step past max_steps.  A
+ * recording forward runs the same node arithmetic and also writes 16 B (FP32)
+ * or 32 B (FP64) per node and step. */
+int lbm_set_recording(lbm_ctx* ctx, void* rec_buf, size_t rec_bytes, int64_t max_steps);
 /* Gradient of L(rho(T)) given dL_drho_T (device float64 [ny][nx]).
  * grad_out (host, 6 doubles): dL/d{rho_max, p_max, rho_min, p_min, G, sigma}
  * (knot entries are 0 unless the shape is Smooth or Modified Smooth).
  * dL_drho0 (device [ny][nx], may be NULL): gradient with respect to the
  * initial density of f^eq(rho0, u = 0).  Synchronises; the forward state at
- * T is restored on return. */
+ * T is restored on return.  After a recorded forward rec_buf may be NULL (the
+ * records are read from the recording buffer); after a checkpointed one it
+ * holds one segment (lbm_adjoint_layout's rec_bytes for the same K). */
 int lbm_adjoint(lbm_ctx* ctx, const double* dL_drho_T, void* rec_buf, size_t rec_bytes, void* adj_buf, size_t adj_bytes,
                 double* grad_out, double* dL_drho0, void* stream);
 /* Replace the four interior knots of a built Smooth / Modified Smooth EOS and

@@ -421,25 +421,46 @@ int lbm_set_checkpointing(lbm_ctx* c, void* ckpt_buf, size_t ckpt_bytes, int K)
     return LBM_OK;
 }
 
+int lbm_set_recording(lbm_ctx* c, void* rec_buf, size_t rec_bytes, int64_t max_steps)
+{
+    if (!c || max_steps < 0 || (max_steps > 0 && !rec_buf)) return LBM_EINVAL;
+    if (c->step != 0) {
+        lbm_set_error("lbm_set_recording: enable recording before the first step");
+        return LBM_ESTATE;
+    }
+    const size_t tsz = c->P.prec == LBM_FP32_SHIFTED ? sizeof(float) : sizeof(double);
+    const size_t per_step = 4 * (size_t)c->P.nx * c->P.ny * tsz;
+    if (max_steps > 0 && rec_bytes / per_step < (size_t)max_steps) {
+        lbm_set_error("lbm_set_recording: buffer smaller than max_steps records");
+        return LBM_EINVAL;
+    }
+    c->rec_all = max_steps > 0 ? rec_buf : nullptr;
+    c->rec_steps = max_steps;
+    return LBM_OK;
+}
+
 int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_bytes, void* adj_buf, size_t adj_bytes,
                 double* grad_out, double* dL_drho0, void* stream)
 {
-    if (!c || !dL_drho_T || !rec_buf || !adj_buf || !grad_out) return LBM_EINVAL;
+    if (!c || !dL_drho_T || !adj_buf || !grad_out) return LBM_EINVAL;
     const lbm_params& P = c->P;
-    if (c->ckpt_K < 1 || c->step < 1) {
-        lbm_set_error("lbm_adjoint: run the forward with checkpointing enabled (lbm_set_checkpointing) first");
+    // a forward recorded from step 0 needs no recomputation
+    const bool recorded = c->rec_all != nullptr && c->step >= 1 && c->step <= c->rec_steps;
+    if (!recorded && (c->ckpt_K < 1 || c->step < 1 || !rec_buf)) {
+        lbm_set_error("lbm_adjoint: run the forward with recording (lbm_set_recording) or checkpointing "
+                      "(lbm_set_checkpointing) enabled first; checkpointing needs rec_buf");
         return LBM_ESTATE;
     }
     if (P.var_tau) {
         lbm_set_error("lbm_adjoint: density-dependent relaxation (Eq. RelaxationTime) is not differentiated");
         return LBM_EINVAL;
     }
-    const int K = c->ckpt_K;
     const int64_t T_end = c->step;
-    const int64_t S = (T_end + K - 1) / K;
-    if (S > c->ckpt_slots) return LBM_ESTATE;
+    const int K = recorded ? 1 : c->ckpt_K;
+    const int64_t S = recorded ? 1 : (T_end + K - 1) / K;
+    if (!recorded && S > c->ckpt_slots) return LBM_ESTATE;
     const AdjLayout L = adj_layout(P, c->ld, c->pop_bytes, K);
-    if (rec_bytes < L.rec_bytes || adj_bytes < L.total) {
+    if ((!recorded && rec_bytes < L.rec_bytes) || adj_bytes < L.total) {
         lbm_set_error("lbm_adjoint: record or adjoint workspace smaller than lbm_adjoint_layout requires");
         return LBM_EINVAL;
     }
@@ -448,7 +469,8 @@ int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_b
     const bool f32 = P.prec == LBM_FP32_SHIFTED;
     const size_t nn = (size_t)P.nx * P.ny, lp = (size_t)c->ld * P.ny;
     // keep the final forward state; the recomputation overwrites the buffers
-    if (!hip_ok(hipMemcpyAsync(ab + L.off_fT, c->buf[c->cur], c->pop_bytes, hipMemcpyDeviceToDevice, s), "save f(T)"))
+    if (!recorded &&
+        !hip_ok(hipMemcpyAsync(ab + L.off_fT, c->buf[c->cur], c->pop_bytes, hipMemcpyDeviceToDevice, s), "save f(T)"))
         return LBM_EHIP;
     void* lam[2] = {ab + L.off_lam0, ab + L.off_lam1};
     double* acc = (double*)(ab + L.off_acc);
@@ -472,7 +494,19 @@ int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_b
     A.kd = {A.c_e, A.c_q, 2.0 * P.sigma, A.inv_G};
     A.kf = {(float)A.c_e, (float)A.c_q, (float)(2.0 * P.sigma), (float)A.inv_G};
     int li = 0;
-    for (int64_t k = S - 1; k >= 0; --k) {
+    if (recorded) {
+        // the forward kept every step's record: transposed steps only, T_end - 1 down to 0
+        for (int64_t j = T_end - 1; j >= 0; --j) {
+            A.rec = (const char*)c->rec_all + (size_t)j * 4 * nn * L.tsz;
+            A.lam_in = lam[li];
+            A.lam_out = lam[li ^ 1];
+            if (f32) hipLaunchKernelGGL(k_adj_blk<float>, dim3(L.blocks), dim3(64 * kAdjWaves), 0, s, A);
+            else hipLaunchKernelGGL(k_adj_blk<double>, dim3(L.blocks), dim3(64 * kAdjWaves), 0, s, A);
+            if (!hip_ok(hipGetLastError(), "adjoint step launch")) return LBM_EHIP;
+            li ^= 1;
+        }
+    }
+    for (int64_t k = recorded ? -1 : S - 1; k >= 0; --k) {
         const int64_t t0 = k * K;
         const int n = (int)((T_end - t0) < K ? (T_end - t0) : K);
         if (!hip_ok(hipMemcpyAsync(c->buf[c->cur], (char*)c->ckpt + k * c->pop_bytes, c->pop_bytes,
@@ -496,7 +530,8 @@ int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_b
         }
     }
     // restore the forward state at T
-    if (!hip_ok(hipMemcpyAsync(c->buf[c->cur], ab + L.off_fT, c->pop_bytes, hipMemcpyDeviceToDevice, s), "restore f(T)"))
+    if (!recorded &&
+        !hip_ok(hipMemcpyAsync(c->buf[c->cur], ab + L.off_fT, c->pop_bytes, hipMemcpyDeviceToDevice, s), "restore f(T)"))
         return LBM_EHIP;
     c->step = T_end;
     if (dL_drho0) {

@@ -25,6 +25,9 @@ struct lbm_ctx {
     void* ckpt;
     int64_t ckpt_slots;
     int ckpt_K;
+    // forward record for the adjoint (lbm_set_recording): every step from 0 on
+    void* rec_all;
+    int64_t rec_steps;
 };
 
 

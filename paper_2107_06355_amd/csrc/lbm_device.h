@@ -337,6 +337,25 @@ __device__ __forceinline__ int load_index(const StepArgs& A, int r)
 // Node update of an interior lane: moments, forced velocity, MRT relaxation with
 // the Eq. LiFS source, inverse transform and store (or the macroscopic outputs).
 // psB = psi(x, y); Ftx, Fty = F~ = F/psi(x) from Eq. ShanChenForce.
+// pre-collision state the adjoint of a step needs at node o: drho, j (unforced), psi
+template <typename T>
+__device__ __forceinline__ void record_node(void* rec, size_t plane, size_t o, T dr, T jx, T jy, T psi)
+{
+    T* rc = (T*)rec;
+    rc[o] = dr;
+    rc[plane + o] = jx;
+    rc[2 * plane + o] = jy;
+    rc[3 * plane + o] = psi;
+}
+
+// unforced momentum j of pulled populations g (the moment rows of Eq. MatrixMRT)
+template <typename T>
+__device__ __forceinline__ void node_j(const T* gp, T& jx, T& jy)
+{
+    jx = (gp[1] - gp[3]) + ((gp[5] - gp[6]) - (gp[7] - gp[8]));
+    jy = (gp[2] - gp[4]) + ((gp[5] + gp[6]) - (gp[7] + gp[8]));
+}
+
 template <typename T, int MODE>
 __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, int y, const Row<T>& P, double drp,
                                              T psB, T Ftx, T Fty, Acc& acc, T o[9], double& o0)
@@ -351,8 +370,8 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
     // moments m = M g (Eq. MatrixMRT rows)
     const T s14 = (gp[1] + gp[2]) + (gp[3] + gp[4]);
     const T s58 = (gp[5] + gp[6]) + (gp[7] + gp[8]);
-    const T jx = (gp[1] - gp[3]) + ((gp[5] - gp[6]) - (gp[7] - gp[8]));
-    const T jy = (gp[2] - gp[4]) + ((gp[5] + gp[6]) - (gp[7] + gp[8]));
+    T jx, jy;
+    node_j<T>(gp, jx, jy);
     const T me = -4 * g0t - s14 + 2 * s58;
     const T mq = 4 * g0t - 2 * s14 + s58;
     const T mqx = -2 * (gp[1] - gp[3]) + ((gp[5] - gp[6]) - (gp[7] - gp[8]));
@@ -373,15 +392,7 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
         if (A.o_fx) A.o_fx[o] = (double)Fx;
         if (A.o_fy) A.o_fy[o] = (double)Fy;
     }
-    if (MODE == MODE_RECORD) {
-        // pre-collision state the adjoint of this step needs: drho, j (unforced), psi
-        T* rc = (T*)A.rec;
-        const size_t o = (size_t)y * A.nx + x;
-        rc[o] = dr;
-        rc[A.rec_plane + o] = jx;
-        rc[2 * A.rec_plane + o] = jy;
-        rc[3 * A.rec_plane + o] = psB;
-    }
+    if (MODE == MODE_RECORD) record_node<T>(A.rec, A.rec_plane, (size_t)y * A.nx + x, dr, jx, jy, psB);
     if (MODE == MODE_STEP_REDUCE || MODE == MODE_MACROS) {
         acc.m += rho_d;
         acc.x += (double)rho * (double)ux;
@@ -568,10 +579,6 @@ inline int validate(const lbm_params* p)
         }
     if (p->kernel_variant < 0 || p->kernel_variant > LBM_VARIANT_BLOCK2) {
         lbm_set_error("lbm: kernel_variant must be 0 (automatic), 1 (row march), 2 (row block) or 3 (two-step block)");
-        return LBM_EINVAL;
-    }
-    if (p->kernel_variant == LBM_VARIANT_BLOCK2 && p->walls) {
-        lbm_set_error("lbm: the two-step block kernel covers periodic lattices only (walls = 0)");
         return LBM_EINVAL;
     }
     if (p->band_rows < 0 || p->band_rows > 4096) {

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
     }
 }
 
-// Two time steps per launch (temporal blocking), periodic lattices.  A
+// Two time steps per launch (temporal blocking).  A
 // workgroup of 16 waves owns an output tile of 10 rows x 58 columns; wave k
 // holds row y0-3+k and lane l column x0-3+l in every phase, so the tile grown
 // by d nodes is the set of (wave, lane) pairs at distance <= d from it:
@@ -217,18 +217,21 @@ __global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
 //      the post-collision populations go to LDS in their storage format
 //   3. pull step t+1 from LDS on the tile grown by 1; rho, psi(t+1) -> LDS
 //   4. collide step t+1 on the tile and store to the destination buffer.
+// With walls the rows beyond them are solid: they carry the ghost psi of
+// Eq. ShanChenForce, and the pulls at the wall rows bounce back half-way.
 // Every node runs the arithmetic of the one-step kernels, and LDS holds the
 // intermediate state exactly as global memory would (FP32 deviations, FP64
 // rest population), so one launch equals two one-step launches.  Memory
 // traffic per output node is one population read (plus the 3-node ring) and
-// one write per two steps.
+// one write per two steps.  MODE_RECORD also stores, for the tile's nodes,
+// what the adjoint of each of the two steps needs (rho - rho_ref, j, psi).
 constexpr int k2Waves = 16, k2Rows = k2Waves - 6, k2Cols = 64 - 6;
 
 // FP32: 8 waves per SIMD, two workgroups per CU (the compiler spills scalar registers
 // to vector lanes to fit).  FP64: the compiler's choice (77 VGPRs, one workgroup per
 // CU); forcing two workgroups spills vector registers to scratch and measured 25%
 // slower on MI355X at 4096^2.
-template <typename T>
+template <typename T, int MODE, bool WALLS>
 __global__ __launch_bounds__(64 * k2Waves) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4)))
 void k_step2_blk(StepArgs A)
 {
@@ -241,6 +244,8 @@ void k_step2_blk(StepArgs A)
     if (logical >= strips * bands) return;  // whole workgroup leaves together
     const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = threadIdx.x & 63;
+    // band-major: the workgroups an XCD runs together cover neighbouring strips and bands
+    // (strip-major order measured 27% more HBM reads at 8192^2 on MI355X)
     const int strip = logical % strips, band = logical / strips;
     const int x0 = strip * k2Cols, y0 = band * k2Rows;
     const int W = min(k2Cols, A.nx - x0), H = min(k2Rows, A.ny - y0);
@@ -258,7 +263,12 @@ void k_step2_blk(StepArgs A)
     L.xm = x == 0 ? A.nx - 1 : x - 1;
     L.xp = x == A.nx - 1 ? 0 : x + 1;
     const int r = y0 - 3 + k;  // unwrapped row; in [0, ny) on the output tile
-    const int rw = (r % A.ny + A.ny) % A.ny;
+    // periodic: rows wrap; walls: rows outside [0, ny) are the solid nodes (ghost psi only).
+    // WALLS is a template parameter so that the periodic kernel carries none of this
+    // (its scalar registers are the occupancy limit).
+    const bool fluid = !WALLS || (r >= 0 && r < A.ny);
+    const int rw = WALLS ? r : (r % A.ny + A.ny) % A.ny;
+    const T ghost = WALLS ? (T)(r < 0 ? A.psi_lo : A.psi_hi) : (T)0;
     Acc acc = {0.0, 0.0, 0.0};
 
     // 1. step t: pull, rho, psi
@@ -266,15 +276,19 @@ void k_step2_blk(StepArgs A)
     double dr = 0.0;
     T ps = (T)0;
     if (dk <= 3 && dl <= 3) {
-        const View<T> V = make_view<T>(A.src, A.plane);
-        pull<T>(V, A, L.x, L.xm, L.xp, rw, R.g0, R.g);
-        dr = node_drho<T>(R.g0, R.g);
-        ps = node_psi<T>(A, dr, true);
+        if (fluid) {
+            const View<T> V = make_view<T>(A.src, A.plane);
+            pull<T>(V, A, L.x, L.xm, L.xp, rw, R.g0, R.g);
+            dr = node_drho<T>(R.g0, R.g);
+            ps = node_psi<T>(A, dr, true);
+        } else {
+            ps = ghost;
+        }
     }
     sps[k][l] = ps;
     __syncthreads();
     // 2. step t: collide on the tile grown by 2, post-collision state to LDS
-    if (dk <= 2 && dl <= 2) {
+    if (dk <= 2 && dl <= 2 && fluid) {
         T Ftx, Fty;
         force_tilde<T>(A, sps[k - 1][l - 1], sps[k - 1][l], sps[k - 1][l + 1], sps[k][l - 1], sps[k][l + 1],
                        sps[k + 1][l - 1], sps[k + 1][l], sps[k + 1][l + 1], Ftx, Fty);
@@ -284,31 +298,58 @@ void k_step2_blk(StepArgs A)
 #pragma unroll
         for (int i = 1; i < 9; ++i) smv[i - 1][k - 1][l] = o[i];
         sg0[k - 1][l] = o0;
+        if (MODE == MODE_RECORD && d == 0) {
+            T jx, jy;
+            node_j<T>(R.g, jx, jy);
+            record_node<T>(A.rec, A.rec_plane, (size_t)r * A.nx + x, (T)dr, jx, jy, ps);
+        }
     }
     __syncthreads();
-    // 3. step t+1: pull from LDS on the tile grown by 1 (f_i(x) = f*_i(x - c_i)), psi(t+1)
-    if (dk <= 1 && dl <= 1) {
+    // 3. step t+1: pull from LDS on the tile grown by 1 (f_i(x) = f*_i(x - c_i), or the node's
+    //    own opposite population where x - c_i is solid), psi(t+1)
+    if (dk <= 1 && dl <= 1 && fluid) {
         const int q = k - 1;  // LDS row of this wave
+        const bool bot = WALLS && r == 0, top = WALLS && r == A.ny - 1;
         R.g0 = sg0[q][l];
         R.g[1] = smv[0][q][l - 1];
         R.g[3] = smv[2][q][l + 1];
-        R.g[2] = smv[1][q - 1][l];
-        R.g[5] = smv[4][q - 1][l - 1];
-        R.g[6] = smv[5][q - 1][l + 1];
-        R.g[4] = smv[3][q + 1][l];
-        R.g[7] = smv[6][q + 1][l + 1];
-        R.g[8] = smv[7][q + 1][l - 1];
+        if (!bot) {
+            R.g[2] = smv[1][q - 1][l];
+            R.g[5] = smv[4][q - 1][l - 1];
+            R.g[6] = smv[5][q - 1][l + 1];
+        } else {
+            R.g[2] = smv[3][q][l];
+            R.g[5] = smv[6][q][l];
+            R.g[6] = smv[7][q][l];
+        }
+        if (!top) {
+            R.g[4] = smv[3][q + 1][l];
+            R.g[7] = smv[6][q + 1][l + 1];
+            R.g[8] = smv[7][q + 1][l - 1];
+        } else {
+            R.g[4] = smv[1][q][l];
+            R.g[7] = smv[4][q][l];
+            R.g[8] = smv[5][q][l];
+        }
         dr = node_drho<T>(R.g0, R.g);
         ps = node_psi<T>(A, dr, true, 1);
         sps[k][l] = ps;
+    } else if (WALLS && dk <= 1 && dl <= 1) {
+        sps[k][l] = ghost;
     }
     __syncthreads();
-    // 4. step t+1: collide on the tile and store
+    // 4. step t+1: collide on the tile and store (tile rows are fluid rows)
     if (d == 0) {
         T Ftx, Fty;
         force_tilde<T>(A, sps[k - 1][l - 1], sps[k - 1][l], sps[k - 1][l + 1], sps[k][l - 1], sps[k][l + 1],
                        sps[k + 1][l - 1], sps[k + 1][l], sps[k + 1][l + 1], Ftx, Fty);
         update_node<T, MODE_STEP>(A, L, r, R, dr, ps, Ftx, Fty, acc);
+        if (MODE == MODE_RECORD) {
+            T jx, jy;
+            node_j<T>(R.g, jx, jy);
+            record_node<T>((char*)A.rec + 4 * A.rec_plane * sizeof(T), A.rec_plane, (size_t)r * A.nx + x, (T)dr, jx,
+                           jy, ps);
+        }
     }
 }
 
@@ -432,9 +473,11 @@ bool hip_ok(hipError_t e, const char* what)
 int resolve_variant(const lbm_params& p)
 {
     int v = p.kernel_variant;
-    if (v == 0 && !p.walls) {
-        // measured on MI355X, 512^2 .. 4096^2 in both precisions: two steps per launch
-        // beat every one-step decomposition on periodic lattices
+    if (v == 0 && (!p.walls || p.prec == LBM_FP64)) {
+        // measured on MI355X: two steps per launch beat every one-step decomposition on
+        // periodic lattices (512^2 .. 16384^2, both precisions) and on the walled
+        // 2048 x 1024 drop impact in FP64 (56.4 vs 61.0 us); in FP32 the walled two-step
+        // kernel (more scalar spills) loses to the row block there (32.5 vs 29.8 us)
         v = LBM_VARIANT_BLOCK2;
     } else if (v == 0) {
         // measured on MI355X: the row block wins while the lattice is cache-resident or
@@ -554,16 +597,52 @@ bool launch_record_step(lbm_ctx* c, void* rec, hipStream_t s)
     return hip_ok(hipGetLastError(), "k_step_blk(record) launch");
 }
 
-// two steps in one launch (LBM_VARIANT_BLOCK2): source buf[cur], result in buf[cur ^ 1]
+// two steps in one launch (LBM_VARIANT_BLOCK2): source buf[cur], result in buf[cur ^ 1];
+// rec non-NULL: also record both steps (rec, then rec + one step's record)
 template <typename T>
-bool launch_step2(lbm_ctx* c, hipStream_t s)
+bool launch_step2(lbm_ctx* c, void* rec, hipStream_t s)
 {
     StepArgs A = c->args;
     A.src = c->buf[c->cur];
     A.dst = c->buf[c->cur ^ 1];
     A.step = c->step;
-    hipLaunchKernelGGL(k_step2_blk<T>, dim3(c->grid2), dim3(64 * k2Waves), 0, s, A);
+    A.rec = rec;
+    A.rec_plane = (size_t)c->P.nx * c->P.ny;
+    const dim3 g(c->grid2), b(64 * k2Waves);
+    if (c->P.walls) {
+        if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, true>), g, b, 0, s, A);
+    } else {
+        if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, false>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, false>), g, b, 0, s, A);
+    }
     return hip_ok(hipGetLastError(), "k_step2_blk launch");
+}
+
+// FP64 mass/momentum partials of the current state (no step), then the reduction
+bool launch_partials(lbm_ctx* c, double* out, long long step, hipStream_t s)
+{
+    StepArgs A = c->args;
+    A.src = c->buf[c->cur];
+    A.dst = nullptr;
+    A.step = c->step;
+    const bool f32 = c->P.prec == LBM_FP32_SHIFTED;
+    if (A.blk) {
+        if (f32) hipLaunchKernelGGL((k_step_blk<float, MODE_MACROS>), dim3(c->grid), dim3(64 * kBlkWaves), 0, s, A);
+        else hipLaunchKernelGGL((k_step_blk<double, MODE_MACROS>), dim3(c->grid), dim3(64 * kBlkWaves), 0, s, A);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_step<float, MODE_MACROS>), dim3(c->grid), dim3(256), 0, s, A);
+        else hipLaunchKernelGGL((k_step<double, MODE_MACROS>), dim3(c->grid), dim3(256), 0, s, A);
+    }
+    if (!hip_ok(hipGetLastError(), "k_step(partials) launch")) return false;
+    return launch_reduce(c, out, step, 1, s);
+}
+
+// record of step t in the forward record buffer (lbm_set_recording)
+void* record_slot(lbm_ctx* c, int64_t t)
+{
+    const size_t tsz = c->P.prec == LBM_FP32_SHIFTED ? sizeof(float) : sizeof(double);
+    return (char*)c->rec_all + (size_t)t * 4 * (size_t)c->P.nx * c->P.ny * tsz;
 }
 
 template <typename T>
@@ -710,6 +789,10 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
     hipStream_t s = (hipStream_t)stream;
     const bool f32 = c->P.prec == LBM_FP32_SHIFTED;
     const int re = c->P.reduce_every;
+    if (c->rec_all && c->step + nsteps > c->rec_steps) {
+        lbm_set_error("lbm_step: the forward record (lbm_set_recording) holds fewer steps");
+        return LBM_ESTATE;
+    }
     for (int64_t k = 0; k < nsteps; ++k) {
         if (c->ckpt_K > 0 && c->step % c->ckpt_K == 0) {
             const int64_t slot = c->step / c->ckpt_K;
@@ -723,14 +806,27 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
                 return LBM_EHIP;
         }
         const bool red = re > 0 && (c->step % re) == 0;
+        void* rec = c->rec_all ? record_slot(c, c->step) : nullptr;
         // two steps in one launch when neither this step nor the next reduces and no
         // checkpoint falls between them
         if (c->blk2 && !red && k + 1 < nsteps && !(re > 0 && (c->step + 1) % re == 0) &&
             !(c->ckpt_K > 0 && (c->step + 1) % c->ckpt_K == 0)) {
-            if (!(f32 ? launch_step2<float>(c, s) : launch_step2<double>(c, s))) return LBM_EHIP;
+            if (!(f32 ? launch_step2<float>(c, rec, s) : launch_step2<double>(c, rec, s))) return LBM_EHIP;
             c->cur ^= 1;
             c->step += 2;
             ++k;
+            continue;
+        }
+        if (rec) {
+            // recording forward: the reduction reads the state first, then the step records
+            if (red) {
+                double* row = c->hist + 4 * (c->hist_count % kHistCap);
+                if (!launch_partials(c, row, (long long)c->step, s)) return LBM_EHIP;
+                c->hist_count++;
+            }
+            if (!launch_record_step(c, rec, s)) return LBM_EHIP;
+            c->cur ^= 1;
+            c->step++;
             continue;
         }
         const int mode = red ? MODE_STEP_REDUCE : MODE_STEP;

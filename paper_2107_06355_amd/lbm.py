@@ -99,6 +99,7 @@ def _signatures():
         "lbm_destroy_batched": ([vp], None),
         "lbm_adjoint_layout": ([C.POINTER(LbmParams), i, C.POINTER(sz), C.POINTER(sz)], i),
         "lbm_set_checkpointing": ([vp, vp, sz, i], i),
+        "lbm_set_recording": ([vp, vp, sz, C.c_int64], i),
         "lbm_adjoint": ([vp, vp, vp, sz, vp, sz, dp, vp, vp], i),
         "lbm_eos_set_knots": ([C.POINTER(LbmEos), d, d, d, d], i),
         "lbm_fd_layout": ([C.POINTER(LbmFdParams), C.POINTER(sz)], i),
@@ -332,13 +333,26 @@ class Lattice:
         _check(load().lbm_set_checkpointing(self._h, self._ckpt.data_ptr(), self._ckpt.numel(), int(K)),
                "lbm_set_checkpointing")
 
+    def enable_recording(self, max_steps: int):
+        """Keep every step's record (rho - rho_ref, j, psi) of the next max_steps steps in HBM so that
+        lbm_adjoint runs no recomputation; call before stepping."""
+        t = self.torch
+        rec, adj = adjoint_layout(self.P, int(max_steps))
+        self._recall = t.empty(rec, dtype=t.uint8, device=self.device)
+        self._rec = None
+        self._adj = t.empty(adj, dtype=t.uint8, device=self.device)
+        _check(load().lbm_set_recording(self._h, self._recall.data_ptr(), self._recall.numel(), int(max_steps)),
+               "lbm_set_recording")
+
     def adjoint(self, dL_drho, want_rho0: bool = False):
         """Gradient of a loss L(rho(T)) given dL/drho(T) [ny][nx]: dict of GRAD_NAMES (+ 'rho0' field)."""
         t = self.torch
         g = self._dev(dL_drho, (self.ny, self.nx))
         out = (C.c_double * 6)()
         r0 = t.empty((self.ny, self.nx), dtype=t.float64, device=self.device) if want_rho0 else None
-        _check(load().lbm_adjoint(self._h, g.data_ptr(), self._rec.data_ptr(), self._rec.numel(), self._adj.data_ptr(),
+        rec = getattr(self, "_rec", None)
+        _check(load().lbm_adjoint(self._h, g.data_ptr(), rec.data_ptr() if rec is not None else None,
+                                  rec.numel() if rec is not None else 0, self._adj.data_ptr(),
                                   self._adj.numel(), out, r0.data_ptr() if r0 is not None else None, self._s()),
                "lbm_adjoint")
         res = dict(zip(GRAD_NAMES, list(out)))

@@ -2,8 +2,10 @@
 
 ``LbmRollout.apply(knots, G, sigma, rho0, spec)`` runs ``spec.steps`` fused steps from
 f^eq(rho0, u = 0) and returns rho(T) as a float64 tensor on the lattice's device; its backward
-calls lbm_adjoint (checkpoint every ``spec.K`` steps, recompute per segment) and returns
-dL/d(knots), dL/dG, dL/dsigma and dL/drho0.  knots = (rho_max, p_max, rho_min, p_min) are the
+calls lbm_adjoint and returns dL/d(knots), dL/dG, dL/dsigma and dL/drho0.  With ``spec.K = None``
+the forward records every step in HBM (16 B per node and step in FP32) and the backward runs
+only the transposed steps; with an integer K it checkpoints every K steps and recomputes each
+segment.  knots = (rho_max, p_max, rho_min, p_min) are the
 four interior points of the Smooth loop (Sec. III.D), treated as free parameters with the
 ellipse coefficients refitted to them; sigma is the Eq. LiFS coefficient, independent of G.
 All arithmetic runs in liblbm; this module only marshals tensors.
@@ -23,7 +25,7 @@ class RolloutSpec:
     nx: int
     ny: int
     steps: int
-    K: int = 200
+    K: int | None = 200                  # None: record every step instead of checkpointing
     prec: int = lbm.FP32_SHIFTED
     params: dict = field(default_factory=dict)   # extra lbm.make_params keywords (tau, walls, ...)
     device: str = "cuda:0"
@@ -43,7 +45,10 @@ def _autograd_function():
             e = lbm.eos_set_knots(spec.eos, *k)
             P = lbm.make_params(spec.nx, spec.ny, e, G=_f(G), sigma=_f(sigma), prec=spec.prec, **spec.params)
             lat = lbm.Lattice(P, rho0.detach(), device=spec.device)
-            lat.enable_checkpointing(spec.K, spec.steps)
+            if spec.K is None:
+                lat.enable_recording(spec.steps)
+            else:
+                lat.enable_checkpointing(spec.K, spec.steps)
             lat.step(spec.steps)
             lat.check()
             rho = lat.macros()["rho"]

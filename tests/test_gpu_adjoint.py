@@ -1,4 +1,5 @@
-"""Discrete adjoint (checkpoint + recompute) against central finite differences of the FP64 oracle.
+"""Discrete adjoint (recorded forward, or checkpoint + recompute) against central finite differences
+of the FP64 oracle.
 
 The loss is L = sum_x w(x) rho(x, T) with a seeded weight field w, so dL/drho(T) = w.
 The parameters are the four Smooth-loop knots (Sec. III.D), G and the Eq. LiFS sigma.
@@ -58,13 +59,18 @@ def _fd(e, s, nx, ny, rho0, w, extra, steps):
     return np.array(g)
 
 
-def _gpu(lbm, kind, prec, steps, K, want_rho0=False):
+def _gpu(lbm, kind, prec, steps, K, want_rho0=False, **pk):
+    """K = None: recorded forward (no recomputation); else checkpoints every K steps."""
     e, s, nx, ny, rho0, w, extra = _case(kind)
     el, sl = lbm.eos_build(lbm.make_eos(**SMOOTH))
     kw = dict(extra)
+    kw.update(pk)
     P = lbm.make_params(nx, ny, el, sigma=sl, tau=TAU, prec=prec, **kw)
     lat = lbm.Lattice(P, rho0, device="cuda:0")
-    lat.enable_checkpointing(K, steps)
+    if K is None:
+        lat.enable_recording(steps)
+    else:
+        lat.enable_checkpointing(K, steps)
     lat.step(steps)
     lat.check()
     before = lat.macros()["rho"].cpu().numpy()
@@ -126,6 +132,44 @@ def test_adjoint_one_segment_equals_many(gpu_lib):
         assert abs(a[n] - b[n]) <= 1e-12 * max(1.0, abs(a[n])), (n, a[n], b[n])
 
 
+@pytest.mark.parametrize("kind,prec_name,variant", [("droplet", "fp64", 0), ("droplet", "fp32", 0),
+                                                   ("droplet", "fp64", 2), ("walls", "fp64", 0)],
+                         ids=["droplet-fp64-twostep", "droplet-fp32-twostep", "droplet-fp64-onestep", "walls-fp64"])
+def test_recorded_forward_equals_recompute(gpu_lib, kind, prec_name, variant):
+    """A forward that records every step (two-step launches on periodic lattices, one-step ones at
+    walls) gives the adjoint of the checkpoint/recompute path without recomputing."""
+    lbm = gpu_lib
+    prec = lbm.FP64 if prec_name == "fp64" else lbm.FP32_SHIFTED
+    a, _ = _gpu(lbm, kind, prec, 21, 8, want_rho0=True, kernel_variant=variant)
+    b, _ = _gpu(lbm, kind, prec, 21, None, want_rho0=True, kernel_variant=variant)
+    tol = 1e-12 if prec == lbm.FP64 else 1e-5
+    for n in NAMES:
+        assert abs(a[n] - b[n]) <= tol * max(abs(a[n]), 1e-300) + 1e-300, (n, a[n], b[n])
+    ra, rb = a["rho0"].cpu().numpy(), b["rho0"].cpu().numpy()
+    assert np.abs(ra - rb).max() <= tol * np.abs(ra).max()
+
+
+def test_recorded_forward_keeps_reductions_and_limits(gpu_lib):
+    """Recording forward with reductions every 5 steps: the FP64 history matches a plain run;
+    stepping past the recorded capacity is refused before any launch."""
+    lbm = gpu_lib
+    e, s = lbm.eos_build(lbm.make_eos(**SMOOTH))
+    rho0 = droplet_density(70, 30, e.rho_v, e.rho_l, R=8, W=4)
+    P = lbm.make_params(70, 30, e, sigma=s, tau=TAU, reduce_every=5)
+    A = lbm.Lattice(P, rho0, device="cuda:0")
+    A.enable_recording(23)
+    A.step(23)
+    B = lbm.Lattice(P, rho0, device="cuda:0")
+    B.step(23)
+    ha, hb = A.history(), B.history()
+    assert ha.shape == hb.shape == (5, 4)
+    np.testing.assert_allclose(ha, hb, rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(A.populations().cpu().numpy(), B.populations().cpu().numpy(), rtol=1e-14, atol=0)
+    with pytest.raises(lbm.LbmError) as ei:
+        A.step(1)
+    assert ei.value.code == lbm.LBM_ESTATE
+
+
 def test_adjoint_error_paths(gpu_lib):
     lbm = gpu_lib
     e, s = lbm.eos_build(lbm.make_eos(**SMOOTH))
@@ -168,3 +212,8 @@ def test_rollout_autograd_matches_direct_adjoint(gpu_lib):
     np.testing.assert_array_equal(knots.grad.numpy(), [g[n] for n in NAMES[:4]])
     assert G.grad.item() == g["G"] and sig.grad.item() == g["sigma"]
     np.testing.assert_array_equal(r0.grad.cpu().numpy(), g["rho0"].cpu().numpy())
+    # the recording front end (K = None) gives the same gradients
+    spec_r = RolloutSpec(eos=el, nx=nx, ny=ny, steps=16, K=None, prec=lbm.FP64, params=dict(tau=TAU))
+    k2 = torch.tensor(knots_of(el), dtype=torch.float64, requires_grad=True)
+    (torch.as_tensor(w, device=rho.device) * rollout(k2, G.detach(), sig.detach(), r0.detach(), spec_r)).sum().backward()
+    np.testing.assert_allclose(k2.grad.numpy(), knots.grad.numpy(), rtol=1e-12)

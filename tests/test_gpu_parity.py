@@ -89,7 +89,7 @@ def test_fp64_shaped_eos_droplet(gpu_lib, shape_kw):
     assert rel_f_err(L, OL) < 1e-12
 
 
-@pytest.mark.parametrize("variant,band", VARIANTS, ids=VARIANT_IDS)
+@pytest.mark.parametrize("variant,band", VARIANTS_P, ids=VARIANT_IDS_P)
 def test_fp64_walls_variable_tau_moving_droplet(gpu_lib, variant, band):
     """Bounce-back walls with ghost psi, Eq. RelaxationTime, a moving droplet over a film."""
     kw = dict(Tr=0.6, a=0.387, shape=1, alpha=0.834, k_vap=2 / 0.387)
@@ -101,6 +101,21 @@ def test_fp64_walls_variable_tau_moving_droplet(gpu_lib, variant, band):
                            uy0=uy0, walls=True, wall=(e.rho_l, e.rho_v), var_tau=True, tau_l=tau_l,
                            tau_v=0.5 + 5 * (tau_l - 0.5), variant=variant, band_rows=band)
     assert rel_f_err(L, OL) < 1e-12
+
+
+@pytest.mark.parametrize("nx,ny,liquid_floor", [(61, 3, False), (60, 11, False), (7, 27, True), (130, 1, True)])
+def test_fp64_walls_two_step_short_channels(gpu_lib, nx, ny, liquid_floor):
+    """Walled lattices shorter than the two-step tile and its ring (1 to 27 rows; one row is a
+    wall row at both ends), a planar interface across x, after 1, 2 and 31 steps.  The floor's
+    solid density is rho_l where the channel is tall or short enough to stay stable with it."""
+    kw = dict(Tr=0.7)
+    e, _, _, _ = both_eos(gpu_lib, **kw)
+    rho0 = planar_density(nx, ny, e.rho_v, e.rho_l, W=5, axis=0)
+    rho0 = rho0 * (1 + 0.01 * random_field(nx, ny, 1.0, 1.0, seed=nx + 100 * ny))
+    wall = (e.rho_l if liquid_floor else e.rho_v, e.rho_v)
+    for steps in (1, 2, 31):
+        L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, steps, tau=TAU_MRT, walls=True, wall=wall, variant=3)
+        assert rel_f_err(L, OL) < 1e-12, (nx, ny, steps)
 
 
 @pytest.mark.parametrize("variant", [1, 2, 3], ids=["march", "block", "block2"])
@@ -282,8 +297,7 @@ def test_unstable_state_is_reported(gpu_lib):
 def test_invalid_parameters_rejected(gpu_lib):
     e, _ = gpu_lib.eos_build(gpu_lib.make_eos(Tr=0.7))
     for bad in (dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.5, 0.5]), dict(G=1.0), dict(prec=1, rho_ref=-1.0),
-                dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.8, 0.9]), dict(kernel_variant=3, walls=True),
-                dict(kernel_variant=4)):
+                dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.8, 0.9]), dict(kernel_variant=4)):
         P = gpu_lib.make_params(8, 8, e, **bad)
         with pytest.raises(gpu_lib.LbmError) as ei:
             gpu_lib.Lattice(P, np.full((8, 8), e.rho_v), device="cuda:0")
