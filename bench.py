@@ -281,8 +281,8 @@ def batched_leg(lbm, steps=20000, n_lattices=64, seed=0):
 def fd_leg(lbm, n=512, steps=2000, dt=0.2):
     """Finite-difference reference solver (MacCormack, FP64) on an n x n periodic droplet: C-S a=0.387 at
     Tr=0.6 with eps of the Li scheme (the paper's FD case), h = 1.  Algorithmic bytes per node and step:
-    predictor (rho, u, v in; 24 B out), corrector (predicted state and the old state in; 24 B out) =
-    120 B (psi and p_EOS are formed in LDS)."""
+    the state (rho, u, v) read once and written once = 48 B (one launch per step; the predicted state,
+    psi and p_EOS live in LDS)."""
     import torch
     from lbm_inputs import droplet_density
 
@@ -299,10 +299,10 @@ def fd_leg(lbm, n=512, steps=2000, dt=0.2):
     F.check()
     sec = ev[0].elapsed_time(ev[1]) / 1e3
     F.close()
-    gbs = 120.0 * n * n * steps / sec / 1e9
+    gbs = 48.0 * n * n * steps / sec / 1e9
     out = {"workload": "FD MacCormack %dx%d periodic droplet, C-S a=0.387 Tr=0.6, h=1, dt=%g, FP64" % (n, n, dt),
            "us_per_step": sec * 1e6 / steps, "Mnode_steps_per_s": n * n * steps / sec / 1e6, "GB/s": gbs,
-           "frac_hbm_peak": gbs / HBM_PEAK_GBS, "bytes_per_node_step": 120, "launches_per_step": 2}
+           "frac_hbm_peak": gbs / HBM_PEAK_GBS, "bytes_per_node_step": 48, "launches_per_step": 1}
     print("# FD solver %dx%d: %.2f us/step, %.0f Mnode-steps/s, %.0f GB/s algorithmic" % (
         n, n, out["us_per_step"], out["Mnode_steps_per_s"], gbs), file=sys.stderr, flush=True)
     return out

@@ -10,17 +10,16 @@
 // (forward in R+, backward in R-), second derivatives and every derivative of
 // psi in Eq. FDforce are central; viscosities from Eq. DynamicViscosity with
 // tau_nu(rho) of Eq. RelaxationTime (Eq. FDviscosityDerivative).
-// Two launches per step (predictor, corrector in place over Q^n: the corrector
-// reads Q^n only at its own node).  Each workgroup owns a 32 x 8 tile and first
-// evaluates p_EOS and psi of its tile plus a two-node halo into LDS (Eq. FDforce
-// reaches two nodes out through the Laplacian of psi), then every thread forms
-// its node's right-hand side from LDS (psi, p) and the state (radius one).
+// One launch per step: each workgroup evaluates the predictor on its tile grown
+// by two nodes in LDS and then the corrector on the tile, writing the new state
+// to the second state buffer (the two buffers swap roles every step).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 
 #include "lbm.h"
 #include "lbm_device.h"
@@ -61,70 +60,40 @@ __device__ __forceinline__ double fd_psi(const FdArgs& A, double r)
     return q > 0.0 ? sqrt(q) : 0.0;
 }
 
-constexpr int kTx = 32, kTy = 8, kHalo = 2;
-constexpr int kLx = kTx + 2 * kHalo, kLy = kTy + 2 * kHalo;
+// One MacCormack step per launch.  A workgroup owns a kTx x kTy output tile.
+// LDS holds the state, p_EOS and psi on the tile grown by 4 (region R4; the
+// predictor at the tile grown by 2 reaches two more nodes through the
+// Laplacian of psi in Eq. FDforce), then the predicted state, p_EOS and psi
+// on the tile grown by 2 (region R2).  Ghost rows beyond the walls are
+// written into both regions by the wall rules, so every stencil reads LDS
+// with the same offsets.  Traffic per node-step: the state read once (plus
+// the four-node ring, mostly from L2) and written once.
+constexpr int kTx = 32, kTy = 16;
+constexpr int kAx = kTx + 8, kAy = kTy + 8;   // R4
+constexpr int kBx = kTx + 4, kBy = kTy + 4;   // R2
 
-// out = a * base + b * (Q + dt R_DIR(Q)) at every node
-template <int DIR>
-__global__ __launch_bounds__(kTx * kTy) void k_fd_stage(FdArgs A, const double* rho, const double* u, const double* v,
-                                                        const double* base_r, const double* base_u,
-                                                        const double* base_v, double wa, double wb, double* o_r,
-                                                        double* o_u, double* o_v)
+// right-hand sides of the mass equation and Eq. FDmomentum at LDS node (a, b)
+// of arrays with row pitch P: one-sided first derivatives (DIR), central second
+// derivatives, and Eq. FDforce from psi with central differences
+template <int DIR, int P>
+__device__ __forceinline__ void fd_rhs(const FdArgs& A, const double* R, const double* U, const double* V,
+                                       const double* Pe, const double* S, int a, int b, double& dr, double& du,
+                                       double& dv)
 {
-    __shared__ double spsi[kLy][kLx], spe[kLy][kLx];
-    const int tid = threadIdx.y * kTx + threadIdx.x;
-    const int i0 = blockIdx.x * kTx, j0 = blockIdx.y * kTy;
-    // p_EOS and psi (Eq. InteractionPotential) of the tile and its halo
-    for (int q = tid; q < kLx * kLy; q += kTx * kTy) {
-        const int ti = q % kLx, tj = q / kLx;
-        int gi = (i0 + ti - kHalo) % A.nx;
-        gi = gi < 0 ? gi + A.nx : gi;
-        int gj = j0 + tj - kHalo;
-        if (A.walls && gj < 0) {
-            // b1 on the bottom wall (psi, rho extrapolated from rows 0 and 1), b2 inside it (Eq. B2)
-            const double r0 = rho[gi], r1 = rho[(size_t)A.nx + gi];
-            const double b1 = 2.0 * fd_psi(A, r0) - fd_psi(A, r1);
-            spe[tj][ti] = dev_eos_p(A.eos, 2.0 * r0 - r1);
-            spsi[tj][ti] = gj == -1 ? b1 : b1 + 2.0 * A.h * (A.psi_wall - b1);
-            continue;
-        }
-        if (A.walls && gj >= A.ny) gj = max(2 * (A.ny - 1) - gj, 0);  // reflexive top layers
-        gj %= A.ny;
-        gj = gj < 0 ? gj + A.ny : gj;
-        const double r = rho[(size_t)gj * A.nx + gi];
-        const double pe = dev_eos_p(A.eos, r);
-        const double qq = (pe - r * (1.0 / 3.0)) * A.two_inv_G;
-        const int rj = j0 + tj - kHalo;
-        if ((!A.walls || (rj >= 0 && rj < A.ny)) && (!(r > 0.0) || !(qq >= 0.0))) fd_flag(A);
-        spe[tj][ti] = pe;
-        spsi[tj][ti] = qq > 0.0 ? sqrt(qq) : 0.0;
-    }
-    __syncthreads();
-    const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
-    if (i >= A.nx || j >= A.ny) return;
-    const int li = threadIdx.x + kHalo, lj = threadIdx.y + kHalo;
-    // neighbours: periodic in x; in y periodic or the wall layers (b1 below row 0: u = v = 0 and rho
-    // extrapolated; above row ny-1 the mirror of row ny-2 with u, v reversed)
-    const bool wbot = A.walls && j == 0, wtop = A.walls && j == A.ny - 1;
-    const int ip = i + 1 == A.nx ? 0 : i + 1, im = i == 0 ? A.nx - 1 : i - 1;
-    const int jp = wtop ? A.ny - 2 : (j + 1 == A.ny ? 0 : j + 1), jm = wbot ? 0 : (j == 0 ? A.ny - 1 : j - 1);
-    const double fm = wbot ? 0.0 : 1.0, fp = wtop ? -1.0 : 1.0;
-    const size_t nxs = (size_t)A.nx;
-    const size_t c = j * nxs + i, xp = j * nxs + ip, xm = j * nxs + im, yp = jp * nxs + i, ym = jm * nxs + i;
-    const size_t pp = jp * nxs + ip, pm = jm * nxs + ip, mp = jp * nxs + im, mm = jm * nxs + im;
+    const int c = b * P + a;
     const double cs2 = 1.0 / 3.0;
-    const double r = rho[c], ux = u[c], uy = v[c];
-    const double r_yp = rho[yp], r_ym = wbot ? 2.0 * r - rho[nxs + i] : rho[ym];
-    const double u_yp = fp * u[yp], u_ym = fm * u[ym], v_yp = fp * v[yp], v_ym = fm * v[ym];
+    const double r = R[c], ux = U[c], uy = V[c];
     // one-sided first derivatives
-    const double rx = (DIR > 0 ? rho[xp] - r : r - rho[xm]) * A.inv_h;
-    const double ry = (DIR > 0 ? r_yp - r : r - r_ym) * A.inv_h;
-    const double u_x = (DIR > 0 ? u[xp] - ux : ux - u[xm]) * A.inv_h, u_y = (DIR > 0 ? u_yp - ux : ux - u_ym) * A.inv_h;
-    const double v_x = (DIR > 0 ? v[xp] - uy : uy - v[xm]) * A.inv_h, v_y = (DIR > 0 ? v_yp - uy : uy - v_ym) * A.inv_h;
-    const double px = (DIR > 0 ? spe[lj][li + 1] - spe[lj][li] : spe[lj][li] - spe[lj][li - 1]) * A.inv_h;
-    const double py = (DIR > 0 ? spe[lj + 1][li] - spe[lj][li] : spe[lj][li] - spe[lj - 1][li]) * A.inv_h;
+    const double rx = (DIR > 0 ? R[c + 1] - r : r - R[c - 1]) * A.inv_h;
+    const double ry = (DIR > 0 ? R[c + P] - r : r - R[c - P]) * A.inv_h;
+    const double u_x = (DIR > 0 ? U[c + 1] - ux : ux - U[c - 1]) * A.inv_h;
+    const double u_y = (DIR > 0 ? U[c + P] - ux : ux - U[c - P]) * A.inv_h;
+    const double v_x = (DIR > 0 ? V[c + 1] - uy : uy - V[c - 1]) * A.inv_h;
+    const double v_y = (DIR > 0 ? V[c + P] - uy : uy - V[c - P]) * A.inv_h;
+    const double px = (DIR > 0 ? Pe[c + 1] - Pe[c] : Pe[c] - Pe[c - 1]) * A.inv_h;
+    const double py = (DIR > 0 ? Pe[c + P] - Pe[c] : Pe[c] - Pe[c - P]) * A.inv_h;
     const double div = u_x + v_y;
-    const double dr = -(r * div + ux * rx + uy * ry);
+    dr = -(r * div + ux * rx + uy * ry);
     // Eq. DynamicViscosity, Eq. RelaxationTime and Eq. FDviscosityDerivative
     double tn = A.tau_nu, dtn = 0.0;
     if (A.var_tau) {
@@ -137,28 +106,26 @@ __global__ __launch_bounds__(kTx * kTy) void k_fd_stage(FdArgs A, const double* 
     const double muB = r * cs2 * (A.tau_e - tn), dmuB = cs2 * (A.tau_e - tn) - r * cs2 * dtn;
     const double mux = dmu * rx, muy = dmu * ry, mBx = dmuB * rx, mBy = dmuB * ry;
     // central second derivatives of the velocity
-    const double u_xx = (u[xp] - 2.0 * ux + u[xm]) * A.inv_h2, u_yy = (u_yp - 2.0 * ux + u_ym) * A.inv_h2;
-    const double v_xx = (v[xp] - 2.0 * uy + v[xm]) * A.inv_h2, v_yy = (v_yp - 2.0 * uy + v_ym) * A.inv_h2;
-    const double u_xy = (fp * u[pp] - fm * u[pm] - fp * u[mp] + fm * u[mm]) * A.inv_4h2;
-    const double v_xy = (fp * v[pp] - fm * v[pm] - fp * v[mp] + fm * v[mm]) * A.inv_4h2;
+    const double u_xx = (U[c + 1] - 2.0 * ux + U[c - 1]) * A.inv_h2, u_yy = (U[c + P] - 2.0 * ux + U[c - P]) * A.inv_h2;
+    const double v_xx = (V[c + 1] - 2.0 * uy + V[c - 1]) * A.inv_h2, v_yy = (V[c + P] - 2.0 * uy + V[c - P]) * A.inv_h2;
+    const double u_xy = (U[c + P + 1] - U[c - P + 1] - U[c + P - 1] + U[c - P - 1]) * A.inv_4h2;
+    const double v_xy = (V[c + P + 1] - V[c - P + 1] - V[c + P - 1] + V[c - P - 1]) * A.inv_4h2;
     // divergence of the viscous stress (Eq. FDstressTensor)
     const double Sx = mux * (2.0 * u_x) + muy * (v_x + u_y) + mu * (2.0 * u_xx + u_yy + v_xy) + mBx * div +
                       muB * (u_xx + v_xy);
     const double Sy = mux * (u_y + v_x) + muy * (2.0 * v_y) + mu * (v_xx + 2.0 * v_yy + u_xy) + mBy * div +
                       muB * (u_xy + v_yy);
     // Eq. FDforce, central differences of psi (the Laplacian at x+-1, y+-1 reaches two nodes out)
-    const double s0 = spsi[lj][li], sxp = spsi[lj][li + 1], sxm = spsi[lj][li - 1];
-    const double syp = spsi[lj + 1][li], sym = spsi[lj - 1][li];
-    const double spp = spsi[lj + 1][li + 1], spm = spsi[lj - 1][li + 1], smp = spsi[lj + 1][li - 1];
-    const double smm = spsi[lj - 1][li - 1];
+    const double s0 = S[c], sxp = S[c + 1], sxm = S[c - 1], syp = S[c + P], sym = S[c - P];
+    const double spp = S[c + P + 1], spm = S[c - P + 1], smp = S[c + P - 1], smm = S[c - P - 1];
     const double sx = (sxp - sxm) * A.inv_2h, sy = (syp - sym) * A.inv_2h;
     const double sxx = (sxp - 2.0 * s0 + sxm) * A.inv_h2, syy = (syp - 2.0 * s0 + sym) * A.inv_h2;
     const double sxy = (spp - spm - smp + smm) * A.inv_4h2;
     const double L = sxx + syy;
-    const double Lxp = (spsi[lj][li + 2] - 2.0 * sxp + s0) * A.inv_h2 + (spp - 2.0 * sxp + spm) * A.inv_h2;
-    const double Lxm = (s0 - 2.0 * sxm + spsi[lj][li - 2]) * A.inv_h2 + (smp - 2.0 * sxm + smm) * A.inv_h2;
-    const double Lyp = (spp - 2.0 * syp + smp) * A.inv_h2 + (spsi[lj + 2][li] - 2.0 * syp + s0) * A.inv_h2;
-    const double Lym = (spm - 2.0 * sym + smm) * A.inv_h2 + (s0 - 2.0 * sym + spsi[lj - 2][li]) * A.inv_h2;
+    const double Lxp = (S[c + 2] - 2.0 * sxp + s0) * A.inv_h2 + (spp - 2.0 * sxp + spm) * A.inv_h2;
+    const double Lxm = (s0 - 2.0 * sxm + S[c - 2]) * A.inv_h2 + (smp - 2.0 * sxm + smm) * A.inv_h2;
+    const double Lyp = (spp - 2.0 * syp + smp) * A.inv_h2 + (S[c + 2 * P] - 2.0 * syp + s0) * A.inv_h2;
+    const double Lym = (spm - 2.0 * sym + smm) * A.inv_h2 + (s0 - 2.0 * sym + S[c - 2 * P]) * A.inv_h2;
     const double Lx = (Lxp - Lxm) * A.inv_2h, Ly = (Lyp - Lym) * A.inv_2h;
     const double gx = sx * sxx + sy * sxy, gy = sx * sxy + sy * syy;
     const double G = A.G;
@@ -166,18 +133,107 @@ __global__ __launch_bounds__(kTx * kTy) void k_fd_stage(FdArgs A, const double* 
     const double Py = -A.eps * G * 0.25 * gy + G * (1.0 / 12.0) * sy * L + G * (1.0 / 6.0) * gy + G * 0.25 * s0 * Ly;
     // Eq. FDmomentum
     const double inv_r = 1.0 / r;
-    const double du = -(ux * u_x + uy * u_y) + (Sx - px - Px) * inv_r;
-    const double dv = -(ux * v_x + uy * v_y) + (Sy - py - Py) * inv_r;
-    const double nr = r + A.dt * dr, nu = ux + A.dt * du, nv = uy + A.dt * dv;
-    if (base_r) {
-        o_r[c] = wa * base_r[c] + wb * nr;
-        o_u[c] = wa * base_u[c] + wb * nu;
-        o_v[c] = wa * base_v[c] + wb * nv;
-    } else {
-        o_r[c] = nr;
-        o_u[c] = nu;
-        o_v[c] = nv;
+    du = -(ux * u_x + uy * u_y) + (Sx - px - Px) * inv_r;
+    dv = -(ux * v_x + uy * v_y) + (Sy - py - Py) * inv_r;
+}
+
+// Ghost rows of a region (pitch P, rows b with global row gj = j_base + b) from its
+// fluid rows: b1 (gj = -1): rho and psi extrapolated, u = v = 0, p = p_EOS(rho_b1);
+// b2 (gj = -2): psi of Eq. B2 only; above row ny-1: the mirror of rows ny-2, ny-3
+// with u, v reversed.  Periodic lattices have no ghost rows.
+template <int P, int NY>
+__device__ __forceinline__ void fd_ghost_rows(const FdArgs& A, double* R, double* U, double* V, double* Pe,
+                                              double* S, int j_base, int tid, int nthreads)
+{
+    for (int q = tid; q < P * NY; q += nthreads) {
+        const int a = q % P, b = q / P, gj = j_base + b;
+        const int c = b * P + a;
+        if (gj == -1 || gj == -2) {
+            const int c0 = (0 - j_base) * P + a, c1 = c0 + P;  // rows 0 and 1 (inside the region)
+            const double b1 = 2.0 * S[c0] - S[c1];
+            if (gj == -1) {
+                R[c] = 2.0 * R[c0] - R[c1];
+                U[c] = 0.0;
+                V[c] = 0.0;
+                Pe[c] = dev_eos_p(A.eos, R[c]);
+                S[c] = b1;
+            } else {
+                S[c] = b1 + 2.0 * A.h * (A.psi_wall - b1);
+            }
+        } else if (gj >= A.ny && gj <= A.ny + 1) {
+            const int cm = (2 * (A.ny - 1) - gj - j_base) * P + a;
+            R[c] = R[cm];
+            U[c] = -U[cm];
+            V[c] = -V[cm];
+            Pe[c] = Pe[cm];
+            S[c] = S[cm];
+        }
     }
+}
+
+__global__ __launch_bounds__(kTx * kTy) void k_fd_step(FdArgs A, const double* rho, const double* u, const double* v,
+                                                       double* o_r, double* o_u, double* o_v)
+{
+    __shared__ double aR[kAy * kAx], aU[kAy * kAx], aV[kAy * kAx], aP[kAy * kAx], aS[kAy * kAx];
+    __shared__ double bR[kBy * kBx], bU[kBy * kBx], bV[kBy * kBx], bP[kBy * kBx], bS[kBy * kBx];
+    const int nt = kTx * kTy, tid = threadIdx.y * kTx + threadIdx.x;
+    const int i0 = blockIdx.x * kTx, j0 = blockIdx.y * kTy;
+    // 1. the state, p_EOS and psi on R4; the rows beyond the walls are filled afterwards
+    for (int q = tid; q < kAx * kAy; q += nt) {
+        const int a = q % kAx, b = q / kAx;
+        int gi = (i0 - 4 + a) % A.nx;
+        gi = gi < 0 ? gi + A.nx : gi;
+        int gj = j0 - 4 + b;
+        if (A.walls && (gj < 0 || gj >= A.ny)) continue;
+        gj %= A.ny;
+        gj = gj < 0 ? gj + A.ny : gj;
+        const size_t g = (size_t)gj * A.nx + gi;
+        const double r = rho[g];
+        const double pe = dev_eos_p(A.eos, r);
+        const double qq = (pe - r * (1.0 / 3.0)) * A.two_inv_G;
+        if (!(r > 0.0) || !(qq >= 0.0)) fd_flag(A);
+        aR[q] = r;
+        aU[q] = u[g];
+        aV[q] = v[g];
+        aP[q] = pe;
+        aS[q] = qq > 0.0 ? sqrt(qq) : 0.0;
+    }
+    __syncthreads();
+    if (A.walls) {
+        fd_ghost_rows<kAx, kAy>(A, aR, aU, aV, aP, aS, j0 - 4, tid, nt);
+        __syncthreads();
+    }
+    // 2. predictor Q* = Q + dt R+(Q) on the fluid nodes of R2
+    for (int q = tid; q < kBx * kBy; q += nt) {
+        const int a = q % kBx, b = q / kBx, gj = j0 - 2 + b;
+        if (A.walls && (gj < 0 || gj >= A.ny)) continue;
+        double dr, du, dv;
+        fd_rhs<+1, kAx>(A, aR, aU, aV, aP, aS, a + 2, b + 2, dr, du, dv);
+        const int c = (b + 2) * kAx + a + 2;
+        const double nr = aR[c] + A.dt * dr;
+        bR[q] = nr;
+        bU[q] = aU[c] + A.dt * du;
+        bV[q] = aV[c] + A.dt * dv;
+        const double pe = dev_eos_p(A.eos, nr);
+        const double qq = (pe - nr * (1.0 / 3.0)) * A.two_inv_G;
+        bP[q] = pe;
+        bS[q] = qq > 0.0 ? sqrt(qq) : 0.0;
+    }
+    __syncthreads();
+    if (A.walls) {
+        fd_ghost_rows<kBx, kBy>(A, bR, bU, bV, bP, bS, j0 - 2, tid, nt);
+        __syncthreads();
+    }
+    // 3. corrector Q^{n+1} = (Q + Q* + dt R-(Q*)) / 2 on the tile
+    const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
+    if (i >= A.nx || j >= A.ny) return;
+    double dr, du, dv;
+    fd_rhs<-1, kBx>(A, bR, bU, bV, bP, bS, threadIdx.x + 2, threadIdx.y + 2, dr, du, dv);
+    const int cb = (threadIdx.y + 2) * kBx + threadIdx.x + 2, ca = (threadIdx.y + 4) * kAx + threadIdx.x + 4;
+    const size_t g = (size_t)j * A.nx + i;
+    o_r[g] = 0.5 * aR[ca] + 0.5 * (bR[cb] + A.dt * dr);
+    o_u[g] = 0.5 * aU[ca] + 0.5 * (bU[cb] + A.dt * du);
+    o_v[g] = 0.5 * aV[ca] + 0.5 * (bV[cb] + A.dt * dv);
 }
 
 FdArgs fd_args(const lbm_fd_ctx* c)
@@ -290,13 +346,13 @@ int lbm_fd_step(lbm_fd_ctx* c, int64_t nsteps, void* stream)
     const dim3 blk(kTx, kTy), grd((c->P.nx + kTx - 1) / kTx, (c->P.ny + kTy - 1) / kTy);
     for (int64_t t = 0; t < nsteps; ++t) {
         FdArgs A = fd_args(c);
-        hipLaunchKernelGGL(k_fd_stage<+1>, grd, blk, 0, s, A, (const double*)c->rho, (const double*)c->u,
-                           (const double*)c->v, (const double*)nullptr, (const double*)nullptr,
-                           (const double*)nullptr, 0.0, 1.0, c->rs, c->us, c->vs);
-        hipLaunchKernelGGL(k_fd_stage<-1>, grd, blk, 0, s, A, (const double*)c->rs, (const double*)c->us,
-                           (const double*)c->vs, (const double*)c->rho, (const double*)c->u, (const double*)c->v,
-                           0.5, 0.5, c->rho, c->u, c->v);
+        hipLaunchKernelGGL(k_fd_step, grd, blk, 0, s, A, (const double*)c->rho, (const double*)c->u,
+                           (const double*)c->v, c->rs, c->us, c->vs);
         if (!ok(hipGetLastError(), "fd step launch")) return LBM_EHIP;
+        // the new state is in (rs, us, vs): swap the roles of the two state buffers
+        std::swap(c->rho, c->rs);
+        std::swap(c->u, c->us);
+        std::swap(c->v, c->vs);
         c->step++;
     }
     return LBM_OK;
