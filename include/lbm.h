@@ -239,8 +239,18 @@ int lbm_batch_layout(int B, const lbm_params* p, size_t* pop_bytes_out, size_t* 
  * float64 fields (ux0, uy0 may be NULL).  Validates every lattice. */
 int lbm_init_batched(lbm_batch** ctx, int B, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes,
                      const double* rho0, const double* ux0, const double* uy0, void* stream);
-/* nsteps time steps of every lattice in one persistent launch (asynchronous). */
+/* nsteps time steps of every lattice (asynchronous).  Persistent mode: one
+ * launch in which one workgroup per lattice loops over the steps.  Grouped
+ * mode: one launch per step with one wavefront per (lattice, 62-column
+ * strip, row), replayed as HIP graphs of 64 steps.  Launches replayed from a
+ * graph keep the step numbers of their capture, so the step that
+ * lbm_status_batched names is exact only within the first capture. */
 int lbm_step_batched(lbm_batch* ctx, int64_t nsteps, void* stream);
+/* Choose how lbm_step_batched runs: LBM_BATCH_AUTO (default: grouped when some
+ * lattice has more than 32 strip-rows, i.e. more than two per wavefront of
+ * its persistent workgroup), LBM_BATCH_PERSISTENT or LBM_BATCH_GROUPED. */
+typedef enum { LBM_BATCH_AUTO = 0, LBM_BATCH_PERSISTENT = 1, LBM_BATCH_GROUPED = 2 } lbm_batch_mode;
+int lbm_set_batch_mode(lbm_batch* ctx, int mode);
 /* Packed rho and forced u of every lattice (outputs may be NULL); synchronises. */
 int lbm_macros_batched(lbm_batch* ctx, double* rho, double* ux, double* uy, void* stream);
 /* LBM_EUNSTABLE if any lattice met psi^2 < 0; first_bad_out = its index or -1. */

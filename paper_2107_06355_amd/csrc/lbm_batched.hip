@@ -1,9 +1,14 @@
-// liblbm.so: many independent small lattices advanced by ONE persistent launch.
+// liblbm.so: many independent lattices advanced together, in one of two ways.
 //
-// Each lattice (its own size, EOS, relaxation times and FP32 shift) is owned
-// by one workgroup of 16 wavefronts that loops over the time steps with a
-// workgroup barrier between steps: neighbouring nodes of a lattice are only
-// ever touched by that workgroup, so no grid-wide synchronisation is needed.
+// Persistent: each lattice (its own size, EOS, relaxation times and FP32
+// shift) is owned by one workgroup of 16 wavefronts that loops over the time
+// steps with a workgroup barrier between steps: neighbouring nodes of a
+// lattice are only ever touched by that workgroup, so no grid-wide
+// synchronisation is needed.  Best for many small lattices (no launch per step).
+// Grouped: one launch per time step over all lattices, one wavefront per
+// (lattice, 62-column strip, row); the launches of a chunk of steps are
+// replayed as a HIP graph.  Best when a large lattice would keep one
+// workgroup busy for many items per step while most CUs idle.
 // Populations of all lattices are packed back to back in one pair of buffers;
 // scalar fields are packed in the same lattice order ([ny_b][nx_b] each).
 // The per-node arithmetic is the fused step of lbm_device.h: pull with
@@ -85,6 +90,52 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_batch(const BatchItem* ite
     }
 }
 
+// One step of every lattice: wave w takes item w of the concatenated item lists
+// (lattice b owns items [item_off[b], item_off[b+1]), item = strip + strips * row).
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_step(const BatchItem* items, const int* item_off, int B, char* buf0,
+                                                    char* buf1, int cur, long long step)
+{
+    const int w = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= item_off[B]) return;
+    int lo = 0, hi = B;  // item_off[lo] <= w < item_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (item_off[mid] <= w) lo = mid;
+        else hi = mid;
+    }
+    StepArgs A = items[lo].A;
+    const size_t off = items[lo].off_bytes;
+    A.src = (cur ? buf1 : buf0) + off;
+    A.dst = (cur ? buf0 : buf1) + off;
+    A.step = step;
+    const int item = w - item_off[lo];
+    const int strip = item % A.strips, y = item / A.strips;
+    Lane L;
+    L.lane = threadIdx.x & 63;
+    const int x0 = strip * kStripW;
+    const int W = min(kStripW, A.nx - x0);
+    const int xr = x0 - 1 + L.lane;
+    L.valid = L.lane <= W + 1;
+    L.interior = L.lane >= 1 && L.lane <= W;
+    int x = xr < 0 ? xr + A.nx : (xr >= A.nx ? xr - A.nx : xr);
+    if (!L.valid) x = 0;
+    L.x = x;
+    L.xm = x == 0 ? A.nx - 1 : x - 1;
+    L.xp = x == A.nx - 1 ? 0 : x + 1;
+    const View<T> V = make_view<T>(A.src, A.plane);
+    Row<T> Rm, Rc, Rp;
+    pull<T>(V, A, L.x, L.xm, L.xp, load_index(A, y - 1), Rm.g0, Rm.g);
+    pull<T>(V, A, L.x, L.xm, L.xp, y, Rc.g0, Rc.g);
+    pull<T>(V, A, L.x, L.xm, L.xp, load_index(A, y + 1), Rp.g0, Rp.g);
+    const double dm = node_drho<T>(Rm.g0, Rm.g), dc = node_drho<T>(Rc.g0, Rc.g), dp = node_drho<T>(Rp.g0, Rp.g);
+    const T psm = (A.walls && y == 0) ? (T)A.psi_lo : node_psi<T>(A, dm, L.valid);
+    const T psc = node_psi<T>(A, dc, L.valid);
+    const T psp = (A.walls && y == A.ny - 1) ? (T)A.psi_hi : node_psi<T>(A, dp, L.valid);
+    Acc acc = {0.0, 0.0, 0.0};
+    collide_row<T, MODE_STEP>(A, L, y, Rc, dc, psm, psc, psp, acc);
+}
+
 template <typename T>
 __global__ void k_batch_init(const BatchItem* items, char* buf0, const double* rho0, const double* ux0,
                              const double* uy0)
@@ -135,7 +186,8 @@ struct Layout {
     std::vector<size_t> off;        // [B+1] byte offsets in a population buffer
     std::vector<long long> cells;   // [B+1] cell offsets in the packed fields
     std::vector<int> ld;
-    size_t ws_bytes;
+    std::vector<int> item_off;      // [B+1] grouped-step items (strips x rows) before each lattice
+    size_t off_items, off_item_off, ws_bytes;
 };
 
 int batch_layout(int B, const lbm_params* p, Layout& L)
@@ -147,6 +199,7 @@ int batch_layout(int B, const lbm_params* p, Layout& L)
     L.off.assign(B + 1, 0);
     L.cells.assign(B + 1, 0);
     L.ld.assign(B, 0);
+    L.item_off.assign(B + 1, 0);
     for (int b = 0; b < B; ++b) {
         if (p[b].prec != p[0].prec) {
             lbm_set_error("lbm batched: every lattice must use the same storage precision");
@@ -161,9 +214,18 @@ int batch_layout(int B, const lbm_params* p, Layout& L)
         L.ld[b] = ld;
         L.off[b + 1] = L.off[b] + ((bytes + 255) & ~(size_t)255);
         L.cells[b + 1] = L.cells[b] + (long long)p[b].nx * p[b].ny;
+        const long long items = (long long)((p[b].nx + kStripW - 1) / kStripW) * p[b].ny;
+        if (L.item_off[b] + items >= (1LL << 31)) {
+            lbm_set_error("lbm batched: too many rows x strips in one batch");
+            return LBM_EINVAL;
+        }
+        L.item_off[b + 1] = L.item_off[b] + (int)items;
     }
-    // workspace: per-lattice error words, then the item records
-    L.ws_bytes = (((size_t)B * 2 * sizeof(unsigned) + 255) & ~(size_t)255) + (size_t)B * sizeof(BatchItem) + 256;
+    // workspace: per-lattice error words, the item records, the grouped-step item offsets
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    L.off_items = al((size_t)B * 2 * sizeof(unsigned));
+    L.off_item_off = L.off_items + al((size_t)B * sizeof(BatchItem));
+    L.ws_bytes = L.off_item_off + al((size_t)(B + 1) * sizeof(int));
     return LBM_OK;
 }
 
@@ -178,10 +240,25 @@ struct lbm_batch {
     int64_t step;
     unsigned* err;
     BatchItem* items;
+    int* item_off;          // device copy of Layout::item_off
+    int grouped;            // 1: one grouped launch per step; 0: persistent workgroups
     hipStream_t cap;        // capture stream (default priority)
-    hipGraphExec_t exec[2]; // one persistent launch of `graph_steps` steps, per starting buffer
+    hipGraphExec_t exec[2]; // per starting buffer: the persistent launch of `graph_steps` steps, or
+                            // kGroupChunk grouped launches
     int64_t graph_steps;
 };
+
+namespace {
+constexpr int kGroupChunk = 64;  // grouped launches per replayed graph (even: buffer parity is kept)
+
+// persistent unless some lattice gives one workgroup more than two items per wave and step
+int auto_grouped(const Layout& L, int B)
+{
+    for (int b = 0; b < B; ++b)
+        if (L.item_off[b + 1] - L.item_off[b] > 2 * kBatchWaves) return 1;
+    return 0;
+}
+}  // namespace
 
 extern "C" {
 
@@ -217,7 +294,9 @@ int lbm_init_batched(lbm_batch** out, int B, const lbm_params* p, void* f_a, voi
     c->buf[0] = (char*)f_a;
     c->buf[1] = (char*)f_b;
     c->err = (unsigned*)ws;
-    c->items = (BatchItem*)((char*)ws + (((size_t)B * 2 * sizeof(unsigned) + 255) & ~(size_t)255));
+    c->items = (BatchItem*)((char*)ws + L.off_items);
+    c->item_off = (int*)((char*)ws + L.off_item_off);
+    c->grouped = auto_grouped(L, B);
     std::vector<BatchItem> host(B);
     std::vector<unsigned> err0(2 * (size_t)B);
     for (int b = 0; b < B; ++b) {
@@ -259,6 +338,8 @@ int lbm_init_batched(lbm_batch** out, int B, const lbm_params* p, void* f_a, voi
     }
     hipStream_t s = (hipStream_t)stream;
     if (!hip_ok(hipMemcpyAsync(c->items, host.data(), sizeof(BatchItem) * B, hipMemcpyHostToDevice, s), "batch items") ||
+        !hip_ok(hipMemcpyAsync(c->item_off, L.item_off.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, s),
+                "batch item offsets") ||
         !hip_ok(hipMemcpyAsync(c->err, err0.data(), sizeof(unsigned) * 2 * B, hipMemcpyHostToDevice, s), "batch errors") ||
         !hip_ok(hipStreamSynchronize(s), "batch init sync")) {
         delete c;
@@ -279,6 +360,23 @@ int lbm_init_batched(lbm_batch** out, int B, const lbm_params* p, void* f_a, voi
     return LBM_OK;
 }
 
+// n grouped launches (one per step) starting from buffer cur at step step0
+static bool launch_grouped(lbm_batch* c, int n, int cur, int64_t step0, hipStream_t s)
+{
+    const int total = c->L.item_off[c->B];
+    const dim3 g((total + 3) / 4), b(256);
+    for (int k = 0; k < n; ++k) {
+        if (c->prec == LBM_FP32_SHIFTED)
+            hipLaunchKernelGGL(k_batch_step<float>, g, b, 0, s, (const BatchItem*)c->items, (const int*)c->item_off, c->B,
+                               c->buf[0], c->buf[1], cur, (long long)(step0 + k));
+        else
+            hipLaunchKernelGGL(k_batch_step<double>, g, b, 0, s, (const BatchItem*)c->items, (const int*)c->item_off,
+                               c->B, c->buf[0], c->buf[1], cur, (long long)(step0 + k));
+        cur ^= 1;
+    }
+    return hip_ok(hipGetLastError(), "k_batch_step launch");
+}
+
 static bool launch_batch(lbm_batch* c, int64_t nsteps, hipStream_t s)
 {
     if (c->prec == LBM_FP32_SHIFTED)
@@ -292,11 +390,59 @@ static bool launch_batch(lbm_batch* c, int64_t nsteps, hipStream_t s)
     return hip_ok(hipGetLastError(), "k_batch launch");
 }
 
+int lbm_set_batch_mode(lbm_batch* c, int mode)
+{
+    if (!c || mode < LBM_BATCH_AUTO || mode > LBM_BATCH_GROUPED) return LBM_EINVAL;
+    const int g = mode == LBM_BATCH_AUTO ? auto_grouped(c->L, c->B) : (mode == LBM_BATCH_GROUPED);
+    if (g != c->grouped) {
+        for (int k = 0; k < 2; ++k)
+            if (c->exec[k]) {
+                (void)hipGraphExecDestroy(c->exec[k]);
+                c->exec[k] = nullptr;
+            }
+        c->graph_steps = 0;
+        c->grouped = g;
+    }
+    return LBM_OK;
+}
+
+// grouped mode: graphs of kGroupChunk launches (one per starting buffer), the rest launched directly.
+// A graph bakes in the step numbers of its capture; they only label the error word's first
+// failing step, which is therefore exact for the first chunk of each parity and approximate after.
+static int step_grouped(lbm_batch* c, int64_t nsteps, hipStream_t s)
+{
+    int64_t done = 0;
+    while (nsteps - done >= kGroupChunk) {
+        if (!c->exec[c->cur]) {
+            hipGraph_t g = nullptr;
+            if (!hip_ok(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "batch capture begin"))
+                return LBM_EHIP;
+            const bool ok = launch_grouped(c, kGroupChunk, c->cur, c->step, c->cap);
+            if (!hip_ok(hipStreamEndCapture(c->cap, &g), "batch capture end") || !ok) return LBM_EHIP;
+            const bool inst =
+                hip_ok(hipGraphInstantiate(&c->exec[c->cur], g, nullptr, nullptr, 0), "batch graph instantiate");
+            (void)hipGraphDestroy(g);
+            if (!inst) return LBM_EHIP;
+        }
+        if (!hip_ok(hipGraphLaunch(c->exec[c->cur], s), "batch graph launch")) return LBM_EHIP;
+        c->step += kGroupChunk;
+        done += kGroupChunk;
+    }
+    const int rest = (int)(nsteps - done);
+    if (rest > 0) {
+        if (!launch_grouped(c, rest, c->cur, c->step, s)) return LBM_EHIP;
+        c->step += rest;
+        if (rest & 1) c->cur ^= 1;
+    }
+    return LBM_OK;
+}
+
 int lbm_step_batched(lbm_batch* c, int64_t nsteps, void* stream)
 {
     if (!c || nsteps < 0) return LBM_EINVAL;
     if (nsteps == 0) return LBM_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (c->grouped) return step_grouped(c, nsteps, s);
     // the persistent launch is captured once per (step count, starting buffer) and replayed
     if (c->graph_steps != nsteps) {
         for (int k = 0; k < 2; ++k)

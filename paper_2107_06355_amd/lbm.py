@@ -21,6 +21,7 @@ FP64, FP32_SHIFTED = 0, 1
 BASE_CS, BASE_PR = 0, 1
 SHAPE_NONE, SHAPE_SMOOTH, SHAPE_MODSMOOTH, SHAPE_PENG = 0, 1, 2, 3
 VARIANT_AUTO, VARIANT_MARCH, VARIANT_BLOCK, VARIANT_BLOCK2 = 0, 1, 2, 3
+BATCH_AUTO, BATCH_PERSISTENT, BATCH_GROUPED = 0, 1, 2
 
 
 class LbmEos(C.Structure):
@@ -94,6 +95,7 @@ def _signatures():
         "lbm_batch_layout": ([i, C.POINTER(LbmParams), C.POINTER(sz), C.POINTER(sz), C.POINTER(C.c_int64)], i),
         "lbm_init_batched": ([C.POINTER(vp), i, C.POINTER(LbmParams), vp, vp, vp, sz, vp, vp, vp, vp], i),
         "lbm_step_batched": ([vp, C.c_int64, vp], i),
+        "lbm_set_batch_mode": ([vp, i], i),
         "lbm_macros_batched": ([vp, vp, vp, vp, vp], i),
         "lbm_status_batched": ([vp, C.POINTER(C.c_int), vp], i),
         "lbm_destroy_batched": ([vp], None),
@@ -391,6 +393,10 @@ class Batch:
 
     def step(self, n: int):
         _check(load().lbm_step_batched(self._h, int(n), C.c_void_p(self.stream.cuda_stream)), "lbm_step_batched")
+
+    def set_mode(self, mode: int):
+        """BATCH_AUTO, BATCH_PERSISTENT (one workgroup per lattice) or BATCH_GROUPED (a launch per step)."""
+        _check(load().lbm_set_batch_mode(self._h, int(mode)), "lbm_set_batch_mode")
 
     def check(self):
         bad = C.c_int(-1)

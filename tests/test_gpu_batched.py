@@ -1,4 +1,5 @@
-"""Batched lattices (one persistent launch, one workgroup per lattice) against the oracle."""
+"""Batched lattices against the oracle, in both launch modes: persistent (one workgroup per
+lattice looping over the steps) and grouped (one launch per step over every lattice's rows)."""
 import numpy as np
 import pytest
 
@@ -50,8 +51,12 @@ def _oracle(kw_eos, nx, ny, extra, tau, kw, rho0, steps):
     return L.macros()
 
 
+MODES = [("persistent", 1), ("grouped", 2)]
+
+
+@pytest.mark.parametrize("mode", [m for _, m in MODES], ids=[n for n, _ in MODES])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batched_mixed_lattices_match_oracle(gpu_lib, prec):
+def test_batched_mixed_lattices_match_oracle(gpu_lib, prec, mode):
     lbm = gpu_lib
     P, rhos, meta = [], [], []
     pr = lbm.FP64 if prec == "fp64" else lbm.FP32_SHIFTED
@@ -63,9 +68,11 @@ def test_batched_mixed_lattices_match_oracle(gpu_lib, prec):
         rhos.append(r0)
         meta.append((kw_eos, nx, ny, extra, tau, kw))
     Bt = lbm.Batch(P, rhos, device="cuda:0")
-    steps = 60
+    Bt.set_mode(mode)
+    steps = 200
     Bt.step(25)
-    Bt.step(35)  # a second, different persistent launch (new graph)
+    Bt.step(35)  # a second, different launch (new graph)
+    Bt.step(140)  # grouped: two 64-step graph replays and 12 direct launches
     Bt.check()
     got = Bt.macros()
     for b, (kw_eos, nx, ny, extra, tau, kw) in enumerate(meta):
@@ -80,19 +87,43 @@ def test_batched_mixed_lattices_match_oracle(gpu_lib, prec):
             assert uerr < 1e-5, (b, uerr)
 
 
-def test_batched_graph_replay_is_deterministic(gpu_lib):
+@pytest.mark.parametrize("mode", [m for _, m in MODES], ids=[n for n, _ in MODES])
+def test_batched_graph_replay_is_deterministic(gpu_lib, mode):
     lbm = gpu_lib
     e, s = lbm.eos_build(lbm.make_eos(**dict(PR, Tr=0.6)))
     P = [lbm.make_params(n, 4, e, sigma=s, prec=lbm.FP32_SHIFTED) for n in (128, 300, 62, 63)]
     rhos = [planar_density(p.nx, 4, e.rho_v, e.rho_l, W=10, axis=0) for p in P]
     a = lbm.Batch(P, rhos, device="cuda:0")
     b = lbm.Batch(P, rhos, device="cuda:0")
+    a.set_mode(mode)
+    b.set_mode(mode)
     for _ in range(3):
-        a.step(11)       # replayed graph, odd step count (buffer parity flips)
-    b.step(33)
+        a.step(71)       # replayed graph, odd step count (buffer parity flips)
+    b.step(213)
     ma, mb = a.macros(), b.macros()
     for x, y in zip(ma, mb):
         assert np.array_equal(x["rho"], y["rho"]) and np.array_equal(x["ux"], y["ux"])
+
+
+def test_batched_modes_agree(gpu_lib):
+    """The two launch modes (and the automatic choice, grouped here: the 2044 x 4 lattice gives its
+    persistent workgroup 33 strips x 4 rows per step) run the same node arithmetic (FP64)."""
+    lbm = gpu_lib
+    e, s = lbm.eos_build(lbm.make_eos(**dict(PR, Tr=0.6)))
+    P = [lbm.make_params(n, 4, e, sigma=s) for n in (2044, 130, 8)]
+    rhos = [planar_density(p.nx, 4, e.rho_v, e.rho_l, W=10, axis=0) for p in P]
+    out = []
+    for mode in (1, 2, 0):
+        Bt = lbm.Batch(P, rhos, device="cuda:0")
+        Bt.set_mode(mode)
+        Bt.step(150)
+        Bt.check()
+        out.append(Bt.macros())
+    for b in range(len(P)):
+        for k in ("rho", "ux", "uy"):
+            scale = np.abs(out[0][b][k]).max() + 1e-300
+            assert np.abs(out[0][b][k] - out[1][b][k]).max() <= 1e-13 * scale, (b, k)
+            assert np.array_equal(out[1][b][k], out[2][b][k]), (b, k)
 
 
 def test_batched_coexistence_sweep(gpu_lib):
