@@ -239,8 +239,9 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
 
 
 def batched_leg(lbm, steps=20000, n_lattices=64, seed=0):
-    """Uneven batched planar sweep: 64 lattices 4 x L_b (L_b = 4 U{32..512}), Tr ~ U(0.35, 0.95), shaped PR,
-    FP32-shifted, one persistent launch per call; aggregate MLUPS and coexistence error against Maxwell."""
+    """Uneven batched planar sweep: 64 lattices L_b x 4 (L_b = 4 U{32..512}), Tr ~ U(0.35, 0.95), shaped PR,
+    FP32-shifted, in the library's automatic launch mode (grouped: one launch per step over every lattice's
+    rows); aggregate MLUPS and coexistence error against Maxwell."""
     import torch
     from lbm_inputs import batched_planar_recipe, planar_density
 
