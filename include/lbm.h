@@ -241,10 +241,12 @@ int lbm_init_batched(lbm_batch** ctx, int B, const lbm_params* p, void* f_a, voi
                      const double* rho0, const double* ux0, const double* uy0, void* stream);
 /* nsteps time steps of every lattice (asynchronous).  Persistent mode: one
  * launch in which one workgroup per lattice loops over the steps.  Grouped
- * mode: one launch per step with one wavefront per (lattice, 62-column
- * strip, row), replayed as HIP graphs of 64 steps.  Launches replayed from a
- * graph keep the step numbers of their capture, so the step that
- * lbm_status_batched names is exact only within the first capture. */
+ * mode: launches over all lattices at once, two steps per launch (whole
+ * columns per workgroup when every lattice is periodic and at most 16 rows
+ * tall, else the two-step tiles), an odd last step on its own, replayed as
+ * HIP graphs of 128 steps.  Launches replayed from a graph keep the step
+ * numbers of their capture, so the step that lbm_status_batched names is
+ * exact only within the first capture. */
 int lbm_step_batched(lbm_batch* ctx, int64_t nsteps, void* stream);
 /* Choose how lbm_step_batched runs: LBM_BATCH_AUTO (default: grouped when some
  * lattice has more than 32 strip-rows, i.e. more than two per wavefront of

@@ -136,6 +136,129 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchItem* items, cons
     collide_row<T, MODE_STEP>(A, L, y, Rc, dc, psm, psc, psp, acc);
 }
 
+// Two steps of every lattice: workgroup w takes two-step tile w of the concatenated tile
+// lists (lattice b owns tiles [tile_off[b], tile_off[b+1]), tile = strip + strips * band);
+// the tile arithmetic is step2_tile of the single-lattice two-step kernel.
+template <typename T, bool WALLS>
+__global__ __launch_bounds__(64 * k2Waves) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4)))
+void k_batch_step2(const BatchItem* items, const int* tile_off, int B, char* buf0, char* buf1, int cur, long long step)
+{
+    __shared__ Step2Lds<T> S;
+    const int w = blockIdx.x;
+    if (w >= tile_off[B]) return;
+    int lo = 0, hi = B;  // tile_off[lo] <= w < tile_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= w) lo = mid;
+        else hi = mid;
+    }
+    StepArgs A = items[lo].A;
+    const size_t off = items[lo].off_bytes;
+    A.src = (cur ? buf1 : buf0) + off;
+    A.dst = (cur ? buf0 : buf1) + off;
+    A.step = step;
+    const int tile = w - tile_off[lo];
+    const int strips = (A.nx + k2Cols - 1) / k2Cols;
+    step2_tile<T, MODE_STEP, WALLS>(A, tile % strips, tile / strips, S);
+}
+
+// Two steps of short periodic lattices (ny <= kFullRows, periodic in y): a workgroup of
+// 64 * max(ny) threads owns a 58-column strip over ALL rows of its lattice, wave k row k.
+// The rows wrap inside the workgroup, so unlike step2_tile there is no ring of rows; only
+// the three-column ring in x is recomputed.  Same phases and node arithmetic as step2_tile.
+constexpr int kFullRows = 16;
+
+template <typename T>
+struct FullLds {
+    T sps[kFullRows][64];
+    T smv[8][kFullRows][64];
+    double sg0[kFullRows][64];
+};
+
+template <typename T>
+__global__ __launch_bounds__(64 * kFullRows) void k_batch_full2(const BatchItem* items, const int* tile_off, int B,
+                                                                 char* buf0, char* buf1, int cur, long long step)
+{
+    __shared__ FullLds<T> S;
+    const int w = blockIdx.x;
+    if (w >= tile_off[B]) return;
+    int lo = 0, hi = B;  // tile_off[lo] <= w < tile_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= w) lo = mid;
+        else hi = mid;
+    }
+    StepArgs A = items[lo].A;
+    const size_t off = items[lo].off_bytes;
+    A.src = (cur ? buf1 : buf0) + off;
+    A.dst = (cur ? buf0 : buf1) + off;
+    A.step = step;
+    const int strip = w - tile_off[lo];
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+    const bool row = k < A.ny;  // waves beyond this lattice's rows only keep the barriers
+    const int km = k == 0 ? A.ny - 1 : k - 1, kp = k + 1 == A.ny ? 0 : k + 1;
+    const int x0 = strip * k2Cols, W = min(k2Cols, A.nx - x0);
+    const int dl = l < 3 ? 3 - l : (l > W + 2 ? l - (W + 2) : 0);
+    Lane L;
+    L.lane = l;
+    L.valid = dl <= 3;
+    L.interior = dl == 0;
+    int x = ((x0 - 3 + l) % A.nx + A.nx) % A.nx;
+    if (dl > 3) x = 0;
+    L.x = x;
+    L.xm = x == 0 ? A.nx - 1 : x - 1;
+    L.xp = x == A.nx - 1 ? 0 : x + 1;
+    Acc acc = {0.0, 0.0, 0.0};
+    // 1. step t: pull, rho, psi
+    Row<T> R;
+    double dr = 0.0;
+    T ps = (T)0;
+    if (row && dl <= 3) {
+        const View<T> V = make_view<T>(A.src, A.plane);
+        pull<T>(V, A, L.x, L.xm, L.xp, k, R.g0, R.g);
+        dr = node_drho<T>(R.g0, R.g);
+        ps = node_psi<T>(A, dr, true);
+    }
+    S.sps[k][l] = ps;
+    __syncthreads();
+    // 2. step t: collide the strip grown by 2 columns into LDS
+    if (row && dl <= 2) {
+        T Ftx, Fty;
+        force_tilde<T>(A, S.sps[km][l - 1], S.sps[km][l], S.sps[km][l + 1], S.sps[k][l - 1], S.sps[k][l + 1],
+                       S.sps[kp][l - 1], S.sps[kp][l], S.sps[kp][l + 1], Ftx, Fty);
+        T o[9];
+        double o0;
+        node_collide<T, MODE_STEP>(A, L, k, R, dr, ps, Ftx, Fty, acc, o, o0);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) S.smv[i - 1][k][l] = o[i];
+        S.sg0[k][l] = o0;
+    }
+    __syncthreads();
+    // 3. step t+1: pull from LDS (rows wrap), psi(t+1)
+    if (row && dl <= 1) {
+        R.g0 = S.sg0[k][l];
+        R.g[1] = S.smv[0][k][l - 1];
+        R.g[3] = S.smv[2][k][l + 1];
+        R.g[2] = S.smv[1][km][l];
+        R.g[5] = S.smv[4][km][l - 1];
+        R.g[6] = S.smv[5][km][l + 1];
+        R.g[4] = S.smv[3][kp][l];
+        R.g[7] = S.smv[6][kp][l + 1];
+        R.g[8] = S.smv[7][kp][l - 1];
+        dr = node_drho<T>(R.g0, R.g);
+        ps = node_psi<T>(A, dr, true, 1);
+        S.sps[k][l] = ps;
+    }
+    __syncthreads();
+    // 4. step t+1: collide the strip and store
+    if (row && dl == 0) {
+        T Ftx, Fty;
+        force_tilde<T>(A, S.sps[km][l - 1], S.sps[km][l], S.sps[km][l + 1], S.sps[k][l - 1], S.sps[k][l + 1],
+                       S.sps[kp][l - 1], S.sps[kp][l], S.sps[kp][l + 1], Ftx, Fty);
+        update_node<T, MODE_STEP>(A, L, k, R, dr, ps, Ftx, Fty, acc);
+    }
+}
+
 template <typename T>
 __global__ void k_batch_init(const BatchItem* items, char* buf0, const double* rho0, const double* ux0,
                              const double* uy0)
@@ -186,8 +309,11 @@ struct Layout {
     std::vector<size_t> off;        // [B+1] byte offsets in a population buffer
     std::vector<long long> cells;   // [B+1] cell offsets in the packed fields
     std::vector<int> ld;
-    std::vector<int> item_off;      // [B+1] grouped-step items (strips x rows) before each lattice
-    size_t off_items, off_item_off, ws_bytes;
+    std::vector<int> item_off;      // [B+1] one-step grouped items (strips x rows) before each lattice
+    std::vector<int> tile_off;      // [B+1] two-step grouped tiles before each lattice
+    std::vector<int> strip_off;     // [B+1] two-step full-height strips before each lattice
+    int any_walls, max_ny;
+    size_t off_items, off_item_off, off_tile_off, off_strip_off, ws_bytes;
 };
 
 int batch_layout(int B, const lbm_params* p, Layout& L)
@@ -200,6 +326,10 @@ int batch_layout(int B, const lbm_params* p, Layout& L)
     L.cells.assign(B + 1, 0);
     L.ld.assign(B, 0);
     L.item_off.assign(B + 1, 0);
+    L.tile_off.assign(B + 1, 0);
+    L.strip_off.assign(B + 1, 0);
+    L.any_walls = 0;
+    L.max_ny = 0;
     for (int b = 0; b < B; ++b) {
         if (p[b].prec != p[0].prec) {
             lbm_set_error("lbm batched: every lattice must use the same storage precision");
@@ -220,12 +350,18 @@ int batch_layout(int B, const lbm_params* p, Layout& L)
             return LBM_EINVAL;
         }
         L.item_off[b + 1] = L.item_off[b] + (int)items;
+        L.tile_off[b + 1] = L.tile_off[b] + ((p[b].nx + k2Cols - 1) / k2Cols) * ((p[b].ny + k2Rows - 1) / k2Rows);
+        L.strip_off[b + 1] = L.strip_off[b] + (p[b].nx + k2Cols - 1) / k2Cols;
+        L.any_walls |= p[b].walls != 0;
+        L.max_ny = p[b].ny > L.max_ny ? p[b].ny : L.max_ny;
     }
     // workspace: per-lattice error words, the item records, the grouped-step item offsets
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     L.off_items = al((size_t)B * 2 * sizeof(unsigned));
     L.off_item_off = L.off_items + al((size_t)B * sizeof(BatchItem));
-    L.ws_bytes = L.off_item_off + al((size_t)(B + 1) * sizeof(int));
+    L.off_tile_off = L.off_item_off + al((size_t)(B + 1) * sizeof(int));
+    L.off_strip_off = L.off_tile_off + al((size_t)(B + 1) * sizeof(int));
+    L.ws_bytes = L.off_strip_off + al((size_t)(B + 1) * sizeof(int));
     return LBM_OK;
 }
 
@@ -240,16 +376,19 @@ struct lbm_batch {
     int64_t step;
     unsigned* err;
     BatchItem* items;
-    int* item_off;          // device copy of Layout::item_off
+    int* item_off;          // device copies of Layout::item_off and Layout::tile_off
+    int* tile_off;
+    int* strip_off;         // device copy of Layout::strip_off (full-height strips)
+    int full;               // 1: every lattice is periodic with ny <= kFullRows (full-height two-step)
     int grouped;            // 1: one grouped launch per step; 0: persistent workgroups
     hipStream_t cap;        // capture stream (default priority)
     hipGraphExec_t exec[2]; // per starting buffer: the persistent launch of `graph_steps` steps, or
-                            // kGroupChunk grouped launches
+                            // kGroupChunk two-step grouped launches
     int64_t graph_steps;
 };
 
 namespace {
-constexpr int kGroupChunk = 64;  // grouped launches per replayed graph (even: buffer parity is kept)
+constexpr int kGroupChunk = 64;  // two-step grouped launches per replayed graph (128 steps)
 
 // persistent unless some lattice gives one workgroup more than two items per wave and step
 int auto_grouped(const Layout& L, int B)
@@ -296,6 +435,9 @@ int lbm_init_batched(lbm_batch** out, int B, const lbm_params* p, void* f_a, voi
     c->err = (unsigned*)ws;
     c->items = (BatchItem*)((char*)ws + L.off_items);
     c->item_off = (int*)((char*)ws + L.off_item_off);
+    c->tile_off = (int*)((char*)ws + L.off_tile_off);
+    c->strip_off = (int*)((char*)ws + L.off_strip_off);
+    c->full = !L.any_walls && L.max_ny <= kFullRows;
     c->grouped = auto_grouped(L, B);
     std::vector<BatchItem> host(B);
     std::vector<unsigned> err0(2 * (size_t)B);
@@ -340,6 +482,10 @@ int lbm_init_batched(lbm_batch** out, int B, const lbm_params* p, void* f_a, voi
     if (!hip_ok(hipMemcpyAsync(c->items, host.data(), sizeof(BatchItem) * B, hipMemcpyHostToDevice, s), "batch items") ||
         !hip_ok(hipMemcpyAsync(c->item_off, L.item_off.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, s),
                 "batch item offsets") ||
+        !hip_ok(hipMemcpyAsync(c->tile_off, L.tile_off.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, s),
+                "batch tile offsets") ||
+        !hip_ok(hipMemcpyAsync(c->strip_off, L.strip_off.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, s),
+                "batch strip offsets") ||
         !hip_ok(hipMemcpyAsync(c->err, err0.data(), sizeof(unsigned) * 2 * B, hipMemcpyHostToDevice, s), "batch errors") ||
         !hip_ok(hipStreamSynchronize(s), "batch init sync")) {
         delete c;
@@ -360,21 +506,35 @@ int lbm_init_batched(lbm_batch** out, int B, const lbm_params* p, void* f_a, voi
     return LBM_OK;
 }
 
-// n grouped launches (one per step) starting from buffer cur at step step0
+// n grouped steps starting from buffer cur at step step0: n / 2 two-step launches, then
+// one one-step launch if n is odd
 static bool launch_grouped(lbm_batch* c, int n, int cur, int64_t step0, hipStream_t s)
 {
-    const int total = c->L.item_off[c->B];
-    const dim3 g((total + 3) / 4), b(256);
-    for (int k = 0; k < n; ++k) {
-        if (c->prec == LBM_FP32_SHIFTED)
-            hipLaunchKernelGGL(k_batch_step<float>, g, b, 0, s, (const BatchItem*)c->items, (const int*)c->item_off, c->B,
-                               c->buf[0], c->buf[1], cur, (long long)(step0 + k));
-        else
-            hipLaunchKernelGGL(k_batch_step<double>, g, b, 0, s, (const BatchItem*)c->items, (const int*)c->item_off,
-                               c->B, c->buf[0], c->buf[1], cur, (long long)(step0 + k));
-        cur ^= 1;
+    const BatchItem* it = c->items;
+    const bool f32 = c->prec == LBM_FP32_SHIFTED, w = c->L.any_walls != 0;
+    const dim3 g2(c->L.tile_off[c->B]), b2(64 * k2Waves);
+    int k = 0;
+    const dim3 gf(c->L.strip_off[c->B]), bf(64 * c->L.max_ny);
+    for (; k + 1 < n; k += 2) {
+        const long long st = (long long)(step0 + k);
+        if (c->full && f32) hipLaunchKernelGGL(k_batch_full2<float>, gf, bf, 0, s, it, c->strip_off, c->B, c->buf[0], c->buf[1], cur, st);
+        else if (c->full) hipLaunchKernelGGL(k_batch_full2<double>, gf, bf, 0, s, it, c->strip_off, c->B, c->buf[0], c->buf[1], cur, st);
+        else if (f32 && !w) hipLaunchKernelGGL((k_batch_step2<float, false>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
+        else if (f32) hipLaunchKernelGGL((k_batch_step2<float, true>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
+        else if (!w) hipLaunchKernelGGL((k_batch_step2<double, false>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
+        else hipLaunchKernelGGL((k_batch_step2<double, true>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
+        cur ^= 1;  // two steps land in the other buffer
     }
-    return hip_ok(hipGetLastError(), "k_batch_step launch");
+    if (k < n) {
+        const dim3 g((c->L.item_off[c->B] + 3) / 4), b(256);
+        if (f32)
+            hipLaunchKernelGGL(k_batch_step<float>, g, b, 0, s, it, (const int*)c->item_off, c->B, c->buf[0], c->buf[1],
+                               cur, (long long)(step0 + k));
+        else
+            hipLaunchKernelGGL(k_batch_step<double>, g, b, 0, s, it, (const int*)c->item_off, c->B, c->buf[0], c->buf[1],
+                               cur, (long long)(step0 + k));
+    }
+    return hip_ok(hipGetLastError(), "grouped batch launch");
 }
 
 static bool launch_batch(lbm_batch* c, int64_t nsteps, hipStream_t s)
@@ -411,13 +571,15 @@ int lbm_set_batch_mode(lbm_batch* c, int mode)
 // failing step, which is therefore exact for the first chunk of each parity and approximate after.
 static int step_grouped(lbm_batch* c, int64_t nsteps, hipStream_t s)
 {
+    const int chunk = 2 * kGroupChunk;  // steps per replayed graph; a two-step launch flips the buffer,
+                                        // so an even number of launches keeps the parity
     int64_t done = 0;
-    while (nsteps - done >= kGroupChunk) {
+    while (nsteps - done >= chunk) {
         if (!c->exec[c->cur]) {
             hipGraph_t g = nullptr;
             if (!hip_ok(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "batch capture begin"))
                 return LBM_EHIP;
-            const bool ok = launch_grouped(c, kGroupChunk, c->cur, c->step, c->cap);
+            const bool ok = launch_grouped(c, chunk, c->cur, c->step, c->cap);
             if (!hip_ok(hipStreamEndCapture(c->cap, &g), "batch capture end") || !ok) return LBM_EHIP;
             const bool inst =
                 hip_ok(hipGraphInstantiate(&c->exec[c->cur], g, nullptr, nullptr, 0), "batch graph instantiate");
@@ -425,14 +587,15 @@ static int step_grouped(lbm_batch* c, int64_t nsteps, hipStream_t s)
             if (!inst) return LBM_EHIP;
         }
         if (!hip_ok(hipGraphLaunch(c->exec[c->cur], s), "batch graph launch")) return LBM_EHIP;
-        c->step += kGroupChunk;
-        done += kGroupChunk;
+        c->step += chunk;
+        done += chunk;
     }
     const int rest = (int)(nsteps - done);
     if (rest > 0) {
         if (!launch_grouped(c, rest, c->cur, c->step, s)) return LBM_EHIP;
         c->step += rest;
-        if (rest & 1) c->cur ^= 1;
+        // each two-step launch and the one-step launch flip the buffer once
+        if (((rest / 2) + (rest & 1)) & 1) c->cur ^= 1;
     }
     return LBM_OK;
 }

@@ -490,6 +490,149 @@ __device__ __forceinline__ void collide_row(const StepArgs& A, const Lane& L, in
 }
 
 
+// Two time steps per launch (temporal blocking).  A
+// workgroup of 16 waves owns an output tile of 10 rows x 58 columns; wave k
+// holds row y0-3+k and lane l column x0-3+l in every phase, so the tile grown
+// by d nodes is the set of (wave, lane) pairs at distance <= d from it:
+//   1. pull step t from the source buffer on the tile grown by 3; rho, psi(t) -> LDS
+//   2. collide step t on the tile grown by 2 (psi of the 3x3 stencil from LDS);
+//      the post-collision populations go to LDS in their storage format
+//   3. pull step t+1 from LDS on the tile grown by 1; rho, psi(t+1) -> LDS
+//   4. collide step t+1 on the tile and store to the destination buffer.
+// With walls the rows beyond them are solid: they carry the ghost psi of
+// Eq. ShanChenForce, and the pulls at the wall rows bounce back half-way.
+// Every node runs the arithmetic of the one-step kernels, and LDS holds the
+// intermediate state exactly as global memory would (FP32 deviations, FP64
+// rest population), so one launch equals two one-step launches.  Memory
+// traffic per output node is one population read (plus the 3-node ring) and
+// one write per two steps.  MODE_RECORD also stores, for the tile's nodes,
+// what the adjoint of each of the two steps needs (rho - rho_ref, j, psi).
+constexpr int k2Waves = 16, k2Rows = k2Waves - 6, k2Cols = 64 - 6;
+
+// LDS of one two-step tile
+template <typename T>
+struct Step2Lds {
+    T sps[k2Waves][64];              // psi of the tile grown by 3 (step t), then by 1 (step t+1)
+    T smv[8][k2Waves - 2][64];       // post-collision moving populations of step t (tile grown by 2)
+    double sg0[k2Waves - 2][64];     // and their FP64 rest population
+};
+
+// Advance output tile (strip, band) of lattice A by two steps (see above).
+template <typename T, int MODE, bool WALLS>
+__device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int band, Step2Lds<T>& S)
+{
+    auto& sps = S.sps;
+    auto& smv = S.smv;
+    auto& sg0 = S.sg0;
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    const int x0 = strip * k2Cols, y0 = band * k2Rows;
+    const int W = min(k2Cols, A.nx - x0), H = min(k2Rows, A.ny - y0);
+    // distance of this lane's column and this wave's row from the output tile
+    const int dl = l < 3 ? 3 - l : (l > W + 2 ? l - (W + 2) : 0);
+    const int dk = k < 3 ? 3 - k : (k > H + 2 ? k - (H + 2) : 0);
+    const int d = max(dl, dk);
+    Lane L;
+    L.lane = l;
+    L.valid = d <= 3;
+    L.interior = d == 0;
+    int x = ((x0 - 3 + l) % A.nx + A.nx) % A.nx;
+    if (dl > 3) x = 0;
+    L.x = x;
+    L.xm = x == 0 ? A.nx - 1 : x - 1;
+    L.xp = x == A.nx - 1 ? 0 : x + 1;
+    const int r = y0 - 3 + k;  // unwrapped row; in [0, ny) on the output tile
+    // periodic: rows wrap; walls: rows outside [0, ny) are the solid nodes (ghost psi only).
+    // WALLS (compile time) says whether walls may occur at all, so that the periodic kernel
+    // carries none of this (its scalar registers are the occupancy limit).
+    const bool walls = WALLS && A.walls;
+    const bool fluid = !walls || (r >= 0 && r < A.ny);
+    const int rw = walls ? r : (r % A.ny + A.ny) % A.ny;
+    const T ghost = walls ? (T)(r < 0 ? A.psi_lo : A.psi_hi) : (T)0;
+    Acc acc = {0.0, 0.0, 0.0};
+
+    // 1. step t: pull, rho, psi
+    Row<T> R;
+    double dr = 0.0;
+    T ps = (T)0;
+    if (dk <= 3 && dl <= 3) {
+        if (fluid) {
+            const View<T> V = make_view<T>(A.src, A.plane);
+            pull<T>(V, A, L.x, L.xm, L.xp, rw, R.g0, R.g);
+            dr = node_drho<T>(R.g0, R.g);
+            ps = node_psi<T>(A, dr, true);
+        } else {
+            ps = ghost;
+        }
+    }
+    sps[k][l] = ps;
+    __syncthreads();
+    // 2. step t: collide on the tile grown by 2, post-collision state to LDS
+    if (dk <= 2 && dl <= 2 && fluid) {
+        T Ftx, Fty;
+        force_tilde<T>(A, sps[k - 1][l - 1], sps[k - 1][l], sps[k - 1][l + 1], sps[k][l - 1], sps[k][l + 1],
+                       sps[k + 1][l - 1], sps[k + 1][l], sps[k + 1][l + 1], Ftx, Fty);
+        T o[9];
+        double o0;
+        node_collide<T, MODE_STEP>(A, L, rw, R, dr, ps, Ftx, Fty, acc, o, o0);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) smv[i - 1][k - 1][l] = o[i];
+        sg0[k - 1][l] = o0;
+        if (MODE == MODE_RECORD && d == 0) {
+            T jx, jy;
+            node_j<T>(R.g, jx, jy);
+            record_node<T>(A.rec, A.rec_plane, (size_t)r * A.nx + x, (T)dr, jx, jy, ps);
+        }
+    }
+    __syncthreads();
+    // 3. step t+1: pull from LDS on the tile grown by 1 (f_i(x) = f*_i(x - c_i), or the node's
+    //    own opposite population where x - c_i is solid), psi(t+1)
+    if (dk <= 1 && dl <= 1 && fluid) {
+        const int q = k - 1;  // LDS row of this wave
+        const bool bot = walls && r == 0, top = walls && r == A.ny - 1;
+        R.g0 = sg0[q][l];
+        R.g[1] = smv[0][q][l - 1];
+        R.g[3] = smv[2][q][l + 1];
+        if (!bot) {
+            R.g[2] = smv[1][q - 1][l];
+            R.g[5] = smv[4][q - 1][l - 1];
+            R.g[6] = smv[5][q - 1][l + 1];
+        } else {
+            R.g[2] = smv[3][q][l];
+            R.g[5] = smv[6][q][l];
+            R.g[6] = smv[7][q][l];
+        }
+        if (!top) {
+            R.g[4] = smv[3][q + 1][l];
+            R.g[7] = smv[6][q + 1][l + 1];
+            R.g[8] = smv[7][q + 1][l - 1];
+        } else {
+            R.g[4] = smv[1][q][l];
+            R.g[7] = smv[4][q][l];
+            R.g[8] = smv[5][q][l];
+        }
+        dr = node_drho<T>(R.g0, R.g);
+        ps = node_psi<T>(A, dr, true, 1);
+        sps[k][l] = ps;
+    } else if (walls && dk <= 1 && dl <= 1) {
+        sps[k][l] = ghost;
+    }
+    __syncthreads();
+    // 4. step t+1: collide on the tile and store (tile rows are fluid rows)
+    if (d == 0) {
+        T Ftx, Fty;
+        force_tilde<T>(A, sps[k - 1][l - 1], sps[k - 1][l], sps[k - 1][l + 1], sps[k][l - 1], sps[k][l + 1],
+                       sps[k + 1][l - 1], sps[k + 1][l], sps[k + 1][l + 1], Ftx, Fty);
+        update_node<T, MODE_STEP>(A, L, r, R, dr, ps, Ftx, Fty, acc);
+        if (MODE == MODE_RECORD) {
+            T jx, jy;
+            node_j<T>(R.g, jx, jy);
+            record_node<T>((char*)A.rec + 4 * A.rec_plane * sizeof(T), A.rec_plane, (size_t)r * A.nx + x, (T)dr, jx,
+                           jy, ps);
+        }
+    }
+}
+
 // ----------------------------------------------------------------- host helpers
 inline DevEos dev_eos(const lbm_eos& e)
 {

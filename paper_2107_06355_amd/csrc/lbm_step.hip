@@ -208,25 +208,6 @@ __global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
     }
 }
 
-// Two time steps per launch (temporal blocking).  A
-// workgroup of 16 waves owns an output tile of 10 rows x 58 columns; wave k
-// holds row y0-3+k and lane l column x0-3+l in every phase, so the tile grown
-// by d nodes is the set of (wave, lane) pairs at distance <= d from it:
-//   1. pull step t from the source buffer on the tile grown by 3; rho, psi(t) -> LDS
-//   2. collide step t on the tile grown by 2 (psi of the 3x3 stencil from LDS);
-//      the post-collision populations go to LDS in their storage format
-//   3. pull step t+1 from LDS on the tile grown by 1; rho, psi(t+1) -> LDS
-//   4. collide step t+1 on the tile and store to the destination buffer.
-// With walls the rows beyond them are solid: they carry the ghost psi of
-// Eq. ShanChenForce, and the pulls at the wall rows bounce back half-way.
-// Every node runs the arithmetic of the one-step kernels, and LDS holds the
-// intermediate state exactly as global memory would (FP32 deviations, FP64
-// rest population), so one launch equals two one-step launches.  Memory
-// traffic per output node is one population read (plus the 3-node ring) and
-// one write per two steps.  MODE_RECORD also stores, for the tile's nodes,
-// what the adjoint of each of the two steps needs (rho - rho_ref, j, psi).
-constexpr int k2Waves = 16, k2Rows = k2Waves - 6, k2Cols = 64 - 6;
-
 // FP32: 8 waves per SIMD, two workgroups per CU (the compiler spills scalar registers
 // to vector lanes to fit).  FP64: the compiler's choice (77 VGPRs, one workgroup per
 // CU); forcing two workgroups spills vector registers to scratch and measured 25%
@@ -235,122 +216,14 @@ template <typename T, int MODE, bool WALLS>
 __global__ __launch_bounds__(64 * k2Waves) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4)))
 void k_step2_blk(StepArgs A)
 {
-    __shared__ T sps[k2Waves][64];
-    __shared__ T smv[8][k2Waves - 2][64];
-    __shared__ double sg0[k2Waves - 2][64];
+    __shared__ Step2Lds<T> S;
     const int strips = (A.nx + k2Cols - 1) / k2Cols, bands = (A.ny + k2Rows - 1) / k2Rows;
     const int nb = gridDim.x;
     const int logical = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);  // XCD-contiguous blocks
     if (logical >= strips * bands) return;  // whole workgroup leaves together
-    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int l = threadIdx.x & 63;
     // band-major: the workgroups an XCD runs together cover neighbouring strips and bands
     // (strip-major order measured 27% more HBM reads at 8192^2 on MI355X)
-    const int strip = logical % strips, band = logical / strips;
-    const int x0 = strip * k2Cols, y0 = band * k2Rows;
-    const int W = min(k2Cols, A.nx - x0), H = min(k2Rows, A.ny - y0);
-    // distance of this lane's column and this wave's row from the output tile
-    const int dl = l < 3 ? 3 - l : (l > W + 2 ? l - (W + 2) : 0);
-    const int dk = k < 3 ? 3 - k : (k > H + 2 ? k - (H + 2) : 0);
-    const int d = max(dl, dk);
-    Lane L;
-    L.lane = l;
-    L.valid = d <= 3;
-    L.interior = d == 0;
-    int x = ((x0 - 3 + l) % A.nx + A.nx) % A.nx;
-    if (dl > 3) x = 0;
-    L.x = x;
-    L.xm = x == 0 ? A.nx - 1 : x - 1;
-    L.xp = x == A.nx - 1 ? 0 : x + 1;
-    const int r = y0 - 3 + k;  // unwrapped row; in [0, ny) on the output tile
-    // periodic: rows wrap; walls: rows outside [0, ny) are the solid nodes (ghost psi only).
-    // WALLS is a template parameter so that the periodic kernel carries none of this
-    // (its scalar registers are the occupancy limit).
-    const bool fluid = !WALLS || (r >= 0 && r < A.ny);
-    const int rw = WALLS ? r : (r % A.ny + A.ny) % A.ny;
-    const T ghost = WALLS ? (T)(r < 0 ? A.psi_lo : A.psi_hi) : (T)0;
-    Acc acc = {0.0, 0.0, 0.0};
-
-    // 1. step t: pull, rho, psi
-    Row<T> R;
-    double dr = 0.0;
-    T ps = (T)0;
-    if (dk <= 3 && dl <= 3) {
-        if (fluid) {
-            const View<T> V = make_view<T>(A.src, A.plane);
-            pull<T>(V, A, L.x, L.xm, L.xp, rw, R.g0, R.g);
-            dr = node_drho<T>(R.g0, R.g);
-            ps = node_psi<T>(A, dr, true);
-        } else {
-            ps = ghost;
-        }
-    }
-    sps[k][l] = ps;
-    __syncthreads();
-    // 2. step t: collide on the tile grown by 2, post-collision state to LDS
-    if (dk <= 2 && dl <= 2 && fluid) {
-        T Ftx, Fty;
-        force_tilde<T>(A, sps[k - 1][l - 1], sps[k - 1][l], sps[k - 1][l + 1], sps[k][l - 1], sps[k][l + 1],
-                       sps[k + 1][l - 1], sps[k + 1][l], sps[k + 1][l + 1], Ftx, Fty);
-        T o[9];
-        double o0;
-        node_collide<T, MODE_STEP>(A, L, rw, R, dr, ps, Ftx, Fty, acc, o, o0);
-#pragma unroll
-        for (int i = 1; i < 9; ++i) smv[i - 1][k - 1][l] = o[i];
-        sg0[k - 1][l] = o0;
-        if (MODE == MODE_RECORD && d == 0) {
-            T jx, jy;
-            node_j<T>(R.g, jx, jy);
-            record_node<T>(A.rec, A.rec_plane, (size_t)r * A.nx + x, (T)dr, jx, jy, ps);
-        }
-    }
-    __syncthreads();
-    // 3. step t+1: pull from LDS on the tile grown by 1 (f_i(x) = f*_i(x - c_i), or the node's
-    //    own opposite population where x - c_i is solid), psi(t+1)
-    if (dk <= 1 && dl <= 1 && fluid) {
-        const int q = k - 1;  // LDS row of this wave
-        const bool bot = WALLS && r == 0, top = WALLS && r == A.ny - 1;
-        R.g0 = sg0[q][l];
-        R.g[1] = smv[0][q][l - 1];
-        R.g[3] = smv[2][q][l + 1];
-        if (!bot) {
-            R.g[2] = smv[1][q - 1][l];
-            R.g[5] = smv[4][q - 1][l - 1];
-            R.g[6] = smv[5][q - 1][l + 1];
-        } else {
-            R.g[2] = smv[3][q][l];
-            R.g[5] = smv[6][q][l];
-            R.g[6] = smv[7][q][l];
-        }
-        if (!top) {
-            R.g[4] = smv[3][q + 1][l];
-            R.g[7] = smv[6][q + 1][l + 1];
-            R.g[8] = smv[7][q + 1][l - 1];
-        } else {
-            R.g[4] = smv[1][q][l];
-            R.g[7] = smv[4][q][l];
-            R.g[8] = smv[5][q][l];
-        }
-        dr = node_drho<T>(R.g0, R.g);
-        ps = node_psi<T>(A, dr, true, 1);
-        sps[k][l] = ps;
-    } else if (WALLS && dk <= 1 && dl <= 1) {
-        sps[k][l] = ghost;
-    }
-    __syncthreads();
-    // 4. step t+1: collide on the tile and store (tile rows are fluid rows)
-    if (d == 0) {
-        T Ftx, Fty;
-        force_tilde<T>(A, sps[k - 1][l - 1], sps[k - 1][l], sps[k - 1][l + 1], sps[k][l - 1], sps[k][l + 1],
-                       sps[k + 1][l - 1], sps[k + 1][l], sps[k + 1][l + 1], Ftx, Fty);
-        update_node<T, MODE_STEP>(A, L, r, R, dr, ps, Ftx, Fty, acc);
-        if (MODE == MODE_RECORD) {
-            T jx, jy;
-            node_j<T>(R.g, jx, jy);
-            record_node<T>((char*)A.rec + 4 * A.rec_plane * sizeof(T), A.rec_plane, (size_t)r * A.nx + x, (T)dr, jx,
-                           jy, ps);
-        }
-    }
+    step2_tile<T, MODE, WALLS>(A, logical % strips, logical / strips, S);
 }
 
 // Fixed-order FP64 reduction of the per-wave partials, two passes: block b sums

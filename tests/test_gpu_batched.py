@@ -97,12 +97,41 @@ def test_batched_graph_replay_is_deterministic(gpu_lib, mode):
     b = lbm.Batch(P, rhos, device="cuda:0")
     a.set_mode(mode)
     b.set_mode(mode)
-    for _ in range(3):
-        a.step(71)       # replayed graph, odd step count (buffer parity flips)
-    b.step(213)
+    if mode == 1:
+        for _ in range(3):
+            a.step(71)       # replayed graph, odd step count (buffer parity flips)
+        b.step(213)
+    else:
+        for n in (128, 128, 7):  # the 128-step graph captured, then replayed; 3 two-step + 1 one-step launches
+            a.step(n)
+        b.step(263)              # the same launches: two graph replays, then the same tail
     ma, mb = a.macros(), b.macros()
     for x, y in zip(ma, mb):
         assert np.array_equal(x["rho"], y["rho"]) and np.array_equal(x["ux"], y["ux"])
+
+
+def test_batched_short_periodic_lattices_full_height(gpu_lib):
+    """Batches of periodic lattices no taller than 16 rows run two steps per launch with whole
+    columns per workgroup (rows wrap inside it): 1, 3, 5 and 16 rows, ragged strips, odd step
+    counts (a final one-step launch), FP64 against the oracle."""
+    lbm = gpu_lib
+    shapes = [(130, 3), (61, 16), (7, 5), (200, 1), (59, 4)]
+    kw = dict(Tr=0.7)
+    e, s = lbm.eos_build(lbm.make_eos(**kw))
+    tau = [1.0, 1.1, 1.2, 1.0, 1.1, 1.0, 1.1, 0.8, 0.8]
+    P = [lbm.make_params(nx, ny, e, sigma=s, tau=tau) for nx, ny in shapes]
+    rhos = [planar_density(nx, ny, e.rho_v, e.rho_l, W=6, axis=0) * (1 + 0.01 * np.sin(np.arange(ny)[:, None] + 0.3 * np.arange(nx)[None, :]))
+            for nx, ny in shapes]
+    Bt = lbm.Batch(P, rhos, device="cuda:0")
+    Bt.set_mode(2)
+    for n in (1, 2, 131):
+        Bt.step(n)
+    Bt.check()
+    got = Bt.macros()
+    for b, (nx, ny) in enumerate(shapes):
+        m = _oracle(kw, nx, ny, {}, tau, {}, rhos[b], 134)
+        err = np.abs(got[b]["rho"] - m["rho"]).max() / m["rho"].max()
+        assert err < 1e-12, (nx, ny, err)
 
 
 def test_batched_modes_agree(gpu_lib):
