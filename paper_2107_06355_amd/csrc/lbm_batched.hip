@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchItem* items, cons
 // lists (lattice b owns tiles [tile_off[b], tile_off[b+1]), tile = strip + strips * band);
 // the tile arithmetic is step2_tile of the single-lattice two-step kernel.
 template <typename T, bool WALLS>
-__global__ __launch_bounds__(64 * k2Waves) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4)))
+__global__ __launch_bounds__(64 * k2WavesOf<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 6)))
 void k_batch_step2(const BatchItem* items, const int* tile_off, int B, char* buf0, char* buf1, int cur, long long step)
 {
     __shared__ Step2Lds<T> S;
@@ -350,7 +350,8 @@ int batch_layout(int B, const lbm_params* p, Layout& L)
             return LBM_EINVAL;
         }
         L.item_off[b + 1] = L.item_off[b] + (int)items;
-        L.tile_off[b + 1] = L.tile_off[b] + ((p[b].nx + k2Cols - 1) / k2Cols) * ((p[b].ny + k2Rows - 1) / k2Rows);
+        const int rows2 = k2waves_of_prec(p[0].prec) - 6;
+        L.tile_off[b + 1] = L.tile_off[b] + ((p[b].nx + k2Cols - 1) / k2Cols) * ((p[b].ny + rows2 - 1) / rows2);
         L.strip_off[b + 1] = L.strip_off[b] + (p[b].nx + k2Cols - 1) / k2Cols;
         L.any_walls |= p[b].walls != 0;
         L.max_ny = p[b].ny > L.max_ny ? p[b].ny : L.max_ny;
@@ -512,7 +513,7 @@ static bool launch_grouped(lbm_batch* c, int n, int cur, int64_t step0, hipStrea
 {
     const BatchItem* it = c->items;
     const bool f32 = c->prec == LBM_FP32_SHIFTED, w = c->L.any_walls != 0;
-    const dim3 g2(c->L.tile_off[c->B]), b2(64 * k2Waves);
+    const dim3 g2(c->L.tile_off[c->B]), b2(64 * k2waves_of_prec(c->prec));
     int k = 0;
     const dim3 gf(c->L.strip_off[c->B]), bf(64 * c->L.max_ny);
     for (; k + 1 < n; k += 2) {

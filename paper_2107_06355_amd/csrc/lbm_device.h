@@ -491,7 +491,7 @@ __device__ __forceinline__ void collide_row(const StepArgs& A, const Lane& L, in
 
 
 // Two time steps per launch (temporal blocking).  A
-// workgroup of 16 waves owns an output tile of 10 rows x 58 columns; wave k
+// workgroup of NW waves owns an output tile of NW - 6 rows x 58 columns; wave k
 // holds row y0-3+k and lane l column x0-3+l in every phase, so the tile grown
 // by d nodes is the set of (wave, lane) pairs at distance <= d from it:
 //   1. pull step t from the source buffer on the tile grown by 3; rho, psi(t) -> LDS
@@ -507,14 +507,20 @@ __device__ __forceinline__ void collide_row(const StepArgs& A, const Lane& L, in
 // traffic per output node is one population read (plus the 3-node ring) and
 // one write per two steps.  MODE_RECORD also stores, for the tile's nodes,
 // what the adjoint of each of the two steps needs (rho - rho_ref, j, psi).
-constexpr int k2Waves = 16, k2Rows = k2Waves - 6, k2Cols = 64 - 6;
+// Waves per two-step workgroup (tile rows = waves - 6): FP32 16, two workgroups per CU at
+// 8 waves per SIMD; FP64 12, two workgroups per CU at the 77 VGPRs the FP64 path needs
+// (measured on MI355X: FP64 8192^2 1468 vs 1553 us/step with 16 waves; FP32 loses with 12).
+template <typename T>
+constexpr int k2WavesOf = sizeof(T) == 4 ? 16 : 12;
+inline int k2waves_of_prec(int prec) { return prec == LBM_FP32_SHIFTED ? k2WavesOf<float> : k2WavesOf<double>; }
+constexpr int k2Cols = 64 - 6;
 
 // LDS of one two-step tile
 template <typename T>
 struct Step2Lds {
-    T sps[k2Waves][64];              // psi of the tile grown by 3 (step t), then by 1 (step t+1)
-    T smv[8][k2Waves - 2][64];       // post-collision moving populations of step t (tile grown by 2)
-    double sg0[k2Waves - 2][64];     // and their FP64 rest population
+    T sps[k2WavesOf<T>][64];            // psi of the tile grown by 3 (step t), then by 1 (step t+1)
+    T smv[8][k2WavesOf<T> - 2][64];     // post-collision moving populations of step t (tile grown by 2)
+    double sg0[k2WavesOf<T> - 2][64];   // and their FP64 rest population
 };
 
 // Advance output tile (strip, band) of lattice A by two steps (see above).
@@ -526,6 +532,7 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
     auto& sg0 = S.sg0;
     const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = threadIdx.x & 63;
+    constexpr int k2Rows = k2WavesOf<T> - 6;
     const int x0 = strip * k2Cols, y0 = band * k2Rows;
     const int W = min(k2Cols, A.nx - x0), H = min(k2Rows, A.ny - y0);
     // distance of this lane's column and this wave's row from the output tile

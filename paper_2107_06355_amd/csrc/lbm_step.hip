@@ -208,16 +208,17 @@ __global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
     }
 }
 
-// FP32: 8 waves per SIMD, two workgroups per CU (the compiler spills scalar registers
-// to vector lanes to fit).  FP64: the compiler's choice (77 VGPRs, one workgroup per
-// CU); forcing two workgroups spills vector registers to scratch and measured 25%
-// slower on MI355X at 4096^2.
+// FP32: 16 waves, 8 waves per SIMD, two workgroups per CU (the compiler spills scalar
+// registers to vector lanes to fit).  FP64: 12 waves, 6 per SIMD (77 VGPRs), two
+// workgroups per CU; 16-wave FP64 workgroups fit only one per CU, and forcing two of
+// them spilled vector registers to scratch (25% slower on MI355X at 4096^2).
 template <typename T, int MODE, bool WALLS>
-__global__ __launch_bounds__(64 * k2Waves) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4)))
+__global__ __launch_bounds__(64 * k2WavesOf<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 6)))
 void k_step2_blk(StepArgs A)
 {
     __shared__ Step2Lds<T> S;
-    const int strips = (A.nx + k2Cols - 1) / k2Cols, bands = (A.ny + k2Rows - 1) / k2Rows;
+    constexpr int rows = k2WavesOf<T> - 6;
+    const int strips = (A.nx + k2Cols - 1) / k2Cols, bands = (A.ny + rows - 1) / rows;
     const int nb = gridDim.x;
     const int logical = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);  // XCD-contiguous blocks
     if (logical >= strips * bands) return;  // whole workgroup leaves together
@@ -427,7 +428,8 @@ void fill_args(lbm_ctx* c)
     const int blocks = A.blk ? A.nwork / kBlkWaves : (A.nwork + kWaves - 1) / kWaves;
     c->grid = (blocks + 7) & ~7;
     c->blk2 = resolve_variant(p) == LBM_VARIANT_BLOCK2;
-    const int blocks2 = ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + k2Rows - 1) / k2Rows);
+    const int rows2 = k2waves_of_prec(p.prec) - 6;
+    const int blocks2 = ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + rows2 - 1) / rows2);
     c->grid2 = (blocks2 + 7) & ~7;
 }
 
@@ -481,7 +483,7 @@ bool launch_step2(lbm_ctx* c, void* rec, hipStream_t s)
     A.step = c->step;
     A.rec = rec;
     A.rec_plane = (size_t)c->P.nx * c->P.ny;
-    const dim3 g(c->grid2), b(64 * k2Waves);
+    const dim3 g(c->grid2), b(64 * k2WavesOf<T>);
     if (c->P.walls) {
         if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true>), g, b, 0, s, A);
         else hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, true>), g, b, 0, s, A);
