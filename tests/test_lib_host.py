@@ -72,3 +72,44 @@ def test_layout_rejects_a_plane_above_4_gib():
     with pytest.raises(lbm.LbmError) as ei:
         lbm.layout(lbm.make_params(23232, 23168, e, sigma=s))
     assert ei.value.code == lbm.LBM_EINVAL
+
+
+def test_automatic_kernel_choice():
+    """lbm_describe resolves the automatic decomposition (host logic only): two steps per launch on
+    periodic lattices in both precisions and on walled FP64 ones; the row block for walled FP32
+    lattices up to 5 * 2^20 cells and the row march above; explicit choices are kept."""
+    e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
+    P32, P64 = lbm.FP32_SHIFTED, lbm.FP64
+    cases = [
+        (dict(nx=512, ny=512, prec=P32), lbm.VARIANT_BLOCK2),
+        (dict(nx=8192, ny=8192, prec=P32), lbm.VARIANT_BLOCK2),
+        (dict(nx=8192, ny=8192, prec=P64), lbm.VARIANT_BLOCK2),
+        (dict(nx=2048, ny=1024, prec=P32, walls=True), lbm.VARIANT_BLOCK),
+        (dict(nx=4096, ny=2048, prec=P32, walls=True), lbm.VARIANT_MARCH),
+        (dict(nx=2048, ny=1024, prec=P64, walls=True), lbm.VARIANT_BLOCK2),
+        (dict(nx=512, ny=512, prec=P32, kernel_variant=lbm.VARIANT_MARCH), lbm.VARIANT_MARCH),
+        (dict(nx=512, ny=512, prec=P32, kernel_variant=lbm.VARIANT_BLOCK), lbm.VARIANT_BLOCK),
+    ]
+    for kw, want in cases:
+        nx, ny = kw.pop("nx"), kw.pop("ny")
+        assert lbm.describe(lbm.make_params(nx, ny, e, sigma=s, **kw))[0] == want, (nx, ny, kw)
+
+
+def test_batch_layout_offsets():
+    """lbm_batch_layout (host): populations packed back to back on 256-byte boundaries, cell
+    offsets in lattice order, and a workspace that grows with the number of lattices."""
+    import ctypes as C
+
+    e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
+    shapes = [(130, 4), (7, 3), (64, 40)]
+    P = (lbm.LbmParams * len(shapes))(*[lbm.make_params(nx, ny, e, sigma=s, prec=lbm.FP32_SHIFTED) for nx, ny in shapes])
+    pb, wb = C.c_size_t(0), C.c_size_t(0)
+    offs = (C.c_int64 * (len(shapes) + 1))()
+    assert lbm.load().lbm_batch_layout(len(shapes), P, C.byref(pb), C.byref(wb), offs) == 0
+    assert list(offs) == [0, 520, 541, 3101]
+    per = [((nx + 63) // 64 * 64) * ny * (8 * 4 + 8) for nx, ny in shapes]
+    assert pb.value == sum((b + 255) // 256 * 256 for b in per)
+    P1 = (lbm.LbmParams * 1)(P[0])
+    wb1 = C.c_size_t(0)
+    assert lbm.load().lbm_batch_layout(1, P1, None, C.byref(wb1), None) == 0
+    assert wb.value > wb1.value > 0
