@@ -89,6 +89,18 @@ def test_fp64_shaped_eos_droplet(gpu_lib, shape_kw):
     assert rel_f_err(L, OL) < 1e-12
 
 
+@pytest.mark.parametrize("variant", [2, 3], ids=["block", "block2"])
+def test_fp64_droplet_1000_steps(gpu_lib, variant):
+    """FP64 path over 1000 steps (shaped PR droplet, MRT, Li forcing) against the oracle run of the
+    same length: the rounding-order differences stay at the 1e-12 level on a relaxing droplet."""
+    kw = dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
+    e, _, _, _ = both_eos(gpu_lib, **kw)
+    nx, ny = 90, 70
+    rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=20, W=12)
+    L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, 1000, tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7], variant=variant)
+    assert rel_f_err(L, OL) < 1e-12
+
+
 @pytest.mark.parametrize("variant,band", VARIANTS_P, ids=VARIANT_IDS_P)
 def test_fp64_walls_variable_tau_moving_droplet(gpu_lib, variant, band):
     """Bounce-back walls with ghost psi, Eq. RelaxationTime, a moving droplet over a film."""
