@@ -216,6 +216,14 @@ int lbm_set_recording(lbm_ctx* ctx, void* rec_buf, size_t rec_bytes, int64_t max
  * holds one segment (lbm_adjoint_layout's rec_bytes for the same K). */
 int lbm_adjoint(lbm_ctx* ctx, const double* dL_drho_T, void* rec_buf, size_t rec_bytes, void* adj_buf, size_t adj_bytes,
                 double* grad_out, double* dL_drho0, void* stream);
+/* lbm_adjoint for a loss on the final density and velocity: dL_drho_T, dL_dux_T,
+ * dL_duy_T (device float64 [ny][nx], any of them NULL for zero, not all) with
+ * u = (j + F/2)/rho of Eq. Momentum, F = psi F~ of Eq. ShanChenForce evaluated on
+ * the final state (what lbm_macros returns).  Same workspaces, outputs and
+ * errors as lbm_adjoint, which is this call with both velocity terms NULL. */
+int lbm_adjoint_fields(lbm_ctx* ctx, const double* dL_drho_T, const double* dL_dux_T, const double* dL_duy_T,
+                       void* rec_buf, size_t rec_bytes, void* adj_buf, size_t adj_bytes, double* grad_out,
+                       double* dL_drho0, void* stream);
 /* Replace the four interior knots of a built Smooth / Modified Smooth EOS and
  * recompute its ellipse coefficients (Sec. III.D); LBM_EINVAL when the knots
  * are out of order or an ellipse would not be real. */

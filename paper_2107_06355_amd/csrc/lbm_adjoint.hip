@@ -213,6 +213,89 @@ __device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T
     o.df[8] = b58 + djx + d4 - djy - d6 - d8;
 }
 
+// dL/drho(x) through psi(rho(x)) (Eq. InteractionPotential: psi' = (p' - 1/3)/(G psi),
+// dpsi/dp = 1/(G psi)) for a given dL/dpsi(x); also adds the psi part of dL/dG to vG and,
+// in the loop of a Smooth / Modified Smooth EOS (Sec. III.D), dL/dp(rho(x)) times the
+// derivatives of p with respect to the loop coefficients to v.
+template <typename T>
+__device__ __forceinline__ T psi_adjoint(const AdjArgs& A, double rho, T psi, T dpsi, double v[kAcc], T& vG)
+{
+    const StepArgs& S = A.S;
+    const DevEos& E = S.eos;
+    const T G = coef<T>(S).G, iG = adj_coef<T>(A).inv_G;
+    T drho_eos = 0;
+    if (psi > (T)0) {
+        vG += dpsi * (-psi * (T)0.5 * iG);
+        const bool in_loop = E.shape != LBM_SHAPE_NONE && rho > E.rho_v && rho < E.rho_l;
+        if (sizeof(T) == 4 && !in_loop && E.shape != LBM_SHAPE_NONE) {
+            // bulk branches in FP32, as in the forward
+            const float r = (float)rho, dpb = dev_base_dpf(E, r);
+            const float dp = rho <= E.rho_v ? E.fk_vap * dpb : dpb;
+            drho_eos = (T)((dp - (1.0f / 3.0f)) * (float)dpsi * rcp((float)G * (float)psi));
+        } else {
+            const double inv_gpsi = A.inv_G / (double)psi;
+            drho_eos = (T)((dev_eos_dp(E, rho) - 1.0 / 3.0) * inv_gpsi * (double)dpsi);
+            const double P = (double)dpsi * inv_gpsi;  // dL/dp(rho(x))
+            if (in_loop && (E.shape == LBM_SHAPE_SMOOTH || E.shape == LBM_SHAPE_MODSMOOTH)) {
+                if (rho <= E.rho_max) {
+                    const double dd = rho - E.rho_max, sq = sqrt(1.0 - dd * dd * E.inv_a1sq);
+                    v[A_PMAX] += P;
+                    v[A_B1] += -P * (1.0 - sq);
+                    v[A_A1] += P * E.b1 * dd * dd * E.inv_a1sq * E.inv_a1sq / (2.0 * sq);
+                    v[A_RMAX] += P * E.b1 * dd * E.inv_a1sq / sq;
+                } else if (rho < E.rho_min) {
+                    const double tt = (rho - E.rho_max) * E.inv_L;
+                    const double h = tt * tt * (3.0 - 2.0 * tt), hp = 6.0 * tt * (1.0 - tt);
+                    v[A_PMAX] += P * (1.0 - h);
+                    v[A_PMIN] += P * h;
+                    v[A_RMAX] += P * (E.p_min - E.p_max) * hp * (tt - 1.0) * E.inv_L;
+                    v[A_RMIN] += P * (E.p_min - E.p_max) * hp * (-tt) * E.inv_L;
+                } else {
+                    const double dd = rho - E.rho_min, sq = sqrt(1.0 - dd * dd * E.inv_a3sq);
+                    v[A_PMIN] += P;
+                    v[A_B3] += P * (1.0 - sq);
+                    v[A_A3] += -P * E.b3 * dd * dd * E.inv_a3sq * E.inv_a3sq / (2.0 * sq);
+                    v[A_RMIN] += -P * E.b3 * dd * E.inv_a3sq / sq;
+                }
+            }
+        }
+    }
+    return drho_eos;
+}
+
+// transpose of Eq. ShanChenForce at (wave k, lane l) of a row block: sum over k of
+// (-G w_k c_k) . dL/dF~(x - c_k) from the LDS planes sfx, sfy (rows k-1, k, k+1)
+template <typename T, int NW>
+__device__ __forceinline__ T force_transpose(const StepArgs& S, const T (&sfx)[NW][64], const T (&sfy)[NW][64], int k,
+                                             int lane, int y)
+{
+    const T G = coef<T>(S).G;
+    const T g3 = -G * (T)(1.0 / 3.0), g12 = -G * (T)(1.0 / 12.0);
+    const bool lo_ok = !S.walls || y >= 1, hi_ok = !S.walls || y + 1 < S.ny;
+    T d = g3 * (sfx[k][lane - 1] - sfx[k][lane + 1]);
+    if (lo_ok) d += g3 * sfy[k - 1][lane];
+    if (hi_ok) d -= g3 * sfy[k + 1][lane];
+    // diagonals: c = (1,1) from (x-1, y-1), (-1,1) from (x+1, y-1), (-1,-1) from (x+1, y+1), (1,-1) from (x-1, y+1)
+    if (lo_ok)
+        d += g12 * ((sfx[k - 1][lane - 1] + sfy[k - 1][lane - 1]) + (-sfx[k - 1][lane + 1] + sfy[k - 1][lane + 1]));
+    if (hi_ok)
+        d += g12 * ((-sfx[k + 1][lane + 1] - sfy[k + 1][lane + 1]) + (sfx[k + 1][lane - 1] - sfy[k + 1][lane - 1]));
+    return d;
+}
+
+// the G dependence of the ghost psi of the solid rows (walls): psi(rho_wall) ~ G^-1/2
+template <typename T>
+__device__ __forceinline__ void ghost_G(const AdjArgs& A, int y, T dfty, T& vG)
+{
+    const StepArgs& S = A.S;
+    if (S.walls && (y == 0 || y == S.ny - 1)) {
+        const T G = coef<T>(S).G, iG = adj_coef<T>(A).inv_G;
+        const T half = (T)0.5;  // 1/3 + 2/12
+        if (y == 0) vG += (G * dfty * half) * ((T)S.psi_lo * (T)-0.5 * iG);
+        if (y == S.ny - 1) vG += (-G * dfty * half) * ((T)S.psi_hi * (T)-0.5 * iG);
+    }
+}
+
 constexpr int kAdjWaves = 12;            // waves (rows) per workgroup
 constexpr int kAdjRows = kAdjWaves - 2;  // output rows per workgroup
 constexpr int kAdjW = 62;                // output columns per wave
@@ -250,67 +333,14 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
     double v[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const bool out = k >= 1 && k <= kAdjRows && y < S.ny && lane >= 1 && lane <= kAdjW && xs < S.nx;
     if (out) {
-        const T G = coef<T>(S).G, iG = adj_coef<T>(A).inv_G;
+        const T iG = adj_coef<T>(A).inv_G;
         T vG = (ftx * L.dftx + fty * L.dfty) * iG;  // F~ = -G sum(...)
         // transpose of Eq. ShanChenForce: dL/dpsi(x) += sum_k (-G w_k c_k) . dL/dF~(x - c_k)
-        const T g3 = -G * (T)(1.0 / 3.0), g12 = -G * (T)(1.0 / 12.0);
-        const bool lo_ok = !S.walls || y >= 1, hi_ok = !S.walls || y + 1 < S.ny;
-        T dpsi = L.dpsi;
-        // axis neighbours: source x - c_k for c = (1,0), (-1,0), (0,1), (0,-1)
-        dpsi += g3 * (sfx[k][lane - 1] - sfx[k][lane + 1]);
-        if (lo_ok) dpsi += g3 * sfy[k - 1][lane];
-        if (hi_ok) dpsi -= g3 * sfy[k + 1][lane];
-        // diagonals: c = (1,1) from (x-1, y-1), (-1,1) from (x+1, y-1), (-1,-1) from (x+1, y+1), (1,-1) from (x-1, y+1)
-        if (lo_ok)
-            dpsi += g12 * ((sfx[k - 1][lane - 1] + sfy[k - 1][lane - 1]) + (-sfx[k - 1][lane + 1] + sfy[k - 1][lane + 1]));
-        if (hi_ok)
-            dpsi += g12 * ((-sfx[k + 1][lane + 1] - sfy[k + 1][lane + 1]) + (sfx[k + 1][lane - 1] - sfy[k + 1][lane - 1]));
+        const T dpsi = L.dpsi + force_transpose<T, kAdjWaves>(S, sfx, sfy, k, lane, y);
         // ghost solid neighbours x + c_k (walls): psi(rho_wall) depends on G; the x parts cancel
-        if (S.walls && (y == 0 || y == S.ny - 1)) {
-            const T half = (T)0.5;  // 1/3 + 2/12
-            if (y == 0) vG += (G * L.dfty * half) * ((T)S.psi_lo * (T)-0.5 * iG);
-            if (y == S.ny - 1) vG += (-G * L.dfty * half) * ((T)S.psi_hi * (T)-0.5 * iG);
-        }
-        // psi(rho) (Eq. InteractionPotential): psi' = (p' - 1/3)/(G psi), dpsi/dp = 1/(G psi)
-        const double rho = S.rho_ref + (double)dr;
-        const DevEos& E = S.eos;
-        T drho_eos = 0;
-        if (psi > (T)0) {
-            vG += dpsi * (-psi * (T)0.5 * iG);
-            const bool in_loop = E.shape != LBM_SHAPE_NONE && rho > E.rho_v && rho < E.rho_l;
-            if (sizeof(T) == 4 && !in_loop && E.shape != LBM_SHAPE_NONE) {
-                // bulk branches in FP32, as in the forward
-                const float r = (float)rho, dpb = dev_base_dpf(E, r);
-                const float dp = rho <= E.rho_v ? E.fk_vap * dpb : dpb;
-                drho_eos = (T)((dp - (1.0f / 3.0f)) * (float)dpsi * rcp((float)G * (float)psi));
-            } else {
-                const double inv_gpsi = A.inv_G / (double)psi;
-                drho_eos = (T)((dev_eos_dp(E, rho) - 1.0 / 3.0) * inv_gpsi * (double)dpsi);
-                const double P = (double)dpsi * inv_gpsi;  // dL/dp(rho(x))
-                if (in_loop && (E.shape == LBM_SHAPE_SMOOTH || E.shape == LBM_SHAPE_MODSMOOTH)) {
-                    if (rho <= E.rho_max) {
-                        const double dd = rho - E.rho_max, sq = sqrt(1.0 - dd * dd * E.inv_a1sq);
-                        v[A_PMAX] = P;
-                        v[A_B1] = -P * (1.0 - sq);
-                        v[A_A1] = P * E.b1 * dd * dd * E.inv_a1sq * E.inv_a1sq / (2.0 * sq);
-                        v[A_RMAX] = P * E.b1 * dd * E.inv_a1sq / sq;
-                    } else if (rho < E.rho_min) {
-                        const double tt = (rho - E.rho_max) * E.inv_L;
-                        const double h = tt * tt * (3.0 - 2.0 * tt), hp = 6.0 * tt * (1.0 - tt);
-                        v[A_PMAX] = P * (1.0 - h);
-                        v[A_PMIN] = P * h;
-                        v[A_RMAX] = P * (E.p_min - E.p_max) * hp * (tt - 1.0) * E.inv_L;
-                        v[A_RMIN] = P * (E.p_min - E.p_max) * hp * (-tt) * E.inv_L;
-                    } else {
-                        const double dd = rho - E.rho_min, sq = sqrt(1.0 - dd * dd * E.inv_a3sq);
-                        v[A_PMIN] = P;
-                        v[A_B3] = P * (1.0 - sq);
-                        v[A_A3] = -P * E.b3 * dd * dd * E.inv_a3sq * E.inv_a3sq / (2.0 * sq);
-                        v[A_RMIN] = -P * E.b3 * dd * E.inv_a3sq / sq;
-                    }
-                }
-            }
-        }
+        ghost_G<T>(A, y, L.dfty, vG);
+        // psi(rho) (Eq. InteractionPotential)
+        const T drho_eos = psi_adjoint<T>(A, S.rho_ref + (double)dr, psi, dpsi, v, vG);
         v[A_G] = (double)vG;
         v[A_SIG] = (double)L.dsig;
         T* Lo = (T*)A.lam_out;
@@ -319,6 +349,90 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
     }
     // fixed-order workgroup sum: each (accumulator, lane) column over the waves in
     // order, then one wave per accumulator sums its 64 columns
+    for (int i = 0; i < kAcc; ++i) sred[i][k][lane] = v[i];
+    __syncthreads();
+    if (k < kAcc) {
+        double s = 0.0;
+        for (int w = 0; w < kAdjWaves; ++w) s += sred[k][w][lane];
+        s = wave_sum(s);
+        if (lane == 0) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
+    }
+}
+
+// Seed of the adjoint for a loss on the final density and velocity: lambda^T_i(x) = dL/df_i(x, T)
+// of the final pulled populations, with u = (j + F/2)/rho (Eq. Momentum), F = psi F~
+// (Eq. ShanChenForce) and psi(rho) (Eq. InteractionPotential).  The psi and F~ paths couple
+// neighbours (radius 1), so the row block of k_adj_blk is used: dL/dF~ of every node of the
+// block (halo included) goes through LDS to the output nodes.  The G and knot derivatives
+// of the final psi are added to the workgroup accumulators.
+template <typename T>
+__global__ __launch_bounds__(64 * kAdjWaves) void k_adj_seed_u(AdjArgs A, const void* fT, const double* dLr,
+                                                               const double* dLux, const double* dLuy)
+{
+    __shared__ T sps[kAdjWaves][64], sfx[kAdjWaves][64], sfy[kAdjWaves][64];
+    __shared__ double sred[kAcc][kAdjWaves][64];
+    const StepArgs& S = A.S;
+    const int lane = threadIdx.x & 63;
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int strip = blockIdx.x % A.strips, band = blockIdx.x / A.strips;
+    const int xs = strip * kAdjW - 1 + lane;  // unwrapped column of this lane
+    const int x = ((xs % S.nx) + S.nx) % S.nx;
+    const int y = band * kAdjRows - 1 + k;    // unwrapped row of this wave
+    const bool fluid = S.walls ? (y >= 0 && y < S.ny) : true;
+    const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y)) : ((y % S.ny) + S.ny) % S.ny;
+    const size_t o = (size_t)yw * S.nx + x;
+    const double acc_prev = (k < kAcc && lane == 0) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
+
+    // the final state at (x, yw): pulled populations, rho, j, psi; dL/dF~ = psi dL/dF, dL/dF = g / (2 rho)
+    const View<T> V = make_view<T>(fT, S.plane);
+    const int xm = x == 0 ? S.nx - 1 : x - 1, xp = x == S.nx - 1 ? 0 : x + 1;
+    double g0;
+    T g[9];
+    pull<T>(V, S, x, xm, xp, yw, g0, g);
+    const double dr = node_drho<T>(g0, g);
+    T psi = node_psi<T>(S, dr, false);
+    if (!fluid) psi = (T)(y < 0 ? S.psi_lo : S.psi_hi);
+    const T rho = (T)(S.rho_ref + dr);
+    const T gx = (fluid && dLux) ? (T)dLux[o] : (T)0, gy = (fluid && dLuy) ? (T)dLuy[o] : (T)0;
+    const T inv = rcp(rho);
+    const T dFx = (T)0.5 * gx * inv, dFy = (T)0.5 * gy * inv;
+    sps[k][lane] = psi;
+    sfx[k][lane] = fluid ? psi * dFx : (T)0;
+    sfy[k][lane] = fluid ? psi * dFy : (T)0;
+    __syncthreads();
+
+    double v[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const bool out = k >= 1 && k <= kAdjRows && y < S.ny && lane >= 1 && lane <= kAdjW && xs < S.nx;
+    if (out) {
+        T ftx, fty;
+        force_tilde<T>(S, sps[k - 1][lane - 1], sps[k - 1][lane], sps[k - 1][lane + 1], sps[k][lane - 1],
+                       sps[k][lane + 1], sps[k + 1][lane - 1], sps[k + 1][lane], sps[k + 1][lane + 1], ftx, fty);
+        T jx, jy;
+        node_j<T>(g, jx, jy);
+        const T ux = (jx + (T)0.5 * psi * ftx) * inv, uy = (jy + (T)0.5 * psi * fty) * inv;
+        const T iG = adj_coef<T>(A).inv_G;
+        const T dftx = psi * dFx, dfty = psi * dFy;
+        T vG = (ftx * dftx + fty * dfty) * iG;  // F~ = -G sum(...)
+        const T dpsi = (dFx * ftx + dFy * fty) + force_transpose<T, kAdjWaves>(S, sfx, sfy, k, lane, y);
+        ghost_G<T>(A, y, dfty, vG);
+        const T drho_eos = psi_adjoint<T>(A, S.rho_ref + dr, psi, dpsi, v, vG);
+        v[A_G] = (double)vG;
+        // direct dependence on rho and j: du/drho = -u/rho, du/dj = 1/rho
+        const T d0 = (dLr ? (T)dLr[o] : (T)0) - (gx * ux + gy * uy) * inv + drho_eos;
+        const T ax = gx * inv, ay = gy * inv;
+        T* Lo = (T*)A.lam_out;
+        const size_t li = (size_t)y * S.ld + x;
+        const size_t P = A.lplane;
+        Lo[li] = d0;
+        Lo[P + li] = d0 + ax;
+        Lo[2 * P + li] = d0 + ay;
+        Lo[3 * P + li] = d0 - ax;
+        Lo[4 * P + li] = d0 - ay;
+        Lo[5 * P + li] = d0 + ax + ay;
+        Lo[6 * P + li] = d0 - ax + ay;
+        Lo[7 * P + li] = d0 - ax - ay;
+        Lo[8 * P + li] = d0 + ax - ay;
+    }
     for (int i = 0; i < kAcc; ++i) sred[i][k][lane] = v[i];
     __syncthreads();
     if (k < kAcc) {
@@ -442,7 +556,16 @@ int lbm_set_recording(lbm_ctx* c, void* rec_buf, size_t rec_bytes, int64_t max_s
 int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_bytes, void* adj_buf, size_t adj_bytes,
                 double* grad_out, double* dL_drho0, void* stream)
 {
-    if (!c || !dL_drho_T || !adj_buf || !grad_out) return LBM_EINVAL;
+    if (!dL_drho_T) return LBM_EINVAL;
+    return lbm_adjoint_fields(c, dL_drho_T, nullptr, nullptr, rec_buf, rec_bytes, adj_buf, adj_bytes, grad_out,
+                              dL_drho0, stream);
+}
+
+int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux_T, const double* dL_duy_T,
+                       void* rec_buf, size_t rec_bytes, void* adj_buf, size_t adj_bytes, double* grad_out,
+                       double* dL_drho0, void* stream)
+{
+    if (!c || !adj_buf || !grad_out || !(dL_drho_T || dL_dux_T || dL_duy_T)) return LBM_EINVAL;
     const lbm_params& P = c->P;
     // a forward recorded from step 0 needs no recomputation
     const bool recorded = c->rec_all != nullptr && c->step >= 1 && c->step <= c->rec_steps;
@@ -477,9 +600,6 @@ int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_b
     const size_t nacc = (size_t)L.blocks * kAcc;
     hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, acc, nacc);
     dim3 g1((P.nx + 127) / 128, P.ny);
-    if (f32) hipLaunchKernelGGL(k_adj_seed<float>, g1, dim3(128), 0, s, P.nx, P.ny, c->ld, lp, dL_drho_T, lam[0]);
-    else hipLaunchKernelGGL(k_adj_seed<double>, g1, dim3(128), 0, s, P.nx, P.ny, c->ld, lp, dL_drho_T, lam[0]);
-    if (!hip_ok(hipGetLastError(), "adjoint seed")) return LBM_EHIP;
 
     AdjArgs A;
     std::memset(&A, 0, sizeof(A));
@@ -493,6 +613,20 @@ int lbm_adjoint(lbm_ctx* c, const double* dL_drho_T, void* rec_buf, size_t rec_b
     A.inv_G = 1.0 / P.G;
     A.kd = {A.c_e, A.c_q, 2.0 * P.sigma, A.inv_G};
     A.kf = {(float)A.c_e, (float)A.c_q, (float)(2.0 * P.sigma), (float)A.inv_G};
+    if (dL_dux_T || dL_duy_T) {
+        // lambda^T from the final state (still in buf[cur]: the recomputation starts after this launch)
+        A.lam_out = lam[0];
+        if (f32)
+            hipLaunchKernelGGL(k_adj_seed_u<float>, dim3(L.blocks), dim3(64 * kAdjWaves), 0, s, A,
+                               (const void*)c->buf[c->cur], dL_drho_T, dL_dux_T, dL_duy_T);
+        else
+            hipLaunchKernelGGL(k_adj_seed_u<double>, dim3(L.blocks), dim3(64 * kAdjWaves), 0, s, A,
+                               (const void*)c->buf[c->cur], dL_drho_T, dL_dux_T, dL_duy_T);
+    } else {
+        if (f32) hipLaunchKernelGGL(k_adj_seed<float>, g1, dim3(128), 0, s, P.nx, P.ny, c->ld, lp, dL_drho_T, lam[0]);
+        else hipLaunchKernelGGL(k_adj_seed<double>, g1, dim3(128), 0, s, P.nx, P.ny, c->ld, lp, dL_drho_T, lam[0]);
+    }
+    if (!hip_ok(hipGetLastError(), "adjoint seed")) return LBM_EHIP;
     int li = 0;
     if (recorded) {
         // the forward kept every step's record: transposed steps only, T_end - 1 down to 0

@@ -103,6 +103,7 @@ def _signatures():
         "lbm_set_checkpointing": ([vp, vp, sz, i], i),
         "lbm_set_recording": ([vp, vp, sz, C.c_int64], i),
         "lbm_adjoint": ([vp, vp, vp, sz, vp, sz, dp, vp, vp], i),
+        "lbm_adjoint_fields": ([vp, vp, vp, vp, vp, sz, vp, sz, dp, vp, vp], i),
         "lbm_eos_set_knots": ([C.POINTER(LbmEos), d, d, d, d], i),
         "lbm_fd_layout": ([C.POINTER(LbmFdParams), C.POINTER(sz)], i),
         "lbm_fd_init": ([C.POINTER(vp), C.POINTER(LbmFdParams), vp, sz, vp, vp, vp, vp], i),
@@ -346,17 +347,22 @@ class Lattice:
         _check(load().lbm_set_recording(self._h, self._recall.data_ptr(), self._recall.numel(), int(max_steps)),
                "lbm_set_recording")
 
-    def adjoint(self, dL_drho, want_rho0: bool = False):
-        """Gradient of a loss L(rho(T)) given dL/drho(T) [ny][nx]: dict of GRAD_NAMES (+ 'rho0' field)."""
+    def adjoint(self, dL_drho, want_rho0: bool = False, dL_dux=None, dL_duy=None):
+        """Gradient of a loss L(rho(T), u(T)) given dL/drho(T), dL/du_x(T), dL/du_y(T) [ny][nx] (None: zero):
+        dict of GRAD_NAMES (+ 'rho0' field)."""
         t = self.torch
-        g = self._dev(dL_drho, (self.ny, self.nx))
+        shp = (self.ny, self.nx)
+        g = self._dev(dL_drho, shp) if dL_drho is not None else None
+        gx = self._dev(dL_dux, shp) if dL_dux is not None else None
+        gy = self._dev(dL_duy, shp) if dL_duy is not None else None
+        ptr = lambda a: a.data_ptr() if a is not None else None
         out = (C.c_double * 6)()
-        r0 = t.empty((self.ny, self.nx), dtype=t.float64, device=self.device) if want_rho0 else None
+        r0 = t.empty(shp, dtype=t.float64, device=self.device) if want_rho0 else None
         rec = getattr(self, "_rec", None)
-        _check(load().lbm_adjoint(self._h, g.data_ptr(), rec.data_ptr() if rec is not None else None,
-                                  rec.numel() if rec is not None else 0, self._adj.data_ptr(),
-                                  self._adj.numel(), out, r0.data_ptr() if r0 is not None else None, self._s()),
-               "lbm_adjoint")
+        _check(load().lbm_adjoint_fields(self._h, ptr(g), ptr(gx), ptr(gy), ptr(rec),
+                                         rec.numel() if rec is not None else 0, self._adj.data_ptr(),
+                                         self._adj.numel(), out, ptr(r0), self._s()),
+               "lbm_adjoint_fields")
         res = dict(zip(GRAD_NAMES, list(out)))
         if r0 is not None:
             res["rho0"] = r0

@@ -1,8 +1,8 @@
 """torch.autograd front end of lbm_adjoint.
 
 ``LbmRollout.apply(knots, G, sigma, rho0, spec)`` runs ``spec.steps`` fused steps from
-f^eq(rho0, u = 0) and returns rho(T) as a float64 tensor on the lattice's device; its backward
-calls lbm_adjoint and returns dL/d(knots), dL/dG, dL/dsigma and dL/drho0.  With ``spec.K = None``
+f^eq(rho0, u = 0) and returns rho(T) and u(T) as float64 tensors on the lattice's device (``rollout``
+keeps rho only); its backward calls lbm_adjoint_fields and returns dL/d(knots), dL/dG, dL/dsigma and dL/drho0.  With ``spec.K = None``
 the forward records every step in HBM (16 B per node and step in FP32) and the backward runs
 only the transposed steps; with an integer K it checkpoints every K steps and recomputes each
 segment.  knots = (rho_max, p_max, rho_min, p_min) are the
@@ -41,6 +41,7 @@ def _autograd_function():
     class LbmRollout(torch.autograd.Function):
         @staticmethod
         def forward(ctx, knots, G, sigma, rho0, spec: RolloutSpec):
+            ctx.set_materialize_grads(False)
             k = [float(v) for v in knots.detach().cpu().double().tolist()]
             e = lbm.eos_set_knots(spec.eos, *k)
             P = lbm.make_params(spec.nx, spec.ny, e, G=_f(G), sigma=_f(sigma), prec=spec.prec, **spec.params)
@@ -51,16 +52,19 @@ def _autograd_function():
                 lat.enable_checkpointing(spec.K, spec.steps)
             lat.step(spec.steps)
             lat.check()
-            rho = lat.macros()["rho"]
+            m = lat.macros()
             ctx.lat = lat
             ctx.meta = (knots.dtype, knots.device, rho0.dtype, rho0.device)
-            return rho
+            return m["rho"], m["ux"], m["uy"]
 
         @staticmethod
-        def backward(ctx, grad_rho):
+        def backward(ctx, g_rho, g_ux, g_uy):
             lat = ctx.lat
             kd, kdev, rd, rdev = ctx.meta
-            g = lat.adjoint(grad_rho.detach().to(torch.float64).contiguous(), want_rho0=ctx.needs_input_grad[3])
+            prep = lambda g: g.detach().to(torch.float64).contiguous() if g is not None else None
+            if g_rho is None and g_ux is None and g_uy is None:
+                g_rho = torch.zeros((lat.ny, lat.nx), dtype=torch.float64, device=lat.device)
+            g = lat.adjoint(prep(g_rho), want_rho0=ctx.needs_input_grad[3], dL_dux=prep(g_ux), dL_duy=prep(g_uy))
             ctx.lat = None
             lat.close()
             gk = torch.tensor([g[n] for n in lbm.GRAD_NAMES[:4]], dtype=kd, device=kdev)
@@ -75,12 +79,18 @@ def _autograd_function():
 _FN = None
 
 
-def rollout(knots, G, sigma, rho0, spec: RolloutSpec):
-    """rho(T) with gradients flowing to knots, G, sigma and rho0 (torch tensors)."""
+def rollout_fields(knots, G, sigma, rho0, spec: RolloutSpec):
+    """(rho(T), u_x(T), u_y(T)) with gradients flowing to knots, G, sigma and rho0 (torch tensors);
+    u is the forced velocity (j + F/2)/rho of Eq. Momentum."""
     global _FN
     if _FN is None:
         _FN = _autograd_function()
     return _FN.apply(knots, G, sigma, rho0, spec)
+
+
+def rollout(knots, G, sigma, rho0, spec: RolloutSpec):
+    """rho(T) with gradients flowing to knots, G, sigma and rho0 (torch tensors)."""
+    return rollout_fields(knots, G, sigma, rho0, spec)[0]
 
 
 def knots_of(e: lbm.LbmEos) -> np.ndarray:

@@ -32,12 +32,16 @@ def _case(kind):
 
 
 def _oracle_loss(e, s, nx, ny, rho0, w, extra, steps, G=-1.0, knots=None, sigma=None):
+    """sum w rho(T), or with w = (w_rho, w_ux, w_uy) sum w_rho rho + w_ux u_x + w_uy u_y at T."""
     ee = O.eos_set_knots(e, *knots) if knots is not None else e
     P = O.make_params(nx, ny, ee, G=G, sigma=s if sigma is None else sigma, tau=TAU, **extra)
     L = O.Lattice(P)
     L.init_eq(rho0)
     L.run(steps)
-    return float((w * L.macros()["rho"]).sum())
+    m = L.macros()
+    if isinstance(w, tuple):
+        return float((w[0] * m["rho"]).sum() + (w[1] * m["ux"]).sum() + (w[2] * m["uy"]).sum())
+    return float((w * m["rho"]).sum())
 
 
 def _fd(e, s, nx, ny, rho0, w, extra, steps):
@@ -170,6 +174,52 @@ def test_recorded_forward_keeps_reductions_and_limits(gpu_lib):
     assert ei.value.code == lbm.LBM_ESTATE
 
 
+@pytest.mark.parametrize("kind", ["droplet", "walls"])
+def test_adjoint_velocity_loss_matches_oracle_finite_differences(gpu_lib, kind):
+    """Loss on the final density AND velocity u = (j + F/2)/rho (lbm_adjoint_fields): the seed carries
+    the F = psi F~ path (neighbours' psi, the EOS knots and G) on top of the transposed steps."""
+    lbm = gpu_lib
+    e, s, nx, ny, rho0, w, extra = _case(kind)
+    rng = np.random.default_rng(12)
+    wx, wy = rng.standard_normal((ny, nx)), rng.standard_normal((ny, nx))
+    el, sl = lbm.eos_build(lbm.make_eos(**SMOOTH))
+    P = lbm.make_params(nx, ny, el, sigma=sl, tau=TAU, prec=lbm.FP64, **extra)
+    lat = lbm.Lattice(P, rho0, device="cuda:0")
+    steps = 14
+    lat.enable_recording(steps)
+    lat.step(steps)
+    g = lat.adjoint(w, want_rho0=True, dL_dux=wx, dL_duy=wy)
+    fd = _fd(e, s, nx, ny, rho0, (w, wx, wy), extra, steps)
+    got = np.array([g[n] for n in NAMES])
+    for n, a, b in zip(NAMES, got, fd):
+        assert abs(a - b) <= 1e-4 * abs(b) + 1e-9 * np.abs(fd).max(), (kind, n, a, b)
+    d0 = g["rho0"].cpu().numpy()
+    for (y, x) in [(ny // 2, nx // 2), (ny // 2, nx // 2 + 7), (1, 3)]:
+        h = 1e-6 * rho0[y, x]
+        rp, rm = rho0.copy(), rho0.copy()
+        rp[y, x] += h
+        rm[y, x] -= h
+        fdr = (_oracle_loss(e, s, nx, ny, rp, (w, wx, wy), extra, steps)
+               - _oracle_loss(e, s, nx, ny, rm, (w, wx, wy), extra, steps)) / (2 * h)
+        assert abs(d0[y, x] - fdr) <= 1e-5 * abs(fdr) + 1e-7, (y, x, d0[y, x], fdr)
+
+
+def test_adjoint_fields_with_zero_velocity_terms_equals_density_seed(gpu_lib):
+    lbm = gpu_lib
+    e, s, nx, ny, rho0, w, extra = _case("droplet")
+    el, sl = lbm.eos_build(lbm.make_eos(**SMOOTH))
+    out = []
+    for zero in (False, True):
+        lat = lbm.Lattice(lbm.make_params(nx, ny, el, sigma=sl, tau=TAU, prec=lbm.FP64), rho0, device="cuda:0")
+        lat.enable_recording(9)
+        lat.step(9)
+        z = np.zeros((ny, nx)) if zero else None
+        out.append(lat.adjoint(w, want_rho0=True, dL_dux=z, dL_duy=z))
+    for n in NAMES:
+        assert abs(out[0][n] - out[1][n]) <= 1e-13 * max(abs(out[0][n]), 1e-300), n
+    np.testing.assert_allclose(out[0]["rho0"].cpu().numpy(), out[1]["rho0"].cpu().numpy(), rtol=1e-13, atol=1e-16)
+
+
 def test_adjoint_error_paths(gpu_lib):
     lbm = gpu_lib
     e, s = lbm.eos_build(lbm.make_eos(**SMOOTH))
@@ -217,3 +267,15 @@ def test_rollout_autograd_matches_direct_adjoint(gpu_lib):
     k2 = torch.tensor(knots_of(el), dtype=torch.float64, requires_grad=True)
     (torch.as_tensor(w, device=rho.device) * rollout(k2, G.detach(), sig.detach(), r0.detach(), spec_r)).sum().backward()
     np.testing.assert_allclose(k2.grad.numpy(), knots.grad.numpy(), rtol=1e-12)
+    # rollout_fields: a loss on u_x flows through the velocity seed
+    from paper_2107_06355_amd.rollout import rollout_fields
+
+    k3 = torch.tensor(knots_of(el), dtype=torch.float64, requires_grad=True)
+    r_, ux_, uy_ = rollout_fields(k3, G.detach(), sig.detach(), r0.detach(), spec_r)
+    wx = torch.as_tensor(np.random.default_rng(4).standard_normal((ny, nx)), device=rho.device)
+    (wx * ux_).sum().backward()
+    lat = lbm.Lattice(lbm.make_params(nx, ny, el, sigma=sl, tau=TAU, prec=lbm.FP64), rho0, device="cuda:0")
+    lat.enable_recording(16)
+    lat.step(16)
+    gd = lat.adjoint(None, dL_dux=wx.cpu().numpy())
+    np.testing.assert_allclose(k3.grad.numpy(), [gd[n] for n in NAMES[:4]], rtol=1e-12)
