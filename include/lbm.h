@@ -53,9 +53,10 @@ typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_prec;
  * MARCH: one wavefront marches up a band of rows of a 62-column strip with
  * two rows of loads in flight; BLOCK: a 12-wavefront workgroup loads 12 rows
  * of a strip, one per wavefront, and shares psi through LDS; BLOCK2: a
- * 16-wavefront workgroup advances a 58 x 10 tile by two time steps per launch
- * and keeps the intermediate populations in LDS (temporal blocking; a step
- * that reduces or checkpoints runs alone on BLOCK). */
+ * 16-wavefront (FP32) or 12-wavefront (FP64) workgroup advances a 58 x 10 or
+ * 58 x 6 tile by two time steps per launch and keeps the intermediate
+ * populations in LDS (temporal blocking; a step that reduces or checkpoints
+ * runs alone on BLOCK).  AUTO is BLOCK2. */
 typedef enum {
     LBM_VARIANT_AUTO = 0,
     LBM_VARIANT_MARCH = 1,

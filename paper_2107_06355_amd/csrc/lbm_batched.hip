@@ -168,8 +168,22 @@ void k_batch_step2(const BatchItem* items, const int* tile_off, int B, char* buf
 // the three-column ring in x is recomputed.  Same phases and node arithmetic as step2_tile.
 constexpr int kFullRows = 16;
 
+// FP32: the lattice's EOS record in LDS (read by node_psi).  FP64 keeps it in its
+// arguments: its 80 KB of LDS per workgroup leave no room beside two workgroups per CU.
 template <typename T>
-struct FullLds {
+struct FullEos {
+    DevEos eos;
+    __device__ const DevEos& get(const StepArgs&) const { return eos; }
+    __device__ void put(const StepArgs& A) { eos = A.eos; }
+};
+template <>
+struct FullEos<double> {
+    __device__ const DevEos& get(const StepArgs& A) const { return A.eos; }
+    __device__ void put(const StepArgs&) {}
+};
+
+template <typename T>
+struct FullLds : FullEos<T> {
     T sps[kFullRows][64];
     T smv[8][kFullRows][64];
     double sg0[kFullRows][64];
@@ -203,21 +217,29 @@ __global__ __launch_bounds__(64 * kFullRows) void k_batch_full2(const BatchItem*
     L.lane = l;
     L.valid = dl <= 3;
     L.interior = dl == 0;
-    int x = ((x0 - 3 + l) % A.nx + A.nx) % A.nx;
+    // columns of lanes with dl <= 3 lie in [-3, nx + 2]: one wrap each way unless nx < 3
+    int x = x0 - 3 + l;
+    if (A.nx >= 3) x = x < 0 ? x + A.nx : (x >= A.nx ? x - A.nx : x);
+    else x = (x % A.nx + A.nx) % A.nx;
     if (dl > 3) x = 0;
     L.x = x;
     L.xm = x == 0 ? A.nx - 1 : x - 1;
     L.xp = x == A.nx - 1 ? 0 : x + 1;
     Acc acc = {0.0, 0.0, 0.0};
-    // 1. step t: pull, rho, psi
+    // 1. step t: pull, rho, psi (the EOS record goes to LDS while the pull is in flight,
+    //    as in step2_tile)
+    if (threadIdx.x == 0) S.put(A);
     Row<T> R;
     double dr = 0.0;
     T ps = (T)0;
     if (row && dl <= 3) {
         const View<T> V = make_view<T>(A.src, A.plane);
         pull<T>(V, A, L.x, L.xm, L.xp, k, R.g0, R.g);
+    }
+    __syncthreads();
+    if (row && dl <= 3) {
         dr = node_drho<T>(R.g0, R.g);
-        ps = node_psi<T>(A, dr, true);
+        ps = node_psi<T>(A, S.get(A), dr, true);
     }
     S.sps[k][l] = ps;
     __syncthreads();
@@ -246,7 +268,7 @@ __global__ __launch_bounds__(64 * kFullRows) void k_batch_full2(const BatchItem*
         R.g[7] = S.smv[6][kp][l + 1];
         R.g[8] = S.smv[7][kp][l - 1];
         dr = node_drho<T>(R.g0, R.g);
-        ps = node_psi<T>(A, dr, true, 1);
+        ps = node_psi<T>(A, S.get(A), dr, true, 1);
         S.sps[k][l] = ps;
     }
     __syncthreads();

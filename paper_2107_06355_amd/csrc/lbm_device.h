@@ -286,10 +286,9 @@ __device__ __forceinline__ float dev_base_dpf(const DevEos& E, float r)
 // FP32, the shaped loop between rho_v and rho_l (the branch junctions) in FP64;
 // the square root is the hardware one (within 1 ulp, no correction sequence).
 template <typename T>
-__device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check, int dstep = 0)
+__device__ __forceinline__ T node_psi(const StepArgs& A, const DevEos& E, double drho, bool check, int dstep = 0)
 {
     const double rho = A.rho_ref + drho;
-    const DevEos& E = A.eos;
     if (sizeof(T) == 4 && E.shape != LBM_SHAPE_NONE && (rho <= E.rho_v || rho >= E.rho_l)) {
         const float r = (float)rho;
         const float pb = dev_base_pf(E, r);
@@ -303,6 +302,11 @@ __device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check
     if (check && !(q >= 0.0 && rho > 0.0)) flag_unstable(A, dstep);
     if (sizeof(T) == 4) return (T)(q > 0.0 ? __builtin_amdgcn_sqrtf((float)q) : 0.0f);
     return (T)(q > 0.0 ? sqrt(q) : 0.0);
+}
+template <typename T>
+__device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check, int dstep = 0)
+{
+    return node_psi<T>(A, A.eos, drho, check, dstep);
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -518,6 +522,7 @@ constexpr int k2Cols = 64 - 6;
 // LDS of one two-step tile
 template <typename T>
 struct Step2Lds {
+    DevEos eos;                          // the lattice's EOS record (read by node_psi)
     T sps[k2WavesOf<T>][64];            // psi of the tile grown by 3 (step t), then by 1 (step t+1)
     T smv[8][k2WavesOf<T> - 2][64];     // post-collision moving populations of step t (tile grown by 2)
     double sg0[k2WavesOf<T> - 2][64];   // and their FP64 rest population
@@ -543,7 +548,10 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
     L.lane = l;
     L.valid = d <= 3;
     L.interior = d == 0;
-    int x = ((x0 - 3 + l) % A.nx + A.nx) % A.nx;
+    // columns of lanes with dl <= 3 lie in [-3, nx + 2]: one wrap each way unless nx < 3
+    int x = x0 - 3 + l;
+    if (A.nx >= 3) x = x < 0 ? x + A.nx : (x >= A.nx ? x - A.nx : x);
+    else x = (x % A.nx + A.nx) % A.nx;
     if (dl > 3) x = 0;
     L.x = x;
     L.xm = x == 0 ? A.nx - 1 : x - 1;
@@ -554,20 +562,29 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
     // carries none of this (its scalar registers are the occupancy limit).
     const bool walls = WALLS && A.walls;
     const bool fluid = !walls || (r >= 0 && r < A.ny);
-    const int rw = walls ? r : (r % A.ny + A.ny) % A.ny;
+    // r lies in [-3, ny + 2] for every wave: one wrap each way unless ny < 3
+    const int rw = walls ? r
+                         : (A.ny >= 3 ? (r < 0 ? r + A.ny : (r >= A.ny ? r - A.ny : r)) : (r % A.ny + A.ny) % A.ny);
     const T ghost = walls ? (T)(r < 0 ? A.psi_lo : A.psi_hi) : (T)0;
     Acc acc = {0.0, 0.0, 0.0};
 
-    // 1. step t: pull, rho, psi
+    // 1. step t: pull, rho, psi.  The EOS record is copied to LDS while the pull is in
+    //    flight: psi reads it there in phases 1 and 3, instead of the launch holding it in
+    //    scalar registers (which spills them to vector lanes at this occupancy).
+    if (threadIdx.x == 0) S.eos = A.eos;
     Row<T> R;
     double dr = 0.0;
     T ps = (T)0;
-    if (dk <= 3 && dl <= 3) {
+    const bool ring3 = dk <= 3 && dl <= 3;
+    if (ring3 && fluid) {
+        const View<T> V = make_view<T>(A.src, A.plane);
+        pull<T>(V, A, L.x, L.xm, L.xp, rw, R.g0, R.g);
+    }
+    __syncthreads();
+    if (ring3) {
         if (fluid) {
-            const View<T> V = make_view<T>(A.src, A.plane);
-            pull<T>(V, A, L.x, L.xm, L.xp, rw, R.g0, R.g);
             dr = node_drho<T>(R.g0, R.g);
-            ps = node_psi<T>(A, dr, true);
+            ps = node_psi<T>(A, S.eos, dr, true);
         } else {
             ps = ghost;
         }
@@ -619,7 +636,7 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
             R.g[8] = smv[5][q][l];
         }
         dr = node_drho<T>(R.g0, R.g);
-        ps = node_psi<T>(A, dr, true, 1);
+        ps = node_psi<T>(A, S.eos, dr, true, 1);
         sps[k][l] = ps;
     } else if (walls && dk <= 1 && dl <= 1) {
         sps[k][l] = ghost;

@@ -346,21 +346,10 @@ bool hip_ok(hipError_t e, const char* what)
 // kernel: one 16-wave workgroup per (strip, band of 14 rows).
 int resolve_variant(const lbm_params& p)
 {
-    int v = p.kernel_variant;
-    if (v == 0 && (!p.walls || p.prec == LBM_FP64)) {
-        // measured on MI355X: two steps per launch beat every one-step decomposition on
-        // periodic lattices (512^2 .. 16384^2, both precisions) and on the walled
-        // 2048 x 1024 drop impact in FP64 (56.4 vs 61.0 us); in FP32 the walled two-step
-        // kernel (more scalar spills) loses to the row block there (32.5 vs 29.8 us)
-        v = LBM_VARIANT_BLOCK2;
-    } else if (v == 0) {
-        // measured on MI355X: the row block wins while the lattice is cache-resident or
-        // the step is FP64; large FP32 lattices prefer the row march (4-row bands)
-        const long long cells = (long long)p.nx * p.ny;
-        const long long limit = p.prec == LBM_FP32_SHIFTED ? (5LL << 20) : (40LL << 20);
-        v = cells <= limit ? LBM_VARIANT_BLOCK : LBM_VARIANT_MARCH;
-    }
-    return v;
+    // measured on MI355X: two steps per launch beat both one-step decompositions on every
+    // lattice timed, periodic (512^2 .. 16384^2) and walled (2048 x 1024 drop impact:
+    // 25.0 vs 30.0 us FP32, 46.9 vs 60.8 us FP64; 8192 x 2048 FP32: 202 vs 300 us)
+    return p.kernel_variant == 0 ? LBM_VARIANT_BLOCK2 : p.kernel_variant;
 }
 
 int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk)

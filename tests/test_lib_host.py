@@ -76,16 +76,15 @@ def test_layout_rejects_a_plane_above_4_gib():
 
 def test_automatic_kernel_choice():
     """lbm_describe resolves the automatic decomposition (host logic only): two steps per launch on
-    periodic lattices in both precisions and on walled FP64 ones; the row block for walled FP32
-    lattices up to 5 * 2^20 cells and the row march above; explicit choices are kept."""
+    periodic and walled lattices in both precisions; explicit choices are kept."""
     e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
     P32, P64 = lbm.FP32_SHIFTED, lbm.FP64
     cases = [
         (dict(nx=512, ny=512, prec=P32), lbm.VARIANT_BLOCK2),
         (dict(nx=8192, ny=8192, prec=P32), lbm.VARIANT_BLOCK2),
         (dict(nx=8192, ny=8192, prec=P64), lbm.VARIANT_BLOCK2),
-        (dict(nx=2048, ny=1024, prec=P32, walls=True), lbm.VARIANT_BLOCK),
-        (dict(nx=4096, ny=2048, prec=P32, walls=True), lbm.VARIANT_MARCH),
+        (dict(nx=2048, ny=1024, prec=P32, walls=True), lbm.VARIANT_BLOCK2),
+        (dict(nx=8192, ny=2048, prec=P32, walls=True), lbm.VARIANT_BLOCK2),
         (dict(nx=2048, ny=1024, prec=P64, walls=True), lbm.VARIANT_BLOCK2),
         (dict(nx=512, ny=512, prec=P32, kernel_variant=lbm.VARIANT_MARCH), lbm.VARIANT_MARCH),
         (dict(nx=512, ny=512, prec=P32, kernel_variant=lbm.VARIANT_BLOCK), lbm.VARIANT_BLOCK),
