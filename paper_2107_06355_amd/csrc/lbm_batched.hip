@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchItem* items, cons
 // lists (lattice b owns tiles [tile_off[b], tile_off[b+1]), tile = strip + strips * band);
 // the tile arithmetic is step2_tile of the single-lattice two-step kernel.
 template <typename T, bool WALLS>
-__global__ __launch_bounds__(64 * k2WavesOf<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 6)))
+__global__ __launch_bounds__(64 * k2WavesOf<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : LBM_K2_EU_F64)))
 void k_batch_step2(const BatchItem* items, const int* tile_off, int B, char* buf0, char* buf1, int cur, long long step)
 {
     __shared__ Step2Lds<T> S;

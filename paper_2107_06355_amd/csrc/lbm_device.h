@@ -27,6 +27,14 @@ namespace lbmk {
 #define LBM_OCCUPANCY_HINT
 #endif
 
+// build-time tuning of the FP64 two-step kernel: waves per workgroup and per SIMD
+#ifndef LBM_K2_WAVES_F64
+#define LBM_K2_WAVES_F64 12
+#endif
+#ifndef LBM_K2_EU_F64
+#define LBM_K2_EU_F64 6
+#endif
+
 constexpr int kStripW = 62;   // interior columns per wave (lanes 0 and 63 are the psi halo)
 
 // ----------------------------------------------------------------- device EOS
@@ -515,7 +523,7 @@ __device__ __forceinline__ void collide_row(const StepArgs& A, const Lane& L, in
 // 8 waves per SIMD; FP64 12, two workgroups per CU at the 77 VGPRs the FP64 path needs
 // (measured on MI355X: FP64 8192^2 1468 vs 1553 us/step with 16 waves; FP32 loses with 12).
 template <typename T>
-constexpr int k2WavesOf = sizeof(T) == 4 ? 16 : 12;
+constexpr int k2WavesOf = sizeof(T) == 4 ? 16 : LBM_K2_WAVES_F64;
 inline int k2waves_of_prec(int prec) { return prec == LBM_FP32_SHIFTED ? k2WavesOf<float> : k2WavesOf<double>; }
 constexpr int k2Cols = 64 - 6;
 

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
 // workgroups per CU; 16-wave FP64 workgroups fit only one per CU, and forcing two of
 // them spilled vector registers to scratch (25% slower on MI355X at 4096^2).
 template <typename T, int MODE, bool WALLS>
-__global__ __launch_bounds__(64 * k2WavesOf<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 6)))
+__global__ __launch_bounds__(64 * k2WavesOf<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : LBM_K2_EU_F64)))
 void k_step2_blk(StepArgs A)
 {
     __shared__ Step2Lds<T> S;
