@@ -648,10 +648,15 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
                     "restore checkpoint"))
             return LBM_EHIP;
         c->step = t0;
-        for (int j = 0; j < n; ++j) {
-            if (!launch_record_step(c, (char*)rec_buf + (size_t)j * 4 * nn * L.tsz, s)) return LBM_EHIP;
+        for (int j = 0; j < n;) {
+            // recompute the segment's records, two steps per launch where the forward's
+            // two-step kernel applies (its two records land in consecutive slots)
+            void* rec = (char*)rec_buf + (size_t)j * 4 * nn * L.tsz;
+            const bool pair = c->blk2 && j + 1 < n;
+            if (!(pair ? launch_record_pair(c, rec, s) : launch_record_step(c, rec, s))) return LBM_EHIP;
             c->cur ^= 1;
-            c->step++;
+            c->step += pair ? 2 : 1;
+            j += pair ? 2 : 1;
         }
         for (int j = n - 1; j >= 0; --j) {
             A.rec = (const char*)rec_buf + (size_t)j * 4 * nn * L.tsz;

@@ -35,6 +35,9 @@ namespace lbmk {
 bool hip_ok(hipError_t e, const char* what);
 bool launch_reduce(lbm_ctx* c, double* out, long long step, int with_step, hipStream_t s);
 bool launch_record_step(lbm_ctx* c, void* rec, hipStream_t s);
+// two recorded steps in one launch (two-step variant only): records of steps t and t+1 in
+// consecutive slots from rec
+bool launch_record_pair(lbm_ctx* c, void* rec, hipStream_t s);
 int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk);
 int resolve_variant(const lbm_params& p);
 }  // namespace lbmk

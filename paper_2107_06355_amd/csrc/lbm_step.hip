@@ -483,6 +483,11 @@ bool launch_step2(lbm_ctx* c, void* rec, hipStream_t s)
     return hip_ok(hipGetLastError(), "k_step2_blk launch");
 }
 
+bool launch_record_pair(lbm_ctx* c, void* rec, hipStream_t s)
+{
+    return c->P.prec == LBM_FP32_SHIFTED ? launch_step2<float>(c, rec, s) : launch_step2<double>(c, rec, s);
+}
+
 // FP64 mass/momentum partials of the current state (no step), then the reduction
 bool launch_partials(lbm_ctx* c, double* out, long long step, hipStream_t s)
 {
