@@ -261,6 +261,40 @@ def test_fp32_mass_drift_droplet(gpu_lib, variant):
     assert np.abs(h[:, 2:]).max() <= 1e-9 * mass[0]
 
 
+def test_fp32_rest_population_ablation_c2(gpu_lib):
+    """Ablation of the exact-mass rest population on the 512^2 droplet (R = 80, shaped PR Tr = 0.5): the
+    same run with the rest population rounded to FP32 after every step (all nine populations in FP32, as a
+    plain FP32 code stores them) drifts far past 1e-10; the FP64 rest population keeps the mass exact."""
+    import torch
+    import bench
+    lbm = gpu_lib
+    e, s = lbm.eos_build(lbm.make_eos(**bench.EOS_KW))
+    n, steps = 512, 10000
+    rho0 = droplet_density(n, n, e.rho_v, e.rho_l, R=80, W=20)
+    drift = {}
+    for naive in (False, True):
+        P = lbm.make_params(n, n, e, sigma=s, tau=bench.TAU, prec=lbm.FP32_SHIFTED, reduce_every=0,
+                            kernel_variant=lbm.VARIANT_BLOCK)
+        L = lbm.Lattice(P, rho0, device="cuda:0")
+        m0 = L.mass_momentum()[0]
+        plane = n * L.ld
+        worst = 0.0
+        for k in range(steps):
+            L.step(1)
+            if naive:
+                # the FP64 rest plane follows the eight FP32 planes of the current buffer
+                rest = L.current_buffer()[32 * plane:40 * plane].view(torch.float64)
+                rest.copy_(rest.float().double())
+            if (k + 1) % 500 == 0:
+                worst = max(worst, abs(L.mass_momentum()[0] / m0 - 1))
+        L.check()
+        drift[naive] = worst
+        print("# C2 mass drift over %d steps: %s rest population %.3e" % (steps, "FP32" if naive else "FP64", worst))
+        L.close()
+    assert drift[False] <= 1e-12, drift
+    assert drift[True] > 1e-9, drift
+
+
 # ---------------------------------------------------------------- the paper's printed result on the GPU
 import json as _json
 import os as _os
