@@ -134,7 +134,20 @@ def cpu_baseline(n, steps, R):
     dt = time.perf_counter() - t0
     return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": "%dx%d droplet, %d time steps from the same initial state (FP64, single thread, %.1f s)"
-                      % (n, n, steps, dt)}
+                      % (n, n, steps, dt), "host": _host_cpu()}
+
+
+def _host_cpu() -> str:
+    """CPU model and the CPUs this process may run on (the oracle uses one of them)."""
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return "%s, %d CPUs available" % (model, len(os.sched_getaffinity(0)))
 
 
 def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
