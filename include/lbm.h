@@ -55,8 +55,9 @@ typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_prec;
  * of a strip, one per wavefront, and shares psi through LDS; BLOCK2: a
  * 16-wavefront (FP32) or 12-wavefront (FP64) workgroup advances a 58 x 10 or
  * 58 x 6 tile by two time steps per launch and keeps the intermediate
- * populations in LDS (temporal blocking; a step that reduces or checkpoints
- * runs alone on BLOCK).  AUTO is BLOCK2. */
+ * populations in LDS (temporal blocking; a reducing step ends a launch, and
+ * checkpoint boundaries and odd counts run single steps on BLOCK).  AUTO is
+ * BLOCK2. */
 typedef enum {
     LBM_VARIANT_AUTO = 0,
     LBM_VARIANT_MARCH = 1,

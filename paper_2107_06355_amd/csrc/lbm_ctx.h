@@ -34,6 +34,7 @@ struct lbm_ctx {
 namespace lbmk {
 bool hip_ok(hipError_t e, const char* what);
 bool launch_reduce(lbm_ctx* c, double* out, long long step, int with_step, hipStream_t s);
+bool launch_reduce_n(lbm_ctx* c, int n, double* out, long long step, int with_step, hipStream_t s);
 bool launch_record_step(lbm_ctx* c, void* rec, hipStream_t s);
 // two recorded steps in one launch (two-step variant only): records of steps t and t+1 in
 // consecutive slots from rec

@@ -655,12 +655,23 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
         T Ftx, Fty;
         force_tilde<T>(A, sps[k - 1][l - 1], sps[k - 1][l], sps[k - 1][l + 1], sps[k][l - 1], sps[k][l + 1],
                        sps[k + 1][l - 1], sps[k + 1][l], sps[k + 1][l + 1], Ftx, Fty);
-        update_node<T, MODE_STEP>(A, L, r, R, dr, ps, Ftx, Fty, acc);
+        update_node<T, MODE == MODE_STEP_REDUCE ? MODE_STEP_REDUCE : MODE_STEP>(A, L, r, R, dr, ps, Ftx, Fty, acc);
         if (MODE == MODE_RECORD) {
             T jx, jy;
             node_j<T>(R.g, jx, jy);
             record_node<T>((char*)A.rec + 4 * A.rec_plane * sizeof(T), A.rec_plane, (size_t)r * A.nx + x, (T)dr, jx,
                            jy, ps);
+        }
+    }
+    if (MODE == MODE_STEP_REDUCE) {
+        // FP64 mass and momentum of step t+1 (each node once: the tile's own), one partial per
+        // (tile, wave) in tile order
+        const double m = wave_sum(acc.m), jx = wave_sum(acc.x), jy = wave_sum(acc.y);
+        if (l == 0) {
+            const size_t w = ((size_t)band * ((A.nx + k2Cols - 1) / k2Cols) + strip) * k2WavesOf<T> + k;
+            A.partials[3 * w + 0] = m;
+            A.partials[3 * w + 1] = jx;
+            A.partials[3 * w + 2] = jy;
         }
     }
 }

@@ -208,10 +208,11 @@ __global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
     }
 }
 
-// FP32: 16 waves, 8 waves per SIMD, two workgroups per CU (the compiler spills scalar
-// registers to vector lanes to fit).  FP64: 12 waves, 6 per SIMD (77 VGPRs), two
+// FP32: 16 waves, 8 waves per SIMD, two workgroups per CU (the EOS record in LDS keeps the
+// scalar registers within the 8-wave budget).  FP64: 12 waves, 6 per SIMD (76 VGPRs), two
 // workgroups per CU; 16-wave FP64 workgroups fit only one per CU, and forcing two of
 // them spilled vector registers to scratch (25% slower on MI355X at 4096^2).
+// MODE_STEP_REDUCE: the second step also leaves the FP64 mass/momentum partials.
 template <typename T, int MODE, bool WALLS>
 __global__ __launch_bounds__(64 * k2WavesOf<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : LBM_K2_EU_F64)))
 void k_step2_blk(StepArgs A)
@@ -370,6 +371,20 @@ int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk)
     return *strips * *nseg;
 }
 
+// per-wave FP64 partial slots the workspace holds: the one-step layout, or one per (tile,
+// wave) of the two-step kernel when it may reduce
+int partial_slots(const lbm_params& p)
+{
+    int strips, seg_h, nseg, blk;
+    int n = decompose(p, &strips, &seg_h, &nseg, &blk);
+    if (resolve_variant(p) == LBM_VARIANT_BLOCK2) {
+        const int w2 = k2waves_of_prec(p.prec), rows2 = w2 - 6;
+        const int n2 = ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + rows2 - 1) / rows2) * w2;
+        n = n2 > n ? n2 : n;
+    }
+    return n;
+}
+
 size_t ws_layout(int nwork, size_t* off_part, size_t* off_hist, size_t* off_red)
 {
     size_t o = 256;  // error word
@@ -424,7 +439,12 @@ void fill_args(lbm_ctx* c)
 
 bool launch_reduce(lbm_ctx* c, double* out, long long step, int with_step, hipStream_t s)
 {
-    const int n = c->args.nwork;
+    return launch_reduce_n(c, c->args.nwork, out, step, with_step, s);
+}
+
+// the same over the first n partial slots
+bool launch_reduce_n(lbm_ctx* c, int n, double* out, long long step, int with_step, hipStream_t s)
+{
     int nb = (n + 1023) / 1024;
     nb = nb < 1 ? 1 : (nb > kRedBlocks ? kRedBlocks : nb);
     const int chunk = (n + nb - 1) / nb;
@@ -464,7 +484,7 @@ bool launch_record_step(lbm_ctx* c, void* rec, hipStream_t s)
 // two steps in one launch (LBM_VARIANT_BLOCK2): source buf[cur], result in buf[cur ^ 1];
 // rec non-NULL: also record both steps (rec, then rec + one step's record)
 template <typename T>
-bool launch_step2(lbm_ctx* c, void* rec, hipStream_t s)
+bool launch_step2(lbm_ctx* c, void* rec, hipStream_t s, bool reduce = false)
 {
     StepArgs A = c->args;
     A.src = c->buf[c->cur];
@@ -475,9 +495,11 @@ bool launch_step2(lbm_ctx* c, void* rec, hipStream_t s)
     const dim3 g(c->grid2), b(64 * k2WavesOf<T>);
     if (c->P.walls) {
         if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true>), g, b, 0, s, A);
+        else if (reduce) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP_REDUCE, true>), g, b, 0, s, A);
         else hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, true>), g, b, 0, s, A);
     } else {
         if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, false>), g, b, 0, s, A);
+        else if (reduce) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP_REDUCE, false>), g, b, 0, s, A);
         else hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, false>), g, b, 0, s, A);
     }
     return hip_ok(hipGetLastError(), "k_step2_blk launch");
@@ -562,9 +584,9 @@ int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* 
     const size_t plane = (size_t)ld * p->ny;
     const size_t bytes = p->prec == LBM_FP32_SHIFTED ? plane * (8 * sizeof(float) + sizeof(double)) : plane * 9 * sizeof(double);
     int strips, seg_h, nseg, blk;
-    const int nwaves = decompose(*p, &strips, &seg_h, &nseg, &blk);
+    decompose(*p, &strips, &seg_h, &nseg, &blk);
     size_t a, b, d;
-    const size_t ws = ws_layout(nwaves, &a, &b, &d);
+    const size_t ws = ws_layout(partial_slots(*p), &a, &b, &d);
     if (ld_out) *ld_out = ld;
     if (pop_bytes_out) *pop_bytes_out = bytes;
     if (ws_bytes_out) *ws_bytes_out = ws;
@@ -618,10 +640,8 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* ws,
     c->step = 0;
     c->ws = (char*)ws;
     c->ws_bytes = ws_bytes;
-    int strips, seg_h, nseg, blk;
-    const int nwaves = decompose(*p, &strips, &seg_h, &nseg, &blk);
     size_t op, oh, orr;
-    ws_layout(nwaves, &op, &oh, &orr);
+    ws_layout(partial_slots(*p), &op, &oh, &orr);
     c->err = (unsigned*)c->ws;
     c->partials = (double*)(c->ws + op);
     c->redblk = (double*)(c->ws + oh - (size_t)kRedBlocks * 3 * sizeof(double));
@@ -676,11 +696,21 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
         }
         const bool red = re > 0 && (c->step % re) == 0;
         void* rec = c->rec_all ? record_slot(c, c->step) : nullptr;
-        // two steps in one launch when neither this step nor the next reduces and no
-        // checkpoint falls between them
-        if (c->blk2 && !red && k + 1 < nsteps && !(re > 0 && (c->step + 1) % re == 0) &&
+        // two steps in one launch when this step does not reduce and no checkpoint falls
+        // between them; if the second step reduces, the launch leaves its partials (a
+        // recording forward reduces in a pass of its own instead)
+        const bool red2 = re > 0 && (c->step + 1) % re == 0;
+        if (c->blk2 && !red && k + 1 < nsteps && !(red2 && rec) &&
             !(c->ckpt_K > 0 && (c->step + 1) % c->ckpt_K == 0)) {
-            if (!(f32 ? launch_step2<float>(c, rec, s) : launch_step2<double>(c, rec, s))) return LBM_EHIP;
+            if (!(f32 ? launch_step2<float>(c, rec, s, red2) : launch_step2<double>(c, rec, s, red2)))
+                return LBM_EHIP;
+            if (red2) {
+                const int w2 = k2waves_of_prec(c->P.prec);
+                const int n2 = ((c->P.nx + k2Cols - 1) / k2Cols) * ((c->P.ny + w2 - 7) / (w2 - 6)) * w2;
+                double* row = c->hist + 4 * (c->hist_count % kHistCap);
+                if (!launch_reduce_n(c, n2, row, (long long)c->step + 1, 1, s)) return LBM_EHIP;
+                c->hist_count++;
+            }
             c->cur ^= 1;
             c->step += 2;
             ++k;

@@ -261,6 +261,43 @@ def test_fp32_mass_drift_droplet(gpu_lib, variant):
     assert np.abs(h[:, 2:]).max() <= 1e-9 * mass[0]
 
 
+@pytest.mark.parametrize("walls", [False, True], ids=["periodic", "walls"])
+@pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
+def test_two_step_launch_reductions_match_one_step(gpu_lib, walls, prec_name):
+    """A reducing step that ends a two-step launch leaves its FP64 partials from that launch: the history
+    rows equal those of one-step launches (same steps, other summation order) for every reduction period."""
+    lbm = gpu_lib
+    e, s = lbm.eos_build(lbm.make_eos(base=0, a=0.387, Tr=0.6, shape=1, alpha=0.834, k_vap=2 / 0.387))
+    nx, ny = 150, 44
+    if walls:
+        rho0, _, _ = droplet_on_film(nx, ny, e.rho_v, e.rho_l, R=9, h=6, gap=3, V=0.0, W=4)
+        extra = dict(walls=True, rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v)
+    else:
+        rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=12, W=4)
+        extra = {}
+    prec = lbm.FP32_SHIFTED if prec_name == "fp32" else lbm.FP64
+    for re in (1, 2, 7, 10):
+        h = []
+        for variant in (lbm.VARIANT_BLOCK2, lbm.VARIANT_BLOCK):
+            P = lbm.make_params(nx, ny, e, sigma=s, tau=[1.0, 1.1, 1.2, 1.0, 1.1, 1.0, 1.1, 0.8, 0.8], prec=prec,
+                                reduce_every=re, kernel_variant=variant, **extra)
+            L = lbm.Lattice(P, rho0, device="cuda:0")
+            L.step(61)
+            L.check()
+            h.append(L.history())
+            L.close()
+        assert h[0].shape == h[1].shape == (len(range(0, 61, re)), 4), (re, h[0].shape, h[1].shape)
+        np.testing.assert_array_equal(h[0][:, 0], np.arange(0, 61, re))
+        np.testing.assert_array_equal(h[0][:, 0], h[1][:, 0])
+        m = h[1][0, 1]
+        # FP64 sums of the same node values in another order; FP32 storage: the one-step and
+        # two-step kernels round the intermediate step alike up to FMA contraction
+        tol = 1e-13 if prec == lbm.FP64 else 1e-9
+        assert np.abs(h[0][:, 1] - h[1][:, 1]).max() <= tol * m, (re, h[0][:, 1] - h[1][:, 1])
+        # momentum: FP32 trajectories of the two kernels differ by FMA contraction
+        assert np.abs(h[0][:, 2:] - h[1][:, 2:]).max() <= (1e-12 if prec == lbm.FP64 else 1e-8) * m, re
+
+
 def test_fp32_rest_population_ablation_c2(gpu_lib):
     """Ablation of the exact-mass rest population on the 512^2 droplet (R = 80, shaped PR Tr = 0.5): the
     same run with the rest population rounded to FP32 after every step (all nine populations in FP32, as a
