@@ -311,10 +311,13 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
     const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int strip = blockIdx.x % A.strips, band = blockIdx.x / A.strips;
     const int xs = strip * kAdjW - 1 + lane;  // unwrapped column of this lane
-    const int x = ((xs % S.nx) + S.nx) % S.nx;
+    // xs lies in [-1, nx + 61] and y in [-1, ny + 9]: one wrap each way on lattices at least
+    // that wide and tall, remainders otherwise
+    const int x = S.nx >= 64 ? wrapx(xs, S.nx) : ((xs % S.nx) + S.nx) % S.nx;
     const int y = band * kAdjRows - 1 + k;    // unwrapped row of this wave
     const bool fluid = S.walls ? (y >= 0 && y < S.ny) : true;
-    const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y)) : ((y % S.ny) + S.ny) % S.ny;
+    const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y))
+                           : (S.ny >= 11 ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
     const size_t o = (size_t)yw * S.nx + x;
     // running sum of accumulator k of this workgroup, read early (updated at the end by lane 0 of wave k)
     const double acc_prev = (k < kAcc && lane == 0) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
@@ -376,10 +379,13 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_seed_u(AdjArgs A, const 
     const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int strip = blockIdx.x % A.strips, band = blockIdx.x / A.strips;
     const int xs = strip * kAdjW - 1 + lane;  // unwrapped column of this lane
-    const int x = ((xs % S.nx) + S.nx) % S.nx;
+    // xs lies in [-1, nx + 61] and y in [-1, ny + 9]: one wrap each way on lattices at least
+    // that wide and tall, remainders otherwise
+    const int x = S.nx >= 64 ? wrapx(xs, S.nx) : ((xs % S.nx) + S.nx) % S.nx;
     const int y = band * kAdjRows - 1 + k;    // unwrapped row of this wave
     const bool fluid = S.walls ? (y >= 0 && y < S.ny) : true;
-    const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y)) : ((y % S.ny) + S.ny) % S.ny;
+    const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y))
+                           : (S.ny >= 11 ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
     const size_t o = (size_t)yw * S.nx + x;
     const double acc_prev = (k < kAcc && lane == 0) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
 

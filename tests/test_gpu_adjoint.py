@@ -19,12 +19,13 @@ NAMES = ("rho_max", "p_max", "rho_min", "p_min", "G", "sigma")
 
 def _case(kind):
     e, s = O.eos_build(O.make_eos(**SMOOTH))
-    if kind == "droplet":
-        nx, ny = 37, 29
+    # the wide lattices (at least 64 columns) take the kernels' single-wrap column indexing
+    if kind in ("droplet", "droplet_wide"):
+        nx, ny = (37, 29) if kind == "droplet" else (70, 29)
         rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=8, W=4)
         extra = {}
     else:
-        nx, ny = 40, 24
+        nx, ny = (40, 24) if kind == "walls" else (70, 24)
         rho0, _, _ = droplet_on_film(nx, ny, e.rho_v, e.rho_l, R=6, h=5, gap=3, V=0.0, W=4)
         extra = dict(walls=True, rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v)
     w = np.random.default_rng(11).standard_normal((ny, nx))
@@ -291,7 +292,7 @@ def _on_oracle_eos(lbm, e):
     return el
 
 
-@pytest.mark.parametrize("kind", ["droplet", "walls"])
+@pytest.mark.parametrize("kind", ["droplet", "walls", "droplet_wide", "walls_wide"])
 @pytest.mark.parametrize("mode", ["recorded", "checkpointed"])
 @pytest.mark.parametrize("target", ["rho", "rho_u"])
 def test_adjoint_fp64_matches_complex_step(gpu_lib, kind, mode, target):
