@@ -168,32 +168,35 @@ void k_batch_step2(const BatchItem* items, const int* tile_off, int B, char* buf
 // the three-column ring in x is recomputed.  Same phases and node arithmetic as step2_tile.
 constexpr int kFullRows = 16;
 
-// FP32: the lattice's EOS record in LDS (read by node_psi).  FP64 keeps it in its
-// arguments: its 80 KB of LDS per workgroup leave no room beside two workgroups per CU.
-template <typename T>
+// The lattice's EOS record in LDS (read by node_psi), except for 16-row FP64 workgroups:
+// their 80 KB of LDS leave no room for it beside a second workgroup per CU.
+template <bool IN_LDS>
 struct FullEos {
     DevEos eos;
     __device__ const DevEos& get(const StepArgs&) const { return eos; }
     __device__ void put(const StepArgs& A) { eos = A.eos; }
 };
 template <>
-struct FullEos<double> {
+struct FullEos<false> {
     __device__ const DevEos& get(const StepArgs& A) const { return A.eos; }
     __device__ void put(const StepArgs&) {}
 };
 
-template <typename T>
-struct FullLds : FullEos<T> {
-    T sps[kFullRows][64];
-    T smv[8][kFullRows][64];
-    double sg0[kFullRows][64];
+// LDS sized for ROWS rows (4, 8 or kFullRows, the smallest that holds max(ny)): shorter
+// lattices fit more workgroups per CU (a 16-row FP32 workgroup takes 45 KB whatever its
+// height, i.e. three per CU)
+template <typename T, int ROWS>
+struct FullLds : FullEos<sizeof(T) == 4 || ROWS < kFullRows> {
+    T sps[ROWS][64];
+    T smv[8][ROWS][64];
+    double sg0[ROWS][64];
 };
 
-template <typename T>
-__global__ __launch_bounds__(64 * kFullRows) void k_batch_full2(const BatchItem* items, const int* tile_off, int B,
-                                                                 char* buf0, char* buf1, int cur, long long step)
+template <typename T, int ROWS>
+__global__ __launch_bounds__(64 * ROWS) void k_batch_full2(const BatchItem* items, const int* tile_off, int B,
+                                                            char* buf0, char* buf1, int cur, long long step)
 {
-    __shared__ FullLds<T> S;
+    __shared__ FullLds<T, ROWS> S;
     const int w = blockIdx.x;
     if (w >= tile_off[B]) return;
     int lo = 0, hi = B;  // tile_off[lo] <= w < tile_off[hi]
@@ -279,6 +282,22 @@ __global__ __launch_bounds__(64 * kFullRows) void k_batch_full2(const BatchItem*
                        S.sps[kp][l - 1], S.sps[kp][l], S.sps[kp][l + 1], Ftx, Fty);
         update_node<T, MODE_STEP>(A, L, k, R, dr, ps, Ftx, Fty, acc);
     }
+}
+
+template <typename T>
+void launch_full2_t(int max_ny, dim3 g, dim3 b, hipStream_t s, const BatchItem* it, const int* off, int B, char* b0,
+                    char* b1, int cur, long long st)
+{
+    if (max_ny <= 4) hipLaunchKernelGGL((k_batch_full2<T, 4>), g, b, 0, s, it, off, B, b0, b1, cur, st);
+    else if (max_ny <= 8) hipLaunchKernelGGL((k_batch_full2<T, 8>), g, b, 0, s, it, off, B, b0, b1, cur, st);
+    else hipLaunchKernelGGL((k_batch_full2<T, kFullRows>), g, b, 0, s, it, off, B, b0, b1, cur, st);
+}
+
+void launch_full2(bool f32, int max_ny, dim3 g, dim3 b, hipStream_t s, const BatchItem* it, const int* off, int B,
+                  char* b0, char* b1, int cur, long long st)
+{
+    if (f32) launch_full2_t<float>(max_ny, g, b, s, it, off, B, b0, b1, cur, st);
+    else launch_full2_t<double>(max_ny, g, b, s, it, off, B, b0, b1, cur, st);
 }
 
 template <typename T>
@@ -540,8 +559,7 @@ static bool launch_grouped(lbm_batch* c, int n, int cur, int64_t step0, hipStrea
     const dim3 gf(c->L.strip_off[c->B]), bf(64 * c->L.max_ny);
     for (; k + 1 < n; k += 2) {
         const long long st = (long long)(step0 + k);
-        if (c->full && f32) hipLaunchKernelGGL(k_batch_full2<float>, gf, bf, 0, s, it, c->strip_off, c->B, c->buf[0], c->buf[1], cur, st);
-        else if (c->full) hipLaunchKernelGGL(k_batch_full2<double>, gf, bf, 0, s, it, c->strip_off, c->B, c->buf[0], c->buf[1], cur, st);
+        if (c->full) launch_full2(f32, c->L.max_ny, gf, bf, s, it, c->strip_off, c->B, c->buf[0], c->buf[1], cur, st);
         else if (f32 && !w) hipLaunchKernelGGL((k_batch_step2<float, false>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
         else if (f32) hipLaunchKernelGGL((k_batch_step2<float, true>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
         else if (!w) hipLaunchKernelGGL((k_batch_step2<double, false>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
