@@ -373,13 +373,19 @@ int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk)
 
 // per-wave FP64 partial slots the workspace holds: the one-step layout, or one per (tile,
 // wave) of the two-step kernel when it may reduce
+// waves of one two-step launch: (tiles) x (waves per tile), one partial slot each
+int two_step_waves(const lbm_params& p)
+{
+    const int w2 = k2waves_of_prec(p.prec), rows2 = w2 - 6;
+    return ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + rows2 - 1) / rows2) * w2;
+}
+
 int partial_slots(const lbm_params& p)
 {
     int strips, seg_h, nseg, blk;
     int n = decompose(p, &strips, &seg_h, &nseg, &blk);
     if (resolve_variant(p) == LBM_VARIANT_BLOCK2) {
-        const int w2 = k2waves_of_prec(p.prec), rows2 = w2 - 6;
-        const int n2 = ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + rows2 - 1) / rows2) * w2;
+        const int n2 = two_step_waves(p);
         n = n2 > n ? n2 : n;
     }
     return n;
@@ -705,10 +711,8 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
             if (!(f32 ? launch_step2<float>(c, rec, s, red2) : launch_step2<double>(c, rec, s, red2)))
                 return LBM_EHIP;
             if (red2) {
-                const int w2 = k2waves_of_prec(c->P.prec);
-                const int n2 = ((c->P.nx + k2Cols - 1) / k2Cols) * ((c->P.ny + w2 - 7) / (w2 - 6)) * w2;
                 double* row = c->hist + 4 * (c->hist_count % kHistCap);
-                if (!launch_reduce_n(c, n2, row, (long long)c->step + 1, 1, s)) return LBM_EHIP;
+                if (!launch_reduce_n(c, two_step_waves(c->P), row, (long long)c->step + 1, 1, s)) return LBM_EHIP;
                 c->hist_count++;
             }
             c->cur ^= 1;
