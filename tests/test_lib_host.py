@@ -112,3 +112,18 @@ def test_batch_layout_offsets():
     wb1 = C.c_size_t(0)
     assert lbm.load().lbm_batch_layout(1, P1, None, C.byref(wb1), None) == 0
     assert wb.value > wb1.value > 0
+
+
+def test_workspace_holds_the_two_step_partials():
+    """A reducing step that ends a two-step launch leaves one FP64 partial triple per (tile, wave): the
+    workspace lbm_layout reports holds them, beside the error word, the per-block sums and the history
+    ring, whichever decomposition has more waves."""
+    e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
+    for nx, ny, prec, waves, rows in ((512, 512, lbm.FP32_SHIFTED, 16, 10), (512, 512, lbm.FP64, 12, 6),
+                                      (130, 37, lbm.FP64, 12, 6), (7, 3, lbm.FP32_SHIFTED, 16, 10)):
+        P = lbm.make_params(nx, ny, e, sigma=s, prec=prec)
+        _, _, ws = lbm.layout(P)
+        tiles = -(-nx // 58) * -(-ny // rows)
+        assert ws >= 256 + tiles * waves * 3 * 8 + 4096 * 4 * 8, (nx, ny, prec, ws)
+        P1 = lbm.make_params(nx, ny, e, sigma=s, prec=prec, kernel_variant=lbm.VARIANT_BLOCK)
+        assert lbm.layout(P1)[2] <= ws  # the one-step layout needs no more
