@@ -22,13 +22,14 @@ def _cs(Tr):
     return kw
 
 
+@pytest.mark.parametrize("shape", [(45, 38), (130, 70)], ids=["45x38", "130x70"])
 @pytest.mark.parametrize("var_tau", [False, True])
-def test_fd_droplet_matches_oracle(gpu_lib, var_tau):
+def test_fd_droplet_matches_oracle(gpu_lib, var_tau, shape):
     lbm = gpu_lib
     kw = _cs(0.7)
     e, s = lbm.eos_build(lbm.make_eos(**kw))
     eo, so = O.eos_build(O.make_eos(**kw))
-    nx, ny, steps = 45, 38, 150
+    (nx, ny), steps = shape, 150
     rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=10, W=8)
     rng = np.random.default_rng(3)
     u0, v0 = 1e-3 * rng.standard_normal((ny, nx)), 1e-3 * rng.standard_normal((ny, nx))
