@@ -60,6 +60,28 @@ def test_512_droplet_whole_field(gpu_lib, prec_name, steps):
     assert np.abs(f_g - f_o).max() <= _bound(lbm, prec, f_o, e.rho_v, steps)
 
 
+
+@pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
+def test_512_droplet_whole_field_100_steps(gpu_lib, prec_name):
+    """The bench's 512^2 droplet from its initial state through 100 steps as bench.py runs them (a
+    reduction at step 0, 49 two-step launches, then a two-step launch whose second step reduces),
+    whole field against 100 oracle steps from the same initial populations."""
+    lbm = gpu_lib
+    prec = lbm.FP64 if prec_name == "fp64" else lbm.FP32_SHIFTED
+    L, e = _lattice(lbm, 512, 80, prec, 0)
+    f0 = L.populations().cpu().numpy()
+    L.step(101)
+    L.check()
+    f_g = L.populations().cpu().numpy()
+    assert L.history().shape[0] == 2  # steps 0 and 100 reduced
+    eo, so = O.eos_build(O.make_eos(**EOS_KW))
+    OL = O.Lattice(O.make_params(512, 512, eo, sigma=so, tau=TAU))
+    OL.set_f(f0)
+    OL.run(101)
+    f_o = OL.get_f()
+    assert np.abs(f_g - f_o).max() <= _bound(lbm, prec, f_o, e.rho_v, 101)
+
+
 def _samples(n, rng):
     xs = {0, 1, 2, 57, 58, 60, 61, 62, 63, 64, 115, 116, 123, 124, 125, n - 63, n - 62, n - 2, n - 1}
     ys = {0, 1, 3, 4, 5, 7, 8, 9, 10, 11, 19, 20, n // 2, n - 5, n - 4, n - 1}
