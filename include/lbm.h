@@ -145,7 +145,11 @@ int lbm_init(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, void* ws,
 
 /* Advance nsteps time steps (Eq. LBE).  Asynchronous: device-side
  * instability is latched in the workspace and reported by lbm_status_check
- * or lbm_macros. */
+ * or lbm_macros.  Steps t with t % reduce_every == 0 also add (t, mass, j_x,
+ * j_y) of the state entering step t to the history (Eq. Density, Eq. Momentum,
+ * FP64 in a fixed order: the same inputs and decomposition give the same bits).
+ * LBM_ESTATE, before any launch, when the steps would pass the end of a
+ * recording (lbm_set_recording) or of the checkpoint buffer. */
 int lbm_step(lbm_ctx* ctx, int64_t nsteps, void* stream);
 
 /* Synchronise `stream` and return LBM_EUNSTABLE if the device error word is

@@ -688,6 +688,15 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
         lbm_set_error("lbm_step: the forward record (lbm_set_recording) holds fewer steps");
         return LBM_ESTATE;
     }
+    // the last checkpoint these steps take (at step t with t % K == 0) must have a slot
+    if (c->ckpt_K > 0 && nsteps > 0) {
+        const int64_t last = c->step + nsteps - 1;
+        const int64_t first_ck = (c->step + c->ckpt_K - 1) / c->ckpt_K * c->ckpt_K;
+        if (first_ck <= last && last / c->ckpt_K >= c->ckpt_slots) {
+            lbm_set_error("lbm_step: checkpoint buffer full (more steps than slots * K)");
+            return LBM_ESTATE;
+        }
+    }
     for (int64_t k = 0; k < nsteps; ++k) {
         if (c->ckpt_K > 0 && c->step % c->ckpt_K == 0) {
             const int64_t slot = c->step / c->ckpt_K;

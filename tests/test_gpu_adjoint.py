@@ -236,6 +236,18 @@ def test_adjoint_error_paths(gpu_lib):
     with pytest.raises(lbm.LbmError) as ei:
         lat2.step(1)  # checkpoint slots exhausted
     assert ei.value.code == lbm.LBM_ESTATE
+    # refused before any launch: a call that would run out of slots part-way leaves the state as it was
+    lat4 = lbm.Lattice(lbm.make_params(16, 16, e, sigma=s), rho0, device="cuda:0")
+    lat4.enable_checkpointing(7, 20)  # slots for the checkpoints at 0, 7 and 14
+    lat4.step(3)
+    before = lat4.populations().cpu().numpy()
+    with pytest.raises(lbm.LbmError) as ei:
+        lat4.step(19)  # would need the checkpoint at 21
+    assert ei.value.code == lbm.LBM_ESTATE
+    assert lat4.state()[0] == 3
+    assert np.array_equal(lat4.populations().cpu().numpy(), before)
+    lat4.step(18)  # up to step 20: still within the slots
+    assert lat4.state()[0] == 21
     lat3 = lbm.Lattice(lbm.make_params(16, 16, e, sigma=s, var_tau=True, tau_l=0.8, tau_v=1.4), rho0, device="cuda:0")
     lat3.enable_checkpointing(4, 8)
     lat3.step(4)
