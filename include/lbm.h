@@ -38,6 +38,10 @@
 extern "C" {
 #endif
 
+/* The library is built with hidden visibility: exactly the declarations of
+ * this header are its exported interface. */
+#pragma GCC visibility push(default)
+
 typedef enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,    /* invalid argument or parameter combination */
@@ -316,6 +320,8 @@ void lbm_fd_destroy(lbm_fd_ctx* ctx);
 
 const char* lbm_strerror(int code);
 const char* lbm_last_error(void);
+
+#pragma GCC visibility pop
 
 #ifdef __cplusplus
 }

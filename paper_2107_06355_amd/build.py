@@ -14,6 +14,8 @@ SOURCES = ["thermo.cpp", "lbm_step.hip", "lbm_batched.hip", "lbm_adjoint.hip", "
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5",
+    # only the declarations of include/lbm.h are exported
+    "-fvisibility=hidden", "-fvisibility-inlines-hidden",
     # no packed FP32 instructions on this target
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
