@@ -127,3 +127,17 @@ def test_workspace_holds_the_two_step_partials():
         assert ws >= 256 + tiles * waves * 3 * 8 + 4096 * 4 * 8, (nx, ny, prec, ws)
         P1 = lbm.make_params(nx, ny, e, sigma=s, prec=prec, kernel_variant=lbm.VARIANT_BLOCK)
         assert lbm.layout(P1)[2] <= ws  # the one-step layout needs no more
+
+
+def test_library_exports_nothing_beyond_the_header():
+    """Hidden visibility: every function the library defines and exports (nm type T) is declared in
+    lbm.h; the internal C++ helpers stay inside."""
+    import shutil
+    import subprocess
+
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[2] for ln in out.splitlines() if len(ln.split()) == 3 and ln.split()[1] == "T"}
+    assert exported == set(declared_symbols()), sorted(exported ^ set(declared_symbols()))
