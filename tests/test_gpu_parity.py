@@ -407,6 +407,32 @@ def test_invalid_parameters_rejected(gpu_lib):
         assert ei.value.code == gpu_lib.LBM_EINVAL
 
 
+
+def test_degenerate_calls(gpu_lib):
+    """Zero steps change nothing; a negative count is refused; a lattice of zero size has no layout."""
+    lbm = gpu_lib
+    e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
+    rho0 = droplet_density(40, 20, e.rho_v, e.rho_l, R=6, W=4)
+    for prec in (lbm.FP64, lbm.FP32_SHIFTED):
+        L = lbm.Lattice(lbm.make_params(40, 20, e, sigma=s, prec=prec, reduce_every=1), rho0, device="cuda:0")
+        L.step(3)
+        a = L.populations().cpu().numpy()
+        h = L.history()
+        L.step(0)
+        L.check()
+        assert L.state()[0] == 3
+        assert np.array_equal(L.populations().cpu().numpy(), a)
+        assert np.array_equal(L.history(), h)
+        with pytest.raises(lbm.LbmError) as ei:
+            L.step(-1)
+        assert ei.value.code == lbm.LBM_EINVAL
+        assert L.state()[0] == 3
+    for nx, ny in ((0, 8), (8, 0)):
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.layout(lbm.make_params(nx, ny, e, sigma=s))
+        assert ei.value.code == lbm.LBM_EINVAL
+
+
 def test_save_load_roundtrip(gpu_lib):
     e, s = gpu_lib.eos_build(gpu_lib.make_eos(Tr=0.7))
     nx, ny = 64, 32
