@@ -322,6 +322,39 @@ def fd_leg(lbm, n=512, steps=2000, dt=0.2):
     return out
 
 
+def drop_impact_leg(lbm, steps=400):
+    """Droplet impact on a film between walls, 2048 x 1024 (R = 100, film 40, V = 0.072, Re = 300, v_r = 1),
+    shaped Peng-Robinson at Tr = 0.47 (density ratio 3.07e4, rims of width 16): time per step of each
+    step-kernel decomposition in both precisions."""
+    import torch
+    from lbm_inputs import droplet_on_film
+
+    nx, ny, tau_l = 2048, 1024, 0.644
+    e, s = lbm.eos_build(lbm.make_eos(**dict(EOS_KW, Tr=0.47)))
+    rho, ux, uy = droplet_on_film(nx, ny, e.rho_v, e.rho_l, R=100, h=40, gap=4, V=0.072, W=16)
+    out = {"workload": "drop impact %dx%d with walls, shaped PR Tr=0.47 (ratio %.3g), Re=300, %d steps"
+                       % (nx, ny, e.rho_l / e.rho_v, steps)}
+    for prec, name in ((lbm.FP32_SHIFTED, "fp32"), (lbm.FP64, "fp64")):
+        for variant, vname in ((1, "row_march"), (2, "row_block"), (3, "two_step")):
+            P = lbm.make_params(nx, ny, e, sigma=s, tau=[1] * 7 + [tau_l] * 2, prec=prec, walls=True,
+                                rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v, reduce_every=0, kernel_variant=variant)
+            L = lbm.Lattice(P, rho, ux, uy, device="cuda:0")
+            L.step(20)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(L.stream)
+            L.step(steps)
+            ev[1].record(L.stream)
+            torch.cuda.synchronize()
+            L.check()
+            us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
+            out["%s_%s_us_per_step" % (name, vname)] = us
+            print("# drop impact %s %s: %.2f us/step, %.0f MLUPS" % (name, vname, us, nx * ny / us),
+                  file=sys.stderr, flush=True)
+            L.close()
+    return out
+
+
 def stability_leg(lbm, steps=3000):
     """Sec. IV stability map: width calibration (batched planar lattices) and 3 EOS x 9 Tr x 12 v_r
     droplet impacts (600 x 250, FP32-shifted); the largest stable simulated density ratio per EOS."""
@@ -372,6 +405,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-lattice sweep leg")
     ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--stability-map", action="store_true", help="add the Sec. IV stability-map leg (~1 min)")
+    ap.add_argument("--drop-impact", action="store_true", help="add the walled drop-impact timing leg (seconds)")
     ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference reference-solver leg")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -489,6 +523,8 @@ def main():
         out["batched"] = batched_leg(lbm)
     if args.stability_map:
         out["stability"] = stability_leg(lbm)
+    if args.drop_impact:
+        out["drop_impact"] = drop_impact_leg(lbm)
     if not args.no_fd:
         out["fd"] = fd_leg(lbm)
         out["fd_4096"] = fd_leg(lbm, n=4096, steps=50)
