@@ -366,6 +366,25 @@ def test_table4_planar_interface(case):
         assert abs(r["E"] - case["E"]) < 0.002  # percentage points; printed to 2 significant digits
 
 
+
+with open(os.path.join(GOLD, "widths_tables_1_3.json")) as _fh:
+    _T13 = json.load(_fh)
+_T13_CASES = [("cs", float(a), int(w)) for w, a in _T13["cs_a"].items()] + \
+             [("smooth", float(al), int(w)) for w, al in _T13["smooth_alpha"].items()]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kind,value,w", _T13_CASES, ids=["%s-w%d" % (k, w) for k, _, w in _T13_CASES])
+def test_tables_1_3_interface_widths(kind, value, w):
+    """The printed parameters give the printed planar interface widths at Tr = 0.5 (Li forcing)."""
+    if kind == "cs":
+        e, s = cs_eos(_T13["Tr"], a=value)
+    else:
+        e, s = cs_eos(_T13["Tr"], shape=O.SHAPE_SMOOTH, alpha=value)
+    r = O.run_planar(e, forcing=O.FORCING_LI, sigma=s)
+    assert r["residual"] < 1e-6
+    assert r["width"] == w
+
 @pytest.mark.slow
 def test_modified_smooth_point():
     c = _T4["modified_smooth"]
