@@ -386,6 +386,38 @@ def test_table4_rows_on_gpu(gpu_lib, case):
             assert abs(E - case["E"]) < 0.002  # percentage points; printed to 2 significant digits
 
 
+
+with open(_os.path.join(_os.path.dirname(__file__), "golden", "widths_tables_1_3.json")) as _fh:
+    _T13 = _json.load(_fh)
+_T13_CASES = [dict(Tr=_T13["Tr"], a=float(a)) for a in _T13["cs_a"].values()] + \
+             [dict(Tr=_T13["Tr"], shape=1, alpha=float(al)) for al in _T13["smooth_alpha"].values()]
+_T13_W = [int(w) for w in _T13["cs_a"]] + [int(w) for w in _T13["smooth_alpha"]]
+
+
+@pytest.mark.parametrize("kw,w", list(zip(_T13_CASES, _T13_W)),
+                         ids=["cs-w%s" % w for w in _T13["cs_a"]] + ["smooth-w%s" % w for w in _T13["smooth_alpha"]])
+def test_tables_1_3_widths_on_gpu(gpu_lib, kw, w):
+    """Tables I and III on the GPU FP64 path (planar 2x200, Li forcing, run to the Sec. III.A
+    criterion): the printed parameters give the printed widths."""
+    e, s = gpu_lib.eos_build(gpu_lib.make_eos(**kw))
+    nx, ny = 2, 200
+    L = gpu_lib.Lattice(gpu_lib.make_params(nx, ny, e, sigma=s), planar_density(nx, ny, e.rho_v, e.rho_l, W=10),
+                        device="cuda:0")
+    prev = L.macros()["rho"].cpu().numpy()
+    res = 1.0
+    for _ in range(4000):
+        L.step(100)
+        cur = L.macros()["rho"].cpu().numpy()
+        res = np.abs(cur - prev).sum() / np.abs(cur).sum()
+        prev = cur
+        if res < 1e-6:
+            break
+    L.check()
+    assert res < 1e-6
+    prof = L.macros()["rho"].cpu().numpy()[:, 0]
+    phi = (prof[: ny // 2 + 1] - prof[0]) / (prof[ny // 2] - prof[0])
+    assert int(((phi > 0.01) & (phi < 0.99)).sum()) == w
+
 # ---------------------------------------------------------------- error paths
 def test_unstable_state_is_reported(gpu_lib):
     e, _ = gpu_lib.eos_build(gpu_lib.make_eos(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5))
