@@ -385,6 +385,24 @@ def test_tables_1_3_interface_widths(kind, value, w):
     assert r["residual"] < 1e-6
     assert r["width"] == w
 
+
+@pytest.mark.slow
+def test_sec3a_cs_li_and_guo_statements():
+    """The statements of Sec. III.A on plain C-S (a = 0.5): Li forcing errs by about 50% at Tr = 0.5 and
+    very little at Tr = 0.7; Guo forcing departs far from Maxwell at Tr = 0.8 and is unstable below it."""
+    with open(os.path.join(GOLD, "sec3a_cs_forcing.json")) as fh:
+        g = json.load(fh)
+    e, s = cs_eos(0.5)
+    E = O.run_planar(e, forcing=O.FORCING_LI, sigma=s)["E"]
+    assert abs(E - g["li_error_at_0.5_percent"]) < 10, E  # "approximately 50%": 51.7 here
+    e, s = cs_eos(g["li_small_above"])
+    assert abs(O.run_planar(e, forcing=O.FORCING_LI, sigma=s)["E"]) < 1.0
+    e, s = cs_eos(g["guo_unstable_below"])
+    assert abs(O.run_planar(e, forcing=O.FORCING_GUO, sigma=0.0)["E"]) > 10
+    e, s = cs_eos(g["guo_unstable_below"] - 0.05)
+    with pytest.raises(O.OracleError):
+        O.run_planar(e, forcing=O.FORCING_GUO, sigma=0.0)
+
 @pytest.mark.slow
 def test_modified_smooth_point():
     c = _T4["modified_smooth"]
