@@ -390,12 +390,16 @@ def test_table4_rows_on_gpu(gpu_lib, case):
 with open(_os.path.join(_os.path.dirname(__file__), "golden", "widths_tables_1_3.json")) as _fh:
     _T13 = _json.load(_fh)
 _T13_CASES = [dict(Tr=_T13["Tr"], a=float(a)) for a in _T13["cs_a"].values()] + \
-             [dict(Tr=_T13["Tr"], shape=1, alpha=float(al)) for al in _T13["smooth_alpha"].values()]
-_T13_W = [int(w) for w in _T13["cs_a"]] + [int(w) for w in _T13["smooth_alpha"]]
+             [dict(Tr=_T13["Tr"], shape=1, alpha=float(al)) for al in _T13["smooth_alpha"].values()] + \
+             [dict(Tr=_T13["Tr"], shape=1, alpha=float(al), k_vap=_T13["raised_vapor_k"])
+              for al in _T13["smooth_raised_vapor_alpha"].values()]
+_T13_W = [int(w) for w in _T13["cs_a"]] + [int(w) for w in _T13["smooth_alpha"]] + \
+         [int(w) for w in _T13["smooth_raised_vapor_alpha"]]
 
 
 @pytest.mark.parametrize("kw,w", list(zip(_T13_CASES, _T13_W)),
-                         ids=["cs-w%s" % w for w in _T13["cs_a"]] + ["smooth-w%s" % w for w in _T13["smooth_alpha"]])
+                         ids=["cs-w%s" % w for w in _T13["cs_a"]] + ["smooth-w%s" % w for w in _T13["smooth_alpha"]] +
+                             ["smooth-raised-vapor-w%s" % w for w in _T13["smooth_raised_vapor_alpha"]])
 def test_tables_1_3_widths_on_gpu(gpu_lib, kw, w):
     """Tables I and III on the GPU FP64 path (planar 2x200, Li forcing, run to the Sec. III.A
     criterion): the printed parameters give the printed widths."""
