@@ -31,7 +31,16 @@ METRIC = "MLUPS + HBM GB/s (%roofline), FP32-shifted vs FP64 D2Q9; adjoint/fwd t
 # algorithmic bytes per cell update: 8 moving populations read + written, rest population FP64 read + written
 BYTES = {"fp32": 8 * 4 * 2 + 8 * 2, "fp64": 9 * 8 * 2}
 # step kernel of each decomposition (lbm_variant): row march, row block, two-step block
-KERNEL_NAME = {1: "k_step<%s, 0>", 2: "k_step_blk<%s, 0>", 3: "k_step2_blk<%s, 0, false>"}
+KERNEL_NAME = {1: "k_step<%s, 0>", 2: "k_step_blk<%s, 0>", 3: "k_step2_blk<%s, 0, false, %s>"}
+MALL_BYTES = 256 << 20  # the library streams its stores when both population buffers fit in it
+
+
+def kernel_name(lbm, var, prec, P):
+    """Name of the step kernel (as rocprofv3 prints it) that advances lattice P in this precision."""
+    t = "float" if prec == "fp32" else "double"
+    if var != lbm.VARIANT_BLOCK2:
+        return KERNEL_NAME[var] % t
+    return KERNEL_NAME[var] % (t, "true" if 2 * lbm.layout(P)[1] <= MALL_BYTES else "false")
 
 EOS_KW = dict(base=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
 TAU = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]
@@ -456,7 +465,7 @@ def main():
                      "ms_per_step": sec * 1e3 / args.steps, "wall_s": wall,
                      "kernel_GB/s": kgbs, "frac_hbm_peak": kgbs / HBM_PEAK_GBS,
                      "avg_launch_us": ksec * 1e6 / (args.steps / spl), "steps_per_launch": spl,
-                     "kernel": KERNEL_NAME[var] % ("float" if prec == "fp32" else "double"),
+                     "kernel": kernel_name(lbm, var, prec, L.P),
                      "rows_per_block": rows, "waves": waves}
         print("# %s %dx%d: %.1f MLUPS (%.2f us/step with reductions); step kernel %.2f us = %.1f GB/s "
               "algorithmic (%.1f%% of 8 TB/s)" % (prec, n, n, mlups, sec * 1e6 / args.steps, ksec * 1e6 / args.steps,

@@ -35,6 +35,7 @@ namespace lbmk {
 #define LBM_K2_EU_F64 6
 #endif
 
+
 constexpr int kStripW = 62;   // interior columns per wave (lanes 0 and 63 are the psi halo)
 
 // ----------------------------------------------------------------- device EOS
@@ -460,7 +461,7 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
 }
 
 // node_collide, then the store of f* at (x, y) of the destination buffer
-template <typename T, int MODE>
+template <typename T, int MODE, bool NT = false>
 __device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, int y, const Row<T>& P, double drp,
                                             T psB, T Ftx, T Fty, Acc& acc)
 {
@@ -469,9 +470,17 @@ __device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, in
     if (!node_collide<T, MODE>(A, L, y, P, drp, psB, Ftx, Fty, acc, o, o0)) return;
     const WView<T> D = make_wview<T>(A.dst, A.plane);
     const uint32_t off = (uint32_t)y * (uint32_t)A.ld + (uint32_t)L.x;
+    if constexpr (NT) {
+        // streaming stores: measured faster on MI355X when both population buffers fit in
+        // the 256 MB MALL, slower on larger FP32 lattices
 #pragma unroll
-    for (int i = 1; i < 9; ++i) *(T*)(D.mv[i] + off * (uint32_t)sizeof(T)) = o[i];
-    *(double*)(D.rest + off * 8u) = o0;
+        for (int i = 1; i < 9; ++i) __builtin_nontemporal_store(o[i], (T*)(D.mv[i] + off * (uint32_t)sizeof(T)));
+        __builtin_nontemporal_store(o0, (double*)(D.rest + off * 8u));
+    } else {
+#pragma unroll
+        for (int i = 1; i < 9; ++i) *(T*)(D.mv[i] + off * (uint32_t)sizeof(T)) = o[i];
+        *(double*)(D.rest + off * 8u) = o0;
+    }
 }
 
 // Eq. ShanChenForce / psi(x): F~ = -G sum_i w(|c_i|^2) psi(x + c_i) c_i, written as
@@ -537,7 +546,7 @@ struct Step2Lds {
 };
 
 // Advance output tile (strip, band) of lattice A by two steps (see above).
-template <typename T, int MODE, bool WALLS>
+template <typename T, int MODE, bool WALLS, bool NT = false>
 __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int band, Step2Lds<T>& S)
 {
     auto& sps = S.sps;
@@ -655,7 +664,7 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
         T Ftx, Fty;
         force_tilde<T>(A, sps[k - 1][l - 1], sps[k - 1][l], sps[k - 1][l + 1], sps[k][l - 1], sps[k][l + 1],
                        sps[k + 1][l - 1], sps[k + 1][l], sps[k + 1][l + 1], Ftx, Fty);
-        update_node<T, MODE == MODE_STEP_REDUCE ? MODE_STEP_REDUCE : MODE_STEP>(A, L, r, R, dr, ps, Ftx, Fty, acc);
+        update_node<T, MODE == MODE_STEP_REDUCE ? MODE_STEP_REDUCE : MODE_STEP, NT>(A, L, r, R, dr, ps, Ftx, Fty, acc);
         if (MODE == MODE_RECORD) {
             T jx, jy;
             node_j<T>(R.g, jx, jy);

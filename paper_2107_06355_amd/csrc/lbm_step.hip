@@ -213,7 +213,7 @@ __global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
 // workgroups per CU; 16-wave FP64 workgroups fit only one per CU, and forcing two of
 // them spilled vector registers to scratch (25% slower on MI355X at 4096^2).
 // MODE_STEP_REDUCE: the second step also leaves the FP64 mass/momentum partials.
-template <typename T, int MODE, bool WALLS>
+template <typename T, int MODE, bool WALLS, bool NT = false>
 __global__ __launch_bounds__(64 * k2WavesOf<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : LBM_K2_EU_F64)))
 void k_step2_blk(StepArgs A)
 {
@@ -225,7 +225,7 @@ void k_step2_blk(StepArgs A)
     if (logical >= strips * bands) return;  // whole workgroup leaves together
     // band-major: the workgroups an XCD runs together cover neighbouring strips and bands
     // (strip-major order measured 27% more HBM reads at 8192^2 on MI355X)
-    step2_tile<T, MODE, WALLS>(A, logical % strips, logical / strips, S);
+    step2_tile<T, MODE, WALLS, NT>(A, logical % strips, logical / strips, S);
 }
 
 // Fixed-order FP64 reduction of the per-wave partials, two passes: block b sums
@@ -499,13 +499,20 @@ bool launch_step2(lbm_ctx* c, void* rec, hipStream_t s, bool reduce = false)
     A.rec = rec;
     A.rec_plane = (size_t)c->P.nx * c->P.ny;
     const dim3 g(c->grid2), b(64 * k2WavesOf<T>);
+    // streaming stores when both population buffers fit in the 256 MB MALL (measured on
+    // MI355X: 4% faster at 512^2 FP32; 1-2% slower on FP32 lattices of 4096^2 and up)
+    const bool nt = 2 * c->pop_bytes <= ((size_t)256 << 20);
     if (c->P.walls) {
         if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true>), g, b, 0, s, A);
+        else if (reduce && nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP_REDUCE, true, true>), g, b, 0, s, A);
         else if (reduce) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP_REDUCE, true>), g, b, 0, s, A);
+        else if (nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, true, true>), g, b, 0, s, A);
         else hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, true>), g, b, 0, s, A);
     } else {
         if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, false>), g, b, 0, s, A);
+        else if (reduce && nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP_REDUCE, false, true>), g, b, 0, s, A);
         else if (reduce) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP_REDUCE, false>), g, b, 0, s, A);
+        else if (nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, false, true>), g, b, 0, s, A);
         else hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, false>), g, b, 0, s, A);
     }
     return hip_ok(hipGetLastError(), "k_step2_blk launch");
