@@ -192,7 +192,7 @@ struct FullLds : FullEos<sizeof(T) == 4 || ROWS < kFullRows> {
     double sg0[ROWS][64];
 };
 
-template <typename T, int ROWS>
+template <typename T, int ROWS, bool NT>
 __global__ __launch_bounds__(64 * ROWS) void k_batch_full2(const BatchItem* items, const int* tile_off, int B,
                                                             char* buf0, char* buf1, int cur, long long step)
 {
@@ -280,24 +280,28 @@ __global__ __launch_bounds__(64 * ROWS) void k_batch_full2(const BatchItem* item
         T Ftx, Fty;
         force_tilde<T>(A, S.sps[km][l - 1], S.sps[km][l], S.sps[km][l + 1], S.sps[k][l - 1], S.sps[k][l + 1],
                        S.sps[kp][l - 1], S.sps[kp][l], S.sps[kp][l + 1], Ftx, Fty);
-        update_node<T, MODE_STEP>(A, L, k, R, dr, ps, Ftx, Fty, acc);
+        update_node<T, MODE_STEP, NT>(A, L, k, R, dr, ps, Ftx, Fty, acc);
     }
 }
 
-template <typename T>
+template <typename T, bool NT>
 void launch_full2_t(int max_ny, dim3 g, dim3 b, hipStream_t s, const BatchItem* it, const int* off, int B, char* b0,
                     char* b1, int cur, long long st)
 {
-    if (max_ny <= 4) hipLaunchKernelGGL((k_batch_full2<T, 4>), g, b, 0, s, it, off, B, b0, b1, cur, st);
-    else if (max_ny <= 8) hipLaunchKernelGGL((k_batch_full2<T, 8>), g, b, 0, s, it, off, B, b0, b1, cur, st);
-    else hipLaunchKernelGGL((k_batch_full2<T, kFullRows>), g, b, 0, s, it, off, B, b0, b1, cur, st);
+    if (max_ny <= 4) hipLaunchKernelGGL((k_batch_full2<T, 4, NT>), g, b, 0, s, it, off, B, b0, b1, cur, st);
+    else if (max_ny <= 8) hipLaunchKernelGGL((k_batch_full2<T, 8, NT>), g, b, 0, s, it, off, B, b0, b1, cur, st);
+    else hipLaunchKernelGGL((k_batch_full2<T, kFullRows, NT>), g, b, 0, s, it, off, B, b0, b1, cur, st);
 }
 
-void launch_full2(bool f32, int max_ny, dim3 g, dim3 b, hipStream_t s, const BatchItem* it, const int* off, int B,
-                  char* b0, char* b1, int cur, long long st)
+// nt: streaming stores, when both population buffers of the batch fit in the 256 MB MALL
+// (as for a single lattice)
+void launch_full2(bool f32, bool nt, int max_ny, dim3 g, dim3 b, hipStream_t s, const BatchItem* it, const int* off,
+                  int B, char* b0, char* b1, int cur, long long st)
 {
-    if (f32) launch_full2_t<float>(max_ny, g, b, s, it, off, B, b0, b1, cur, st);
-    else launch_full2_t<double>(max_ny, g, b, s, it, off, B, b0, b1, cur, st);
+    if (f32 && nt) launch_full2_t<float, true>(max_ny, g, b, s, it, off, B, b0, b1, cur, st);
+    else if (f32) launch_full2_t<float, false>(max_ny, g, b, s, it, off, B, b0, b1, cur, st);
+    else if (nt) launch_full2_t<double, true>(max_ny, g, b, s, it, off, B, b0, b1, cur, st);
+    else launch_full2_t<double, false>(max_ny, g, b, s, it, off, B, b0, b1, cur, st);
 }
 
 template <typename T>
@@ -559,7 +563,9 @@ static bool launch_grouped(lbm_batch* c, int n, int cur, int64_t step0, hipStrea
     const dim3 gf(c->L.strip_off[c->B]), bf(64 * c->L.max_ny);
     for (; k + 1 < n; k += 2) {
         const long long st = (long long)(step0 + k);
-        if (c->full) launch_full2(f32, c->L.max_ny, gf, bf, s, it, c->strip_off, c->B, c->buf[0], c->buf[1], cur, st);
+        if (c->full)
+            launch_full2(f32, 2 * c->L.off[c->B] <= ((size_t)256 << 20), c->L.max_ny, gf, bf, s, it, c->strip_off, c->B,
+                         c->buf[0], c->buf[1], cur, st);
         else if (f32 && !w) hipLaunchKernelGGL((k_batch_step2<float, false>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
         else if (f32) hipLaunchKernelGGL((k_batch_step2<float, true>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
         else if (!w) hipLaunchKernelGGL((k_batch_step2<double, false>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
