@@ -301,7 +301,7 @@ constexpr int kAdjRows = kAdjWaves - 2;  // output rows per workgroup
 constexpr int kAdjW = 62;                // output columns per wave
 static_assert(kAcc <= kAdjWaves, "one wave per accumulator in the workgroup sum");
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
 {
     __shared__ T sfx[kAdjWaves][64], sfy[kAdjWaves][64];
@@ -348,7 +348,11 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
         v[A_SIG] = (double)L.dsig;
         T* Lo = (T*)A.lam_out;
         const size_t li = (size_t)y * S.ld + x;
-        for (int i = 0; i < 9; ++i) Lo[i * A.lplane + li] = L.df[i] + drho_eos;
+        for (int i = 0; i < 9; ++i) {
+            // streaming stores when both lambda buffers fit in the MALL (as the forward does)
+            if constexpr (NT) __builtin_nontemporal_store((T)(L.df[i] + drho_eos), Lo + i * A.lplane + li);
+            else Lo[i * A.lplane + li] = L.df[i] + drho_eos;
+        }
     }
     // fixed-order workgroup sum: each (accumulator, lane) column over the waves in
     // order, then one wave per accumulator sums its 64 columns
@@ -475,6 +479,15 @@ __global__ void k_adj_rho0(int nx, int ny, int ld, size_t lplane, const void* la
 __global__ void k_zero(double* p, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+void launch_adj_step(bool f32, bool nt, int blocks, hipStream_t s, const AdjArgs& A)
+{
+    const dim3 g(blocks), b(64 * kAdjWaves);
+    if (f32 && nt) hipLaunchKernelGGL((k_adj_blk<float, true>), g, b, 0, s, A);
+    else if (f32) hipLaunchKernelGGL((k_adj_blk<float, false>), g, b, 0, s, A);
+    else if (nt) hipLaunchKernelGGL((k_adj_blk<double, true>), g, b, 0, s, A);
+    else hipLaunchKernelGGL((k_adj_blk<double, false>), g, b, 0, s, A);
 }
 
 struct AdjLayout {
@@ -613,6 +626,7 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
     A.acc = acc;
     A.strips = L.strips;
     A.lplane = lp;
+    const bool nt = 2 * 9 * lp * L.tsz <= ((size_t)256 << 20);  // both lambda buffers fit in the MALL
     A.rplane = nn;
     A.c_e = 1.0 / (P.tau[1] - 0.5);
     A.c_q = 1.0 / (P.tau[2] - 0.5);
@@ -640,8 +654,7 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
             A.rec = (const char*)c->rec_all + (size_t)j * 4 * nn * L.tsz;
             A.lam_in = lam[li];
             A.lam_out = lam[li ^ 1];
-            if (f32) hipLaunchKernelGGL(k_adj_blk<float>, dim3(L.blocks), dim3(64 * kAdjWaves), 0, s, A);
-            else hipLaunchKernelGGL(k_adj_blk<double>, dim3(L.blocks), dim3(64 * kAdjWaves), 0, s, A);
+            launch_adj_step(f32, nt, L.blocks, s, A);
             if (!hip_ok(hipGetLastError(), "adjoint step launch")) return LBM_EHIP;
             li ^= 1;
         }
@@ -668,8 +681,7 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
             A.rec = (const char*)rec_buf + (size_t)j * 4 * nn * L.tsz;
             A.lam_in = lam[li];
             A.lam_out = lam[li ^ 1];
-            if (f32) hipLaunchKernelGGL(k_adj_blk<float>, dim3(L.blocks), dim3(64 * kAdjWaves), 0, s, A);
-            else hipLaunchKernelGGL(k_adj_blk<double>, dim3(L.blocks), dim3(64 * kAdjWaves), 0, s, A);
+            launch_adj_step(f32, nt, L.blocks, s, A);
             if (!hip_ok(hipGetLastError(), "adjoint step launch")) return LBM_EHIP;
             li ^= 1;
         }

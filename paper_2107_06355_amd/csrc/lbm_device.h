@@ -351,14 +351,15 @@ __device__ __forceinline__ int load_index(const StepArgs& A, int r)
 // the Eq. LiFS source, inverse transform and store (or the macroscopic outputs).
 // psB = psi(x, y); Ftx, Fty = F~ = F/psi(x) from Eq. ShanChenForce.
 // pre-collision state the adjoint of a step needs at node o: drho, j (unforced), psi
+// (streaming stores: a record is read back only by the adjoint, long after)
 template <typename T>
 __device__ __forceinline__ void record_node(void* rec, size_t plane, size_t o, T dr, T jx, T jy, T psi)
 {
     T* rc = (T*)rec;
-    rc[o] = dr;
-    rc[plane + o] = jx;
-    rc[2 * plane + o] = jy;
-    rc[3 * plane + o] = psi;
+    __builtin_nontemporal_store(dr, rc + o);
+    __builtin_nontemporal_store(jx, rc + plane + o);
+    __builtin_nontemporal_store(jy, rc + 2 * plane + o);
+    __builtin_nontemporal_store(psi, rc + 3 * plane + o);
 }
 
 // unforced momentum j of pulled populations g (the moment rows of Eq. MatrixMRT)
