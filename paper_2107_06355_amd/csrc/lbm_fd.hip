@@ -171,6 +171,7 @@ __device__ __forceinline__ void fd_ghost_rows(const FdArgs& A, double* R, double
     }
 }
 
+template <bool NT>
 __global__ __launch_bounds__(kTx * kTy) void k_fd_step(FdArgs A, const double* rho, const double* u, const double* v,
                                                        double* o_r, double* o_u, double* o_v)
 {
@@ -231,9 +232,19 @@ __global__ __launch_bounds__(kTx * kTy) void k_fd_step(FdArgs A, const double* r
     fd_rhs<-1, kBx>(A, bR, bU, bV, bP, bS, threadIdx.x + 2, threadIdx.y + 2, dr, du, dv);
     const int cb = (threadIdx.y + 2) * kBx + threadIdx.x + 2, ca = (threadIdx.y + 4) * kAx + threadIdx.x + 4;
     const size_t g = (size_t)j * A.nx + i;
-    o_r[g] = 0.5 * aR[ca] + 0.5 * (bR[cb] + A.dt * dr);
-    o_u[g] = 0.5 * aU[ca] + 0.5 * (bU[cb] + A.dt * du);
-    o_v[g] = 0.5 * aV[ca] + 0.5 * (bV[cb] + A.dt * dv);
+    const double nr = 0.5 * aR[ca] + 0.5 * (bR[cb] + A.dt * dr);
+    const double nu = 0.5 * aU[ca] + 0.5 * (bU[cb] + A.dt * du);
+    const double nv = 0.5 * aV[ca] + 0.5 * (bV[cb] + A.dt * dv);
+    if constexpr (NT) {
+        // streaming stores when both state buffers fit in the MALL (as the LBM kernels do)
+        __builtin_nontemporal_store(nr, o_r + g);
+        __builtin_nontemporal_store(nu, o_u + g);
+        __builtin_nontemporal_store(nv, o_v + g);
+    } else {
+        o_r[g] = nr;
+        o_u[g] = nu;
+        o_v[g] = nv;
+    }
 }
 
 FdArgs fd_args(const lbm_fd_ctx* c)
@@ -344,10 +355,16 @@ int lbm_fd_step(lbm_fd_ctx* c, int64_t nsteps, void* stream)
     if (!c || nsteps < 0) return LBM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const dim3 blk(kTx, kTy), grd((c->P.nx + kTx - 1) / kTx, (c->P.ny + kTy - 1) / kTy);
+    // both state buffers (2 x 3 fields x 8 B per node) in the 256 MB MALL: streaming stores
+    const bool nt = (size_t)c->P.nx * c->P.ny * 48 <= ((size_t)256 << 20);
     for (int64_t t = 0; t < nsteps; ++t) {
         FdArgs A = fd_args(c);
-        hipLaunchKernelGGL(k_fd_step, grd, blk, 0, s, A, (const double*)c->rho, (const double*)c->u,
-                           (const double*)c->v, c->rs, c->us, c->vs);
+        if (nt)
+            hipLaunchKernelGGL(k_fd_step<true>, grd, blk, 0, s, A, (const double*)c->rho, (const double*)c->u,
+                               (const double*)c->v, c->rs, c->us, c->vs);
+        else
+            hipLaunchKernelGGL(k_fd_step<false>, grd, blk, 0, s, A, (const double*)c->rho, (const double*)c->u,
+                               (const double*)c->v, c->rs, c->us, c->vs);
         if (!ok(hipGetLastError(), "fd step launch")) return LBM_EHIP;
         // the new state is in (rs, us, vs): swap the roles of the two state buffers
         std::swap(c->rho, c->rs);
