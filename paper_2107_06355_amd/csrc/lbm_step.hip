@@ -503,13 +503,15 @@ bool launch_step2(lbm_ctx* c, void* rec, hipStream_t s, bool reduce = false)
     // MI355X: 4% faster at 512^2 FP32; 1-2% slower on FP32 lattices of 4096^2 and up)
     const bool nt = 2 * c->pop_bytes <= ((size_t)256 << 20);
     if (c->P.walls) {
-        if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true>), g, b, 0, s, A);
+        if (rec && nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true, true>), g, b, 0, s, A);
+        else if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true>), g, b, 0, s, A);
         else if (reduce && nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP_REDUCE, true, true>), g, b, 0, s, A);
         else if (reduce) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP_REDUCE, true>), g, b, 0, s, A);
         else if (nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, true, true>), g, b, 0, s, A);
         else hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, true>), g, b, 0, s, A);
     } else {
-        if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, false>), g, b, 0, s, A);
+        if (rec && nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, false, true>), g, b, 0, s, A);
+        else if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, false>), g, b, 0, s, A);
         else if (reduce && nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP_REDUCE, false, true>), g, b, 0, s, A);
         else if (reduce) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP_REDUCE, false>), g, b, 0, s, A);
         else if (nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_STEP, false, true>), g, b, 0, s, A);
