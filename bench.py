@@ -32,7 +32,7 @@ METRIC = "MLUPS + HBM GB/s (%roofline), FP32-shifted vs FP64 D2Q9; adjoint/fwd t
 BYTES = {"fp32": 8 * 4 * 2 + 8 * 2, "fp64": 9 * 8 * 2}
 # step kernel of each decomposition (lbm_variant): row march, row block, two-step block
 KERNEL_NAME = {1: "k_step<%s, 0>", 2: "k_step_blk<%s, 0>", 3: "k_step2_blk<%s, 0, false, %s>"}
-MALL_BYTES = 256 << 20  # the library streams its stores when both population buffers fit in it
+STREAM_BYTES = 64 << 20  # the library streams its stores when both population buffers take at most this
 
 
 def kernel_name(lbm, var, prec, P):
@@ -40,7 +40,7 @@ def kernel_name(lbm, var, prec, P):
     t = "float" if prec == "fp32" else "double"
     if var != lbm.VARIANT_BLOCK2:
         return KERNEL_NAME[var] % t
-    return KERNEL_NAME[var] % (t, "true" if 2 * lbm.layout(P)[1] <= MALL_BYTES else "false")
+    return KERNEL_NAME[var] % (t, "true" if 2 * lbm.layout(P)[1] <= STREAM_BYTES else "false")
 
 EOS_KW = dict(base=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
 TAU = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]

@@ -626,7 +626,7 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
     A.acc = acc;
     A.strips = L.strips;
     A.lplane = lp;
-    const bool nt = 2 * 9 * lp * L.tsz <= ((size_t)256 << 20);  // both lambda buffers fit in the MALL
+    const bool nt = 2 * 9 * lp * L.tsz <= kStreamBytes;  // streaming lambda stores on small lattices
     A.rplane = nn;
     A.c_e = 1.0 / (P.tau[1] - 0.5);
     A.c_q = 1.0 / (P.tau[2] - 0.5);

@@ -293,7 +293,7 @@ void launch_full2_t(int max_ny, dim3 g, dim3 b, hipStream_t s, const BatchItem* 
     else hipLaunchKernelGGL((k_batch_full2<T, kFullRows, NT>), g, b, 0, s, it, off, B, b0, b1, cur, st);
 }
 
-// nt: streaming stores, when both population buffers of the batch fit in the 256 MB MALL
+// nt: streaming stores, when both population buffers of the batch are small (kStreamBytes)
 // (as for a single lattice)
 void launch_full2(bool f32, bool nt, int max_ny, dim3 g, dim3 b, hipStream_t s, const BatchItem* it, const int* off,
                   int B, char* b0, char* b1, int cur, long long st)
@@ -564,7 +564,7 @@ static bool launch_grouped(lbm_batch* c, int n, int cur, int64_t step0, hipStrea
     for (; k + 1 < n; k += 2) {
         const long long st = (long long)(step0 + k);
         if (c->full)
-            launch_full2(f32, 2 * c->L.off[c->B] <= ((size_t)256 << 20), c->L.max_ny, gf, bf, s, it, c->strip_off, c->B,
+            launch_full2(f32, 2 * c->L.off[c->B] <= kStreamBytes, c->L.max_ny, gf, bf, s, it, c->strip_off, c->B,
                          c->buf[0], c->buf[1], cur, st);
         else if (f32 && !w) hipLaunchKernelGGL((k_batch_step2<float, false>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);
         else if (f32) hipLaunchKernelGGL((k_batch_step2<float, true>), g2, b2, 0, s, it, c->tile_off, c->B, c->buf[0], c->buf[1], cur, st);

@@ -36,6 +36,13 @@ namespace lbmk {
 #endif
 
 
+// Kernels store their new state with the non-temporal hint when both of its buffers
+// together take at most this many bytes.  Measured on MI355X: faster at 12-38 MB (512^2
+// lattices in both precisions: 4%; 64 batched planar lattices: 20%; the adjoint's lambda:
+// 6%; the finite-difference solver: 9%), slower at 168 MB (walled 2048 x 1024 FP32:
+// 23.6 -> 27.7 us/step) and beyond.
+constexpr size_t kStreamBytes = (size_t)64 << 20;
+
 constexpr int kStripW = 62;   // interior columns per wave (lanes 0 and 63 are the psi halo)
 
 // ----------------------------------------------------------------- device EOS
@@ -472,8 +479,7 @@ __device__ __forceinline__ void update_node(const StepArgs& A, const Lane& L, in
     const WView<T> D = make_wview<T>(A.dst, A.plane);
     const uint32_t off = (uint32_t)y * (uint32_t)A.ld + (uint32_t)L.x;
     if constexpr (NT) {
-        // streaming stores: measured faster on MI355X when both population buffers fit in
-        // the 256 MB MALL, slower on larger FP32 lattices
+        // streaming stores (the callers choose them for small lattices: kStreamBytes)
 #pragma unroll
         for (int i = 1; i < 9; ++i) __builtin_nontemporal_store(o[i], (T*)(D.mv[i] + off * (uint32_t)sizeof(T)));
         __builtin_nontemporal_store(o0, (double*)(D.rest + off * 8u));

@@ -355,8 +355,8 @@ int lbm_fd_step(lbm_fd_ctx* c, int64_t nsteps, void* stream)
     if (!c || nsteps < 0) return LBM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const dim3 blk(kTx, kTy), grd((c->P.nx + kTx - 1) / kTx, (c->P.ny + kTy - 1) / kTy);
-    // both state buffers (2 x 3 fields x 8 B per node) in the 256 MB MALL: streaming stores
-    const bool nt = (size_t)c->P.nx * c->P.ny * 48 <= ((size_t)256 << 20);
+    // streaming stores when both state buffers (2 x 3 fields x 8 B per node) are small
+    const bool nt = (size_t)c->P.nx * c->P.ny * 48 <= kStreamBytes;
     for (int64_t t = 0; t < nsteps; ++t) {
         FdArgs A = fd_args(c);
         if (nt)

@@ -499,9 +499,8 @@ bool launch_step2(lbm_ctx* c, void* rec, hipStream_t s, bool reduce = false)
     A.rec = rec;
     A.rec_plane = (size_t)c->P.nx * c->P.ny;
     const dim3 g(c->grid2), b(64 * k2WavesOf<T>);
-    // streaming stores when both population buffers fit in the 256 MB MALL (measured on
-    // MI355X: 4% faster at 512^2 FP32; 1-2% slower on FP32 lattices of 4096^2 and up)
-    const bool nt = 2 * c->pop_bytes <= ((size_t)256 << 20);
+    // streaming stores for small lattices (kStreamBytes)
+    const bool nt = 2 * c->pop_bytes <= kStreamBytes;
     if (c->P.walls) {
         if (rec && nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true, true>), g, b, 0, s, A);
         else if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true>), g, b, 0, s, A);
