@@ -12,7 +12,7 @@ Further legs (in the same JSON line): an HBM sweep of larger lattices, the adjoi
 droplet loss (cost against the forward, agreement with central differences), a plain
 device-copy calibration and the FP64 CPU oracle on a bounded sample.
 
-Prints ONE JSON line (rank 0).  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line (rank 0).  --gpus N with N > 1 exits: the library runs the hot path on one GPU.
 """
 from __future__ import annotations
 
@@ -418,7 +418,7 @@ def main():
     ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference reference-solver leg")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs the hot path on ONE GPU; --gpus %d is not supported" % args.gpus,
+        print("bench.py: the library runs the hot path on ONE GPU; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
