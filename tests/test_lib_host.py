@@ -141,3 +141,20 @@ def test_library_exports_nothing_beyond_the_header():
                          check=True).stdout
     exported = {ln.split()[2] for ln in out.splitlines() if len(ln.split()) == 3 and ln.split()[1] == "T"}
     assert exported == set(declared_symbols()), sorted(exported ^ set(declared_symbols()))
+
+
+def test_bench_names_the_kernel_the_library_launches():
+    """bench.py names the timed two-step instance (streaming stores or not) from its own copy of the
+    library's streaming-store threshold; the two copies must agree, or the bench would time and
+    price one instance while the profile summaries describe another."""
+    import bench
+    src = open(os.path.join(ROOT, "paper_2107_06355_amd", "csrc", "lbm_device.h")).read()
+    m = re.search(r"constexpr size_t kStreamBytes = \(size_t\)(\d+) << (\d+);", src)
+    assert m, "kStreamBytes not found"
+    assert bench.STREAM_BYTES == int(m.group(1)) << int(m.group(2))
+    e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
+    # 512^2 FP32-shifted: 2 x 10.5 MB -> streamed; 2048 x 1024 FP32-shifted: 2 x 84 MB -> plain
+    P = lbm.make_params(512, 512, e, sigma=s, prec=lbm.FP32_SHIFTED)
+    assert bench.kernel_name(lbm, lbm.VARIANT_BLOCK2, "fp32", P) == "k_step2_blk<float, 0, false, true>"
+    P = lbm.make_params(2048, 1024, e, sigma=s, prec=lbm.FP32_SHIFTED)
+    assert bench.kernel_name(lbm, lbm.VARIANT_BLOCK2, "fp32", P) == "k_step2_blk<float, 0, false, false>"
