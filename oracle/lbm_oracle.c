@@ -36,12 +36,26 @@
  *
  * Quadratures: composite Simpson in the variable s = ln(rho), split at the
  * knots of the shaped EOS (Sec. III.A states Simpson's rule).
+ *
+ * Threads: built with -DOR_OMP -fopenmp, the three node loops of a time step
+ * (fields, collision, streaming) are split over rows by OpenMP.  Every node
+ * still runs the same arithmetic on the same inputs, and no sum crosses nodes,
+ * so the threaded build gives the same bits as the single-threaded one.
  */
 #include "lbm_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+
+#ifdef OR_OMP
+#include <omp.h>
+#define OR_PARALLEL_ROWS _Pragma("omp parallel for schedule(static)")
+#define OR_PARALLEL_ROWS_FLAG _Pragma("omp parallel for schedule(static) reduction(|:flag)")
+#else
+#define OR_PARALLEL_ROWS
+#define OR_PARALLEL_ROWS_FLAG
+#endif
 
 /* ---------------------------------------------------------------- */
 /* D2Q9 (Eq. VelocitySet), weights (Sec. II.A), M (Eq. MatrixMRT)   */
@@ -784,7 +798,8 @@ static double psi_at(const or_lattice* L, int x, int y)
  * psi is NaN instead (see or_run_window) */
 static int fields(or_lattice* L, int poison)
 {
-    int nx = L->P.nx, ny = L->P.ny, bad = 0;
+    int nx = L->P.nx, ny = L->P.ny, flag = 0; /* some node has psi^2 < 0 */
+    OR_PARALLEL_ROWS_FLAG
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             double r = 0;
@@ -794,9 +809,9 @@ static int fields(or_lattice* L, int poison)
             double ps = psi_of(&L->P, r, &b);
             if (b && poison) ps = NAN;
             L->psi[(size_t)y * nx + x] = ps;
-            bad |= b;
+            flag |= b;
         }
-    return bad;
+    return flag;
 }
 
 /* Eq. ShanChenForce divided by psi(x): F~ = -G sum_i w(|c_i|^2) psi(x+c_i) c_i */
@@ -837,8 +852,9 @@ void or_force_tilde_field(int nx, int ny, const double* psi, int walls, double p
 
 static int one_step(or_lattice* L, int poison)
 {
-    int nx = L->P.nx, ny = L->P.ny;
+    int nx = L->P.nx, ny = L->P.ny, flag = 0; /* some post-collision value is not finite */
     if (fields(L, poison) && !poison) return OR_EUNSTABLE;
+    OR_PARALLEL_ROWS_FLAG
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             double f[9], fo[9], Ftx, Fty;
@@ -847,11 +863,13 @@ static int one_step(or_lattice* L, int poison)
             double ps = L->psi[(size_t)y * nx + x];
             or_collide_node(&L->P, f, ps * Ftx, ps * Fty, ps, Ftx, Fty, fo);
             for (int i = 0; i < 9; ++i) {
-                if (!isfinite(fo[i]) && !poison) return OR_EUNSTABLE;
+                flag |= !isfinite(fo[i]);
                 L->fs[IDX(i, x, y)] = fo[i];
             }
         }
+    if (flag && !poison) return OR_EUNSTABLE;
     /* streaming, Eq. LBE left-hand side; bounce-back at the walls */
+    OR_PARALLEL_ROWS
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x)
             for (int i = 0; i < 9; ++i) {
@@ -867,6 +885,15 @@ static int one_step(or_lattice* L, int poison)
             }
     L->step++;
     return OR_OK;
+}
+
+int or_threads(void)
+{
+#ifdef OR_OMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 int or_run(or_lattice* L, long long nsteps)
@@ -897,6 +924,7 @@ int or_macros(or_lattice* L, double* rho, double* ux, double* uy, double* psi, d
 {
     int nx = L->P.nx, ny = L->P.ny;
     int bad = fields(L, 0);
+    OR_PARALLEL_ROWS
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t c = (size_t)y * nx + x;

@@ -92,6 +92,7 @@ void   or_init_eq(or_lattice* L, const double* rho, const double* ux, const doub
 void   or_set_f(or_lattice* L, const double* f);
 void   or_get_f(const or_lattice* L, double* f);
 int    or_run(or_lattice* L, long long nsteps);
+int    or_threads(void);  /* threads of a time step: 1, or OpenMP's count in the -DOR_OMP build */
 int    or_run_window(or_lattice* L, long long nsteps); /* psi^2 < 0 gives NaN psi instead of stopping */
 long long or_fail_step(const or_lattice* L);
 int    or_macros(or_lattice* L, double* rho, double* ux, double* uy, double* psi, double* p,

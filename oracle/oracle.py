@@ -19,8 +19,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _SRC_FD = os.path.join(_HERE, "fd_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
+# the same source with its node loops split over rows by OpenMP (-DOR_OMP): same bits, more cores
+_LIB_OMP = os.path.join(_HERE, "liblbm_oracle_omp.so")
 _lock = threading.Lock()
 _lib = None
+_lib_omp = None
 
 OR_OK, OR_EINVAL, OR_EUNSTABLE, OR_ENOROOT = 0, -1, -2, -5
 BASE_CS, BASE_PR = 0, 1
@@ -73,25 +76,31 @@ class OrFdParams(C.Structure):
     ]
 
 
+def _stale(path: str) -> bool:
+    return not os.path.exists(path) or os.path.getmtime(path) < max(
+        os.path.getmtime(_SRC), os.path.getmtime(_SRC_FD), os.path.getmtime(os.path.join(_HERE, "lbm_oracle.h")))
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no vector intrinsics)."""
+    """Compile the oracle with gcc (plain -O2, no vector intrinsics), single-threaded and with
+    OpenMP over the rows of each node loop."""
     with _lock:
-        if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
-            os.path.getmtime(_SRC), os.path.getmtime(_SRC_FD), os.path.getmtime(os.path.join(_HERE, "lbm_oracle.h"))
-        ):
-            tmp = _LIB + ".tmp%d" % os.getpid()
-            subprocess.check_call(
-                ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, _SRC_FD, "-lm"]
-            )
-            os.replace(tmp, _LIB)
+        for out, extra in ((_LIB, []), (_LIB_OMP, ["-DOR_OMP", "-fopenmp"])):
+            if force or _stale(out):
+                tmp = out + ".tmp%d" % os.getpid()
+                subprocess.check_call(
+                    ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", *extra, "-o", tmp, _SRC, _SRC_FD, "-lm"]
+                )
+                os.replace(tmp, out)
     return _LIB
 
 
-def lib():
-    global _lib
-    if _lib is None:
+def lib(omp: bool = False):
+    """The single-threaded oracle library, or (omp=True) its OpenMP build."""
+    global _lib, _lib_omp
+    if (_lib_omp if omp else _lib) is None:
         build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(_LIB_OMP if omp else _LIB)
         d, i, p = C.c_double, C.c_int, C.c_void_p
         dp = C.POINTER(C.c_double)
         L.or_eos_build.argtypes = [C.POINTER(OrEos), d, dp]
@@ -131,8 +140,12 @@ def lib():
         L.or_feq.argtypes = [d, d, d, dp]
         L.or_force_tilde_field.argtypes = [i, i, dp, i, d, d, d, dp, dp]
         L.or_matrix.argtypes = [dp, dp]
-        _lib = L
-    return _lib
+        L.or_threads.restype = i
+        if omp:
+            _lib_omp = L
+        else:
+            _lib = L
+    return _lib_omp if omp else _lib
 
 
 def _ptr(a: np.ndarray | None):
@@ -283,54 +296,63 @@ class FdSolver:
 
 
 class Lattice:
-    """FP64 oracle lattice; populations f_i(t, x) stored [9][ny][nx]."""
+    """FP64 oracle lattice; populations f_i(t, x) stored [9][ny][nx].
 
-    def __init__(self, P: OrParams):
+    omp=True runs the OpenMP build (rows of each node loop split over threads; the same
+    bits as the single-threaded build)."""
+
+    def __init__(self, P: OrParams, omp: bool = False):
         self.P = P
         self.nx, self.ny = P.nx, P.ny
-        self._h = lib().or_lattice_new(C.byref(P))
+        self._L = lib(omp)
+        self._h = self._L.or_lattice_new(C.byref(P))
         if not self._h:
             raise OracleError("invalid lattice size")
         self.step = 0
 
+    @property
+    def threads(self) -> int:
+        """Threads a time step of this lattice uses (1 for the single-threaded build)."""
+        return int(self._L.or_threads())
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().or_lattice_free(h)
+            self._L.or_lattice_free(h)
             self._h = None
 
     def init_eq(self, rho, ux=None, uy=None):
         rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(self.ny, self.nx)
         ux = None if ux is None else np.ascontiguousarray(ux, dtype=np.float64).reshape(self.ny, self.nx)
         uy = None if uy is None else np.ascontiguousarray(uy, dtype=np.float64).reshape(self.ny, self.nx)
-        lib().or_init_eq(self._h, _ptr(rho), _ptr(ux), _ptr(uy))
+        self._L.or_init_eq(self._h, _ptr(rho), _ptr(ux), _ptr(uy))
         self.step = 0
 
     def set_f(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, self.ny, self.nx)
-        lib().or_set_f(self._h, _ptr(f))
+        self._L.or_set_f(self._h, _ptr(f))
 
     def get_f(self) -> np.ndarray:
         f = np.empty((9, self.ny, self.nx))
-        lib().or_get_f(self._h, _ptr(f))
+        self._L.or_get_f(self._h, _ptr(f))
         return f
 
     def run(self, nsteps: int) -> None:
-        st = lib().or_run(self._h, int(nsteps))
+        st = self._L.or_run(self._h, int(nsteps))
         if st != OR_OK:
-            raise OracleError("oracle run unstable at step %d" % lib().or_fail_step(self._h))
+            raise OracleError("oracle run unstable at step %d" % self._L.or_fail_step(self._h))
         self.step += int(nsteps)
 
     def run_window(self, nsteps: int) -> None:
         """Steps of a periodic window cut from a larger lattice: nodes the cut makes unphysical
         get NaN psi instead of stopping the run; NaN then spreads two nodes per step at most."""
-        lib().or_run_window(self._h, int(nsteps))
+        self._L.or_run_window(self._h, int(nsteps))
         self.step += int(nsteps)
 
     def macros(self) -> dict:
         shp = (self.ny, self.nx)
         out = {k: np.empty(shp) for k in ("rho", "ux", "uy", "psi", "p", "Fx", "Fy")}
-        st = lib().or_macros(self._h, *[_ptr(out[k]) for k in ("rho", "ux", "uy", "psi", "p", "Fx", "Fy")])
+        st = self._L.or_macros(self._h, *[_ptr(out[k]) for k in ("rho", "ux", "uy", "psi", "p", "Fx", "Fy")])
         if st != OR_OK:
             raise OracleError("psi not real")
         return out

@@ -303,14 +303,14 @@ def test_fp32_rest_population_ablation_c2(gpu_lib):
     same run with the rest population rounded to FP32 after every step (all nine populations in FP32, as a
     plain FP32 code stores them) drifts far past 1e-10; the FP64 rest population keeps the mass exact."""
     import torch
-    import bench
+    from lbm_inputs import STATIC_DROPLET_512
     lbm = gpu_lib
-    e, s = lbm.eos_build(lbm.make_eos(**bench.EOS_KW))
+    e, s = lbm.eos_build(lbm.make_eos(**STATIC_DROPLET_512["eos"]))
     n, steps = 512, 10000
     rho0 = droplet_density(n, n, e.rho_v, e.rho_l, R=80, W=20)
     drift = {}
     for naive in (False, True):
-        P = lbm.make_params(n, n, e, sigma=s, tau=bench.TAU, prec=lbm.FP32_SHIFTED, reduce_every=0,
+        P = lbm.make_params(n, n, e, sigma=s, tau=STATIC_DROPLET_512["tau"], prec=lbm.FP32_SHIFTED, reduce_every=0,
                             kernel_variant=lbm.VARIANT_BLOCK)
         L = lbm.Lattice(P, rho0, device="cuda:0")
         m0 = L.mass_momentum()[0]
@@ -354,12 +354,13 @@ def _t4_eos_kw(c):
 
 @pytest.mark.parametrize("case", _T4_CASES, ids=[c["name"] for c in _T4_CASES])
 def test_table4_rows_on_gpu(gpu_lib, case):
-    """Table IV (planar 2x200, all tau = 1, W = 10 start, run to the Sec. III.A criterion) and the
-    Modified Smooth point of Sec. IV.C on the GPU FP64 path: E, w and gamma as printed."""
+    """Table IV (planar 2x200, all tau = 1 except the Tr = 0.5 Peng row, W = 10 start, run to the Sec. III.A
+    criterion) and the Modified Smooth point of Sec. IV.C on the GPU FP64 path: E, w and gamma as printed."""
     e, s = gpu_lib.eos_build(gpu_lib.make_eos(**_t4_eos_kw(case)))
     sig = s if case["forcing"] == "li" else 0.0
     nx, ny = 2, 200
-    P = gpu_lib.make_params(nx, ny, e, sigma=sig)
+    tau = [case["tau"]] * 9 if "tau" in case else None  # the Peng row at Tr = 0.5: reading of the relaxation times
+    P = gpu_lib.make_params(nx, ny, e, sigma=sig, tau=tau)
     L = gpu_lib.Lattice(P, planar_density(nx, ny, e.rho_v, e.rho_l, W=10), device="cuda:0")
     prev = L.macros()["rho"].cpu().numpy()
     res = 1.0
@@ -383,7 +384,7 @@ def test_table4_rows_on_gpu(gpu_lib, case):
         if case["E"] > 1.0:
             assert E == pytest.approx(case["E"], rel=0.01)
         else:
-            assert abs(E - case["E"]) < 0.002  # percentage points; printed to 2 significant digits
+            assert abs(E - case["E"]) < case.get("E_tol", 0.002)  # percentage points; printed to 2 significant digits
 
 
 

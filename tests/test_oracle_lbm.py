@@ -356,14 +356,54 @@ with open(os.path.join(GOLD, "table4.json")) as _fh:
 def test_table4_planar_interface(case):
     e, s = _table4_eos(case)
     forcing = O.FORCING_LI if case["forcing"] == "li" else O.FORCING_GUO
-    r = O.run_planar(e, forcing=forcing, sigma=s if forcing == O.FORCING_LI else 0.0)
+    tau = [case["tau"]] * 9 if "tau" in case else None  # the Peng row at Tr = 0.5: reading of the relaxation times
+    r = O.run_planar(e, forcing=forcing, sigma=s if forcing == O.FORCING_LI else 0.0, tau=tau)
     assert r["residual"] < 1e-6
     assert r["width"] == case["w"]
     assert r["gamma"] == pytest.approx(case["gamma"], rel=0.06)
     if case["E"] > 1.0:
         assert r["E"] == pytest.approx(case["E"], rel=0.01)
     else:
-        assert abs(r["E"] - case["E"]) < 0.002  # percentage points; printed to 2 significant digits
+        # percentage points; printed to 2 significant digits
+        assert abs(r["E"] - case["E"]) < case.get("E_tol", 0.002)
+
+
+with open(os.path.join(GOLD, "table2_peng.json")) as _fh:
+    _T2 = json.load(_fh)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("w", sorted(_T2["r_theta"], key=int))
+def test_table2_peng_widths_and_errors(w):
+    """Table II: the printed r_theta give the printed widths at Tr = 0.5 with Guo forcing, and the vapor
+    errors the text of Sec. III.C quotes (close to 0.12% at w = 7, below 0.1% beyond).  The relaxation
+    times are all 2.5 (reading of the Peng-loop runs); the steady state is that of tau = 1."""
+    e, _ = cs_eos(_T2["Tr"], a=_T2["a"], shape=O.SHAPE_PENG, r_theta=_T2["r_theta"][w])
+    r = O.run_planar(e, forcing=O.FORCING_GUO, sigma=0.0, tau=[_T2["tau"]] * 9)
+    assert r["residual"] < 1e-6
+    assert r["width"] == int(w)
+    if w in _T2["error_close_to_percent"]:
+        assert abs(r["E"] - _T2["error_close_to_percent"][w]) < 0.02, r["E"]
+    if w in _T2["error_below_percent"]:
+        assert abs(r["E"]) < _T2["error_below_percent"][w], r["E"]
+
+
+@pytest.mark.slow
+def test_peng_steady_state_does_not_depend_on_tau_and_tau_one_collapses():
+    """What the Peng-loop reading rests on.  (1) Guo forcing: the Table IV Peng row at Tr = 0.6, which runs
+    with every tau = 1, gives the same w, E and gamma with every tau = 2.5.  (2) At Tr = 0.5 with every
+    tau = 1 the planar interface sharpens until a vapor node next to it is drained: the oracle reports
+    psi not real within 50 steps for every r_theta of Tables II and IV."""
+    c = [c for c in _T4["cases"] if c["shape"] == "peng" and c["Tr"] == 0.6][0]
+    e, _ = _table4_eos(c)
+    r1 = O.run_planar(e, forcing=O.FORCING_GUO, sigma=0.0)
+    r25 = O.run_planar(e, forcing=O.FORCING_GUO, sigma=0.0, tau=[2.5] * 9)
+    assert r1["width"] == r25["width"] == c["w"]
+    assert abs(r1["E"] - r25["E"]) < 0.001 and r25["gamma"] == pytest.approx(r1["gamma"], rel=1e-3)
+    for a, rt in [(_T2["a"], v) for v in _T2["r_theta"].values()] + [(0.363, 0.44)]:
+        e, _ = cs_eos(0.5, a=a, shape=O.SHAPE_PENG, r_theta=rt)
+        with pytest.raises(O.OracleError):
+            O.run_planar(e, forcing=O.FORCING_GUO, sigma=0.0, max_steps=100)
 
 
 
@@ -434,6 +474,47 @@ def test_cs_density_ratio_at_tr035():
     r = O.run_planar(e, sigma=s)
     assert r["residual"] < 1e-6
     assert r["rho_l"] / r["rho_v"] == pytest.approx(g["cs_Tr035_ratio"], rel=2e-3)
+
+
+@pytest.mark.slow
+def test_laplace_law_on_oracle_droplets():
+    """Laplace's law on the oracle: static droplets of a Smooth C-S fluid (a = 0.5, Tr = 0.7, alpha = 0.6,
+    Li forcing with sigma from eps) on a 128^2 periodic lattice, R = 16 ... 32, run to rest.  In 2-D the
+    jump p_in - p_out is gamma / R_s at the surface of tension R_s; the measured equimolar radius R_e sits
+    an offset delta of about one node from it, so dp = gamma / (R_e - delta) = gamma / R_e + gamma delta /
+    R_e^2 + ...: a fit dp = a + b / R_e + c / R_e^2 must give b = gamma of the planar interface of the same
+    fluid (Eq. SurfaceTension) and a = 0 (no jump across a flat interface).  Tolerance 4%: Eq. SurfaceTension
+    integrates the second-order continuum pressure tensor, whose neglected lattice terms are of relative
+    order (1/w)^2 ~ 1% at the width w = 11 here, plus the O((delta/R)^2) truncation of the fit."""
+    e, s = cs_eos(0.7, shape=O.SHAPE_SMOOTH, alpha=0.6, k_vap=1.0)
+    pl = O.run_planar(e, sigma=s, ny=200, nx=2, W=10, tol=1e-8, max_steps=200000)
+    N = 128
+    y, x = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    r = np.hypot(x - N / 2, y - N / 2)
+    edge = np.minimum(np.minimum(x, N - 1 - x), np.minimum(y, N - 1 - y)) < 8
+    dp, Re = [], []
+    for R in (16, 20, 24, 32):
+        L = O.Lattice(O.make_params(N, N, e, sigma=s), omp=True)
+        L.init_eq(droplet_density(N, N, pl["rho_v"], pl["rho_l"], R=R, W=pl["width"]))
+        prev = L.macros()["rho"]
+        for _ in range(100):
+            L.run(1000)
+            m = L.macros()
+            res = np.abs(m["rho"] - prev).sum() / np.abs(m["rho"]).sum()
+            prev = m["rho"]
+            if res < 1e-9:
+                break
+        assert res < 1e-9
+        rho, p = m["rho"], m["p"]
+        core = r < 0.5 * R
+        rin, rout = rho[core].mean(), rho[edge].mean()
+        Re.append(np.sqrt((rho - rout).sum() / (np.pi * (rin - rout))))
+        dp.append(p[core].mean() - p[edge].mean())
+    inv, dp = 1.0 / np.array(Re), np.array(dp)
+    c, b, a = np.polyfit(inv, dp, 2)
+    assert b == pytest.approx(pl["gamma"], rel=0.04), (b, pl["gamma"], c)
+    assert abs(a) <= 0.01 * dp.max(), a
+    assert np.abs(np.polyval([c, b, a], inv) - dp).max() <= 1e-3 * dp.max()
 
 
 # ---------------------------------------------------------------- finite-difference reference solver
@@ -521,3 +602,115 @@ def test_fd_oracle_wall_solid_layer_one_step_closed_form():
     np.testing.assert_allclose(r, np.repeat(r_want[:, None], nx, axis=1), rtol=1e-14, atol=0)
     np.testing.assert_allclose(v, np.repeat(v_want[:, None], nx, axis=1), rtol=1e-12, atol=1e-20)
     assert np.abs(u).max() == 0.0
+
+
+def test_fd_oracle_wall_b1_extrapolates_density_one_step_closed_form():
+    """Eq. B1: the layer b1 on the bottom wall takes rho_b1 = 2 rho_0 - rho_1 (linear extrapolation
+    from rows 0 and 1), not a copy of row 0.  Rest state whose psi is exactly linear in y,
+    psi_j = psi_a + s j, with psi_wall of Eq. B2 chosen so that the solid layer continues the line:
+    every second and third difference of psi vanishes, so Eq. FDforce is zero and one MacCormack
+    step is set by the pressure and the walls alone.  Worked out by hand:
+      predictor (forward differences, b1 not read): rho* = rho, v*_j = -dt (p_{j+1} - p_j) / (h rho_j);
+      corrector at row 0 (backward differences, v = 0 on b1, central v_yy), with
+      D = (rho_0 - rho_b1) / h the backward density difference:
+        rho_0 <- rho_0 - dt/2 (rho_0 v*_0 / h + v*_0 D),
+        v_0   <- (v*_0 + dt (-v*_0^2 / h - (p_0 - p(rho_b1)) / (h rho_0) + S_y / rho_0)) / 2,
+        S_y = 2 mu' D v*_0 / h + mu (2 (v*_1 - 2 v*_0) / h^2) + mu_B' D v*_0 / h + mu_B (v*_1 - 2 v*_0) / h^2
+      (mu = rho/3 (tau_nu - 1/2), mu_B = rho/3 (tau_e - tau_nu), primes: d/drho).  Eq. B1 gives
+      D = (rho_1 - rho_0)/h; a copy of row 0 would give D = 0 and p(rho_b1) = p_0."""
+    e, _ = cs_eos(0.7)
+    nx, ny, h, dt, te, tn, G = 3, 10, 1.0, 0.1, 1.1, 0.8, -1.0
+
+    def psi_of(r):
+        return math.sqrt(2 * (O.eos_p(e, r)[0] - r / 3) / G)
+
+    def rho_of(ps):
+        lo, hi = 0.5 * e.rho_v, e.rho_max  # psi increases with rho on the vapor branch
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if psi_of(mid) < ps else (lo, mid)
+        return 0.5 * (lo + hi)
+
+    ps_a = psi_of(e.rho_v)
+    sl = 0.02 * ps_a
+    rho = np.array([rho_of(ps_a + sl * j) for j in range(ny)])
+    psi = np.array([psi_of(r) for r in rho])
+    np.testing.assert_allclose(np.diff(psi, 2), 0, atol=1e-13 * ps_a)  # linear to rounding
+    P = O.make_fd_params(nx, ny, e, h=h, dt=dt, G=G, tau_e=te, tau_nu=tn, walls=True)
+    P.psi_wall = ps_a - sl - sl / (2 * h)  # b2 = b1 + 2h (psi_wall - b1) = psi_a - 2 s
+    F = O.FdSolver(P)
+    F.set(np.repeat(rho[:, None], nx, axis=1))
+    F.run(1)
+    r, u, v = F.get()
+    p = O.eos_p(e, rho)
+    vs = -dt * (p[1:] - p[:-1]) / (h * rho[:-1])  # predictor v*_j (rows 0 .. ny-2)
+
+    def row0(rho_b1):
+        D = (rho[0] - rho_b1) / h
+        mu, muB = rho[0] / 3 * (tn - 0.5), rho[0] / 3 * (te - tn)
+        dmu, dmuB = (tn - 0.5) / 3, (te - tn) / 3
+        vy, vyy = vs[0] / h, (vs[1] - 2 * vs[0]) / h ** 2
+        Sy = dmu * D * 2 * vy + mu * 2 * vyy + dmuB * D * vy + muB * vyy
+        r0 = rho[0] - dt / 2 * (rho[0] * vy + vs[0] * D)
+        v0 = (vs[0] + dt * (-vs[0] * vy - (p[0] - O.eos_p(e, rho_b1)[0]) / (h * rho[0]) + Sy / rho[0])) / 2
+        return r0, v0
+
+    r_b1, v_b1 = row0(2 * rho[0] - rho[1])
+    r_copy, v_copy = row0(rho[0])
+    assert r[0, 0] == pytest.approx(r_b1, rel=1e-13)
+    assert v[0, 0] == pytest.approx(v_b1, rel=1e-10)
+    # the copy reading is far outside these tolerances
+    assert abs(r_copy - r_b1) > 1e6 * 1e-13 * r_b1 and abs(v_copy - v_b1) > 1e3 * 1e-10 * abs(v_b1)
+    np.testing.assert_array_equal(r[0], r[0, 0])
+    assert np.abs(u).max() < 1e-20
+
+
+# ---------------------------------------------------------------- threaded build
+@pytest.mark.parametrize("case", ["droplet", "walls_var_tau", "unstable"])
+def test_openmp_oracle_is_bitwise_the_single_threaded_one(case):
+    """The OpenMP build splits each node loop over rows; every node still runs the same arithmetic,
+    so populations, macros and the failing step agree bit for bit with the single-threaded build."""
+    e, s = cs_eos(Tr=0.6, shape=O.SHAPE_SMOOTH, alpha=0.6, k_vap=4.0)
+    nx, ny = 70, 53
+    ux = uy = None
+    if case == "droplet":
+        P = O.make_params(nx, ny, e, sigma=s, tau=[1.0, 1.1, 1.2, 1.0, 1.1, 1.0, 1.1, 0.8, 0.8])
+        rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=12, W=5)
+        steps = 40
+    elif case == "walls_var_tau":
+        from lbm_inputs import droplet_on_film
+
+        P = O.make_params(nx, ny, e, sigma=s, walls=True, rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v,
+                          var_tau=True, tau_l=0.7, tau_v=1.3)
+        rho0, ux, uy = droplet_on_film(nx, ny, e.rho_v, e.rho_l, R=10, h=8, gap=3, V=0.05, W=5)
+        steps = 40
+    else:
+        # a width-1 interface at a deep quench drives psi^2 through zero within a few steps
+        e, s = cs_eos(Tr=0.4)
+        P = O.make_params(nx, ny, e, sigma=s)
+        rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=12, W=0.5)
+        steps = 200
+    out = []
+    for omp in (False, True):
+        L = O.Lattice(P, omp=omp)
+        L.init_eq(rho0, ux, uy)
+        try:
+            L.run(steps)
+            fail = None
+        except O.OracleError as ex:
+            fail = str(ex)
+        out.append((L.get_f(), fail, None if fail else L.macros()))
+    assert out[0][1] == out[1][1]
+    if case == "unstable":
+        assert out[0][1] is not None
+        return
+    assert np.array_equal(out[0][0], out[1][0])
+    for k in out[0][2]:
+        assert np.array_equal(out[0][2][k], out[1][2][k], equal_nan=True), k
+
+
+def test_openmp_oracle_uses_several_threads():
+    e, s = cs_eos()
+    L = O.Lattice(O.make_params(8, 8, e, sigma=s), omp=True)
+    assert L.threads >= min(2, len(os.sched_getaffinity(0)))
+    assert O.Lattice(O.make_params(8, 8, e, sigma=s)).threads == 1
