@@ -1,9 +1,9 @@
 """Seeded synthetic input generators shared by the tests, the oracle driver and bench.py.
 
-This module holds only initial density/velocity fields and workload recipes; it holds
-none of the method's arithmetic (no EOS, no collision, no force).  Every field is
-analytic (the paper's workloads are analytic initial conditions), and every random
-choice comes from ``numpy.random.default_rng(seed)``.
+This module holds only initial density/velocity fields and workload recipes (plain
+parameter values); it holds none of the method's arithmetic (no EOS, no collision, no
+force).  Every field is analytic (the paper's workloads are analytic initial
+conditions), and every random choice comes from ``numpy.random.default_rng(seed)``.
 """
 from __future__ import annotations
 
@@ -79,3 +79,38 @@ def batched_planar_recipe(n_lattices: int = 64, seed: int = 0, Tr_lo: float = 0.
     lengths = 4 * rng.integers(L_lo, L_hi + 1, size=n_lattices)
     trs = rng.uniform(Tr_lo, Tr_hi, size=n_lattices)
     return [int(v) for v in lengths], [float(t) for t in trs]
+
+
+# ---------------------------------------------------------------------------
+# Workload recipes: parameter values only, shared by bench.py, the GPU tests and the
+# script that writes the oracle's stored results (tests/golden/).
+# ---------------------------------------------------------------------------
+# Shaped Peng-Robinson (a = 2/49, b = 2/21, omega = 0.344) with the Smooth loop
+# (alpha = 0.3), raised vapor slope k_vap = 4 and EOS scale 0.25; Tr is set per workload.
+SHAPED_PR = dict(base=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.344, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
+
+# Static droplet (Laplace workload): 512 x 512 periodic, Tr = 0.5, R = 80, tanh rim of width 20,
+# MRT with every rate 1 except the shear rates (tau_nu = 0.7), Li forcing with sigma from eps.
+STATIC_DROPLET_512 = dict(nx=512, ny=512, eos=dict(SHAPED_PR, Tr=0.5), tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7],
+                          R=80, W=20, steps=50000)
+
+# Droplet impact on a liquid film between walls: 2048 x 1024, Tr = 0.47 (density ratio 3.07e4),
+# droplet R = 100 moving at V = 0.072 with its rim 4 nodes above a film of height 40 = 0.2 D,
+# tanh rims of width 16; shear relaxation time tau_l = 0.644 (Re = V D / nu = 300), every other
+# rate 1; ghost densities rho_l below the bottom wall and rho_v above the top wall.
+DROP_IMPACT_2048 = dict(nx=2048, ny=1024, eos=dict(SHAPED_PR, Tr=0.47), tau_l=0.644, R=100, h=40, gap=4, V=0.072,
+                        W=16, parity_steps=2000)
+
+
+def drop_impact_tau(recipe: dict) -> list:
+    """Relaxation times of the drop-impact workload in the moment order (shear pair last)."""
+    return [1.0] * 7 + [recipe["tau_l"]] * 2
+
+
+def static_droplet_fields(recipe: dict, rho_v: float, rho_l: float) -> np.ndarray:
+    return droplet_density(recipe["nx"], recipe["ny"], rho_v, rho_l, R=recipe["R"], W=recipe["W"])
+
+
+def drop_impact_fields(recipe: dict, rho_v: float, rho_l: float):
+    return droplet_on_film(recipe["nx"], recipe["ny"], rho_v, rho_l, R=recipe["R"], h=recipe["h"],
+                           gap=recipe["gap"], V=recipe["V"], W=recipe["W"])

@@ -9,8 +9,7 @@ G dL/dG = sigma dL/dsigma; a recorded forward against checkpoints + recomputatio
 import numpy as np
 import pytest
 
-import bench
-from lbm_inputs import droplet_density
+from lbm_inputs import STATIC_DROPLET_512, droplet_density
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +18,7 @@ NAMES = ("rho_max", "p_max", "rho_min", "p_min", "G", "sigma")
 
 
 def _setup(lbm):
-    e, s = lbm.eos_build(lbm.make_eos(**bench.EOS_KW))
+    e, s = lbm.eos_build(lbm.make_eos(**STATIC_DROPLET_512["eos"]))
     return e, s, droplet_density(N, N, e.rho_v, e.rho_l, R=R, W=W0)
 
 
@@ -33,7 +32,7 @@ def _loss_grad(e, rho):
 
 def _forward(lbm, e, s, rho0, prec, mode=None, G=-1.0, sig=None, knots=None):
     ee = lbm.eos_set_knots(e, *knots) if knots is not None else e
-    P = lbm.make_params(N, N, ee, G=G, sigma=s if sig is None else sig, tau=bench.TAU, prec=prec, reduce_every=0)
+    P = lbm.make_params(N, N, ee, G=G, sigma=s if sig is None else sig, tau=STATIC_DROPLET_512["tau"], prec=prec, reduce_every=0)
     lat = lbm.Lattice(P, rho0, device="cuda:0")
     if mode == "record":
         lat.enable_recording(STEPS)

@@ -16,11 +16,11 @@ import numpy as np
 import pytest
 
 import oracle as O
-from lbm_inputs import droplet_density
+from lbm_inputs import STATIC_DROPLET_512, droplet_density
 
 pytestmark = pytest.mark.gpu
 
-EOS_KW = dict(base=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
+EOS_KW = STATIC_DROPLET_512["eos"]
 TAU = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]
 W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 
@@ -29,6 +29,24 @@ def _bound(lbm, prec, f_o, rho_v, steps=1):
     if prec == lbm.FP64:
         return 1e-12 * np.abs(f_o).max()
     return steps * 2e-6 * np.abs(f_o - W9.reshape((9,) + (1,) * (f_o.ndim - 1)) * rho_v).max()
+
+
+# FP32-shifted: relative density error per step allowed on vapor nodes.  The whole-field bound above
+# is set by the liquid's deviations from w rho_v; this one looks at the vapor alone.  A vapor node's
+# populations deviate little from w rho_v, so their FP32 rounding (2^-24 of the deviation) is far
+# below 1e-7 of rho_v; what reaches the vapor density is the FP32 rounding of psi near the interface
+# entering the force, of order 2^-24 |G| psi^2 per step, which stays below 1e-6 of rho_v.
+VAPOR_REL_PER_STEP = 1e-6
+
+
+def _check_vapor(lbm, prec, f_g, f_o, e, steps):
+    """Relative density error on the vapor nodes (rho below the Maxwell mid density)."""
+    if prec == lbm.FP64:
+        return
+    rg, ro = f_g.sum(axis=0), f_o.sum(axis=0)
+    vap = ro < 0.5 * (e.rho_v + e.rho_l)
+    err = (np.abs(rg - ro) / ro)[vap].max()
+    assert err <= min(1e-3, VAPOR_REL_PER_STEP * steps), err
 
 
 def _lattice(lbm, n, R, prec, steps, variant=0):
@@ -58,7 +76,7 @@ def test_512_droplet_whole_field(gpu_lib, prec_name, steps):
     OL.run(steps)
     f_o = OL.get_f()
     assert np.abs(f_g - f_o).max() <= _bound(lbm, prec, f_o, e.rho_v, steps)
-
+    _check_vapor(lbm, prec, f_g, f_o, e, steps)
 
 
 @pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
@@ -80,6 +98,7 @@ def test_512_droplet_whole_field_100_steps(gpu_lib, prec_name):
     OL.run(101)
     f_o = OL.get_f()
     assert np.abs(f_g - f_o).max() <= _bound(lbm, prec, f_o, e.rho_v, 101)
+    _check_vapor(lbm, prec, f_g, f_o, e, 101)
 
 
 def _samples(n, rng):
@@ -140,3 +159,4 @@ def test_large_droplet_sampled_nodes(gpu_lib, n, prec_name, variant, steps):
     err = np.abs(f_g - f_o)
     worst = np.unravel_index(np.argmax(err), err.shape)
     assert err.max() <= _bound(lbm, prec, f_o, e.rho_v, steps), (pts[worst[1]], err.max())
+    _check_vapor(lbm, prec, f_g, f_o, e, steps)

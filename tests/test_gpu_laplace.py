@@ -9,11 +9,11 @@ import numpy as np
 import pytest
 
 import oracle as O
-from lbm_inputs import droplet_density, planar_density
+from lbm_inputs import STATIC_DROPLET_512, droplet_density, planar_density
 
 pytestmark = pytest.mark.gpu
 
-EOS_KW = dict(base=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
+EOS_KW = STATIC_DROPLET_512["eos"]
 TAU = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]
 N = 512
 RADII = (40, 60, 80, 100, 120)
