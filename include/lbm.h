@@ -141,7 +141,9 @@ int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int*
 
 /* Create a context over caller buffers f_a, f_b (lbm_layout bytes each) and
  * workspace ws, and write the initial state f_i(0) = f^eq_i(rho0, u0)
- * (Sec. III.A) into f_a.  rho0, ux0, uy0: device float64 [ny][nx]; ux0/uy0
+ * (Sec. III.A) into f_a; in LBM_FP32_SHIFTED the FP64 rest population takes
+ * what the eight FP32-rounded moving populations leave of rho0, so that each
+ * node's mass is rho0 exactly.  rho0, ux0, uy0: device float64 [ny][nx]; ux0/uy0
  * may be NULL (u = 0).  Validates parameters (LBM_EINVAL): tau > 1/2,
  * rho_ref > 0 in FP32 mode, G < 0, buffers non-NULL and distinct. */
 int lbm_init(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes,
@@ -181,7 +183,11 @@ int lbm_history(lbm_ctx* ctx, double* host_rows, int max_rows, int* n_out, void*
 int lbm_state(lbm_ctx* ctx, int64_t* step_out, int* cur_out);
 
 /* Checkpoint / restore of the whole population state to caller memory
- * (device or host pointer of lbm_layout bytes).  Synchronous. */
+ * (device or host pointer of lbm_layout bytes).  Synchronous.  lbm_load sets
+ * the step counter to `step`; with step != 0 it also turns recording and
+ * checkpointing off (their contents belong to the trajectory before the
+ * load), so a later lbm_adjoint returns LBM_ESTATE until the forward is run
+ * again from step 0 with them re-enabled. */
 int lbm_save(lbm_ctx* ctx, void* dst, void* stream);
 int lbm_load(lbm_ctx* ctx, const void* src, int64_t step, void* stream);
 
@@ -241,9 +247,11 @@ int lbm_eos_set_knots(lbm_eos* e, double rho_max, double p_max, double rho_min, 
 
 /* ------------------------------------------------------------------------
  * Batched lattices: B independent lattices (own size, EOS, relaxation times,
- * FP32 shift; one storage precision for all) advanced by ONE persistent
- * launch in which one workgroup owns one lattice and loops over the steps.
- * The launch is captured in a HIP graph and replayed.  Population buffers
+ * FP32 shift; one storage precision for all) advanced together, either by
+ * grouped launches over every lattice at once or by one persistent launch in
+ * which one workgroup owns one lattice and loops over the steps (see
+ * lbm_step_batched and lbm_set_batch_mode for which runs when).  Either is
+ * captured in HIP graphs and replayed.  Population buffers
  * hold the lattices back to back (lbm_batch_layout gives the sizes); scalar
  * fields are packed in lattice order, lattice b occupying
  * [cell_offsets[b], cell_offsets[b+1]) as [ny_b][nx_b].
@@ -279,8 +287,9 @@ void lbm_destroy_batched(lbm_batch* ctx);
 
 /* ------------------------------------------------------------------------
  * Finite-difference reference solver (appendix "Finite Difference Method"):
- * the mass equation and Eq. FDmomentum for rho, u, v on a doubly periodic
- * mesh of spacing h (LBM units, c = 1, c_s^2 = 1/3), viscous stress of
+ * the mass equation and Eq. FDmomentum for rho, u, v on a mesh of spacing h
+ * (LBM units, c = 1, c_s^2 = 1/3), periodic in x and, in y, periodic or
+ * bounded by the wall layers described below; viscous stress of
  * Eq. StressTensor with Eq. DynamicViscosity (tau_nu(rho) of
  * Eq. RelaxationTime when var_tau), pseudopotential pressure tensor through
  * Eq. FDforce, MacCormack predictor (forward one-sided first derivatives) and
@@ -310,7 +319,8 @@ int lbm_fd_layout(const lbm_fd_params* p, size_t* bytes);
  * rest).  The buffer holds all solver state; the context holds only pointers. */
 int lbm_fd_init(lbm_fd_ctx** ctx, const lbm_fd_params* p, void* buf, size_t buf_bytes, const double* rho0,
                 const double* u0, const double* v0, void* stream);
-/* nsteps predictor-corrector steps (asynchronous, two launches each). */
+/* nsteps predictor-corrector steps (asynchronous; one launch per step, the
+ * predicted state kept in LDS). */
 int lbm_fd_step(lbm_fd_ctx* ctx, int64_t nsteps, void* stream);
 /* Copy rho, u, v (device float64 [ny][nx], any may be NULL); asynchronous. */
 int lbm_fd_fields(lbm_fd_ctx* ctx, double* rho, double* u, double* v, void* stream);

@@ -314,8 +314,6 @@ __global__ void k_batch_init(const BatchItem* items, char* buf0, const double* r
     const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     const int op[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-    const double w9[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
-                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
     void* dst = buf0 + off;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < A.nx * A.ny; c += gridDim.x * blockDim.x) {
         const int x = c % A.nx, y = c / A.nx;
@@ -331,10 +329,7 @@ __global__ void k_batch_init(const BatchItem* items, char* buf0, const double* r
             sx = sx < 0 ? sx + A.nx : (sx >= A.nx ? sx - A.nx : sx);
             sy = sy < 0 ? sy + A.ny : (sy >= A.ny ? sy - A.ny : sy);
             const long long s = coff + (long long)sy * A.nx + sx;
-            const double r = rho0[s], ux = ux0 ? ux0[s] : 0.0, uy = uy0 ? uy0[s] : 0.0;
-            const double cu = cx[k] * ux + cy[k] * uy;
-            const double feq = w9[k] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
-            const double g = feq - w9[k] * A.rho_ref;
+            const double g = init_population<T>(k, rho0[s], ux0 ? ux0[s] : 0.0, uy0 ? uy0[s] : 0.0, A.rho_ref);
             if (j == 0) Plane<T>::restw(dst, A.plane)[o] = g;
             else Plane<T>::movw(dst, A.plane, j)[o] = (T)g;
         }

@@ -167,6 +167,26 @@ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __constant__ double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
+// Initial state (Sec. III.A): the shifted population g_k = f^eq_k(rho, u) - w_k rho_ref of
+// Eq. EquilibriumDistribution, in FP64.  For the rest population (k = 0) of the FP32-shifted
+// storage it returns instead what the eight FP32-rounded moving populations of the same node
+// leave of rho - rho_ref, so that the node mass is rho exactly from the first step on (the
+// invariant the collision keeps, see node_collide).
+template <typename T>
+__device__ inline double init_population(int k, double rho, double ux, double uy, double rho_ref)
+{
+    constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    auto g = [&](int i) {
+        const double cu = cx[i] * ux + cy[i] * uy;
+        return kW[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy)) - kW[i] * rho_ref;
+    };
+    if (k != 0 || sizeof(T) == 8) return g(k);
+    double moving = 0.0;
+    for (int i = 1; i < 9; ++i) moving += (double)(T)g(i);
+    return (rho - rho_ref) - moving;
+}
+
 template <typename T>
 struct Plane;
 template <>

@@ -301,10 +301,7 @@ __global__ void k_init(StepArgs A, const double* rho0, const double* ux0, const 
         sx = sx < 0 ? sx + A.nx : (sx >= A.nx ? sx - A.nx : sx);
         sy = sy < 0 ? sy + A.ny : (sy >= A.ny ? sy - A.ny : sy);
         const size_t c = (size_t)sy * A.nx + sx;
-        const double r = rho0[c], ux = ux0 ? ux0[c] : 0.0, uy = uy0 ? uy0[c] : 0.0;
-        const double cu = cx[k] * ux + cy[k] * uy;
-        const double feq = kW[k] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
-        const double g = feq - kW[k] * A.rho_ref;
+        const double g = init_population<T>(k, rho0[c], ux0 ? ux0[c] : 0.0, uy0 ? uy0[c] : 0.0, A.rho_ref);
         if (j == 0) Plane<T>::restw(A.dst, A.plane)[off] = g;
         else Plane<T>::movw(A.dst, A.plane, j)[off] = (T)g;
     }
@@ -869,6 +866,15 @@ int lbm_load(lbm_ctx* c, const void* src, int64_t step, void* stream)
         !hip_ok(hipStreamSynchronize(s), "lbm_load sync"))
         return LBM_EHIP;
     c->step = step;
+    if (step != 0) {
+        // the records and checkpoints belong to another trajectory: an adjoint over them would mix
+        // the two, so the loaded state carries none (lbm_adjoint then reports LBM_ESTATE)
+        c->rec_all = nullptr;
+        c->rec_steps = 0;
+        c->ckpt = nullptr;
+        c->ckpt_K = 0;
+        c->ckpt_slots = 0;
+    }
     return LBM_OK;
 }
 

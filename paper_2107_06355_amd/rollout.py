@@ -67,10 +67,13 @@ def _autograd_function():
             g = lat.adjoint(prep(g_rho), want_rho0=ctx.needs_input_grad[3], dL_dux=prep(g_ux), dL_duy=prep(g_uy))
             ctx.lat = None
             lat.close()
-            gk = torch.tensor([g[n] for n in lbm.GRAD_NAMES[:4]], dtype=kd, device=kdev)
-            gG = torch.tensor(g["G"], dtype=torch.float64)
-            gs = torch.tensor(g["sigma"], dtype=torch.float64)
-            gr = g["rho0"].to(dtype=rd, device=rdev) if "rho0" in g else None
+            need = ctx.needs_input_grad
+            # a position whose forward input was not a tensor needing grad (a Python float G, say)
+            # gets None, as autograd requires
+            gk = torch.tensor([g[n] for n in lbm.GRAD_NAMES[:4]], dtype=kd, device=kdev) if need[0] else None
+            gG = torch.tensor(g["G"], dtype=torch.float64) if need[1] else None
+            gs = torch.tensor(g["sigma"], dtype=torch.float64) if need[2] else None
+            gr = g["rho0"].to(dtype=rd, device=rdev) if need[3] and "rho0" in g else None
             return gk, gG, gs, gr, None
 
     return LbmRollout
