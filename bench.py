@@ -1,22 +1,32 @@
 """Throughput of the fused shaped-EOS pseudopotential D2Q9 step on one MI355X.
 
-Default workload: static droplet (R=80, tanh rim of width 20) on a 512x512 periodic lattice,
-shaped Peng-Robinson EOS (a=2/49, b=2/21, omega=0.344) at Tr=0.5 with the Smooth vdW-loop
-replacement (alpha=0.3), raised vapor sound speed (k_vap=4), EOS scale 0.25, MRT with
-tau_nu=0.7 and Li forcing with sigma from eps; FP32-shifted storage (rho_ref = rho_v) with
-FP64 mass/momentum reductions every 100 steps, 50k steps; the same in FP64.  One "step" is
-one time step of the whole hot path.  Inputs are resident in HBM before the timed region
-starts.  The roofline figure times the step kernel alone on the stream it is launched on.
+Headline workload: droplet impact on a liquid film between walls (Sec. IV.B), 2048 x 1024,
+droplet R = 100 at V = 0.072 onto a film of height 40 = 0.2 D, Re = 300 (tau_l = 0.644),
+shaped Peng-Robinson EOS (a = 2/49, b = 2/21, omega = 0.344) at Tr = 0.47 (density ratio
+3.07e4) with the Smooth loop (alpha = 0.3), raised vapor slope (k_vap = 4), EOS scale 0.25,
+Li forcing with sigma from eps; FP32-shifted storage (rho_ref = rho_v) with FP64
+mass/momentum reductions.  One "step" is one time step of the whole hot path.  Inputs are
+resident in HBM before the timed region starts.  The same workload in FP64, and the
+512 x 512 static droplet in both precisions, are secondary legs.
 
-Further legs (in the same JSON line): an HBM sweep of larger lattices, the adjoint of the
-droplet loss (cost against the forward, agreement with central differences), a plain
-device-copy calibration and the FP64 CPU oracle on a bounded sample.
+The roofline figure times the step kernel alone, with HIP events on the stream it is
+launched on.  achieved = algorithmic bytes per launch (80 B per cell update in FP32-shifted,
+144 B in FP64, times the cell updates one launch makes) / average launch time;
+measured_GB/s = the HBM bytes per launch that the committed PMC summary (profiles/) gives
+for that kernel and workload, over the same launch time.
+
+Further legs (in the same JSON line): per-case parity of both full-size workloads against
+the FP64 oracle's stored results, an HBM sweep of larger lattices, the batched planar sweep,
+the finite-difference reference solver, the adjoint of the droplet loss (cost against the
+forward, agreement with central differences), a plain device-copy calibration and the FP64
+CPU oracle on a bounded sample of the headline workload (one thread and all cores).
 
 Prints ONE JSON line (rank 0).  --gpus N with N > 1 exits: the library runs the hot path on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
 import sys
@@ -30,53 +40,176 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + HBM GB/s (%roofline), FP32-shifted vs FP64 D2Q9; adjoint/fwd time"
 # algorithmic bytes per cell update: 8 moving populations read + written, rest population FP64 read + written
 BYTES = {"fp32": 8 * 4 * 2 + 8 * 2, "fp64": 9 * 8 * 2}
-# step kernel of each decomposition (lbm_variant): row march, row block, two-step block
-KERNEL_NAME = {1: "k_step<%s, 0>", 2: "k_step_blk<%s, 0>", 3: "k_step2_blk<%s, 0, false, %s>"}
 STREAM_BYTES = 64 << 20  # the library streams its stores when both population buffers take at most this
+LEGS = ("c3", "c2", "parity", "sweep", "batched", "fd", "adjoint", "cpu")
 
 
-def kernel_name(lbm, var, prec, P):
-    """Name of the step kernel (as rocprofv3 prints it) that advances lattice P in this precision."""
-    t = "float" if prec == "fp32" else "double"
-    if var != lbm.VARIANT_BLOCK2:
-        return KERNEL_NAME[var] % t
-    return KERNEL_NAME[var] % (t, "true" if 2 * lbm.layout(P)[1] <= STREAM_BYTES else "false")
-
-EOS_KW = dict(base=1, a=2 / 49, b=2 / 21, R=1.0, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
-TAU = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]
+def _prec_name(prec_id, lbm):
+    return "fp32" if prec_id == lbm.FP32_SHIFTED else "fp64"
 
 
-def workload_name(n, R):
+def kernel_name(lbm, P):
+    """Name of the step kernel (as rocprofv3 prints it) that advances lattice P, and its steps per launch."""
+    var = lbm.describe(P)[0]
+    t = "float" if P.prec == lbm.FP32_SHIFTED else "double"
+    if var == lbm.VARIANT_MARCH:
+        return "k_step<%s, 0>" % t, 1
+    if var == lbm.VARIANT_BLOCK:
+        return "k_step_blk<%s, 0>" % t, 1
+    nt = 2 * lbm.layout(P)[1] <= STREAM_BYTES
+    return "k_step2_blk<%s, 0, %s, %s>" % (t, "true" if P.walls else "false", "true" if nt else "false"), 2
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+def drop_impact_lattice(lbm, prec, reduce_every, variant=0):
+    """The headline workload (lbm_inputs.DROP_IMPACT_2048)."""
+    from lbm_inputs import DROP_IMPACT_2048 as R, drop_impact_fields, drop_impact_tau
+
+    e, s = lbm.eos_build(lbm.make_eos(**R["eos"]))
+    rho, ux, uy = drop_impact_fields(R, e.rho_v, e.rho_l)
+    P = lbm.make_params(R["nx"], R["ny"], e, sigma=s, tau=drop_impact_tau(R), prec=prec, walls=True,
+                        rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v, reduce_every=reduce_every, kernel_variant=variant)
+    return lbm.Lattice(P, rho, ux, uy, device="cuda:0"), e
+
+
+def drop_impact_name(e=None):
+    from lbm_inputs import DROP_IMPACT_2048 as R
+
+    ratio = "" if e is None else " (density ratio %.3g)" % (e.rho_l / e.rho_v)
+    return ("droplet impact on a film between walls %dx%d, R=%d, film %d, V=%g, Re=300, shaped PR Tr=0.47%s "
+            "(Smooth alpha=0.3, k_vap=4, scale 0.25), Li forcing" % (R["nx"], R["ny"], R["R"], R["h"], R["V"], ratio))
+
+
+def droplet_lattice(lbm, n, prec, reduce_every, R=None, variant=0):
+    """Static droplet on an n x n periodic lattice (the 512 x 512 workload, or the roofline sweep with R = n/6)."""
+    from lbm_inputs import STATIC_DROPLET_512 as S, droplet_density
+
+    e, s = lbm.eos_build(lbm.make_eos(**S["eos"]))
+    R = n // 6 if R is None else R
+    rho0 = droplet_density(n, n, e.rho_v, e.rho_l, R=R, W=S["W"])
+    P = lbm.make_params(n, n, e, sigma=s, tau=S["tau"], prec=prec, reduce_every=reduce_every, kernel_variant=variant)
+    return lbm.Lattice(P, rho0, device="cuda:0"), e
+
+
+def droplet_name(n, R):
     return ("static droplet %dx%d periodic, R=%d, shaped PR Tr=0.5 (Smooth alpha=0.3, k_vap=4, scale 0.25), "
             "MRT tau_nu=0.7, Li forcing" % (n, n, R))
 
 
-def make_lattice(lbm, n, prec, R=None, reduce_every=100, band_rows=0, variant=0):
-    """Static droplet on an n x n periodic lattice; R defaults to n/6 (the roofline sweep)."""
-    from lbm_inputs import droplet_density
-
-    e, s = lbm.eos_build(lbm.make_eos(**EOS_KW))
-    R = n // 6 if R is None else R
-    rho0 = droplet_density(n, n, e.rho_v, e.rho_l, R=R, W=20)
-    P = lbm.make_params(n, n, e, sigma=s, tau=TAU, prec=lbm.FP32_SHIFTED if prec == "fp32" else lbm.FP64,
-                        reduce_every=reduce_every, band_rows=band_rows, kernel_variant=variant)
-    return lbm.Lattice(P, rho0, device="cuda:0"), e, s, rho0
-
-
+# ---------------------------------------------------------------------------
+# timing
+# ---------------------------------------------------------------------------
 def time_steps(L, steps, warmup):
+    """Seconds for `steps` steps after `warmup` untimed ones, by HIP events on the lattice's stream."""
     import torch
 
     L.step(warmup)
     torch.cuda.synchronize()
-    stream = L.stream
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record(stream)
+    ev0.record(L.stream)
     L.step(steps)
-    ev1.record(stream)
+    ev1.record(L.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return ev0.elapsed_time(ev1) / 1e3, wall
+
+
+def reduce_schedule(steps, warmup, every=100):
+    """Reduction interval for a timed window [warmup, warmup + steps): `every`, shortened to the
+    window length when the window is shorter, so that the window always holds a reducing step; and
+    the number of reducing steps (t % interval == 0) inside it."""
+    re = max(1, min(every, steps))
+    n = (warmup + steps - 1) // re - (warmup - 1) // re if warmup > 0 else (steps - 1) // re + 1
+    return re, n
+
+
+def traffic_rows():
+    """Machine-readable PMC rows of every committed summary: {(kernel, workload, prec): (bytes, sha256)}."""
+    rows = {}
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if line.startswith("| traffic |"):
+                cells = [c.strip() for c in line.strip().strip("|").split("|")]
+                # | traffic | kernel | workload | prec | bytes/launch | sources sha256 |
+                if len(cells) >= 6:
+                    rows[(cells[1], cells[2], cells[3])] = (float(cells[4]), cells[5])
+    return rows
+
+
+def sources_digest() -> str:
+    """SHA-256 over the sources of the step kernels (a PMC summary is valid only for these)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("lbm_device.h", "lbm_step.hip"):
+        with open(os.path.join(ROOT, "paper_2107_06355_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, prec):
+    """HBM bytes per launch of `kernel` on `workload` from the committed PMC summaries, or None when
+    there is none or the kernel sources changed since the counters were taken."""
+    row = traffic_rows().get((kernel, workload, prec))
+    if row is None or row[1] != sources_digest():
+        return None
+    return row[0]
+
+
+def workload_leg(lbm, make, prec, steps, warmup, kernel_steps):
+    """One workload in one precision: the whole hot path over the timed window (reductions
+    included), then the step kernel alone over `kernel_steps` steps for the roofline."""
+    import torch
+
+    re, nred = reduce_schedule(steps, warmup)
+    L, e = make(prec, re)
+    sec, wall = time_steps(L, steps, warmup)
+    L.check()
+    hist = L.history()
+    mass = hist[:, 1]
+    cells = L.nx * L.ny
+    kname, spl = kernel_name(lbm, L.P)
+    L.close()
+    del L
+    L, e = make(prec, 0)
+    ksteps = max(spl, kernel_steps - kernel_steps % spl)
+    ksec, _ = time_steps(L, ksteps, 20)
+    L.check()
+    L.close()
+    del L
+    torch.cuda.empty_cache()
+    pn = _prec_name(prec, lbm)
+    launch_us = ksec * 1e6 / (ksteps // spl)
+    alg = BYTES[pn] * cells * spl  # algorithmic bytes of one launch
+    out = {"MLUPS": cells * steps / sec / 1e6, "ms_per_step": sec * 1e3 / steps, "wall_s": wall,
+           "reduce_every": re, "reductions_in_window": nred,
+           "mass_drift_over_run": float(abs(mass / mass[0] - 1).max()) if len(mass) else None,
+           "kernel": kname, "steps_per_launch": spl, "kernel_steps_timed": ksteps,
+           "avg_launch_us": launch_us, "kernel_us_per_step": launch_us / spl,
+           "algorithmic_bytes_per_launch": alg, "kernel_GB/s": alg / launch_us / 1e3,
+           "frac_hbm_peak": alg / launch_us / 1e3 / HBM_PEAK_GBS}
+    return out
+
+
+def roofline(r, workload, prec, calib):
+    t = measured_traffic(r["kernel"], workload, prec)
+    out = {"bound": "hbm", "achieved": r["kernel_GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": r["kernel_GB/s"] / HBM_PEAK_GBS, "traffic": t,
+           "kernel": r["kernel"], "bytes_per_cell_update": BYTES[prec],
+           "cell_updates_per_launch": r["algorithmic_bytes_per_launch"] // BYTES[prec],
+           "steps_per_launch": r["steps_per_launch"], "avg_launch_us": r["avg_launch_us"],
+           "basis": "achieved = %d B per cell update x cell updates per launch / avg launch time (one-step "
+                    "equivalent: a two-step launch moves the populations through HBM once for two updates)"
+                    % BYTES[prec],
+           "copy_ceiling_frac": r["kernel_GB/s"] / calib["GB/s"]}
+    if t is not None:
+        out["measured_GB/s"] = t / r["avg_launch_us"] / 1e3
+        out["measured_frac"] = out["measured_GB/s"] / HBM_PEAK_GBS
+        out["traffic_over_algorithmic"] = t / r["algorithmic_bytes_per_launch"]
+    return out
 
 
 def copy_bandwidth(nbytes=1 << 31, reps=20):
@@ -101,53 +234,88 @@ def copy_bandwidth(nbytes=1 << 31, reps=20):
     return {"bytes_moved": 2 * nbytes, "GB/s": 2 * nbytes / sec / 1e9, "us": sec * 1e6}
 
 
-def sources_digest() -> str:
-    """SHA-256 over the sources of the step kernels (a PMC summary is valid only for these)."""
-    import hashlib
+# ---------------------------------------------------------------------------
+# per-case parity against the oracle's stored results
+# ---------------------------------------------------------------------------
+def parity_leg(lbm):
+    """Both full-size workloads from their initial state to the oracle's stored step count, in both
+    precisions, compared with the FP64 oracle's stored fields (tests/golden/)."""
+    import numpy as np
+    import torch
 
-    h = hashlib.sha256()
-    for f in ("lbm_device.h", "lbm_step.hip"):
-        with open(os.path.join(ROOT, "paper_2107_06355_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import fullsize
+
+    out = {"targets": {"rho_v_rel_err": 1e-3, "rho_l_rel_err": 1e-5, "u_linf": 1e-5, "mass_drift": 1e-10,
+                       "applies_to": "fp32"}}
+    cases = (("static_droplet_512", lambda prec: droplet_lattice(lbm, 512, prec, 100, R=80)),
+             ("drop_impact_2048", lambda prec: drop_impact_lattice(lbm, prec, 100)))
+    for name, make in cases:
+        if not os.path.exists(fullsize.path(name)):
+            out[name] = None
+            continue
+        g = fullsize.load(name)
+        res = {"workload": droplet_name(512, 80) if name == "static_droplet_512" else drop_impact_name(),
+               "steps": g["steps"]}
+        for prec in (lbm.FP32_SHIFTED, lbm.FP64):
+            L, e = make(prec)
+            L.step(g["steps"])
+            L.check()
+            m = L.macros()
+            rho, ux, uy = (m[k].cpu().numpy() for k in ("rho", "ux", "uy"))
+            h = L.history()
+            r = fullsize.compare(name, g, rho, ux, uy, mass0=g["mass0"])
+            r["mass_drift_history"] = float(np.abs(h[:, 1] / h[0, 1] - 1).max())
+            res[_prec_name(prec, lbm)] = r
+            L.close()
+            del L
+            torch.cuda.empty_cache()
+        out[name] = res
+        f = res["fp32"]
+        print("# parity %s fp32 vs oracle after %d steps: rho_v %.1e rho_l %.1e u_linf %.1e (vapor nodes %.1e); "
+              "fp64 rho %.1e u %.1e" % (name, g["steps"], f["rho_v_rel_err"], f["rho_l_rel_err"], f["u_linf"],
+                                        f["rho_vapor_nodes_max_rel_err"],
+                                        max(res["fp64"]["rho_vapor_nodes_max_rel_err"],
+                                            res["fp64"]["rho_liquid_nodes_max_rel_err"]), res["fp64"]["u_linf"]),
+              file=sys.stderr, flush=True)
+    return out
 
 
-def measured_traffic(kernel, n, prec):
-    """HBM bytes per launch of `kernel` at n x n from the committed PMC summary, or None when there is
-    none for this kernel/size or the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_step_droplet_pmc_hbm_traffic.md")
-    if not os.path.exists(path):
-        return None
-    want = "%s n=%d %s" % (kernel, n, prec)
-    digest = sources_digest()
-    for line in open(path):
-        if line.startswith("| traffic |"):
-            cells = [c.strip() for c in line.strip().strip("|").split("|")]
-            # | traffic | kernel n=.. prec | bytes/launch | sources sha256 |
-            if len(cells) >= 4 and cells[1] == want and cells[3] == digest:
-                return float(cells[2])
-    return None
-
-
-def cpu_baseline(n, steps, R):
-    """The FP64 oracle on a bounded sample of the same workload (single thread)."""
+# ---------------------------------------------------------------------------
+# CPU baseline
+# ---------------------------------------------------------------------------
+def cpu_baseline(steps_one, steps_all):
+    """The FP64 oracle on a bounded sample of the headline workload: `steps_one` time steps single-threaded
+    and `steps_all` with the oracle's OpenMP build on every core this process may use."""
     import oracle as O
-    from lbm_inputs import droplet_density
+    from lbm_inputs import DROP_IMPACT_2048 as R, drop_impact_fields, drop_impact_tau
 
-    eo, so = O.eos_build(O.make_eos(**EOS_KW))
-    rho0 = droplet_density(n, n, eo.rho_v, eo.rho_l, R=R, W=20)
-    L = O.Lattice(O.make_params(n, n, eo, sigma=so, tau=TAU))
-    L.init_eq(rho0)
-    t0 = time.perf_counter()
-    L.run(steps)
-    dt = time.perf_counter() - t0
-    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "%dx%d droplet, %d time steps from the same initial state (FP64, single thread, %.1f s)"
-                      % (n, n, steps, dt), "host": _host_cpu()}
+    eo, so = O.eos_build(O.make_eos(**R["eos"]))
+    rho, ux, uy = drop_impact_fields(R, eo.rho_v, eo.rho_l)
+    P = O.make_params(R["nx"], R["ny"], eo, sigma=so, tau=drop_impact_tau(R), walls=True, rho_wall_lo=eo.rho_l,
+                      rho_wall_hi=eo.rho_v)
+    cells = R["nx"] * R["ny"]
+    legs = {}
+    for omp, steps in ((False, steps_one), (True, steps_all)):
+        L = O.Lattice(P, omp=omp)
+        L.init_eq(rho, ux, uy)
+        t0 = time.perf_counter()
+        L.run(steps)
+        dt = time.perf_counter() - t0
+        legs[omp] = {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": L.threads, "kind": "oracle",
+                     "sample": "%s, first %d time steps (FP64, %s, %.1f s)" % (
+                         drop_impact_name(), steps, "%d threads (OpenMP build)" % L.threads if omp else "single thread",
+                         dt)}
+        del L
+    out = dict(legs[True])
+    out["host"] = _host_cpu()
+    out["single_thread"] = legs[False]
+    print("# cpu baseline (oracle): %.2f MLUPS on %d threads, %.2f MLUPS on one" % (
+        out["value"], out["cores"], legs[False]["value"]), file=sys.stderr, flush=True)
+    return out
 
 
 def _host_cpu() -> str:
-    """CPU model and the CPUs this process may run on (the oracle uses one of them)."""
     model = "unknown CPU"
     try:
         for line in open("/proc/cpuinfo"):
@@ -159,14 +327,50 @@ def _host_cpu() -> str:
     return "%s, %d CPUs available" % (model, len(os.sched_getaffinity(0)))
 
 
+# ---------------------------------------------------------------------------
+# secondary legs
+# ---------------------------------------------------------------------------
+def sweep_leg(lbm, sides, steps, only=""):
+    out = []
+    for side in sides:
+        for prec in (lbm.FP32_SHIFTED, lbm.FP64):
+            pn = _prec_name(prec, lbm)
+            if only and pn != only:
+                continue
+            L, e = droplet_lattice(lbm, side, prec, 0)
+            kname, spl = kernel_name(lbm, L.P)
+            n = max(spl, steps - steps % spl)
+            sec, _ = time_steps(L, n, 20)
+            L.check()
+            cells = side * side
+            gbs = BYTES[pn] * cells * n / sec / 1e9
+            launch_us = sec * 1e6 / (n // spl)
+            row = {"n": side, "prec": pn, "kernel": kname, "MLUPS": cells * n / sec / 1e6, "GB/s": gbs,
+                   "frac_hbm_peak": gbs / HBM_PEAK_GBS, "us_per_step": sec * 1e6 / n, "avg_launch_us": launch_us,
+                   "steps_per_launch": spl}
+            t = measured_traffic(kname, "droplet %dx%d" % (side, side), pn)
+            if t is not None:
+                row["measured_GB/s"] = t / launch_us / 1e3
+                row["measured_frac"] = row["measured_GB/s"] / HBM_PEAK_GBS
+            out.append(row)
+            print("# sweep %s %dx%d: %.0f MLUPS, %.0f GB/s algorithmic (%.1f%%), %.2f us per launch" % (
+                pn, side, side, row["MLUPS"], gbs, 100 * gbs / HBM_PEAK_GBS, launch_us), file=sys.stderr, flush=True)
+            L.close()
+            del L
+            import torch
+
+            torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
     """Adjoint of the static-droplet loss (far-field vapor density + interface width): cost against the
     plain forward, and, in FP64, agreement with central differences of the same forward (h = 1e-6)."""
     import torch
-    from lbm_inputs import droplet_density
+    from lbm_inputs import STATIC_DROPLET_512 as S, droplet_density
     from paper_2107_06355_amd.rollout import vapor_width_loss
 
-    e, s = lbm.eos_build(lbm.make_eos(**EOS_KW))
+    e, s = lbm.eos_build(lbm.make_eos(**S["eos"]))
     rho0 = droplet_density(n, n, e.rho_v, e.rho_l, R=R, W=W0)
 
     def loss_grad(rho):
@@ -176,7 +380,7 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
         return float(L.detach()), r.grad
 
     def run(prec, mode=None, ee=e, G=-1.0, sig=s):
-        P = lbm.make_params(n, n, ee, G=G, sigma=sig, tau=TAU, prec=prec, reduce_every=0)
+        P = lbm.make_params(n, n, ee, G=G, sigma=sig, tau=S["tau"], prec=prec, reduce_every=0)
         lat = lbm.Lattice(P, rho0, device="cuda:0")
         if mode == "checkpoint":
             lat.enable_checkpointing(K, steps)
@@ -184,8 +388,9 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
             lat.enable_recording(steps)
         return lat
 
-    out = {"workload": "static droplet %dx%d R=%d W0=%g, shaped PR Tr=0.5, %d steps; the forward records every "
-                       "step (primary) or checkpoints every %d steps and recomputes" % (n, n, R, W0, steps, K)}
+    out = {"workload": "static droplet %dx%d R=%d W0=%g, shaped PR Tr=0.5, %d steps; the forward checkpoints every "
+                       "%d steps and the adjoint recomputes each segment (the specified mode), or the forward "
+                       "records every step" % (n, n, R, W0, steps, K)}
     for prec, name in ((lbm.FP32_SHIFTED, "fp32"), (lbm.FP64, "fp64")):
         plain = run(prec)
         plain.step(50)
@@ -199,7 +404,7 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
         torch.cuda.synchronize()
         t_fwd = ev[0].elapsed_time(ev[1])
         res = {"forward_ms": t_fwd}
-        for mode in ("record", "checkpoint"):
+        for mode in ("checkpoint", "record"):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
             lat = run(prec, mode)
             ev[0].record(lat.stream)
@@ -222,14 +427,17 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
             lat.close()
             del lat
             torch.cuda.empty_cache()
-        res["grad"] = res["record"]["grad"]
-        res["adjoint_over_forward"] = res["record"]["adjoint_over_forward"]
+        # the specified mode (checkpoint every K steps) is the headline; the recorded one is a variant
+        res["grad"] = res["checkpoint"]["grad"]
+        res["adjoint_over_forward"] = res["checkpoint"]["adjoint_over_forward"]
+        res["adjoint_over_forward_recorded"] = res["record"]["adjoint_over_forward"]
         res["record_vs_checkpoint_max_rel_diff"] = max(
             abs(res["record"]["grad"][k] - res["checkpoint"]["grad"][k]) / max(abs(res["checkpoint"]["grad"][k]), 1e-300)
             for k in res["record"]["grad"])
         out[name] = res
+    out["adjoint_over_forward_checkpointed"] = {k: out[k]["adjoint_over_forward"] for k in ("fp32", "fp64")}
+    out["adjoint_over_forward_recorded"] = {k: out[k]["adjoint_over_forward_recorded"] for k in ("fp32", "fp64")}
     if fd_check:
-        # central differences of the FP64 forward, relative step 1e-6
         base = [e.rho_max, e.p_max, e.rho_min, e.p_min]
 
         def L_of(knots=None, G=-1.0, sig=s):
@@ -250,27 +458,25 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
             fd[nm] = (L_of(kp) - L_of(km)) / (2 * h)
         fd["G"] = (L_of(G=-1.0 + 1e-6) - L_of(G=-1.0 - 1e-6)) / 2e-6
         fd["sigma"] = (L_of(sig=s * (1 + 1e-6)) - L_of(sig=s * (1 - 1e-6))) / (2e-6 * s)
-        g64 = out["fp64"]["grad"]
         out["fd_fp64"] = fd
-        out["rel_err_fp64_vs_fd"] = {k: abs(g64[k] - fd[k]) / max(abs(fd[k]), 1e-300) for k in fd}
-        g32 = out["fp32"]["grad"]
-        out["rel_err_fp32_vs_fd"] = {k: abs(g32[k] - fd[k]) / max(abs(fd[k]), 1e-300) for k in fd}
-        print("# adjoint vs FD (fp64): max rel err %.2e" % max(out["rel_err_fp64_vs_fd"].values()),
+        for name in ("fp64", "fp32"):
+            g = out[name]["grad"]
+            out["rel_err_%s_vs_fd" % name] = {k: abs(g[k] - fd[k]) / max(abs(fd[k]), 1e-300) for k in fd}
+        print("# adjoint vs FD (fp64, checkpointed): max rel err %.2e" % max(out["rel_err_fp64_vs_fd"].values()),
               file=sys.stderr, flush=True)
     return out
 
 
 def batched_leg(lbm, steps=20000, n_lattices=64, seed=0):
     """Uneven batched planar sweep: 64 lattices L_b x 4 (L_b = 4 U{32..512}), Tr ~ U(0.35, 0.95), shaped PR,
-    FP32-shifted, in the library's automatic launch mode (grouped: one launch per step over every lattice's
-    rows); aggregate MLUPS and coexistence error against Maxwell."""
+    FP32-shifted, in the library's automatic launch mode; aggregate MLUPS and coexistence error against Maxwell."""
     import torch
-    from lbm_inputs import batched_planar_recipe, planar_density
+    from lbm_inputs import SHAPED_PR, batched_planar_recipe, planar_density
 
     lengths, trs = batched_planar_recipe(n_lattices=n_lattices, seed=seed)
     P, rhos, eos = [], [], []
     for L, Tr in zip(lengths, trs):
-        e, s = lbm.eos_build(lbm.make_eos(**dict(EOS_KW, Tr=Tr)))
+        e, s = lbm.eos_build(lbm.make_eos(**dict(SHAPED_PR, Tr=Tr)))
         P.append(lbm.make_params(L, 4, e, sigma=s, tau=[1.0] * 9, prec=lbm.FP32_SHIFTED))
         rhos.append(planar_density(L, 4, e.rho_v, e.rho_l, W=20, axis=0))
         eos.append(e)
@@ -331,36 +537,22 @@ def fd_leg(lbm, n=512, steps=2000, dt=0.2):
     return out
 
 
-def drop_impact_leg(lbm, steps=400):
-    """Droplet impact on a film between walls, 2048 x 1024 (R = 100, film 40, V = 0.072, Re = 300, v_r = 1),
-    shaped Peng-Robinson at Tr = 0.47 (density ratio 3.07e4, rims of width 16): time per step of each
-    step-kernel decomposition in both precisions."""
+def drop_impact_variants_leg(lbm, steps=400):
+    """The headline workload on each step-kernel decomposition, both precisions (time per step)."""
     import torch
-    from lbm_inputs import droplet_on_film
 
-    nx, ny, tau_l = 2048, 1024, 0.644
-    e, s = lbm.eos_build(lbm.make_eos(**dict(EOS_KW, Tr=0.47)))
-    rho, ux, uy = droplet_on_film(nx, ny, e.rho_v, e.rho_l, R=100, h=40, gap=4, V=0.072, W=16)
-    out = {"workload": "drop impact %dx%d with walls, shaped PR Tr=0.47 (ratio %.3g), Re=300, %d steps"
-                       % (nx, ny, e.rho_l / e.rho_v, steps)}
-    for prec, name in ((lbm.FP32_SHIFTED, "fp32"), (lbm.FP64, "fp64")):
+    out = {"workload": drop_impact_name()}
+    for prec in (lbm.FP32_SHIFTED, lbm.FP64):
         for variant, vname in ((1, "row_march"), (2, "row_block"), (3, "two_step")):
-            P = lbm.make_params(nx, ny, e, sigma=s, tau=[1] * 7 + [tau_l] * 2, prec=prec, walls=True,
-                                rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v, reduce_every=0, kernel_variant=variant)
-            L = lbm.Lattice(P, rho, ux, uy, device="cuda:0")
-            L.step(20)
-            torch.cuda.synchronize()
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-            ev[0].record(L.stream)
-            L.step(steps)
-            ev[1].record(L.stream)
-            torch.cuda.synchronize()
+            L, e = drop_impact_lattice(lbm, prec, 0, variant)
+            sec, _ = time_steps(L, steps, 20)
             L.check()
-            us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
-            out["%s_%s_us_per_step" % (name, vname)] = us
-            print("# drop impact %s %s: %.2f us/step, %.0f MLUPS" % (name, vname, us, nx * ny / us),
-                  file=sys.stderr, flush=True)
+            us = sec * 1e6 / steps
+            out["%s_%s_us_per_step" % (_prec_name(prec, lbm), vname)] = us
+            print("# drop impact %s %s: %.2f us/step" % (_prec_name(prec, lbm), vname, us), file=sys.stderr, flush=True)
             L.close()
+            del L
+            torch.cuda.empty_cache()
     return out
 
 
@@ -383,44 +575,38 @@ def stability_leg(lbm, steps=3000):
            "map": {k: {"%.2f" % Tr: "".join("S" if m[(Tr, vr)] else "." for vr in S.VRS) for Tr in S.TRS}
                    for k, m in smap.items()},
            "vr": list(S.VRS)}
-    print("# stability map: calibration %.1f s, %d impacts in %.1f s; best ratio %s" % (
-        t1 - t0, runs, t2 - t1, {k: (None if v is None else round(v[0])) for k, v in best.items()}),
-        file=sys.stderr, flush=True)
+    print("# stability map: calibration %.1f s, %d impacts in %.1f s" % (t1 - t0, runs, t2 - t1),
+          file=sys.stderr, flush=True)
     return out
 
 
+# ---------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50000)
-    ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--n", type=int, default=512, help="lattice side of the timed workload")
-    ap.add_argument("--radius", type=int, default=80, help="droplet radius of the timed workload")
-    ap.add_argument("--sweep", default="2048,4096,8192,16384",
-                    help="extra lattice sides for the HBM roofline ('' = none)")
+    ap.add_argument("--steps", type=int, default=2000, help="timed steps of each workload leg")
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--kernel-steps", type=int, default=2000, help="steps over which the step kernel is timed alone")
+    ap.add_argument("--legs", default=",".join(LEGS), help="comma list of: " + ", ".join(LEGS))
+    ap.add_argument("--only", default="", help="fp32 | fp64: time one precision of the workload legs")
+    ap.add_argument("--sweep", default="2048,4096,8192,16384", help="lattice sides of the HBM sweep")
     ap.add_argument("--sweep-steps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=300)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", default="", help="fp32 | fp64: time just one precision of the main workload")
-    ap.add_argument("--band-rows", type=int, default=0, help="rows per wave band (0 = the library's choice)")
-    ap.add_argument("--sweep-band-rows", default="", help="comma list of band heights to time in the sweep")
-    ap.add_argument("--calib-only", action="store_true", help="only measure the plain copy bandwidth")
-    ap.add_argument("--variant", type=int, default=0, help="step-kernel decomposition: 0 auto, 1 row march, 2 row block")
-    ap.add_argument("--sweep-variants", default="", help="comma list of kernel variants for the sweep")
-    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost / gradient leg")
-    ap.add_argument("--adjoint-only", action="store_true")
-    ap.add_argument("--no-adjoint-fd", action="store_true", help="skip the finite-difference check of the adjoint")
+    ap.add_argument("--cpu-steps", type=int, default=20, help="oracle steps of the single-threaded CPU leg")
+    ap.add_argument("--cpu-omp-steps", type=int, default=60, help="oracle steps of the all-core CPU leg")
     ap.add_argument("--adjoint-steps", type=int, default=4000)
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched-lattice sweep leg")
-    ap.add_argument("--batched-only", action="store_true")
+    ap.add_argument("--no-adjoint-fd", action="store_true", help="skip the finite-difference check of the adjoint")
     ap.add_argument("--stability-map", action="store_true", help="add the Sec. IV stability-map leg (~1 min)")
-    ap.add_argument("--drop-impact", action="store_true", help="add the walled drop-impact timing leg (seconds)")
-    ap.add_argument("--no-fd", action="store_true", help="skip the finite-difference reference-solver leg")
+    ap.add_argument("--drop-impact-variants", action="store_true",
+                    help="add the headline workload on each step-kernel decomposition")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the library runs the hot path on ONE GPU; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    legs = [v.strip() for v in args.legs.split(",") if v.strip()]
+    bad = [v for v in legs if v not in LEGS]
+    if bad:
+        ap.error("unknown legs %s" % bad)
 
     import torch
 
@@ -431,116 +617,69 @@ def main():
     calib = copy_bandwidth()
     print("# device copy: %.0f GB/s (read+write, %d MiB buffers)" % (calib["GB/s"], calib["bytes_moved"] >> 21),
           file=sys.stderr, flush=True)
-    if args.calib_only:
-        print(json.dumps({"copy": calib}), flush=True)
-        return
-    if args.batched_only:
-        print(json.dumps({"batched": batched_leg(lbm)}), flush=True)
-        return
-    if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_leg(lbm, steps=args.adjoint_steps, fd_check=not args.no_adjoint_fd)}), flush=True)
-        return
-    n = args.n
+    precs = [p for p in (lbm.FP32_SHIFTED, lbm.FP64) if not args.only or _prec_name(p, lbm) == args.only]
+    out = {}
     res = {}
-    for prec in ("fp32", "fp64"):
-        if args.only and prec != args.only:
+    for leg, make, wname in (
+            ("c3", lambda prec, re: drop_impact_lattice(lbm, prec, re), "drop impact 2048x1024"),
+            ("c2", lambda prec, re: droplet_lattice(lbm, 512, prec, re, R=80), "droplet 512x512")):
+        if leg not in legs:
             continue
-        # the metric: the whole hot path, FP64 mass/momentum reductions every 100 steps
-        L, e, s, _ = make_lattice(lbm, n, prec, R=args.radius, band_rows=args.band_rows, variant=args.variant)
-        var, rows, waves = lbm.describe(L.P)
-        sec, wall = time_steps(L, args.steps, args.warmup)
-        L.check()
-        L.close()
-        del L
-        # the roofline: the step kernel alone (no reduction launches in the timed region)
-        L, e, s, _ = make_lattice(lbm, n, prec, R=args.radius, reduce_every=0, band_rows=args.band_rows,
-                                  variant=args.variant)
-        ksec, _ = time_steps(L, args.steps, args.warmup)
-        L.check()
-        cells = n * n
-        spl = 2 if var == lbm.VARIANT_BLOCK2 else 1  # time steps per launch of the step kernel
-        mlups = cells * args.steps / sec / 1e6
-        kgbs = BYTES[prec] * cells * args.steps / ksec / 1e9
-        res[prec] = {"MLUPS": mlups, "GB/s_step": BYTES[prec] * cells * args.steps / sec / 1e9,
-                     "ms_per_step": sec * 1e3 / args.steps, "wall_s": wall,
-                     "kernel_GB/s": kgbs, "frac_hbm_peak": kgbs / HBM_PEAK_GBS,
-                     "avg_launch_us": ksec * 1e6 / (args.steps / spl), "steps_per_launch": spl,
-                     "kernel": kernel_name(lbm, var, prec, L.P),
-                     "rows_per_block": rows, "waves": waves}
-        print("# %s %dx%d: %.1f MLUPS (%.2f us/step with reductions); step kernel %.2f us = %.1f GB/s "
-              "algorithmic (%.1f%% of 8 TB/s)" % (prec, n, n, mlups, sec * 1e6 / args.steps, ksec * 1e6 / args.steps,
-                                                   kgbs, 100 * kgbs / HBM_PEAK_GBS), file=sys.stderr, flush=True)
-        L.close()
-        del L
-        torch.cuda.empty_cache()
+        res[leg] = {}
+        for prec in precs:
+            pn = _prec_name(prec, lbm)
+            r = workload_leg(lbm, make, prec, args.steps, args.warmup, args.kernel_steps)
+            r["roofline"] = roofline(r, wname, pn, calib)
+            res[leg][pn] = r
+            print("# %s %s: %.1f MLUPS (%.2f us/step, %d reductions in the window); step kernel %.2f us per launch "
+                  "of %d steps = %.0f GB/s algorithmic (%.1f%% of 8 TB/s)%s" % (
+                      wname, pn, r["MLUPS"], r["ms_per_step"] * 1e3, r["reductions_in_window"], r["avg_launch_us"],
+                      r["steps_per_launch"], r["kernel_GB/s"], 100 * r["frac_hbm_peak"],
+                      "" if r["roofline"].get("measured_GB/s") is None else
+                      ", %.0f GB/s measured (%.1f%%)" % (r["roofline"]["measured_GB/s"],
+                                                        100 * r["roofline"]["measured_frac"])),
+                  file=sys.stderr, flush=True)
+    head_leg = "c3" if "c3" in res else ("c2" if "c2" in res else None)
+    if head_leg is not None:
+        pn = "fp32" if "fp32" in res[head_leg] else "fp64"
+        r = res[head_leg][pn]
+        if head_leg == "c3":
+            from lbm_inputs import DROP_IMPACT_2048
 
-    sweep = []
-    bands = [int(v) for v in args.sweep_band_rows.split(",") if v.strip()] or [0]
-    variants = [int(v) for v in args.sweep_variants.split(",") if v.strip()] or [args.variant]
-    combos = [(v, b) for v in variants for b in (bands if v == 1 else [0])]
-    for side in [int(v) for v in args.sweep.split(",") if v.strip()]:
-        for prec in ("fp32", "fp64"):
-            if args.only and prec != args.only:
-                continue
-            for variant, band in combos:
-                L, e, s, _ = make_lattice(lbm, side, prec, reduce_every=0, band_rows=band, variant=variant)
-                sec, wall = time_steps(L, args.sweep_steps, 20)
-                L.check()
-                cells = side * side
-                gbs = BYTES[prec] * cells * args.sweep_steps / sec / 1e9
-                sweep.append({"n": side, "prec": prec, "variant": variant, "band_rows": band,
-                              "MLUPS": cells * args.sweep_steps / sec / 1e6,
-                              "GB/s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
-                              "avg_launch_us": sec * 1e6 / args.sweep_steps})
-                print("# sweep %s %dx%d variant=%d band=%d: %.0f MLUPS, %.0f GB/s (%.1f%%), %.2f us/step" % (
-                    prec, side, side, variant, band, sweep[-1]["MLUPS"], gbs, 100 * gbs / HBM_PEAK_GBS,
-                    sweep[-1]["avg_launch_us"]), file=sys.stderr, flush=True)
-                L.close()
-                del L
-                torch.cuda.empty_cache()
-
-    main_prec = "fp32" if "fp32" in res else "fp64"
-    r = res[main_prec]
-    out = {
-        "metric": METRIC,
-        "value": r["MLUPS"],
-        "unit": "MLUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": r["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if main_prec == "fp32" else "f64",
-        "data": "synthetic",
-        "config": {"workload": workload_name(n, args.radius), "lattice": [n, n], "storage": main_prec,
-                   "reduce_every": 100},
-        "roofline": {"bound": "hbm", "achieved": r["kernel_GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["kernel_GB/s"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(r["kernel"], n, main_prec),
-                     "kernel": r["kernel"], "bytes_per_cell": BYTES[main_prec],
-                     "cell_updates_per_launch": n * n * r["steps_per_launch"],
-                     "steps_per_launch": r["steps_per_launch"], "avg_launch_us": r["avg_launch_us"],
-                     "copy_ceiling_frac": r["kernel_GB/s"] / calib["GB/s"]},
-        "fp64": res.get("fp64"),
-        "fp32": res.get("fp32"),
-        "sweep": sweep,
-        "copy_calibration": calib,
-    }
-    if not args.no_batched:
+            e, _ = lbm.eos_build(lbm.make_eos(**DROP_IMPACT_2048["eos"]))
+            cfg = {"workload": drop_impact_name(e), "lattice": [2048, 1024], "walls": "top and bottom",
+                   "storage": pn, "reduce_every": r["reduce_every"],
+                   "reductions_in_window": r["reductions_in_window"]}
+        else:
+            cfg = {"workload": droplet_name(512, 80), "lattice": [512, 512], "storage": pn,
+                   "reduce_every": r["reduce_every"], "reductions_in_window": r["reductions_in_window"]}
+        out.update({
+            "metric": METRIC, "value": r["MLUPS"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32" if pn == "fp32" else "f64", "data": "synthetic", "config": cfg,
+            "roofline": r["roofline"]})
+    if "c3" in res:
+        out["drop_impact_2048x1024"] = res["c3"]
+    if "c2" in res:
+        out["static_droplet_512x512"] = res["c2"]
+    if "parity" in legs:
+        out["parity"] = parity_leg(lbm)
+    if "sweep" in legs:
+        out["sweep"] = sweep_leg(lbm, [int(v) for v in args.sweep.split(",") if v.strip()], args.sweep_steps, args.only)
+    if "batched" in legs:
         out["batched"] = batched_leg(lbm)
-    if args.stability_map:
-        out["stability"] = stability_leg(lbm)
-    if args.drop_impact:
-        out["drop_impact"] = drop_impact_leg(lbm)
-    if not args.no_fd:
+    if "fd" in legs:
         out["fd"] = fd_leg(lbm)
         out["fd_4096"] = fd_leg(lbm, n=4096, steps=50)
-    if not args.no_adjoint:
+    if args.drop_impact_variants:
+        out["drop_impact_variants"] = drop_impact_variants_leg(lbm)
+    if args.stability_map:
+        out["stability"] = stability_leg(lbm)
+    if "adjoint" in legs:
         out["adjoint"] = adjoint_leg(lbm, steps=args.adjoint_steps, fd_check=not args.no_adjoint_fd)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_steps, args.radius)
+    out["copy_calibration"] = calib
+    if "cpu" in legs:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps, args.cpu_omp_steps)
     print(json.dumps(out), flush=True)
 
 

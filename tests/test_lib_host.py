@@ -144,9 +144,9 @@ def test_library_exports_nothing_beyond_the_header():
 
 
 def test_bench_names_the_kernel_the_library_launches():
-    """bench.py names the timed two-step instance (streaming stores or not) from its own copy of the
-    library's streaming-store threshold; the two copies must agree, or the bench would time and
-    price one instance while the profile summaries describe another."""
+    """bench.py names the timed two-step instance (walls or not, streaming stores or not) from its own
+    copy of the library's streaming-store threshold; the two copies must agree, or the bench would time
+    and price one instance while the profile summaries describe another."""
     import bench
     src = open(os.path.join(ROOT, "paper_2107_06355_amd", "csrc", "lbm_device.h")).read()
     m = re.search(r"constexpr size_t kStreamBytes = \(size_t\)(\d+) << (\d+);", src)
@@ -155,6 +155,21 @@ def test_bench_names_the_kernel_the_library_launches():
     e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
     # 512^2 FP32-shifted: 2 x 10.5 MB -> streamed; 2048 x 1024 FP32-shifted: 2 x 84 MB -> plain
     P = lbm.make_params(512, 512, e, sigma=s, prec=lbm.FP32_SHIFTED)
-    assert bench.kernel_name(lbm, lbm.VARIANT_BLOCK2, "fp32", P) == "k_step2_blk<float, 0, false, true>"
-    P = lbm.make_params(2048, 1024, e, sigma=s, prec=lbm.FP32_SHIFTED)
-    assert bench.kernel_name(lbm, lbm.VARIANT_BLOCK2, "fp32", P) == "k_step2_blk<float, 0, false, false>"
+    assert bench.kernel_name(lbm, P) == ("k_step2_blk<float, 0, false, true>", 2)
+    P = lbm.make_params(2048, 1024, e, sigma=s, prec=lbm.FP32_SHIFTED, walls=True, rho_wall_lo=e.rho_l,
+                        rho_wall_hi=e.rho_v)
+    assert bench.kernel_name(lbm, P) == ("k_step2_blk<float, 0, true, false>", 2)
+    P = lbm.make_params(2048, 1024, e, sigma=s, prec=lbm.FP64, kernel_variant=lbm.VARIANT_BLOCK)
+    assert bench.kernel_name(lbm, P) == ("k_step_blk<double, 0>", 1)
+
+
+def test_bench_reduction_schedule_puts_a_reducing_step_in_every_window():
+    """Whatever --steps and --warmup are, the timed window [warmup, warmup + steps) holds at least one
+    step t with t % reduce_every == 0, and the count the bench reports is the true count."""
+    import bench
+    for steps in (1, 2, 19, 20, 99, 100, 101, 2000, 50000):
+        for warmup in (0, 1, 5, 99, 100, 1000):
+            re_, n = bench.reduce_schedule(steps, warmup)
+            true = sum(1 for t in range(warmup, warmup + steps) if t % re_ == 0)
+            assert n == true >= 1, (steps, warmup, re_, n, true)
+            assert re_ <= 100
