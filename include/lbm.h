@@ -149,6 +149,22 @@ int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int*
 int lbm_init(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes,
              const double* rho0, const double* ux0, const double* uy0, void* stream);
 
+/* lbm_init for callers that cannot allocate (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the workspace is the
+ * library's own static array of 16 MiB per GPU instead of a caller buffer,
+ * and the context is the library's one static context for the current
+ * device.  Allocates nothing, host or device; the caller still passes f_a,
+ * f_b and the initial fields, and lbm_step, lbm_macros and the rest take the
+ * returned context as usual.  Each call re-initialises the device's context
+ * (a later call on the same device ends the earlier one; lbm_destroy on it
+ * does nothing).  LBM_EINVAL when the lattice needs more workspace than
+ * 16 MiB (lbm_layout's ws_bytes: two-step lattices up to about 4096 x 4096
+ * fit), LBM_EHIP when the array's device address cannot be looked up.  The
+ * array keeps the last call's contents, and every call on one GPU shares it:
+ * calls that overlap on one GPU race. */
+int lbm_init_static(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, const double* rho0,
+                    const double* ux0, const double* uy0, void* stream);
+
 /* Advance nsteps time steps (Eq. LBE).  Asynchronous: device-side
  * instability is latched in the workspace and reported by lbm_status_check
  * or lbm_macros.  Steps t with t % reduce_every == 0 also add (t, mass, j_x,

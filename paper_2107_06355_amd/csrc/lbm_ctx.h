@@ -28,6 +28,8 @@ struct lbm_ctx {
     // forward record for the adjoint (lbm_set_recording): every step from 0 on
     void* rec_all;
     int64_t rec_steps;
+    // the per-device context of lbm_init_static (lbm_destroy leaves it alone)
+    bool is_static;
 };
 
 

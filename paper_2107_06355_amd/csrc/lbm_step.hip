@@ -29,6 +29,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "lbm.h"
@@ -618,29 +619,33 @@ int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int*
     return LBM_OK;
 }
 
-int lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes,
-             const double* rho0, const double* ux0, const double* uy0, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Checks of lbm_init's arguments; the workspace size a lattice needs goes to *need.
+int check_init(const lbm_params* p, void* f_a, void* f_b, const double* rho0, size_t* need)
 {
-    if (!out) {
-        lbm_set_error("lbm_init: null context pointer");
-        return LBM_EINVAL;
-    }
-    *out = nullptr;
     int st = validate(p);
     if (st != LBM_OK) return st;
-    if (!f_a || !f_b || f_a == f_b || !ws || !rho0) {
-        lbm_set_error("lbm_init: population buffers must be non-NULL and distinct; ws and rho0 non-NULL");
+    if (!f_a || !f_b || f_a == f_b || !rho0) {
+        lbm_set_error("lbm_init: population buffers must be non-NULL and distinct; rho0 non-NULL");
         return LBM_EINVAL;
     }
     int ld;
+    size_t pop_bytes;
+    lbm_layout(p, &ld, &pop_bytes, need);
+    return LBM_OK;
+}
+
+// Fill context c over the caller's population buffers and the workspace ws, and write the
+// initial state (lbm_init and lbm_init_static)
+int init_ctx(lbm_ctx* c, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes, const double* rho0,
+             const double* ux0, const double* uy0, void* stream)
+{
+    int ld;
     size_t pop_bytes, need;
     lbm_layout(p, &ld, &pop_bytes, &need);
-    if (ws_bytes < need) {
-        lbm_set_error("lbm_init: workspace smaller than lbm_layout requires");
-        return LBM_EINVAL;
-    }
-    lbm_ctx* c = new (std::nothrow) lbm_ctx();
-    if (!c) return LBM_EINVAL;
     c->P = *p;
     c->ld = ld;
     c->plane = (size_t)ld * p->ny;
@@ -663,19 +668,107 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* ws,
     hipStream_t s = (hipStream_t)stream;
     const unsigned init_err[2] = {0u, 0xffffffffu};
     if (!hip_ok(hipMemcpyAsync(c->err, init_err, sizeof(init_err), hipMemcpyHostToDevice, s), "lbm_init error word") ||
-        !hip_ok(hipStreamSynchronize(s), "lbm_init sync")) {
-        delete c;
+        !hip_ok(hipStreamSynchronize(s), "lbm_init sync"))
         return LBM_EHIP;
-    }
     StepArgs A = c->args;
     A.dst = c->buf[0];
     dim3 g((p->nx + 127) / 128, p->ny);
     if (p->prec == LBM_FP32_SHIFTED) hipLaunchKernelGGL(k_init<float>, g, dim3(128), 0, s, A, rho0, ux0, uy0);
     else hipLaunchKernelGGL(k_init<double>, g, dim3(128), 0, s, A, rho0, ux0, uy0);
-    if (!hip_ok(hipGetLastError(), "k_init launch")) {
-        delete c;
-        return LBM_EHIP;
+    if (!hip_ok(hipGetLastError(), "k_init launch")) return LBM_EHIP;
+    return LBM_OK;
+}
+
+// Workspace of lbm_init_static: one file-scope array per GPU (each device the library runs
+// on holds its own copy until the process ends).  Host code never names the array except to
+// look its address up: the name is a host stand-in, and a kernel given it would fault.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+char* g_scratch[kMaxDevices];        // device address of `scratch` on each device, once looked up
+lbm_ctx g_static_ctx[kMaxDevices];   // the one context per device that lbm_init_static hands out
+std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch array (looked up once per device).
+char* scratch_of_current_device(int* dev_out)
+{
+    int dev = -1;
+    if (!hip_ok(hipGetDevice(&dev), "lbm_init_static hipGetDevice")) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        lbm_set_error("lbm_init_static: device index beyond the library's table");
+        return nullptr;
     }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (!hip_ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "lbm_init_static hipGetSymbolAddress") || !ptr)
+            return nullptr;
+        g_scratch[dev] = (char*)ptr;
+    }
+    *dev_out = dev;
+    return g_scratch[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_init(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes,
+             const double* rho0, const double* ux0, const double* uy0, void* stream)
+{
+    if (!out) {
+        lbm_set_error("lbm_init: null context pointer");
+        return LBM_EINVAL;
+    }
+    *out = nullptr;
+    size_t need;
+    int st = check_init(p, f_a, f_b, rho0, &need);
+    if (st != LBM_OK) return st;
+    if (!ws) {
+        lbm_set_error("lbm_init: ws must be non-NULL");
+        return LBM_EINVAL;
+    }
+    if (ws_bytes < need) {
+        lbm_set_error("lbm_init: workspace smaller than lbm_layout requires");
+        return LBM_EINVAL;
+    }
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_EINVAL;
+    st = init_ctx(c, p, f_a, f_b, ws, ws_bytes, rho0, ux0, uy0, stream);
+    if (st != LBM_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_init_static(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, const double* rho0, const double* ux0,
+                    const double* uy0, void* stream)
+{
+    if (!out) {
+        lbm_set_error("lbm_init_static: null context pointer");
+        return LBM_EINVAL;
+    }
+    *out = nullptr;
+    size_t need;
+    int st = check_init(p, f_a, f_b, rho0, &need);
+    if (st != LBM_OK) return st;
+    if (need > kScratchBytes) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "lbm_init_static: the lattice needs %zu bytes of workspace, more than the "
+                                        "library's static %zu", need, kScratchBytes);
+        lbm_set_error(buf);
+        return LBM_EINVAL;
+    }
+    int dev = -1;
+    char* ws = scratch_of_current_device(&dev);
+    if (!ws) return LBM_EHIP;
+    lbm_ctx* c = &g_static_ctx[dev];
+    *c = lbm_ctx();
+    c->is_static = true;
+    st = init_ctx(c, p, f_a, f_b, ws, kScratchBytes, rho0, ux0, uy0, stream);
+    if (st != LBM_OK) return st;
     *out = c;
     return LBM_OK;
 }
@@ -878,6 +971,9 @@ int lbm_load(lbm_ctx* c, const void* src, int64_t step, void* stream)
     return LBM_OK;
 }
 
-void lbm_destroy(lbm_ctx* c) { delete c; }
+void lbm_destroy(lbm_ctx* c)
+{
+    if (c && !c->is_static) delete c;  // the context of lbm_init_static belongs to the library
+}
 
 }  // extern "C"

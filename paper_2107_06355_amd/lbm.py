@@ -83,6 +83,7 @@ def _signatures():
         "lbm_layout": ([C.POINTER(LbmParams), C.POINTER(C.c_int), C.POINTER(sz), C.POINTER(sz)], i),
         "lbm_describe": ([C.POINTER(LbmParams), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], i),
         "lbm_init": ([C.POINTER(vp), C.POINTER(LbmParams), vp, vp, vp, sz, vp, vp, vp, vp], i),
+        "lbm_init_static": ([C.POINTER(vp), C.POINTER(LbmParams), vp, vp, vp, vp, vp, vp], i),
         "lbm_step": ([vp, C.c_int64, vp], i),
         "lbm_status_check": ([vp, vp], i),
         "lbm_macros": ([vp, vp, vp, vp, vp, vp, vp, vp, dp, vp], i),
@@ -228,7 +229,10 @@ def describe(P: LbmParams) -> tuple[int, int, int]:
 class Lattice:
     """A lattice whose populations live in two torch byte tensors on a HIP device."""
 
-    def __init__(self, P: LbmParams, rho0, ux0=None, uy0=None, device="cuda", stream=None):
+    def __init__(self, P: LbmParams, rho0, ux0=None, uy0=None, device="cuda", stream=None,
+                 static_workspace: bool = False):
+        """static_workspace: lbm_init_static (the library's own workspace and context for this device,
+        which the next such Lattice on the device takes over) instead of lbm_init."""
         import torch
 
         self.torch = torch
@@ -239,15 +243,19 @@ class Lattice:
         self.ld, pop_bytes, ws_bytes = layout(P)
         self.pop_bytes = pop_bytes
         self.f = [torch.empty(pop_bytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
-        self.ws = torch.zeros(ws_bytes, dtype=torch.uint8, device=self.device)
+        self.ws = None if static_workspace else torch.zeros(ws_bytes, dtype=torch.uint8, device=self.device)
         shp = (self.ny, self.nx)
         r = self._dev(rho0, shp)
         u = None if ux0 is None else self._dev(ux0, shp)
         v = None if uy0 is None else self._dev(uy0, shp)
         h = C.c_void_p(0)
-        _check(load().lbm_init(C.byref(h), C.byref(P), self.f[0].data_ptr(), self.f[1].data_ptr(),
-                               self.ws.data_ptr(), ws_bytes, r.data_ptr(), u.data_ptr() if u is not None else None,
-                               v.data_ptr() if v is not None else None, self._s()), "lbm_init")
+        up, vp_ = (u.data_ptr() if u is not None else None), (v.data_ptr() if v is not None else None)
+        if static_workspace:
+            _check(load().lbm_init_static(C.byref(h), C.byref(P), self.f[0].data_ptr(), self.f[1].data_ptr(),
+                                          r.data_ptr(), up, vp_, self._s()), "lbm_init_static")
+        else:
+            _check(load().lbm_init(C.byref(h), C.byref(P), self.f[0].data_ptr(), self.f[1].data_ptr(),
+                                   self.ws.data_ptr(), ws_bytes, r.data_ptr(), up, vp_, self._s()), "lbm_init")
         self._keep = (r, u, v)
         self._h = h
 
