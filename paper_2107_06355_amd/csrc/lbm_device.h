@@ -133,6 +133,10 @@ struct StepArgs {
     int nx, ny, ld, walls;
     int strips, seg_h, nseg, nwork;
     int var_tau, blk;        // blk: 1 = row-block (LDS) kernel, 0 = row-march kernel
+    // two-step tiles (k_step2_blk): strips and bands of the lattice, patch columns, and
+    // whether the tiles run in patch order (host-computed: no integer division per workgroup)
+    int strips2, bands2, pcols2, patched;
+    unsigned pcols2_magic;   // ceil(2^32 / pcols2): p / pcols2 = umulhi(p, magic) for the p used
     double G, sigma;
     double s[9];             // relaxation rates 1/tau
     double tau_v, dtau_drho, tau_lo, tau_hi, rho_v_tau;
@@ -563,6 +567,41 @@ constexpr int k2WavesOf = sizeof(T) == 4 ? 16 : LBM_K2_WAVES_F64;
 inline int k2waves_of_prec(int prec) { return prec == LBM_FP32_SHIFTED ? k2WavesOf<float> : k2WavesOf<double>; }
 constexpr int k2Cols = 64 - 6;
 
+// Order of the two-step tiles within the range of tiles one XCD runs (k_step2_blk maps
+// blockIdx to XCD-contiguous ranges): patches of 8 strips x 8 bands, patch rows from the top,
+// patches left to right, tiles band-major inside a patch; slots of edge patches beyond the
+// lattice have no tile and return at once.  The 64 workgroups an XCD runs at once (32 CUs x 2)
+// then cover one patch, and the three-node ring each tile re-reads above, below and beside it
+// belongs to tiles of the same patch that were just loaded into that XCD's L2.  Band-major
+// order over whole lattice rows leaves the ring rows above and below to HBM once a lattice
+// row of tiles outgrows the L2.  Measured at 8192^2 (MI355X, PMC), band-major -> patches:
+// FP64 reads 144 -> 84 B per cell and launch, FP32 63 -> 45 B (the floor is 72 and 40).
+constexpr int kPatchW = 8, kPatchH = 8;
+// Lattices of at most this many tiles run in one or two rounds of the chip's 512 workgroup
+// slots; their tile order does not decide what the L2 holds, and they keep band-major order.
+// So do lattices under two patches wide: a band then holds fewer than 16 tiles, band-major
+// order already keeps the ring in L2, and patches would leave many slots empty.
+constexpr int kPatchMinTiles = 1024;
+inline int patch_grid(int strips, int bands, bool patched)
+{
+    if (!patched) return (strips * bands + 7) & ~7;
+    return ((strips + kPatchW - 1) / kPatchW) * ((bands + kPatchH - 1) / kPatchH) * kPatchW * kPatchH;
+}
+// tile of XCD-contiguous slot `logical`; false when the slot has none
+__device__ __forceinline__ bool two_step_tile(const StepArgs& A, int logical, int& strip, int& band)
+{
+    if (A.patched) {
+        const int p = logical / (kPatchW * kPatchH), w = logical % (kPatchW * kPatchH);
+        const int pr = (int)__umulhi((unsigned)p, A.pcols2_magic), pc = p - pr * A.pcols2;
+        strip = pc * kPatchW + w % kPatchW;
+        band = pr * kPatchH + w / kPatchW;
+        return strip < A.strips2 && band < A.bands2;
+    }
+    band = logical / A.strips2;
+    strip = logical - band * A.strips2;
+    return logical < A.strips2 * A.bands2;
+}
+
 // LDS of one two-step tile
 template <typename T>
 struct Step2Lds {
@@ -593,9 +632,10 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
     L.valid = d <= 3;
     L.interior = d == 0;
     // columns of lanes with dl <= 3 lie in [-3, nx + 2]: one wrap each way unless nx < 3
+    // (lattices 1 or 2 wide: x mod 2 = (x + 4) & 1 for x >= -4; no integer division)
     int x = x0 - 3 + l;
     if (A.nx >= 3) x = x < 0 ? x + A.nx : (x >= A.nx ? x - A.nx : x);
-    else x = (x % A.nx + A.nx) % A.nx;
+    else x = A.nx == 1 ? 0 : ((x + 4) & 1);
     if (dl > 3) x = 0;
     L.x = x;
     L.xm = x == 0 ? A.nx - 1 : x - 1;
@@ -606,9 +646,11 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
     // carries none of this (its scalar registers are the occupancy limit).
     const bool walls = WALLS && A.walls;
     const bool fluid = !walls || (r >= 0 && r < A.ny);
-    // r lies in [-3, ny + 2] for every wave: one wrap each way unless ny < 3
+    // r lies in [-3, ny + 2] for every wave: one wrap each way unless ny < 3 (then r >= -3, and
+    // r mod 2 = (r + 4) & 1)
     const int rw = walls ? r
-                         : (A.ny >= 3 ? (r < 0 ? r + A.ny : (r >= A.ny ? r - A.ny : r)) : (r % A.ny + A.ny) % A.ny);
+                         : (A.ny >= 3 ? (r < 0 ? r + A.ny : (r >= A.ny ? r - A.ny : r))
+                                      : (A.ny == 1 ? 0 : ((r + 4) & 1)));
     const T ghost = walls ? (T)(r < 0 ? A.psi_lo : A.psi_hi) : (T)0;
     Acc acc = {0.0, 0.0, 0.0};
 

@@ -219,14 +219,11 @@ __global__ __launch_bounds__(64 * k2WavesOf<T>) __attribute__((amdgpu_waves_per_
 void k_step2_blk(StepArgs A)
 {
     __shared__ Step2Lds<T> S;
-    constexpr int rows = k2WavesOf<T> - 6;
-    const int strips = (A.nx + k2Cols - 1) / k2Cols, bands = (A.ny + rows - 1) / rows;
     const int nb = gridDim.x;
     const int logical = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);  // XCD-contiguous blocks
-    if (logical >= strips * bands) return;  // whole workgroup leaves together
-    // band-major: the workgroups an XCD runs together cover neighbouring strips and bands
-    // (strip-major order measured 27% more HBM reads at 8192^2 on MI355X)
-    step2_tile<T, MODE, WALLS, NT>(A, logical % strips, logical / strips, S);
+    int strip, band;
+    if (!two_step_tile(A, logical, strip, band)) return;  // whole workgroup leaves together
+    step2_tile<T, MODE, WALLS, NT>(A, strip, band, S);
 }
 
 // Fixed-order FP64 reduction of the per-wave partials, two passes: block b sums
@@ -433,12 +430,19 @@ void fill_args(lbm_ctx* c)
     A.psi_hi = p.walls ? psi_host(p.rho_wall_hi) : 0.0;
     A.partials = c->partials;
     A.err = c->err;
+    const int rows2 = k2waves_of_prec(p.prec) - 6;
+    A.strips2 = (p.nx + k2Cols - 1) / k2Cols;
+    A.bands2 = (p.ny + rows2 - 1) / rows2;
+    A.pcols2 = (A.strips2 + kPatchW - 1) / kPatchW;
+    const long long patches = (long long)A.pcols2 * ((A.bands2 + kPatchH - 1) / kPatchH);
+    A.patched = A.strips2 * A.bands2 > kPatchMinTiles && A.strips2 >= 2 * kPatchW && patches * A.pcols2 < (1LL << 32);
+    // umulhi(p, ceil(2^32/d)) = p / d exactly while p * d < 2^32 (the rounding excess of the
+    // multiplier is below d, so it moves p/d by less than p*d/2^32 / d < 1/d)
+    A.pcols2_magic = (unsigned)((((unsigned long long)1 << 32) + A.pcols2 - 1) / A.pcols2);
     const int blocks = A.blk ? A.nwork / kBlkWaves : (A.nwork + kWaves - 1) / kWaves;
     c->grid = (blocks + 7) & ~7;
     c->blk2 = resolve_variant(p) == LBM_VARIANT_BLOCK2;
-    const int rows2 = k2waves_of_prec(p.prec) - 6;
-    const int blocks2 = ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + rows2 - 1) / rows2);
-    c->grid2 = (blocks2 + 7) & ~7;
+    c->grid2 = patch_grid(c->args.strips2, c->args.bands2, c->args.patched);
 }
 
 bool launch_reduce(lbm_ctx* c, double* out, long long step, int with_step, hipStream_t s)
