@@ -591,8 +591,10 @@ def main():
     ap.add_argument("--only", default="", help="fp32 | fp64: time one precision of the workload legs")
     ap.add_argument("--sweep", default="2048,4096,8192,16384", help="lattice sides of the HBM sweep")
     ap.add_argument("--sweep-steps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=20, help="oracle steps of the single-threaded CPU leg")
-    ap.add_argument("--cpu-omp-steps", type=int, default=60, help="oracle steps of the all-core CPU leg")
+    # about 10 s of host work each (2048 x 1024 FP64 oracle: ~0.36 s per step on one core,
+    # ~0.03 s on 16)
+    ap.add_argument("--cpu-steps", type=int, default=30, help="oracle steps of the single-threaded CPU leg")
+    ap.add_argument("--cpu-omp-steps", type=int, default=360, help="oracle steps of the all-core CPU leg")
     ap.add_argument("--adjoint-steps", type=int, default=4000)
     ap.add_argument("--no-adjoint-fd", action="store_true", help="skip the finite-difference check of the adjoint")
     ap.add_argument("--stability-map", action="store_true", help="add the Sec. IV stability-map leg (~1 min)")

@@ -136,7 +136,10 @@ struct StepArgs {
     // two-step tiles (k_step2_blk): strips and bands of the lattice, patch columns, and
     // whether the tiles run in patch order (host-computed: no integer division per workgroup)
     int strips2, bands2, pcols2, patched;
-    unsigned pcols2_magic;   // ceil(2^32 / pcols2): p / pcols2 = umulhi(p, magic) for the p used
+    int pw_last;             // width in strips of the last patch column (1..8)
+    // ceil(2^32 / d) for d = 8 strips2 (tiles per patch row) and d = pw_last:
+    // n / d = umulhi(n, magic) for every n the kernel divides
+    unsigned prow_magic, pwl_magic;
     double G, sigma;
     double s[9];             // relaxation rates 1/tau
     double tau_v, dtau_drho, tau_lo, tau_hi, rho_v_tau;
@@ -569,33 +572,42 @@ constexpr int k2Cols = 64 - 6;
 
 // Order of the two-step tiles within the range of tiles one XCD runs (k_step2_blk maps
 // blockIdx to XCD-contiguous ranges): patches of 8 strips x 8 bands, patch rows from the top,
-// patches left to right, tiles band-major inside a patch; slots of edge patches beyond the
-// lattice have no tile and return at once.  The 64 workgroups an XCD runs at once (32 CUs x 2)
-// then cover one patch, and the three-node ring each tile re-reads above, below and beside it
-// belongs to tiles of the same patch that were just loaded into that XCD's L2.  Band-major
-// order over whole lattice rows leaves the ring rows above and below to HBM once a lattice
-// row of tiles outgrows the L2.  Measured at 8192^2 (MI355X, PMC), band-major -> patches:
-// FP64 reads 144 -> 84 B per cell and launch, FP32 63 -> 45 B (the floor is 72 and 40).
+// patches left to right, tiles band-major inside a patch.  The last patch column is as wide
+// as the strips left (1 to 8), so a patch row holds 8 x strips slots and only the bands past
+// the lattice in the last patch row are empty slots.  The 64 workgroups an XCD runs at once
+// (32 CUs x 2) then cover one patch, and the three-node ring each tile re-reads above, below
+// and beside it belongs to tiles of the same patch that were just loaded into that XCD's L2.
+// Band-major order over whole lattice rows leaves the ring rows above and below to HBM once
+// a lattice row of tiles outgrows the L2.  Measured at 8192^2 (MI355X, PMC), band-major ->
+// patches: FP64 reads 144 -> 84 B per cell and launch, FP32 63 -> 45 B (the floor is 72 and 40).
 constexpr int kPatchW = 8, kPatchH = 8;
 // Lattices of at most this many tiles run in one or two rounds of the chip's 512 workgroup
 // slots; their tile order does not decide what the L2 holds, and they keep band-major order.
-// So do lattices under two patches wide: a band then holds fewer than 16 tiles, band-major
-// order already keeps the ring in L2, and patches would leave many slots empty.
+// So do lattices under two patches wide or tall: band-major order already keeps their ring
+// in L2, and short lattices would leave most slots of their one patch row empty.
 constexpr int kPatchMinTiles = 1024;
 inline int patch_grid(int strips, int bands, bool patched)
 {
     if (!patched) return (strips * bands + 7) & ~7;
-    return ((strips + kPatchW - 1) / kPatchW) * ((bands + kPatchH - 1) / kPatchH) * kPatchW * kPatchH;
+    return (((bands + kPatchH - 1) / kPatchH) * kPatchH * strips + 7) & ~7;
 }
 // tile of XCD-contiguous slot `logical`; false when the slot has none
 __device__ __forceinline__ bool two_step_tile(const StepArgs& A, int logical, int& strip, int& band)
 {
     if (A.patched) {
-        const int p = logical / (kPatchW * kPatchH), w = logical % (kPatchW * kPatchH);
-        const int pr = (int)__umulhi((unsigned)p, A.pcols2_magic), pc = p - pr * A.pcols2;
-        strip = pc * kPatchW + w % kPatchW;
-        band = pr * kPatchH + w / kPatchW;
-        return strip < A.strips2 && band < A.bands2;
+        const unsigned pr = __umulhi((unsigned)logical, A.prow_magic);  // patch row
+        const int rem = logical - (int)pr * (kPatchH * A.strips2);
+        const int pc = rem / (kPatchW * kPatchH);                         // patch column
+        if (pc < A.pcols2 - 1) {
+            strip = pc * kPatchW + rem % kPatchW;
+            band = (int)pr * kPatchH + (rem % (kPatchW * kPatchH)) / kPatchW;
+        } else {
+            const int w = rem - (A.pcols2 - 1) * (kPatchW * kPatchH);
+            const int q = (int)__umulhi((unsigned)w, A.pwl_magic);
+            strip = (A.pcols2 - 1) * kPatchW + (w - q * A.pw_last);
+            band = (int)pr * kPatchH + q;
+        }
+        return band < A.bands2;
     }
     band = logical / A.strips2;
     strip = logical - band * A.strips2;

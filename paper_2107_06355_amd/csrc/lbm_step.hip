@@ -434,11 +434,17 @@ void fill_args(lbm_ctx* c)
     A.strips2 = (p.nx + k2Cols - 1) / k2Cols;
     A.bands2 = (p.ny + rows2 - 1) / rows2;
     A.pcols2 = (A.strips2 + kPatchW - 1) / kPatchW;
-    const long long patches = (long long)A.pcols2 * ((A.bands2 + kPatchH - 1) / kPatchH);
-    A.patched = A.strips2 * A.bands2 > kPatchMinTiles && A.strips2 >= 2 * kPatchW && patches * A.pcols2 < (1LL << 32);
-    // umulhi(p, ceil(2^32/d)) = p / d exactly while p * d < 2^32 (the rounding excess of the
-    // multiplier is below d, so it moves p/d by less than p*d/2^32 / d < 1/d)
-    A.pcols2_magic = (unsigned)((((unsigned long long)1 << 32) + A.pcols2 - 1) / A.pcols2);
+    A.pw_last = A.strips2 - (A.pcols2 - 1) * kPatchW;
+    // umulhi(n, ceil(2^32/d)) = n / d exactly while n * d < 2^32: the multiplier exceeds
+    // 2^32/d by less than 1, which moves n/d by less than n/2^32 < 1/d.  The kernel divides
+    // slots (below the grid size) by 8 x strips and offsets within a patch row (below 64) by
+    // pw_last.
+    const long long prow = (long long)kPatchH * A.strips2;
+    const long long slots = ((A.bands2 + kPatchH - 1) / kPatchH) * prow;
+    A.patched = A.strips2 * A.bands2 > kPatchMinTiles && A.strips2 >= 2 * kPatchW && A.bands2 >= 2 * kPatchH &&
+                (slots + 8) * prow < (1LL << 32);
+    A.prow_magic = (unsigned)((((unsigned long long)1 << 32) + prow - 1) / prow);
+    A.pwl_magic = (unsigned)((((unsigned long long)1 << 32) + A.pw_last - 1) / A.pw_last);
     const int blocks = A.blk ? A.nwork / kBlkWaves : (A.nwork + kWaves - 1) / kWaves;
     c->grid = (blocks + 7) & ~7;
     c->blk2 = resolve_variant(p) == LBM_VARIANT_BLOCK2;
