@@ -137,8 +137,9 @@ struct StepArgs {
     // whether the tiles run in patch order (host-computed: no integer division per workgroup)
     int strips2, bands2, pcols2, patched;
     int pw_last;             // width in strips of the last patch column (1..8)
-    // ceil(2^32 / d) for d = 8 strips2 (tiles per patch row) and d = pw_last:
-    // n / d = umulhi(n, magic) for every n the kernel divides
+    // ceil(2^32 / d) for d = 8 strips2 (tiles per patch row) and d = pw_last > 1 (2^32 does
+    // not fit for d = 1, which needs no division): n / d = umulhi(n, magic) for every n the
+    // kernel divides
     unsigned prow_magic, pwl_magic;
     double G, sigma;
     double s[9];             // relaxation rates 1/tau
@@ -603,7 +604,7 @@ __device__ __forceinline__ bool two_step_tile(const StepArgs& A, int logical, in
             band = (int)pr * kPatchH + (rem % (kPatchW * kPatchH)) / kPatchW;
         } else {
             const int w = rem - (A.pcols2 - 1) * (kPatchW * kPatchH);
-            const int q = (int)__umulhi((unsigned)w, A.pwl_magic);
+            const int q = A.pw_last == 1 ? w : (int)__umulhi((unsigned)w, A.pwl_magic);
             strip = (A.pcols2 - 1) * kPatchW + (w - q * A.pw_last);
             band = (int)pr * kPatchH + q;
         }

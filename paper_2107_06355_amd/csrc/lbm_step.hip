@@ -444,7 +444,7 @@ void fill_args(lbm_ctx* c)
     A.patched = A.strips2 * A.bands2 > kPatchMinTiles && A.strips2 >= 2 * kPatchW && A.bands2 >= 2 * kPatchH &&
                 (slots + 8) * prow < (1LL << 32);
     A.prow_magic = (unsigned)((((unsigned long long)1 << 32) + prow - 1) / prow);
-    A.pwl_magic = (unsigned)((((unsigned long long)1 << 32) + A.pw_last - 1) / A.pw_last);
+    A.pwl_magic = A.pw_last > 1 ? (unsigned)((((unsigned long long)1 << 32) + A.pw_last - 1) / A.pw_last) : 0u;
     const int blocks = A.blk ? A.nwork / kBlkWaves : (A.nwork + kWaves - 1) / kWaves;
     c->grid = (blocks + 7) & ~7;
     c->blk2 = resolve_variant(p) == LBM_VARIANT_BLOCK2;

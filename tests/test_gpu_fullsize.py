@@ -160,3 +160,39 @@ def test_large_droplet_sampled_nodes(gpu_lib, n, prec_name, variant, steps):
     worst = np.unravel_index(np.argmax(err), err.shape)
     assert err.max() <= _bound(lbm, prec, f_o, e.rho_v, steps), (pts[worst[1]], err.max())
     _check_vapor(lbm, prec, f_g, f_o, e, steps)
+
+
+# Lattices whose two-step tiles run in 8 x 8-tile patches (more than 1024 tiles, at least 16 strips
+# and 16 bands) with a ragged last patch column and patch row: 1000 x 1100 periodic has 18 strips
+# (last patch column 2 strips wide) and 110 FP32 bands (last patch row 6 bands); 986 x 1203 with
+# walls has 17 strips (last column 1 strip wide) and 121 FP32 / 201 FP64 bands (last patch row
+# 1 band).  Every tile must be updated exactly once per launch: the whole field after four
+# two-step launches against eight oracle steps from the same populations.
+@pytest.mark.parametrize("case", [(1000, 1100, False), (986, 1203, True)], ids=["periodic-1000x1100", "walls-986x1203"])
+@pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
+def test_patch_ordered_lattice_whole_field(gpu_lib, prec_name, case):
+    lbm = gpu_lib
+    nx, ny, walls = case
+    prec = lbm.FP64 if prec_name == "fp64" else lbm.FP32_SHIFTED
+    e, s = lbm.eos_build(lbm.make_eos(**EOS_KW))
+    rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=150, W=20)
+    # vapor ghosts on both walls: the bulk next to them is vapor (a liquid ghost beside vapor
+    # makes psi^2 < 0 at the first step, in the oracle as well)
+    kw = dict(walls=True, rho_wall_lo=e.rho_v, rho_wall_hi=e.rho_v) if walls else {}
+    P = lbm.make_params(nx, ny, e, sigma=s, tau=TAU, prec=prec, reduce_every=0, **kw)
+    L = lbm.Lattice(P, rho0, device="cuda:0")
+    assert lbm.describe(P)[0] == lbm.VARIANT_BLOCK2
+    L.step(20)
+    f_t = L.populations().cpu().numpy()
+    L.step(8)
+    L.check()
+    f_g = L.populations().cpu().numpy()
+    L.close()
+    eo, so = O.eos_build(O.make_eos(**EOS_KW))
+    okw = dict(walls=True, rho_wall_lo=eo.rho_v, rho_wall_hi=eo.rho_v) if walls else {}
+    OL = O.Lattice(O.make_params(nx, ny, eo, sigma=so, tau=TAU, **okw), omp=True)
+    OL.set_f(f_t)
+    OL.run(8)
+    f_o = OL.get_f()
+    assert np.abs(f_g - f_o).max() <= _bound(lbm, prec, f_o, e.rho_v, 8)
+    _check_vapor(lbm, prec, f_g, f_o, e, 8)
