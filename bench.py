@@ -50,14 +50,15 @@ def _prec_name(prec_id, lbm):
 
 def kernel_name(lbm, P):
     """Name of the step kernel (as rocprofv3 prints it) that advances lattice P, and its steps per launch."""
-    var = lbm.describe(P)[0]
+    var, rows, waves = lbm.describe(P)
     t = "float" if P.prec == lbm.FP32_SHIFTED else "double"
     if var == lbm.VARIANT_MARCH:
         return "k_step<%s, 0>" % t, 1
     if var == lbm.VARIANT_BLOCK:
         return "k_step_blk<%s, 0>" % t, 1
     nt = 2 * lbm.layout(P)[1] <= STREAM_BYTES
-    return "k_step2_blk<%s, 0, %s, %s>" % (t, "true" if P.walls else "false", "true" if nt else "false"), 2
+    kern = "k_step2_rows2" if rows + 6 == 2 * waves else "k_step2_blk"  # two rows per wavefront, or one
+    return "%s<%s, 0, %s, %s>" % (kern, t, "true" if P.walls else "false", "true" if nt else "false"), 2
 
 
 # ---------------------------------------------------------------------------

@@ -57,11 +57,12 @@ typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_prec;
  * MARCH: one wavefront marches up a band of rows of a 62-column strip with
  * two rows of loads in flight; BLOCK: a 12-wavefront workgroup loads 12 rows
  * of a strip, one per wavefront, and shares psi through LDS; BLOCK2: a
- * 16-wavefront (FP32) or 12-wavefront (FP64) workgroup advances a 58 x 10 or
- * 58 x 6 tile by two time steps per launch and keeps the intermediate
- * populations in LDS (temporal blocking; a reducing step ends a launch, and
- * checkpoint boundaries and odd counts run single steps on BLOCK).  AUTO is
- * BLOCK2. */
+ * workgroup advances a tile 58 columns wide by two time steps per launch and
+ * keeps the intermediate populations in LDS (temporal blocking; a reducing
+ * step ends a launch, and checkpoint boundaries and odd counts run single
+ * steps on BLOCK).  The tile: FP64, 8 wavefronts of two rows each, 10 rows;
+ * FP32, 16 wavefronts of one row, 10 rows, or on lattices of at least 4096
+ * such tiles 12 wavefronts of two rows, 18 rows.  AUTO is BLOCK2. */
 typedef enum {
     LBM_VARIANT_AUTO = 0,
     LBM_VARIANT_MARCH = 1,
@@ -136,7 +137,9 @@ typedef struct lbm_ctx lbm_ctx;
 int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* ws_bytes_out);
 
 /* Which step-kernel decomposition the parameters select (the automatic
- * choice resolved), the rows per band or block, and the wavefront count. */
+ * choice resolved), the rows per band or block, and the wavefront count; for
+ * BLOCK2 the output rows of a two-step tile and the wavefronts of its
+ * workgroup (rows + 6 = wavefronts x rows per wavefront). */
 int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int* waves_out);
 
 /* Create a context over caller buffers f_a, f_b (lbm_layout bytes each) and

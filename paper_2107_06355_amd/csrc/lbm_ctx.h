@@ -21,6 +21,7 @@ struct lbm_ctx {
     int64_t hist_count;
     int grid;
     int blk2, grid2;  // LBM_VARIANT_BLOCK2: two-step launches and their grid
+    bool rows2;       // two-step tiles with two rows per wave (k_step2_rows2)
     // checkpoints for the adjoint: the state f*(t) at every t = K*slot
     void* ckpt;
     int64_t ckpt_slots;

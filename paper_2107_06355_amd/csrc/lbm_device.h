@@ -570,6 +570,35 @@ template <typename T>
 constexpr int k2WavesOf = sizeof(T) == 4 ? 16 : LBM_K2_WAVES_F64;
 inline int k2waves_of_prec(int prec) { return prec == LBM_FP32_SHIFTED ? k2WavesOf<float> : k2WavesOf<double>; }
 constexpr int k2Cols = 64 - 6;
+// Two rows per wave (step2_tile_rows, k_step2_rows2): a workgroup of NW waves holds the 2 NW
+// rows of its tile grown by 3 (wave k holds rows k and k + NW), so the tile is 2 NW - 6 rows
+// tall and the ring rows both steps recompute are a smaller share of its work: per output
+// row, 2.4 collisions and 2.8 pulls for 16 waves x 1 row, 2.2 and 2.4 for 12 x 2.  FP32: 12
+// waves (18-row tiles, 63 KB of LDS, two workgroups per CU); FP64: 8 waves (10-row tiles
+// instead of the 6 rows of 12 x 1, 73 KB, two per CU).  Measured on MI355X (two A/B runs per
+// precision): FP64 2048^2 .. 16384^2 8.5 - 17% faster, 512^2 8% faster, the walled 2048 x 1024
+// impact 2%; FP32 4096^2 .. 16384^2 13 - 17% faster, 2048^2 2.5%, but the impact lattice (4
+// rounds and 4 workgroups of the chip's 512 slots) no faster and 512^2 (261 tiles on 256 CUs)
+// 30% slower.  So FP32 takes two-row tiles on lattices of at least kRows2MinTiles of them.
+template <typename T>
+constexpr int k2rWavesOf = sizeof(T) == 4 ? 12 : 8;
+template <typename T>
+constexpr int k2rRowsOf = 2 * k2rWavesOf<T> - 6;
+constexpr int kRows2MinTiles = 4096;
+// waves per workgroup and output rows of the single-lattice two-step tile, and whether it
+// has two rows per wave
+struct TwoStepShape {
+    int waves, rows;
+    bool rows2;
+};
+inline TwoStepShape two_step_shape(const lbm_params& p)
+{
+    if (p.prec != LBM_FP32_SHIFTED) return {k2rWavesOf<double>, k2rRowsOf<double>, true};
+    const long long strips = (p.nx + k2Cols - 1) / k2Cols;
+    if (strips * ((p.ny + k2rRowsOf<float> - 1) / k2rRowsOf<float>) >= kRows2MinTiles)
+        return {k2rWavesOf<float>, k2rRowsOf<float>, true};
+    return {k2WavesOf<float>, k2WavesOf<float> - 6, false};
+}
 
 // Order of the two-step tiles within the range of tiles one XCD runs (k_step2_blk maps
 // blockIdx to XCD-contiguous ranges): patches of 8 strips x 8 bands, patch rows from the top,
@@ -760,6 +789,185 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
         const double m = wave_sum(acc.m), jx = wave_sum(acc.x), jy = wave_sum(acc.y);
         if (l == 0) {
             const size_t w = ((size_t)band * ((A.nx + k2Cols - 1) / k2Cols) + strip) * k2WavesOf<T> + k;
+            A.partials[3 * w + 0] = m;
+            A.partials[3 * w + 1] = jx;
+            A.partials[3 * w + 2] = jy;
+        }
+    }
+}
+
+template <typename T, int NW, int RPW>
+struct Step2RowsLds {
+    static constexpr int NR = NW * RPW;  // rows of the tile grown by 3
+    DevEos eos;                          // the lattice's EOS record (read by node_psi)
+    T sps[NR][64];                       // psi of the tile grown by 3 (step t), then by 1 (step t+1)
+    T smv[8][NR - 2][64];                // post-collision moving populations of step t (tile grown by 2)
+    double sg0[NR - 2][64];              // and their FP64 rest population
+};
+
+// step2_tile with RPW rows per wave: a workgroup of NW waves holds the NW * RPW rows of the
+// tile grown by 3 (wave k holds rows k + j NW, j < RPW), in the same four phases and with the
+// same node arithmetic.  The rows of one wave are processed one after the other inside each
+// phase; their loads are issued together.
+template <typename T, int MODE, bool WALLS, bool NT, int NW, int RPW>
+__device__ __forceinline__ void step2_tile_rows(const StepArgs& A, int strip, int band, Step2RowsLds<T, NW, RPW>& S)
+{
+    constexpr int NR = NW * RPW;
+    auto& sps = S.sps;
+    auto& smv = S.smv;
+    auto& sg0 = S.sg0;
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    constexpr int k2Rows = NR - 6;
+    const int x0 = strip * k2Cols, y0 = band * k2Rows;
+    const int W = min(k2Cols, A.nx - x0), H = min(k2Rows, A.ny - y0);
+    // distance of this lane's column from the output tile
+    const int dl = l < 3 ? 3 - l : (l > W + 2 ? l - (W + 2) : 0);
+    Lane L;
+    L.lane = l;
+    L.valid = true;
+    L.interior = true;
+    // columns of lanes with dl <= 3 lie in [-3, nx + 2]: one wrap each way unless nx < 3
+    // (lattices 1 or 2 wide: x mod 2 = (x + 4) & 1 for x >= -4; no integer division)
+    int x = x0 - 3 + l;
+    if (A.nx >= 3) x = x < 0 ? x + A.nx : (x >= A.nx ? x - A.nx : x);
+    else x = A.nx == 1 ? 0 : ((x + 4) & 1);
+    if (dl > 3) x = 0;
+    L.x = x;
+    L.xm = x == 0 ? A.nx - 1 : x - 1;
+    L.xp = x == A.nx - 1 ? 0 : x + 1;
+    const bool walls = WALLS && A.walls;
+    // per row kk of this wave (kk = k + j NW): distance from the output tile, unwrapped lattice
+    // row (in [0, ny) on the output tile), wrapped row, fluid.  Recomputed where needed (scalar
+    // arithmetic) rather than held across the barriers.
+    auto dk_of = [&](int kk) { return kk < 3 ? 3 - kk : (kk > H + 2 ? kk - (H + 2) : 0); };
+    auto r_of = [&](int kk) { return y0 - 3 + kk; };
+    auto fluid_of = [&](int r) { return !walls || (r >= 0 && r < A.ny); };
+    // r lies in [-3, ny + 2] for the rows that load: one wrap each way unless ny < 3 (then
+    // r >= -3, and r mod 2 = (r + 4) & 1)
+    auto rw_of = [&](int r) {
+        return walls ? r
+                     : (A.ny >= 3 ? (r < 0 ? r + A.ny : (r >= A.ny ? r - A.ny : r))
+                                  : (A.ny == 1 ? 0 : ((r + 4) & 1)));
+    };
+    auto ghost_of = [&](int r) { return walls ? (T)(r < 0 ? A.psi_lo : A.psi_hi) : (T)0; };
+    Acc acc = {0.0, 0.0, 0.0};
+
+    // 1. step t: pull, rho, psi.  The EOS record is copied to LDS while the pull is in
+    //    flight: psi reads it there in phases 1 and 3, instead of the launch holding it in
+    //    scalar registers (which spills them to vector lanes at this occupancy).
+    if (threadIdx.x == 0) S.eos = A.eos;
+    Row<T> R[RPW];
+    double dr[RPW];
+    T ps[RPW];
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+        const int kk = k + j * NW, r = r_of(kk);
+        dr[j] = 0.0;
+        ps[j] = (T)0;
+        if (dk_of(kk) <= 3 && dl <= 3 && fluid_of(r)) {
+            const View<T> V = make_view<T>(A.src, A.plane);
+            pull<T>(V, A, L.x, L.xm, L.xp, rw_of(r), R[j].g0, R[j].g);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+        const int kk = k + j * NW, r = r_of(kk);
+        if (dk_of(kk) <= 3 && dl <= 3) {
+            if (fluid_of(r)) {
+                dr[j] = node_drho<T>(R[j].g0, R[j].g);
+                ps[j] = node_psi<T>(A, S.eos, dr[j], true);
+            } else {
+                ps[j] = ghost_of(r);
+            }
+        }
+        sps[kk][l] = ps[j];
+    }
+    __syncthreads();
+    // 2. step t: collide on the tile grown by 2, post-collision state to LDS
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+        const int kk = k + j * NW, r = r_of(kk), dk = dk_of(kk);
+        if (dk <= 2 && dl <= 2 && fluid_of(r)) {
+            T Ftx, Fty;
+            force_tilde<T>(A, sps[kk - 1][l - 1], sps[kk - 1][l], sps[kk - 1][l + 1], sps[kk][l - 1], sps[kk][l + 1],
+                           sps[kk + 1][l - 1], sps[kk + 1][l], sps[kk + 1][l + 1], Ftx, Fty);
+            T o[9];
+            double o0;
+            node_collide<T, MODE_STEP>(A, L, rw_of(r), R[j], dr[j], ps[j], Ftx, Fty, acc, o, o0);
+#pragma unroll
+            for (int i = 1; i < 9; ++i) smv[i - 1][kk - 1][l] = o[i];
+            sg0[kk - 1][l] = o0;
+            if (MODE == MODE_RECORD && dk == 0 && dl == 0) {
+                T jx, jy;
+                node_j<T>(R[j].g, jx, jy);
+                record_node<T>(A.rec, A.rec_plane, (size_t)r * A.nx + x, (T)dr[j], jx, jy, ps[j]);
+            }
+        }
+    }
+    __syncthreads();
+    // 3. step t+1: pull from LDS on the tile grown by 1 (f_i(x) = f*_i(x - c_i), or the node's
+    //    own opposite population where x - c_i is solid), psi(t+1)
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+        const int kk = k + j * NW, r = r_of(kk), dk = dk_of(kk);
+        if (dk <= 1 && dl <= 1 && fluid_of(r)) {
+            const int q = kk - 1;  // LDS row of this row
+            const bool bot = walls && r == 0, top = walls && r == A.ny - 1;
+            R[j].g0 = sg0[q][l];
+            R[j].g[1] = smv[0][q][l - 1];
+            R[j].g[3] = smv[2][q][l + 1];
+            if (!bot) {
+                R[j].g[2] = smv[1][q - 1][l];
+                R[j].g[5] = smv[4][q - 1][l - 1];
+                R[j].g[6] = smv[5][q - 1][l + 1];
+            } else {
+                R[j].g[2] = smv[3][q][l];
+                R[j].g[5] = smv[6][q][l];
+                R[j].g[6] = smv[7][q][l];
+            }
+            if (!top) {
+                R[j].g[4] = smv[3][q + 1][l];
+                R[j].g[7] = smv[6][q + 1][l + 1];
+                R[j].g[8] = smv[7][q + 1][l - 1];
+            } else {
+                R[j].g[4] = smv[1][q][l];
+                R[j].g[7] = smv[4][q][l];
+                R[j].g[8] = smv[5][q][l];
+            }
+            dr[j] = node_drho<T>(R[j].g0, R[j].g);
+            ps[j] = node_psi<T>(A, S.eos, dr[j], true, 1);
+            sps[kk][l] = ps[j];
+        } else if (walls && dk <= 1 && dl <= 1) {
+            sps[kk][l] = ghost_of(r);
+        }
+    }
+    __syncthreads();
+    // 4. step t+1: collide on the tile and store (tile rows are fluid rows)
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+        const int kk = k + j * NW, r = r_of(kk);
+        if (dk_of(kk) == 0 && dl == 0) {
+            T Ftx, Fty;
+            force_tilde<T>(A, sps[kk - 1][l - 1], sps[kk - 1][l], sps[kk - 1][l + 1], sps[kk][l - 1], sps[kk][l + 1],
+                           sps[kk + 1][l - 1], sps[kk + 1][l], sps[kk + 1][l + 1], Ftx, Fty);
+            update_node<T, MODE == MODE_STEP_REDUCE ? MODE_STEP_REDUCE : MODE_STEP, NT>(A, L, r, R[j], dr[j], ps[j],
+                                                                                          Ftx, Fty, acc);
+            if (MODE == MODE_RECORD) {
+                T jx, jy;
+                node_j<T>(R[j].g, jx, jy);
+                record_node<T>((char*)A.rec + 4 * A.rec_plane * sizeof(T), A.rec_plane, (size_t)r * A.nx + x,
+                               (T)dr[j], jx, jy, ps[j]);
+            }
+        }
+    }
+    if (MODE == MODE_STEP_REDUCE) {
+        // FP64 mass and momentum of step t+1 (each node once: the tile's own), one partial per
+        // (tile, wave) in tile order
+        const double m = wave_sum(acc.m), jx = wave_sum(acc.x), jy = wave_sum(acc.y);
+        if (l == 0) {
+            const size_t w = ((size_t)band * ((A.nx + k2Cols - 1) / k2Cols) + strip) * NW + k;
             A.partials[3 * w + 0] = m;
             A.partials[3 * w + 1] = jx;
             A.partials[3 * w + 2] = jy;

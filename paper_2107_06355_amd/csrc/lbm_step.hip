@@ -226,6 +226,20 @@ void k_step2_blk(StepArgs A)
     step2_tile<T, MODE, WALLS, NT>(A, strip, band, S);
 }
 
+// The same with two rows per wave (step2_tile_rows; the shape two_step_shape picks): FP32 12
+// waves at two workgroups per CU (6 waves per SIMD), FP64 8 waves (4 per SIMD).
+template <typename T, int MODE, bool WALLS, bool NT = false>
+__global__ __launch_bounds__(64 * k2rWavesOf<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4)))
+void k_step2_rows2(StepArgs A)
+{
+    __shared__ Step2RowsLds<T, k2rWavesOf<T>, 2> S;
+    const int nb = gridDim.x;
+    const int logical = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);  // XCD-contiguous blocks
+    int strip, band;
+    if (!two_step_tile(A, logical, strip, band)) return;  // whole workgroup leaves together
+    step2_tile_rows<T, MODE, WALLS, NT, k2rWavesOf<T>, 2>(A, strip, band, S);
+}
+
 // Fixed-order FP64 reduction of the per-wave partials, two passes: block b sums
 // the contiguous chunk b of the partials (thread-strided, then a tree), and one
 // block sums the block results.  The order depends only on the sizes, so the
@@ -371,8 +385,8 @@ int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk)
 // waves of one two-step launch: (tiles) x (waves per tile), one partial slot each
 int two_step_waves(const lbm_params& p)
 {
-    const int w2 = k2waves_of_prec(p.prec), rows2 = w2 - 6;
-    return ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + rows2 - 1) / rows2) * w2;
+    const TwoStepShape sh = two_step_shape(p);
+    return ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + sh.rows - 1) / sh.rows) * sh.waves;
 }
 
 int partial_slots(const lbm_params& p)
@@ -430,9 +444,10 @@ void fill_args(lbm_ctx* c)
     A.psi_hi = p.walls ? psi_host(p.rho_wall_hi) : 0.0;
     A.partials = c->partials;
     A.err = c->err;
-    const int rows2 = k2waves_of_prec(p.prec) - 6;
+    const TwoStepShape sh = two_step_shape(p);
+    c->rows2 = sh.rows2;
     A.strips2 = (p.nx + k2Cols - 1) / k2Cols;
-    A.bands2 = (p.ny + rows2 - 1) / rows2;
+    A.bands2 = (p.ny + sh.rows - 1) / sh.rows;
     A.pcols2 = (A.strips2 + kPatchW - 1) / kPatchW;
     A.pw_last = A.strips2 - (A.pcols2 - 1) * kPatchW;
     // umulhi(n, ceil(2^32/d)) = n / d exactly while n * d < 2^32: the multiplier exceeds
@@ -506,9 +521,27 @@ bool launch_step2(lbm_ctx* c, void* rec, hipStream_t s, bool reduce = false)
     A.step = c->step;
     A.rec = rec;
     A.rec_plane = (size_t)c->P.nx * c->P.ny;
-    const dim3 g(c->grid2), b(64 * k2WavesOf<T>);
+    const dim3 g(c->grid2), b(64 * (c->rows2 ? k2rWavesOf<T> : k2WavesOf<T>));
     // streaming stores for small lattices (kStreamBytes)
     const bool nt = 2 * c->pop_bytes <= kStreamBytes;
+    if (c->rows2) {
+        if (c->P.walls) {
+            if (rec && nt) hipLaunchKernelGGL((k_step2_rows2<T, MODE_RECORD, true, true>), g, b, 0, s, A);
+            else if (rec) hipLaunchKernelGGL((k_step2_rows2<T, MODE_RECORD, true>), g, b, 0, s, A);
+            else if (reduce && nt) hipLaunchKernelGGL((k_step2_rows2<T, MODE_STEP_REDUCE, true, true>), g, b, 0, s, A);
+            else if (reduce) hipLaunchKernelGGL((k_step2_rows2<T, MODE_STEP_REDUCE, true>), g, b, 0, s, A);
+            else if (nt) hipLaunchKernelGGL((k_step2_rows2<T, MODE_STEP, true, true>), g, b, 0, s, A);
+            else hipLaunchKernelGGL((k_step2_rows2<T, MODE_STEP, true>), g, b, 0, s, A);
+        } else {
+            if (rec && nt) hipLaunchKernelGGL((k_step2_rows2<T, MODE_RECORD, false, true>), g, b, 0, s, A);
+            else if (rec) hipLaunchKernelGGL((k_step2_rows2<T, MODE_RECORD, false>), g, b, 0, s, A);
+            else if (reduce && nt) hipLaunchKernelGGL((k_step2_rows2<T, MODE_STEP_REDUCE, false, true>), g, b, 0, s, A);
+            else if (reduce) hipLaunchKernelGGL((k_step2_rows2<T, MODE_STEP_REDUCE, false>), g, b, 0, s, A);
+            else if (nt) hipLaunchKernelGGL((k_step2_rows2<T, MODE_STEP, false, true>), g, b, 0, s, A);
+            else hipLaunchKernelGGL((k_step2_rows2<T, MODE_STEP, false>), g, b, 0, s, A);
+        }
+        return hip_ok(hipGetLastError(), "k_step2_rows2 launch");
+    }
     if (c->P.walls) {
         if (rec && nt) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true, true>), g, b, 0, s, A);
         else if (rec) hipLaunchKernelGGL((k_step2_blk<T, MODE_RECORD, true>), g, b, 0, s, A);
@@ -623,9 +656,16 @@ int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int*
     }
     int strips, seg_h, nseg, blk;
     const int nw = decompose(*p, &strips, &seg_h, &nseg, &blk);
-    if (variant_out) *variant_out = resolve_variant(*p);
-    if (band_rows_out) *band_rows_out = seg_h;
-    if (waves_out) *waves_out = nw;
+    const int v = resolve_variant(*p);
+    if (variant_out) *variant_out = v;
+    if (v == LBM_VARIANT_BLOCK2) {
+        const TwoStepShape sh = two_step_shape(*p);
+        if (band_rows_out) *band_rows_out = sh.rows;
+        if (waves_out) *waves_out = sh.waves;
+    } else {
+        if (band_rows_out) *band_rows_out = seg_h;
+        if (waves_out) *waves_out = nw;
+    }
     return LBM_OK;
 }
 

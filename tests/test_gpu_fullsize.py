@@ -168,7 +168,11 @@ def test_large_droplet_sampled_nodes(gpu_lib, n, prec_name, variant, steps):
 # walls has 17 strips (last column 1 strip wide) and 121 FP32 / 201 FP64 bands (last patch row
 # 1 band).  Every tile must be updated exactly once per launch: the whole field after four
 # two-step launches against eight oracle steps from the same populations.
-@pytest.mark.parametrize("case", [(1000, 1100, False), (986, 1203, True)], ids=["periodic-1000x1100", "walls-986x1203"])
+# FP64 runs these in tiles of two rows per wavefront (10 rows); FP32 in one-row tiles here, and in
+# two-row tiles (18 rows) on 2100 x 2000 periodic (37 strips, last patch column 5 wide; 112 bands, the
+# last 2 rows tall: 4144 tiles) and 2090 x 2030 with walls (37 strips; 113 bands, the last 14 rows).
+@pytest.mark.parametrize("case", [(1000, 1100, False), (986, 1203, True), (2100, 2000, False), (2090, 2030, True)],
+                         ids=["periodic-1000x1100", "walls-986x1203", "periodic-2100x2000", "walls-2090x2030"])
 @pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
 def test_patch_ordered_lattice_whole_field(gpu_lib, prec_name, case):
     lbm = gpu_lib
@@ -181,7 +185,10 @@ def test_patch_ordered_lattice_whole_field(gpu_lib, prec_name, case):
     kw = dict(walls=True, rho_wall_lo=e.rho_v, rho_wall_hi=e.rho_v) if walls else {}
     P = lbm.make_params(nx, ny, e, sigma=s, tau=TAU, prec=prec, reduce_every=0, **kw)
     L = lbm.Lattice(P, rho0, device="cuda:0")
-    assert lbm.describe(P)[0] == lbm.VARIANT_BLOCK2
+    v, rows, waves = lbm.describe(P)
+    assert v == lbm.VARIANT_BLOCK2
+    assert (rows, waves) == ((10, 16) if (prec == lbm.FP32_SHIFTED and nx < 2048) else
+                             (18, 12) if prec == lbm.FP32_SHIFTED else (10, 8)), (rows, waves)
     L.step(20)
     f_t = L.populations().cpu().numpy()
     L.step(8)

@@ -119,8 +119,9 @@ def test_workspace_holds_the_two_step_partials():
     workspace lbm_layout reports holds them, beside the error word, the per-block sums and the history
     ring, whichever decomposition has more waves."""
     e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
-    for nx, ny, prec, waves, rows in ((512, 512, lbm.FP32_SHIFTED, 16, 10), (512, 512, lbm.FP64, 12, 6),
-                                      (130, 37, lbm.FP64, 12, 6), (7, 3, lbm.FP32_SHIFTED, 16, 10)):
+    for nx, ny, prec, waves, rows in ((512, 512, lbm.FP32_SHIFTED, 16, 10), (512, 512, lbm.FP64, 8, 10),
+                                      (130, 37, lbm.FP64, 8, 10), (7, 3, lbm.FP32_SHIFTED, 16, 10),
+                                      (2048, 2048, lbm.FP32_SHIFTED, 12, 18)):
         P = lbm.make_params(nx, ny, e, sigma=s, prec=prec)
         _, _, ws = lbm.layout(P)
         tiles = -(-nx // 58) * -(-ny // rows)
@@ -161,6 +162,26 @@ def test_bench_names_the_kernel_the_library_launches():
     assert bench.kernel_name(lbm, P) == ("k_step2_blk<float, 0, true, false>", 2)
     P = lbm.make_params(2048, 1024, e, sigma=s, prec=lbm.FP64, kernel_variant=lbm.VARIANT_BLOCK)
     assert bench.kernel_name(lbm, P) == ("k_step_blk<double, 0>", 1)
+    # two rows per wavefront: every FP64 two-step lattice, and FP32 lattices of 4096 or more such tiles
+    P = lbm.make_params(2048, 1024, e, sigma=s, prec=lbm.FP64, walls=True, rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v)
+    assert bench.kernel_name(lbm, P) == ("k_step2_rows2<double, 0, true, false>", 2)
+    P = lbm.make_params(8192, 8192, e, sigma=s, prec=lbm.FP32_SHIFTED)
+    assert bench.kernel_name(lbm, P) == ("k_step2_rows2<float, 0, false, false>", 2)
+
+
+def test_two_step_tile_shape():
+    """lbm_describe reports the two-step tile the library launches: FP64 8 wavefronts of two rows (10-row
+    tiles) on every lattice; FP32 16 wavefronts of one row (10 rows), or 12 of two rows (18 rows) once
+    the lattice holds at least 4096 of those 58 x 18 tiles."""
+    e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
+    P32, P64 = lbm.FP32_SHIFTED, lbm.FP64
+    for nx, ny, prec, want in [(512, 512, P64, (10, 8)), (1, 1, P64, (10, 8)), (2048, 1024, P64, (10, 8)),
+                               (512, 512, P32, (10, 16)), (2048, 1024, P32, (10, 16)),
+                               (2048, 2048, P32, (18, 12)),  # 36 strips x 114 bands = 4104 tiles
+                               (2048, 2030, P32, (10, 16)),  # 36 x 113 = 4068
+                               (8192, 8192, P32, (18, 12))]:
+        v, rows, waves = lbm.describe(lbm.make_params(nx, ny, e, sigma=s, prec=prec))
+        assert v == lbm.VARIANT_BLOCK2 and (rows, waves) == want, (nx, ny, prec, rows, waves)
 
 
 def test_bench_reduction_schedule_puts_a_reducing_step_in_every_window():
