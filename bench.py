@@ -48,30 +48,52 @@ def _prec_name(prec_id, lbm):
     return "fp32" if prec_id == lbm.FP32_SHIFTED else "fp64"
 
 
-def kernel_name(lbm, P):
-    """Name of the step kernel (as rocprofv3 prints it) that advances lattice P, and its steps per launch."""
+# two-step tile height per precision (lbm_params.tile_rows) of the benchmark's lattices: -1 = the
+# fastest of the library's candidates, timed when a lattice is created (--tile-rows sets others)
+TILE_ROWS = {"fp32": -1, "fp64": -1}
+
+
+def _tile_rows(lbm, prec, tile_rows):
+    return TILE_ROWS[_prec_name(prec, lbm)] if tile_rows is None else tile_rows
+
+
+def kernel_name(lbm, P, shape=None):
+    """Name of the step kernel (as rocprofv3 prints it) that advances lattice P, and its steps per launch.
+    shape: (tile rows, wavefronts) of the two-step tile a lattice runs (Lattice.tile_shape()); by default
+    the one lbm_describe reports for P."""
     var, rows, waves = lbm.describe(P)
+    if shape is not None and var == lbm.VARIANT_BLOCK2:
+        rows, waves = shape
     t = "float" if P.prec == lbm.FP32_SHIFTED else "double"
     if var == lbm.VARIANT_MARCH:
         return "k_step<%s, 0>" % t, 1
     if var == lbm.VARIANT_BLOCK:
         return "k_step_blk<%s, 0>" % t, 1
     nt = 2 * lbm.layout(P)[1] <= STREAM_BYTES
-    kern = "k_step2_rows2" if rows + 6 == 2 * waves else "k_step2_blk"  # two rows per wavefront, or one
+    # one row per wavefront: tiles of waves - 6 rows; two: up to 2 waves - 6
+    kern = "k_step2_rows2" if rows > waves - 6 else "k_step2_blk"
     return "%s<%s, 0, %s, %s>" % (kern, t, "true" if P.walls else "false", "true" if nt else "false"), 2
 
 
 # ---------------------------------------------------------------------------
 # workloads
 # ---------------------------------------------------------------------------
-def drop_impact_lattice(lbm, prec, reduce_every, variant=0):
-    """The headline workload (lbm_inputs.DROP_IMPACT_2048)."""
+def tiles_of(lbm, L):
+    """'58xH tiles' of a two-step lattice, else ''."""
+    if lbm.describe(L.P)[0] != lbm.VARIANT_BLOCK2:
+        return ""
+    return "58x%d tiles" % L.tile_shape()[0]
+
+
+def drop_impact_lattice(lbm, prec, reduce_every, variant=0, tile_rows=None):
+    """The headline workload (lbm_inputs.DROP_IMPACT_2048); tile_rows None: TILE_ROWS."""
     from lbm_inputs import DROP_IMPACT_2048 as R, drop_impact_fields, drop_impact_tau
 
     e, s = lbm.eos_build(lbm.make_eos(**R["eos"]))
     rho, ux, uy = drop_impact_fields(R, e.rho_v, e.rho_l)
     P = lbm.make_params(R["nx"], R["ny"], e, sigma=s, tau=drop_impact_tau(R), prec=prec, walls=True,
-                        rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v, reduce_every=reduce_every, kernel_variant=variant)
+                        rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v, reduce_every=reduce_every, kernel_variant=variant,
+                        tile_rows=_tile_rows(lbm, prec, tile_rows))
     return lbm.Lattice(P, rho, ux, uy, device="cuda:0"), e
 
 
@@ -83,14 +105,15 @@ def drop_impact_name(e=None):
             "(Smooth alpha=0.3, k_vap=4, scale 0.25), Li forcing" % (R["nx"], R["ny"], R["R"], R["h"], R["V"], ratio))
 
 
-def droplet_lattice(lbm, n, prec, reduce_every, R=None, variant=0):
+def droplet_lattice(lbm, n, prec, reduce_every, R=None, variant=0, tile_rows=None):
     """Static droplet on an n x n periodic lattice (the 512 x 512 workload, or the roofline sweep with R = n/6)."""
     from lbm_inputs import STATIC_DROPLET_512 as S, droplet_density
 
     e, s = lbm.eos_build(lbm.make_eos(**S["eos"]))
     R = n // 6 if R is None else R
     rho0 = droplet_density(n, n, e.rho_v, e.rho_l, R=R, W=S["W"])
-    P = lbm.make_params(n, n, e, sigma=s, tau=S["tau"], prec=prec, reduce_every=reduce_every, kernel_variant=variant)
+    P = lbm.make_params(n, n, e, sigma=s, tau=S["tau"], prec=prec, reduce_every=reduce_every, kernel_variant=variant,
+                        tile_rows=_tile_rows(lbm, prec, tile_rows))
     return lbm.Lattice(P, rho0, device="cuda:0"), e
 
 
@@ -172,10 +195,13 @@ def workload_leg(lbm, make, prec, steps, warmup, kernel_steps):
     hist = L.history()
     mass = hist[:, 1]
     cells = L.nx * L.ny
-    kname, spl = kernel_name(lbm, L.P)
+    tiles = tiles_of(lbm, L)
+    shape = L.tile_shape() if tiles else None
     L.close()
     del L
-    L, e = make(prec, 0)
+    # the step kernel alone, in the tile shape the window ran
+    L, e = make(prec, 0, shape[0] if shape else 0)
+    kname, spl = kernel_name(lbm, L.P, shape)
     ksteps = max(spl, kernel_steps - kernel_steps % spl)
     ksec, _ = time_steps(L, ksteps, 20)
     L.check()
@@ -188,7 +214,8 @@ def workload_leg(lbm, make, prec, steps, warmup, kernel_steps):
     out = {"MLUPS": cells * steps / sec / 1e6, "ms_per_step": sec * 1e3 / steps, "wall_s": wall,
            "reduce_every": re, "reductions_in_window": nred,
            "mass_drift_over_run": float(abs(mass / mass[0] - 1).max()) if len(mass) else None,
-           "kernel": kname, "steps_per_launch": spl, "kernel_steps_timed": ksteps,
+           "kernel": kname, "tiles": tiles, "steps_per_launch": spl,
+           "kernel_steps_timed": ksteps,
            "avg_launch_us": launch_us, "kernel_us_per_step": launch_us / spl,
            "algorithmic_bytes_per_launch": alg, "kernel_GB/s": alg / launch_us / 1e3,
            "frac_hbm_peak": alg / launch_us / 1e3 / HBM_PEAK_GBS}
@@ -196,10 +223,10 @@ def workload_leg(lbm, make, prec, steps, warmup, kernel_steps):
 
 
 def roofline(r, workload, prec, calib):
-    t = measured_traffic(r["kernel"], workload, prec)
+    t = measured_traffic(r["kernel"], workload + (", " + r["tiles"] if r.get("tiles") else ""), prec)
     out = {"bound": "hbm", "achieved": r["kernel_GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": r["kernel_GB/s"] / HBM_PEAK_GBS, "traffic": t,
-           "kernel": r["kernel"], "bytes_per_cell_update": BYTES[prec],
+           "kernel": r["kernel"], "tiles": r.get("tiles", ""), "bytes_per_cell_update": BYTES[prec],
            "cell_updates_per_launch": r["algorithmic_bytes_per_launch"] // BYTES[prec],
            "steps_per_launch": r["steps_per_launch"], "avg_launch_us": r["avg_launch_us"],
            "basis": "achieved = %d B per cell update x cell updates per launch / avg launch time (one-step "
@@ -339,23 +366,25 @@ def sweep_leg(lbm, sides, steps, only=""):
             if only and pn != only:
                 continue
             L, e = droplet_lattice(lbm, side, prec, 0)
-            kname, spl = kernel_name(lbm, L.P)
+            tiles = tiles_of(lbm, L)
+            kname, spl = kernel_name(lbm, L.P, L.tile_shape() if tiles else None)
             n = max(spl, steps - steps % spl)
             sec, _ = time_steps(L, n, 20)
             L.check()
             cells = side * side
             gbs = BYTES[pn] * cells * n / sec / 1e9
             launch_us = sec * 1e6 / (n // spl)
-            row = {"n": side, "prec": pn, "kernel": kname, "MLUPS": cells * n / sec / 1e6, "GB/s": gbs,
+            row = {"n": side, "prec": pn, "kernel": kname, "tiles": tiles, "MLUPS": cells * n / sec / 1e6, "GB/s": gbs,
                    "frac_hbm_peak": gbs / HBM_PEAK_GBS, "us_per_step": sec * 1e6 / n, "avg_launch_us": launch_us,
                    "steps_per_launch": spl}
-            t = measured_traffic(kname, "droplet %dx%d" % (side, side), pn)
+            t = measured_traffic(kname, "droplet %dx%d" % (side, side) + (", " + tiles if tiles else ""), pn)
             if t is not None:
                 row["measured_GB/s"] = t / launch_us / 1e3
                 row["measured_frac"] = row["measured_GB/s"] / HBM_PEAK_GBS
             out.append(row)
-            print("# sweep %s %dx%d: %.0f MLUPS, %.0f GB/s algorithmic (%.1f%%), %.2f us per launch" % (
-                pn, side, side, row["MLUPS"], gbs, 100 * gbs / HBM_PEAK_GBS, launch_us), file=sys.stderr, flush=True)
+            print("# sweep %s %dx%d: %.0f MLUPS, %.0f GB/s algorithmic (%.1f%%), %.2f us per launch (%s, %s)" % (
+                pn, side, side, row["MLUPS"], gbs, 100 * gbs / HBM_PEAK_GBS, launch_us, kname, tiles),
+                file=sys.stderr, flush=True)
             L.close()
             del L
             import torch
@@ -592,6 +621,9 @@ def main():
     ap.add_argument("--only", default="", help="fp32 | fp64: time one precision of the workload legs")
     ap.add_argument("--sweep", default="2048,4096,8192,16384", help="lattice sides of the HBM sweep")
     ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--tile-rows", default="-1,-1",
+                    help="two-step tile height FP32,FP64 (lbm_params.tile_rows): -1 timed at lattice creation, "
+                         "0 the library's rule, 10..18 / 5..10 a fixed height")
     # about 10 s of host work each (2048 x 1024 FP64 oracle: ~0.36 s per step on one core,
     # ~0.03 s on 16)
     ap.add_argument("--cpu-steps", type=int, default=30, help="oracle steps of the single-threaded CPU leg")
@@ -605,6 +637,11 @@ def main():
     if args.gpus != 1:
         print("bench.py: the library runs the hot path on ONE GPU; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
+        sys.exit(2)
+    try:
+        TILE_ROWS["fp32"], TILE_ROWS["fp64"] = (int(v) for v in args.tile_rows.split(","))
+    except ValueError:
+        print("bench.py: --tile-rows takes two integers, FP32,FP64", file=sys.stderr)
         sys.exit(2)
     legs = [v.strip() for v in args.legs.split(",") if v.strip()]
     bad = [v for v in legs if v not in LEGS]
@@ -624,8 +661,9 @@ def main():
     out = {}
     res = {}
     for leg, make, wname in (
-            ("c3", lambda prec, re: drop_impact_lattice(lbm, prec, re), "drop impact 2048x1024"),
-            ("c2", lambda prec, re: droplet_lattice(lbm, 512, prec, re, R=80), "droplet 512x512")):
+            ("c3", lambda prec, re, h=None: drop_impact_lattice(lbm, prec, re, tile_rows=h), "drop impact 2048x1024"),
+            ("c2", lambda prec, re, h=None: droplet_lattice(lbm, 512, prec, re, R=80, tile_rows=h),
+             "droplet 512x512")):
         if leg not in legs:
             continue
         res[leg] = {}
@@ -635,9 +673,9 @@ def main():
             r["roofline"] = roofline(r, wname, pn, calib)
             res[leg][pn] = r
             print("# %s %s: %.1f MLUPS (%.2f us/step, %d reductions in the window); step kernel %.2f us per launch "
-                  "of %d steps = %.0f GB/s algorithmic (%.1f%% of 8 TB/s)%s" % (
+                  "of %d steps = %.0f GB/s algorithmic (%.1f%% of 8 TB/s; %s, %s)%s" % (
                       wname, pn, r["MLUPS"], r["ms_per_step"] * 1e3, r["reductions_in_window"], r["avg_launch_us"],
-                      r["steps_per_launch"], r["kernel_GB/s"], 100 * r["frac_hbm_peak"],
+                      r["steps_per_launch"], r["kernel_GB/s"], 100 * r["frac_hbm_peak"], r["kernel"], r["tiles"],
                       "" if r["roofline"].get("measured_GB/s") is None else
                       ", %.0f GB/s measured (%.1f%%)" % (r["roofline"]["measured_GB/s"],
                                                         100 * r["roofline"]["measured_frac"])),
@@ -646,16 +684,17 @@ def main():
     if head_leg is not None:
         pn = "fp32" if "fp32" in res[head_leg] else "fp64"
         r = res[head_leg][pn]
+        tiles = {"tiles": r["tiles"], "tile_rows_mode": TILE_ROWS[pn]}
         if head_leg == "c3":
             from lbm_inputs import DROP_IMPACT_2048
 
             e, _ = lbm.eos_build(lbm.make_eos(**DROP_IMPACT_2048["eos"]))
             cfg = {"workload": drop_impact_name(e), "lattice": [2048, 1024], "walls": "top and bottom",
                    "storage": pn, "reduce_every": r["reduce_every"],
-                   "reductions_in_window": r["reductions_in_window"]}
+                   "reductions_in_window": r["reductions_in_window"], **tiles}
         else:
             cfg = {"workload": droplet_name(512, 80), "lattice": [512, 512], "storage": pn,
-                   "reduce_every": r["reduce_every"], "reductions_in_window": r["reductions_in_window"]}
+                   "reduce_every": r["reduce_every"], "reductions_in_window": r["reductions_in_window"], **tiles}
         out.update({
             "metric": METRIC, "value": r["MLUPS"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",

@@ -126,6 +126,13 @@ typedef struct {
     double tau_l, tau_v, rho_v_tau, rho_l_tau; /* Eq. RelaxationTime */
     double rho_ref;      /* shift of the FP32 storage (LBM_FP32_SHIFTED), > 0 */
     lbm_eos eos;         /* built by lbm_eos_build */
+    int tile_rows;       /* LBM_VARIANT_BLOCK2 tile height: 0 = the library's choice (below);
+                          * -1 = the fastest candidate, timed on the device by lbm_init
+                          * (FP32: one-row tiles and two-row heights 14..18; FP64: 7..10);
+                          * > 0 = that height (FP32: 10 = one row per wavefront, 11..18 =
+                          * two rows; FP64: 5..10).  Populations do not depend on it beyond
+                          * the compiler's FMA contraction between the one- and two-row
+                          * kernels; the order of the FP64 reduction partials does. */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -139,7 +146,10 @@ int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* 
 /* Which step-kernel decomposition the parameters select (the automatic
  * choice resolved), the rows per band or block, and the wavefront count; for
  * BLOCK2 the output rows of a two-step tile and the wavefronts of its
- * workgroup (rows + 6 = wavefronts x rows per wavefront). */
+ * workgroup (rows + 6 = wavefronts x rows per wavefront; two rows per
+ * wavefront when rows + 6 < 2 x wavefronts + 1, i.e. rows > wavefronts - 6).
+ * With tile_rows = -1 this is the shape before lbm_init times the candidates:
+ * lbm_tile_shape reports the one a context runs. */
 int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int* waves_out);
 
 /* Create a context over caller buffers f_a, f_b (lbm_layout bytes each) and
@@ -167,6 +177,13 @@ int lbm_init(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, void* ws,
  * calls that overlap on one GPU race. */
 int lbm_init_static(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, const double* rho0,
                     const double* ux0, const double* uy0, void* stream);
+
+/* The two-step tile a context runs (LBM_VARIANT_BLOCK2): output rows and
+ * wavefronts per workgroup, as lbm_describe reports them, after lbm_init's
+ * timing when tile_rows = -1 (lbm_init then times 3 launches of each
+ * candidate on f_b, reading the initial state in f_a, and synchronises the
+ * stream).  LBM_EINVAL for a null context or another variant. */
+int lbm_tile_shape(const lbm_ctx* ctx, int* rows_out, int* waves_out);
 
 /* Advance nsteps time steps (Eq. LBE).  Asynchronous: device-side
  * instability is latched in the workspace and reported by lbm_status_check

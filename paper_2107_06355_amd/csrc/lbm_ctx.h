@@ -22,6 +22,7 @@ struct lbm_ctx {
     int grid;
     int blk2, grid2;  // LBM_VARIANT_BLOCK2: two-step launches and their grid
     bool rows2;       // two-step tiles with two rows per wave (k_step2_rows2)
+    lbmk::TwoStepShape shape;  // the two-step tile it runs (lbm_params.tile_rows; timed for -1)
     // checkpoints for the adjoint: the state f*(t) at every t = K*slot
     void* ckpt;
     int64_t ckpt_slots;

@@ -137,6 +137,7 @@ struct StepArgs {
     // whether the tiles run in patch order (host-computed: no integer division per workgroup)
     int strips2, bands2, pcols2, patched;
     int pw_last;             // width in strips of the last patch column (1..8)
+    int rows2t;              // output rows of a two-step tile with two rows per wave (<= 2 NW - 6)
     // ceil(2^32 / d) for d = 8 strips2 (tiles per patch row) and d = pw_last > 1 (2^32 does
     // not fit for d = 1, which needs no division): n / d = umulhi(n, magic) for every n the
     // kernel divides
@@ -585,19 +586,66 @@ constexpr int k2rWavesOf = sizeof(T) == 4 ? 12 : 8;
 template <typename T>
 constexpr int k2rRowsOf = 2 * k2rWavesOf<T> - 6;
 constexpr int kRows2MinTiles = 4096;
+// Workgroups the chip runs at once with two two-step workgroups per CU (256 CUs).
+constexpr int kTwoStepSlots = 512;
 // waves per workgroup and output rows of the single-lattice two-step tile, and whether it
 // has two rows per wave
 struct TwoStepShape {
     int waves, rows;
     bool rows2;
 };
+// the shape of an explicit tile height h (lbm_params.tile_rows > 0)
+inline TwoStepShape shape_of_height(bool f32, int h)
+{
+    if (f32 && h == k2WavesOf<float> - 6) return {k2WavesOf<float>, h, false};
+    return {f32 ? k2rWavesOf<float> : k2rWavesOf<double>, h, true};
+}
+// Heights lbm_params.tile_rows may name: FP32 10 (one row per wave) .. 18, FP64 5 .. 10.
+inline bool tile_rows_valid(const lbm_params& p)
+{
+    if (p.tile_rows == 0 || p.tile_rows == -1) return true;
+    const bool f32 = p.prec == LBM_FP32_SHIFTED;
+    const int lo = f32 ? k2WavesOf<float> - 6 : k2rRowsOf<double> / 2, hi = f32 ? k2rRowsOf<float> : k2rRowsOf<double>;
+    return p.tile_rows >= lo && p.tile_rows <= hi;
+}
+// The library's choice (tile_rows 0, and the shape before timing for -1): FP64 two-row tiles
+// of 10 rows; FP32 one-row tiles of 10 rows, or two-row tiles of 18 on lattices of at least
+// kRows2MinTiles of them (measured: see k2rWavesOf).
 inline TwoStepShape two_step_shape(const lbm_params& p)
 {
-    if (p.prec != LBM_FP32_SHIFTED) return {k2rWavesOf<double>, k2rRowsOf<double>, true};
+    const bool f32 = p.prec == LBM_FP32_SHIFTED;
+    if (p.tile_rows > 0) return shape_of_height(f32, p.tile_rows);
+    if (!f32) return {k2rWavesOf<double>, k2rRowsOf<double>, true};
     const long long strips = (p.nx + k2Cols - 1) / k2Cols;
     if (strips * ((p.ny + k2rRowsOf<float> - 1) / k2rRowsOf<float>) >= kRows2MinTiles)
         return {k2rWavesOf<float>, k2rRowsOf<float>, true};
     return {k2WavesOf<float>, k2WavesOf<float> - 6, false};
+}
+// Candidates lbm_init times for tile_rows = -1, the library's choice first.  How the tiles of a
+// launch fill the chip's rounds of workgroups, its XCDs and its L2s makes the best height
+// depend on the lattice by up to 9% (measured on MI355X, FP32: the walled 2048 x 1024 impact
+// 47.6 us per launch with 16-row tiles against 49.7 with 18 and 51.2 with one-row tiles;
+// 4096 x 2048 184.5 us with 17 rows against 201.7 with 18 and 213.7 with 16; 8192^2 best with
+// 18).  Lattices the chip runs in one round keep the library's choice.
+constexpr int kMaxShapes = 8;
+inline int two_step_candidates(const lbm_params& p, TwoStepShape out[kMaxShapes])
+{
+    const bool f32 = p.prec == LBM_FP32_SHIFTED;
+    int n = 0;
+    out[n++] = two_step_shape(p);
+    if (p.tile_rows != -1) return n;
+    const long long strips = (p.nx + k2Cols - 1) / k2Cols;
+    const int hmax = f32 ? k2rRowsOf<float> : k2rRowsOf<double>;
+    if (strips * ((p.ny + hmax - 1) / hmax) <= kTwoStepSlots) return n;
+    const int lo = f32 ? hmax - 4 : hmax - 3;
+    auto add = [&](TwoStepShape sh) {
+        for (int i = 0; i < n; ++i)
+            if (out[i].rows == sh.rows && out[i].rows2 == sh.rows2) return;
+        out[n++] = sh;
+    };
+    if (f32) add({k2WavesOf<float>, k2WavesOf<float> - 6, false});
+    for (int h = hmax; h >= lo; --h) add(shape_of_height(f32, h));
+    return n;
 }
 
 // Order of the two-step tiles within the range of tiles one XCD runs (k_step2_blk maps
@@ -818,7 +866,7 @@ __device__ __forceinline__ void step2_tile_rows(const StepArgs& A, int strip, in
     auto& sg0 = S.sg0;
     const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = threadIdx.x & 63;
-    constexpr int k2Rows = NR - 6;
+    const int k2Rows = A.rows2t;  // at most NR - 6
     const int x0 = strip * k2Cols, y0 = band * k2Rows;
     const int W = min(k2Cols, A.nx - x0), H = min(k2Rows, A.ny - y0);
     // distance of this lane's column from the output tile
@@ -1062,6 +1110,10 @@ inline int validate(const lbm_params* p)
             lbm_set_error("lbm: every relaxation time must exceed 1/2");
             return LBM_EINVAL;
         }
+    if (!tile_rows_valid(*p)) {
+        lbm_set_error("lbm: tile_rows must be 0 (automatic), -1 (timed at lbm_init), 10..18 (FP32) or 5..10 (FP64)");
+        return LBM_EINVAL;
+    }
     if (p->kernel_variant < 0 || p->kernel_variant > LBM_VARIANT_BLOCK2) {
         lbm_set_error("lbm: kernel_variant must be 0 (automatic), 1 (row march), 2 (row block) or 3 (two-step block)");
         return LBM_EINVAL;

@@ -383,10 +383,23 @@ int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk)
 // per-wave FP64 partial slots the workspace holds: the one-step layout, or one per (tile,
 // wave) of the two-step kernel when it may reduce
 // waves of one two-step launch: (tiles) x (waves per tile), one partial slot each
-int two_step_waves(const lbm_params& p)
+// per-(tile, wave) partials of a reducing two-step launch with tile shape sh
+int two_step_waves(const lbm_params& p, const TwoStepShape& sh)
 {
-    const TwoStepShape sh = two_step_shape(p);
     return ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + sh.rows - 1) / sh.rows) * sh.waves;
+}
+
+// the most any candidate shape of p needs (the workspace holds them)
+int two_step_waves_max(const lbm_params& p)
+{
+    TwoStepShape cand[kMaxShapes];
+    const int n = two_step_candidates(p, cand);
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        const int w = two_step_waves(p, cand[i]);
+        m = w > m ? w : m;
+    }
+    return m;
 }
 
 int partial_slots(const lbm_params& p)
@@ -394,7 +407,7 @@ int partial_slots(const lbm_params& p)
     int strips, seg_h, nseg, blk;
     int n = decompose(p, &strips, &seg_h, &nseg, &blk);
     if (resolve_variant(p) == LBM_VARIANT_BLOCK2) {
-        const int n2 = two_step_waves(p);
+        const int n2 = two_step_waves_max(p);
         n = n2 > n ? n2 : n;
     }
     return n;
@@ -444,8 +457,9 @@ void fill_args(lbm_ctx* c)
     A.psi_hi = p.walls ? psi_host(p.rho_wall_hi) : 0.0;
     A.partials = c->partials;
     A.err = c->err;
-    const TwoStepShape sh = two_step_shape(p);
+    const TwoStepShape sh = c->shape;
     c->rows2 = sh.rows2;
+    A.rows2t = sh.rows;
     A.strips2 = (p.nx + k2Cols - 1) / k2Cols;
     A.bands2 = (p.ny + sh.rows - 1) / sh.rows;
     A.pcols2 = (A.strips2 + kPatchW - 1) / kPatchW;
@@ -669,6 +683,17 @@ int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int*
     return LBM_OK;
 }
 
+int lbm_tile_shape(const lbm_ctx* c, int* rows_out, int* waves_out)
+{
+    if (!c || !c->blk2) {
+        lbm_set_error("lbm_tile_shape: a context of the two-step variant is required");
+        return LBM_EINVAL;
+    }
+    if (rows_out) *rows_out = c->shape.rows;
+    if (waves_out) *waves_out = c->shape.waves;
+    return LBM_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -685,6 +710,54 @@ int check_init(const lbm_params* p, void* f_a, void* f_b, const double* rho0, si
     int ld;
     size_t pop_bytes;
     lbm_layout(p, &ld, &pop_bytes, need);
+    return LBM_OK;
+}
+
+// tile_rows = -1: time each candidate two-step tile shape on the second population buffer,
+// reading the initial state, and keep the fastest.  Three rounds over the candidates, each
+// candidate one launch to warm up and then 3 timed, and a candidate's time is its best round,
+// so that a stall in one round does not decide.  The error word is reset afterwards: the
+// timed launches take the lattice's first two steps, which the real run repeats.
+int time_tile_shapes(lbm_ctx* c, hipStream_t s)
+{
+    TwoStepShape cand[kMaxShapes];
+    const int n = two_step_candidates(c->P, cand);
+    if (n <= 1) return LBM_OK;
+    hipEvent_t e0, e1;
+    if (!hip_ok(hipEventCreate(&e0), "tile timing event")) return LBM_EHIP;
+    if (!hip_ok(hipEventCreate(&e1), "tile timing event")) {
+        (void)hipEventDestroy(e0);
+        return LBM_EHIP;
+    }
+    const bool f32 = c->P.prec == LBM_FP32_SHIFTED;
+    float best_ms[kMaxShapes];
+    bool ok = true;
+    for (int round = 0; round < 3 && ok; ++round) {
+        for (int i = 0; i < n && ok; ++i) {
+            c->shape = cand[i];
+            fill_args(c);
+            for (int r = 0; r < 4 && ok; ++r) {
+                if (r == 1) ok = hip_ok(hipEventRecord(e0, s), "tile timing");
+                if (ok) ok = f32 ? launch_step2<float>(c, nullptr, s) : launch_step2<double>(c, nullptr, s);
+            }
+            float ms = 0.0f;
+            ok = ok && hip_ok(hipEventRecord(e1, s), "tile timing") && hip_ok(hipEventSynchronize(e1), "tile timing") &&
+                 hip_ok(hipEventElapsedTime(&ms, e0, e1), "tile timing");
+            if (ok && (round == 0 || ms < best_ms[i])) best_ms[i] = ms;
+        }
+    }
+    int best = 0;
+    for (int i = 1; i < n && ok; ++i)
+        if (best_ms[i] < best_ms[best]) best = i;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok) return LBM_EHIP;
+    c->shape = cand[best];
+    fill_args(c);
+    const unsigned init_err[2] = {0u, 0xffffffffu};
+    if (!hip_ok(hipMemcpyAsync(c->err, init_err, sizeof(init_err), hipMemcpyHostToDevice, s), "lbm_init error word") ||
+        !hip_ok(hipStreamSynchronize(s), "lbm_init sync"))
+        return LBM_EHIP;
     return LBM_OK;
 }
 
@@ -714,6 +787,7 @@ int init_ctx(lbm_ctx* c, const lbm_params* p, void* f_a, void* f_b, void* ws, si
     c->hist = (double*)(c->ws + oh);
     c->red = (double*)(c->ws + orr);
     c->hist_count = 0;
+    c->shape = two_step_shape(*p);
     fill_args(c);
     hipStream_t s = (hipStream_t)stream;
     const unsigned init_err[2] = {0u, 0xffffffffu};
@@ -726,6 +800,7 @@ int init_ctx(lbm_ctx* c, const lbm_params* p, void* f_a, void* f_b, void* ws, si
     if (p->prec == LBM_FP32_SHIFTED) hipLaunchKernelGGL(k_init<float>, g, dim3(128), 0, s, A, rho0, ux0, uy0);
     else hipLaunchKernelGGL(k_init<double>, g, dim3(128), 0, s, A, rho0, ux0, uy0);
     if (!hip_ok(hipGetLastError(), "k_init launch")) return LBM_EHIP;
+    if (c->blk2 && p->tile_rows == -1) return time_tile_shapes(c, s);
     return LBM_OK;
 }
 
@@ -869,7 +944,8 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
                 return LBM_EHIP;
             if (red2) {
                 double* row = c->hist + 4 * (c->hist_count % kHistCap);
-                if (!launch_reduce_n(c, two_step_waves(c->P), row, (long long)c->step + 1, 1, s)) return LBM_EHIP;
+                if (!launch_reduce_n(c, two_step_waves(c->P, c->shape), row, (long long)c->step + 1, 1, s))
+                    return LBM_EHIP;
                 c->hist_count++;
             }
             c->cur ^= 1;

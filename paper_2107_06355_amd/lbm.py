@@ -52,6 +52,7 @@ class LbmParams(C.Structure):
         ("tau_l", C.c_double), ("tau_v", C.c_double), ("rho_v_tau", C.c_double), ("rho_l_tau", C.c_double),
         ("rho_ref", C.c_double),
         ("eos", LbmEos),
+        ("tile_rows", C.c_int),
     ]
 
 
@@ -84,6 +85,7 @@ def _signatures():
         "lbm_describe": ([C.POINTER(LbmParams), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], i),
         "lbm_init": ([C.POINTER(vp), C.POINTER(LbmParams), vp, vp, vp, sz, vp, vp, vp, vp], i),
         "lbm_init_static": ([C.POINTER(vp), C.POINTER(LbmParams), vp, vp, vp, vp, vp, vp], i),
+        "lbm_tile_shape": ([vp, C.POINTER(C.c_int), C.POINTER(C.c_int)], i),
         "lbm_step": ([vp, C.c_int64, vp], i),
         "lbm_status_check": ([vp, vp], i),
         "lbm_macros": ([vp, vp, vp, vp, vp, vp, vp, vp, dp, vp], i),
@@ -194,7 +196,8 @@ GRAD_NAMES = ("rho_max", "p_max", "rho_min", "p_min", "G", "sigma")
 
 def make_params(nx, ny, eos: LbmEos, G=-1.0, sigma=0.0, tau=None, prec=FP64, rho_ref=None, walls=False,
                 rho_wall_lo=0.0, rho_wall_hi=0.0, var_tau=False, tau_l=1.0, tau_v=1.0, rho_v_tau=None,
-                rho_l_tau=None, reduce_every=0, band_rows=0, kernel_variant=0) -> LbmParams:
+                rho_l_tau=None, reduce_every=0, band_rows=0, kernel_variant=0, tile_rows=0) -> LbmParams:
+    """tile_rows: two-step tile height (0: the library's choice, -1: timed by lbm_init, else that height)."""
     P = LbmParams()
     P.nx, P.ny, P.walls, P.prec, P.var_tau, P.reduce_every = nx, ny, int(walls), prec, int(var_tau), reduce_every
     P.band_rows = band_rows
@@ -209,6 +212,7 @@ def make_params(nx, ny, eos: LbmEos, G=-1.0, sigma=0.0, tau=None, prec=FP64, rho
     P.rho_l_tau = eos.rho_l if rho_l_tau is None else rho_l_tau
     P.rho_ref = (eos.rho_v if rho_ref is None else rho_ref) if prec == FP32_SHIFTED else 0.0
     P.eos = eos
+    P.tile_rows = tile_rows
     return P
 
 
@@ -287,6 +291,12 @@ class Lattice:
 
     def check(self):
         _check(load().lbm_status_check(self._h, self._s()), "lbm_status_check")
+
+    def tile_shape(self) -> tuple[int, int]:
+        """(output rows, wavefronts per workgroup) of the two-step tile this lattice runs."""
+        r, w = C.c_int(0), C.c_int(0)
+        _check(load().lbm_tile_shape(self._h, C.byref(r), C.byref(w)), "lbm_tile_shape")
+        return r.value, w.value
 
     def macros(self) -> dict:
         t = self.torch

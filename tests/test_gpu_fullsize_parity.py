@@ -3,7 +3,8 @@
 512 x 512 static droplet (shaped Peng-Robinson, Tr = 0.5, density ratio 1.1e4, R = 80) after
 50,000 steps, and the 2048 x 1024 droplet impact on a film between walls (Tr = 0.47, density
 ratio 3.07e4) over its first 2,000 steps, each from its initial state with the launch sequence
-bench.py times (two-step launches, a reduction every 100 steps).  The oracle's fields are
+bench.py times (two-step launches in the tile shape lbm_init times as fastest, a reduction every 100
+steps).  The oracle's fields are
 stored by tests/golden/make_fullsize_goldens.py (FP64 oracle only): the density and the forced
 velocity on a grid of sample nodes and along one full row and one full column.
 
@@ -51,16 +52,19 @@ def _run(lbm, name, prec, steps):
     if name == "static_droplet_512":
         r = STATIC_DROPLET_512
         e, s = lbm.eos_build(lbm.make_eos(**r["eos"]))
-        P = lbm.make_params(r["nx"], r["ny"], e, sigma=s, tau=r["tau"], prec=prec, reduce_every=100)
+        P = lbm.make_params(r["nx"], r["ny"], e, sigma=s, tau=r["tau"], prec=prec, reduce_every=100,
+                            tile_rows=-1)
         L = lbm.Lattice(P, static_droplet_fields(r, e.rho_v, e.rho_l), device="cuda:0")
     else:
         r = DROP_IMPACT_2048
         e, s = lbm.eos_build(lbm.make_eos(**r["eos"]))
         rho, ux, uy = drop_impact_fields(r, e.rho_v, e.rho_l)
         P = lbm.make_params(r["nx"], r["ny"], e, sigma=s, tau=drop_impact_tau(r), prec=prec, walls=True,
-                            rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v, reduce_every=100)
+                            rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v, reduce_every=100, tile_rows=-1)
         L = lbm.Lattice(P, rho, ux, uy, device="cuda:0")
     assert lbm.describe(P)[0] == lbm.VARIANT_BLOCK2
+    print("# %s %s: two-step tiles of %d rows, %d wavefronts" % (name, "fp64" if prec == lbm.FP64 else "fp32",
+                                                                 *L.tile_shape()))
     L.step(steps)
     L.check()
     m = L.macros()

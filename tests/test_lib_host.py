@@ -1,6 +1,7 @@
 """CPU-side checks of the product library: it loads, exports every symbol include/lbm.h
 declares, and its host thermodynamics (lbm_eos_build, a host-only computation) agrees with
 the independently written oracle."""
+import ctypes as C
 import os
 import re
 
@@ -167,21 +168,56 @@ def test_bench_names_the_kernel_the_library_launches():
     assert bench.kernel_name(lbm, P) == ("k_step2_rows2<double, 0, true, false>", 2)
     P = lbm.make_params(8192, 8192, e, sigma=s, prec=lbm.FP32_SHIFTED)
     assert bench.kernel_name(lbm, P) == ("k_step2_rows2<float, 0, false, false>", 2)
+    # a lower two-row height (explicit, or timed at lbm_init and passed as the lattice's shape)
+    for prec, t, h in ((lbm.FP32_SHIFTED, "float", 11), (lbm.FP64, "double", 5)):
+        P = lbm.make_params(2048, 1024, e, sigma=s, prec=prec, walls=True, rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v,
+                            tile_rows=h)
+        assert bench.kernel_name(lbm, P) == ("k_step2_rows2<%s, 0, true, false>" % t, 2)
+    P = lbm.make_params(2048, 1024, e, sigma=s, prec=lbm.FP32_SHIFTED, walls=True, rho_wall_lo=e.rho_l,
+                        rho_wall_hi=e.rho_v)
+    assert bench.kernel_name(lbm, P, (16, 12)) == ("k_step2_rows2<float, 0, true, false>", 2)
+    assert bench.kernel_name(lbm, P, (10, 16)) == ("k_step2_blk<float, 0, true, false>", 2)
 
 
 def test_two_step_tile_shape():
-    """lbm_describe reports the two-step tile the library launches: FP64 8 wavefronts of two rows (10-row
-    tiles) on every lattice; FP32 16 wavefronts of one row (10 rows), or 12 of two rows (18 rows) once
-    the lattice holds at least 4096 of those 58 x 18 tiles."""
+    """lbm_describe reports the two-step tile the library launches: FP64 8 wavefronts of two rows (tiles
+    of up to 10 rows) on every lattice; FP32 16 wavefronts of one row (10 rows), or 12 of two rows (up to
+    18 rows) once the lattice holds at least 4096 of those 58 x 18 tiles.  The two-row height is the
+    tallest unless a lower one fills the chip's rounds of 512 workgroups clearly better."""
     e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
     P32, P64 = lbm.FP32_SHIFTED, lbm.FP64
     for nx, ny, prec, want in [(512, 512, P64, (10, 8)), (1, 1, P64, (10, 8)), (2048, 1024, P64, (10, 8)),
                                (512, 512, P32, (10, 16)), (2048, 1024, P32, (10, 16)),
-                               (2048, 2048, P32, (18, 12)),  # 36 strips x 114 bands = 4104 tiles
-                               (2048, 2030, P32, (10, 16)),  # 36 x 113 = 4068
+                               (2048, 2048, P32, (18, 12)),  # 36 strips x 114 18-row bands = 4104 tiles
+                               (2048, 2030, P32, (10, 16)),  # 36 x 113 = 4068 18-row tiles
                                (8192, 8192, P32, (18, 12))]:
         v, rows, waves = lbm.describe(lbm.make_params(nx, ny, e, sigma=s, prec=prec))
         assert v == lbm.VARIANT_BLOCK2 and (rows, waves) == want, (nx, ny, prec, rows, waves)
+    # an explicit height (tile_rows > 0): FP32 10 is the one-row tile, 11..18 two rows; FP64 5..10
+    for prec, h, want in [(P32, 10, (10, 16)), (P32, 16, (16, 12)), (P32, 11, (11, 12)), (P64, 7, (7, 8))]:
+        assert lbm.describe(lbm.make_params(2048, 1024, e, sigma=s, prec=prec, tile_rows=h))[1:] == want
+    # tile_rows = -1 reports the library's choice (lbm_init then times the candidates), and the workspace
+    # holds the partials of the largest candidate
+    P = lbm.make_params(2048, 1024, e, sigma=s, prec=P32, tile_rows=-1)
+    assert lbm.describe(P)[1:] == (10, 16)
+    ws_timed = lbm.layout(P)[2]
+    for h in (10, 14, 15, 16, 17, 18):
+        assert lbm.layout(lbm.make_params(2048, 1024, e, sigma=s, prec=P32, tile_rows=h))[2] <= ws_timed
+
+
+def test_tile_rows_outside_the_shapes_are_refused():
+    """lbm_init refuses tile_rows outside -1, 0, 10..18 (FP32) or 5..10 (FP64) before touching a device."""
+    e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
+    for prec, h in [(lbm.FP32_SHIFTED, 9), (lbm.FP32_SHIFTED, 19), (lbm.FP64, 4), (lbm.FP64, 11), (lbm.FP64, -2)]:
+        P = lbm.make_params(64, 64, e, sigma=s, prec=prec, tile_rows=h)
+        ld, pb, wb = lbm.layout(P)
+        f = (C.c_char * pb)()
+        g = (C.c_char * pb)()
+        ws = (C.c_char * wb)()
+        rho = (C.c_double * (64 * 64))()
+        ctx = C.c_void_p()
+        rc = lbm.load().lbm_init(C.byref(ctx), C.byref(P), f, g, ws, wb, rho, None, None, None)
+        assert rc == lbm.LBM_EINVAL and b"tile_rows" in lbm.load().lbm_last_error(), (prec, h, rc)
 
 
 def test_bench_reduction_schedule_puts_a_reducing_step_in_every_window():
