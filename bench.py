@@ -412,15 +412,19 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
     def run(prec, mode=None, ee=e, G=-1.0, sig=s):
         P = lbm.make_params(n, n, ee, G=G, sigma=sig, tau=S["tau"], prec=prec, reduce_every=0)
         lat = lbm.Lattice(P, rho0, device="cuda:0")
-        if mode == "checkpoint":
-            lat.enable_checkpointing(K, steps)
+        if mode in ("checkpoint", "checkpoint_one_stream"):
+            # two record segments: the next segment's recomputation overlaps the current one's
+            # transposed steps on a second stream; one segment: both on the lattice's stream
+            lat.enable_checkpointing(K, steps, overlap=mode == "checkpoint")
         elif mode == "record":
             lat.enable_recording(steps)
         return lat
 
     out = {"workload": "static droplet %dx%d R=%d W0=%g, shaped PR Tr=0.5, %d steps; the forward checkpoints every "
-                       "%d steps and the adjoint recomputes each segment (the specified mode), or the forward "
-                       "records every step" % (n, n, R, W0, steps, K)}
+                       "%d steps and the adjoint recomputes each segment (the specified mode; the next segment's "
+                       "recomputation overlaps the current one's transposed steps on a second stream, or runs on "
+                       "the lattice's stream: checkpoint_one_stream), or the forward records every step"
+                       % (n, n, R, W0, steps, K)}
     for prec, name in ((lbm.FP32_SHIFTED, "fp32"), (lbm.FP64, "fp64")):
         plain = run(prec)
         plain.step(50)
@@ -434,7 +438,7 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
         torch.cuda.synchronize()
         t_fwd = ev[0].elapsed_time(ev[1])
         res = {"forward_ms": t_fwd}
-        for mode in ("checkpoint", "record"):
+        for mode in ("checkpoint", "checkpoint_one_stream", "record"):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
             lat = run(prec, mode)
             ev[0].record(lat.stream)

@@ -519,6 +519,40 @@ AdjLayout adj_layout(const lbm_params& p, int ld, size_t pop_bytes, int K)
 
 }  // namespace
 
+namespace lbmk {
+// A second stream (default priority) for the checkpointed adjoint's recomputation, and the
+// events that order it against the caller's stream: rec_ready[h] once half h of the record
+// buffer holds a segment, adj_done[h] once the transposed steps have read it.  open() makes
+// the new stream wait for everything already queued on the caller's stream; the destructor
+// drains the stream before destroying it.
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t rec_ready[2] = {nullptr, nullptr}, adj_done[2] = {nullptr, nullptr};
+    hipEvent_t start = nullptr;
+    bool used[2] = {false, false};  // adj_done[h] recorded
+    bool open(hipStream_t caller)
+    {
+        if (!hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "adjoint stream")) return false;
+        for (int h = 0; h < 2; ++h)
+            if (!hip_ok(hipEventCreateWithFlags(&rec_ready[h], hipEventDisableTiming), "adjoint event") ||
+                !hip_ok(hipEventCreateWithFlags(&adj_done[h], hipEventDisableTiming), "adjoint event"))
+                return false;
+        return hip_ok(hipEventCreateWithFlags(&start, hipEventDisableTiming), "adjoint event") &&
+               hip_ok(hipEventRecord(start, caller), "adjoint event") &&
+               hip_ok(hipStreamWaitEvent(s, start, 0), "adjoint wait");
+    }
+    ~AuxStream()
+    {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        for (hipEvent_t e : {rec_ready[0], rec_ready[1], adj_done[0], adj_done[1], start})
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace lbmk
+
 extern "C" {
 
 int lbm_adjoint_layout(const lbm_params* p, int K, size_t* rec_bytes, size_t* adj_bytes)
@@ -584,6 +618,7 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
                        void* rec_buf, size_t rec_bytes, void* adj_buf, size_t adj_bytes, double* grad_out,
                        double* dL_drho0, void* stream)
 {
+    using lbmk::AuxStream;
     if (!c || !adj_buf || !grad_out || !(dL_drho_T || dL_dux_T || dL_duy_T)) return LBM_EINVAL;
     const lbm_params& P = c->P;
     // a forward recorded from step 0 needs no recomputation
@@ -659,31 +694,54 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
             li ^= 1;
         }
     }
+    // A record buffer of two segments lets the recomputation of segment k - 1 run on a
+    // second stream beside the transposed steps of segment k (the segments alternate
+    // between the halves): both kernels are latency-bound at the sizes the adjoint runs,
+    // and each fills the issue slots the other leaves.  The recomputation touches only
+    // the lattice's population buffers and its half of the records; the transposed steps
+    // only lambda, the accumulators and the other half.
+    const bool piped = !recorded && S > 1 && rec_bytes >= 2 * L.rec_bytes;
+    AuxStream aux;
+    if (piped && !aux.open(s)) return LBM_EHIP;
+    hipStream_t sr = piped ? aux.s : s;  // the recomputation's stream
     for (int64_t k = recorded ? -1 : S - 1; k >= 0; --k) {
         const int64_t t0 = k * K;
         const int n = (int)((T_end - t0) < K ? (T_end - t0) : K);
+        const int half = piped ? (int)(k & 1) : 0;
+        char* seg = (char*)rec_buf + (size_t)half * L.rec_bytes;
+        // the transposed steps of segment k + 2 read this half last (the first two segments
+        // find it unused)
+        if (piped && aux.used[half] && !hip_ok(hipStreamWaitEvent(sr, aux.adj_done[half], 0), "adjoint wait"))
+            return LBM_EHIP;
         if (!hip_ok(hipMemcpyAsync(c->buf[c->cur], (char*)c->ckpt + k * c->pop_bytes, c->pop_bytes,
-                                   hipMemcpyDeviceToDevice, s),
+                                   hipMemcpyDeviceToDevice, sr),
                     "restore checkpoint"))
             return LBM_EHIP;
         c->step = t0;
         for (int j = 0; j < n;) {
             // recompute the segment's records, two steps per launch where the forward's
             // two-step kernel applies (its two records land in consecutive slots)
-            void* rec = (char*)rec_buf + (size_t)j * 4 * nn * L.tsz;
+            void* rec = seg + (size_t)j * 4 * nn * L.tsz;
             const bool pair = c->blk2 && j + 1 < n;
-            if (!(pair ? launch_record_pair(c, rec, s) : launch_record_step(c, rec, s))) return LBM_EHIP;
+            if (!(pair ? launch_record_pair(c, rec, sr) : launch_record_step(c, rec, sr))) return LBM_EHIP;
             c->cur ^= 1;
             c->step += pair ? 2 : 1;
             j += pair ? 2 : 1;
         }
+        if (piped && !(hip_ok(hipEventRecord(aux.rec_ready[half], sr), "adjoint event") &&
+                       hip_ok(hipStreamWaitEvent(s, aux.rec_ready[half], 0), "adjoint wait")))
+            return LBM_EHIP;
         for (int j = n - 1; j >= 0; --j) {
-            A.rec = (const char*)rec_buf + (size_t)j * 4 * nn * L.tsz;
+            A.rec = (const char*)seg + (size_t)j * 4 * nn * L.tsz;
             A.lam_in = lam[li];
             A.lam_out = lam[li ^ 1];
             launch_adj_step(f32, nt, L.blocks, s, A);
             if (!hip_ok(hipGetLastError(), "adjoint step launch")) return LBM_EHIP;
             li ^= 1;
+        }
+        if (piped) {
+            if (!hip_ok(hipEventRecord(aux.adj_done[half], s), "adjoint event")) return LBM_EHIP;
+            aux.used[half] = true;
         }
     }
     // restore the forward state at T

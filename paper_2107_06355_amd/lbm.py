@@ -343,13 +343,15 @@ class Lattice:
     def load_state(self, buf, step: int):
         _check(load().lbm_load(self._h, buf.data_ptr(), int(step), self._s()), "lbm_load")
 
-    def enable_checkpointing(self, K: int, max_steps: int):
-        """Keep the state every K steps (up to max_steps) for lbm_adjoint; call before stepping."""
+    def enable_checkpointing(self, K: int, max_steps: int, overlap: bool = True):
+        """Keep the state every K steps (up to max_steps) for lbm_adjoint; call before stepping.
+        overlap: give lbm_adjoint a record buffer of two segments, so that it recomputes the next
+        segment on a second stream while the transposed steps run over the current one."""
         t = self.torch
         slots = max(1, -(-int(max_steps) // int(K)))
         self._ckpt = t.empty(slots * self.pop_bytes, dtype=t.uint8, device=self.device)
         rec, adj = adjoint_layout(self.P, K)
-        self._rec = t.empty(rec, dtype=t.uint8, device=self.device)
+        self._rec = t.empty(rec * (2 if overlap else 1), dtype=t.uint8, device=self.device)
         self._adj = t.empty(adj, dtype=t.uint8, device=self.device)
         _check(load().lbm_set_checkpointing(self._h, self._ckpt.data_ptr(), self._ckpt.numel(), int(K)),
                "lbm_set_checkpointing")
