@@ -41,7 +41,7 @@ METRIC = "MLUPS + HBM GB/s (%roofline), FP32-shifted vs FP64 D2Q9; adjoint/fwd t
 # algorithmic bytes per cell update: 8 moving populations read + written, rest population FP64 read + written
 BYTES = {"fp32": 8 * 4 * 2 + 8 * 2, "fp64": 9 * 8 * 2}
 STREAM_BYTES = 64 << 20  # the library streams its stores when both population buffers take at most this
-LEGS = ("c3", "c2", "parity", "sweep", "batched", "fd", "adjoint", "cpu")
+LEGS = ("c3", "c2", "parity", "sweep", "aa", "batched", "fd", "adjoint", "cpu")
 
 
 def _prec_name(prec_id, lbm):
@@ -501,6 +501,42 @@ def adjoint_leg(lbm, n=512, R=80, W0=20.0, steps=4000, K=200, fd_check=True):
     return out
 
 
+def aa_leg(lbm, steps=1000, big_steps=20):
+    """The in-place AA variant (one population buffer, two launches per step) on the drop-impact
+    lattice and on the 8192^2 droplet: time per step, the one-step-equivalent algorithmic rate,
+    and the device memory of populations + workspace against the two-buffer default."""
+    import torch
+
+    out = []
+    for wl, make, n in (("drop impact 2048x1024", lambda prec: drop_impact_lattice(lbm, prec, 0, variant=lbm.VARIANT_AA),
+                         steps),
+                        ("droplet 8192x8192", lambda prec: droplet_lattice(lbm, 8192, prec, 0, variant=lbm.VARIANT_AA),
+                         big_steps)):
+        for prec in (lbm.FP32_SHIFTED, lbm.FP64):
+            pn = _prec_name(prec, lbm)
+            L, e = make(prec)
+            sec, _ = time_steps(L, n, 10)
+            L.check()
+            cells = L.nx * L.ny
+            gbs = BYTES[pn] * cells * n / sec / 1e9
+            _, pop, ws = lbm.layout(L.P)
+            q = lbm.make_params(L.nx, L.ny, e, prec=prec)
+            _, pop2, ws2 = lbm.layout(q)
+            row = {"workload": wl, "prec": pn, "us_per_step": sec * 1e6 / n, "MLUPS": cells * n / sec / 1e6,
+                   "GB/s": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS, "device_bytes": pop + ws,
+                   "device_bytes_two_buffer": 2 * pop2 + ws2}
+            out.append(row)
+            print("# aa %s %s: %.2f us/step, %.0f MLUPS, %.0f GB/s algorithmic (%.1f%%); %.2f GB of device memory "
+                  "against %.2f GB with two buffers" % (wl, pn, row["us_per_step"], row["MLUPS"], gbs,
+                                                       100 * gbs / HBM_PEAK_GBS, row["device_bytes"] / 1e9,
+                                                       row["device_bytes_two_buffer"] / 1e9),
+                  file=sys.stderr, flush=True)
+            L.close()
+            del L
+            torch.cuda.empty_cache()
+    return out
+
+
 def batched_leg(lbm, steps=20000, n_lattices=64, seed=0):
     """Uneven batched planar sweep: 64 lattices L_b x 4 (L_b = 4 U{32..512}), Tr ~ U(0.35, 0.95), shaped PR,
     FP32-shifted, in the library's automatic launch mode; aggregate MLUPS and coexistence error against Maxwell."""
@@ -712,6 +748,8 @@ def main():
         out["parity"] = parity_leg(lbm)
     if "sweep" in legs:
         out["sweep"] = sweep_leg(lbm, [int(v) for v in args.sweep.split(",") if v.strip()], args.sweep_steps, args.only)
+    if "aa" in legs:
+        out["aa"] = aa_leg(lbm)
     if "batched" in legs:
         out["batched"] = batched_leg(lbm)
     if "fd" in legs:

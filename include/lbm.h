@@ -62,12 +62,20 @@ typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_prec;
  * step ends a launch, and checkpoint boundaries and odd counts run single
  * steps on BLOCK).  The tile: FP64, 8 wavefronts of two rows each, 10 rows;
  * FP32, 16 wavefronts of one row, 10 rows, or on lattices of at least 4096
- * such tiles 12 wavefronts of two rows, 18 rows.  AUTO is BLOCK2. */
+ * such tiles 12 wavefronts of two rows, 18 rows.  AUTO is BLOCK2.
+ * AA: one population buffer updated in place with the AA access pattern
+ * (even steps read and write each node's own slots, odd steps read from and
+ * write to the neighbours, bounce-back included), for lattices whose second
+ * buffer would not fit.  psi of the neighbours cannot be formed in the same
+ * pass, so each step is two launches (psi of every node into a workspace
+ * plane, then the update): about 1.6x the HBM traffic of the pull variants.
+ * No adjoint (recording and checkpointing refuse it) and no batched use. */
 typedef enum {
     LBM_VARIANT_AUTO = 0,
     LBM_VARIANT_MARCH = 1,
     LBM_VARIANT_BLOCK = 2,
-    LBM_VARIANT_BLOCK2 = 3
+    LBM_VARIANT_BLOCK2 = 3,
+    LBM_VARIANT_AA = 4
 } lbm_variant;
 typedef enum { LBM_BASE_CS = 0, LBM_BASE_PR = 1 } lbm_base;
 typedef enum {
@@ -138,7 +146,7 @@ typedef struct {
 typedef struct lbm_ctx lbm_ctx;
 
 /* Layout query: row pitch, bytes of ONE population buffer (the caller
- * allocates two), and bytes of the workspace.  LBM_EINVAL when a population
+ * allocates two; one for LBM_VARIANT_AA), and bytes of the workspace.  LBM_EINVAL when a population
  * plane (64-aligned row pitch x ny x 8 bytes) would reach 4 GiB: offsets
  * inside a plane are 32-bit (the largest square lattice is 23168^2). */
 int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* ws_bytes_out);
@@ -158,7 +166,10 @@ int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int*
  * what the eight FP32-rounded moving populations leave of rho0, so that each
  * node's mass is rho0 exactly.  rho0, ux0, uy0: device float64 [ny][nx]; ux0/uy0
  * may be NULL (u = 0).  Validates parameters (LBM_EINVAL): tau > 1/2,
- * rho_ref > 0 in FP32 mode, G < 0, buffers non-NULL and distinct. */
+ * rho_ref > 0 in FP32 mode, G < 0, buffers non-NULL and distinct
+ * (LBM_VARIANT_AA: f_a only, f_b NULL; it holds f^eq(rho0, u0) at each node
+ * itself, where the other variants store it one node upstream for their
+ * first pull). */
 int lbm_init(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, void* ws, size_t ws_bytes,
              const double* rho0, const double* ux0, const double* uy0, void* stream);
 
@@ -207,7 +218,8 @@ int lbm_macros(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* psi, d
                double* Fx, double* Fy, double* host_mass_mom, void* stream);
 
 /* Distributions f_i(t, x) of Eq. LBE at the current time (pulled), as
- * float64 [9][ny][nx] on the device.  Asynchronous. */
+ * float64 [9][ny][nx] on the device, whichever variant and (AA) layout
+ * holds them.  Asynchronous. */
 int lbm_populations(lbm_ctx* ctx, double* f_out, void* stream);
 
 /* FP64 reduction history written by lbm_step when reduce_every > 0:
@@ -215,7 +227,8 @@ int lbm_populations(lbm_ctx* ctx, double* f_out, void* stream);
  * returns the row count through n_out.  Synchronises `stream`. */
 int lbm_history(lbm_ctx* ctx, double* host_rows, int max_rows, int* n_out, void* stream);
 
-/* Current step counter and the buffer that holds the current state (0: f_a, 1: f_b). */
+/* Current step counter and the buffer that holds the current state (0: f_a, 1: f_b;
+ * always 0 for LBM_VARIANT_AA, whose layout follows the parity of the step). */
 int lbm_state(lbm_ctx* ctx, int64_t* step_out, int* cur_out);
 
 /* Checkpoint / restore of the whole population state to caller memory
@@ -223,7 +236,9 @@ int lbm_state(lbm_ctx* ctx, int64_t* step_out, int* cur_out);
  * the step counter to `step`; with step != 0 it also turns recording and
  * checkpointing off (their contents belong to the trajectory before the
  * load), so a later lbm_adjoint returns LBM_ESTATE until the forward is run
- * again from step 0 with them re-enabled. */
+ * again from step 0 with them re-enabled.  LBM_VARIANT_AA saves its buffer as
+ * it lies, in the layout of the current step's parity: load it with a step of
+ * the same parity. */
 int lbm_save(lbm_ctx* ctx, void* dst, void* stream);
 int lbm_load(lbm_ctx* ctx, const void* src, int64_t step, void* stream);
 

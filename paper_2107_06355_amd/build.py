@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 
-SOURCES = ["thermo.cpp", "lbm_step.hip", "lbm_batched.hip", "lbm_adjoint.hip", "lbm_fd.hip"]
+SOURCES = ["thermo.cpp", "lbm_step.hip", "lbm_batched.hip", "lbm_adjoint.hip", "lbm_fd.hip", "lbm_aa.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5",

@@ -574,6 +574,10 @@ int lbm_adjoint_layout(const lbm_params* p, int K, size_t* rec_bytes, size_t* ad
 int lbm_set_checkpointing(lbm_ctx* c, void* ckpt_buf, size_t ckpt_bytes, int K)
 {
     if (!c || (K > 0 && !ckpt_buf)) return LBM_EINVAL;
+    if (c->aa && K > 0) {
+        lbm_set_error("lbm_set_checkpointing: the in-place AA variant has no adjoint");
+        return LBM_EINVAL;
+    }
     if (c->step != 0) {
         lbm_set_error("lbm_set_checkpointing: enable checkpointing before the first step");
         return LBM_ESTATE;
@@ -591,6 +595,10 @@ int lbm_set_checkpointing(lbm_ctx* c, void* ckpt_buf, size_t ckpt_bytes, int K)
 int lbm_set_recording(lbm_ctx* c, void* rec_buf, size_t rec_bytes, int64_t max_steps)
 {
     if (!c || max_steps < 0 || (max_steps > 0 && !rec_buf)) return LBM_EINVAL;
+    if (c->aa && max_steps > 0) {
+        lbm_set_error("lbm_set_recording: the in-place AA variant has no adjoint");
+        return LBM_EINVAL;
+    }
     if (c->step != 0) {
         lbm_set_error("lbm_set_recording: enable recording before the first step");
         return LBM_ESTATE;

@@ -377,6 +377,10 @@ int batch_layout(int B, const lbm_params* p, Layout& L)
         }
         const int st = validate(&p[b]);
         if (st != LBM_OK) return st;
+        if (p[b].kernel_variant == LBM_VARIANT_AA) {
+            lbm_set_error("lbm batched: the in-place AA variant runs single lattices only");
+            return LBM_EINVAL;
+        }
         const int ld = (p[b].nx + 63) & ~63;
         const size_t plane = (size_t)ld * p[b].ny;
         const size_t bytes = p[b].prec == LBM_FP32_SHIFTED ? plane * (8 * sizeof(float) + sizeof(double))

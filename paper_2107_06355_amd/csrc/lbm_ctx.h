@@ -32,6 +32,10 @@ struct lbm_ctx {
     int64_t rec_steps;
     // the per-device context of lbm_init_static (lbm_destroy leaves it alone)
     bool is_static;
+    // LBM_VARIANT_AA: one population buffer updated in place (buf[0] == buf[1]) and the psi
+    // plane of the workspace
+    bool aa;
+    void* aa_psi;
 };
 
 
@@ -44,5 +48,14 @@ bool launch_record_step(lbm_ctx* c, void* rec, hipStream_t s);
 // consecutive slots from rec
 bool launch_record_pair(lbm_ctx* c, void* rec, hipStream_t s);
 int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk);
+// LBM_VARIANT_AA (lbm_aa.hip): partial-sum slots of a reducing step, bytes of the psi plane,
+// one step of c->step's parity in place (MODE_STEP or MODE_STEP_REDUCE), the macroscopic
+// fields (out: rho, ux, uy, psi, p, Fx, Fy, any NULL) and the FP64 populations
+int aa_slots(const lbm_params& p);
+size_t aa_psi_bytes(const lbm_params& p, int ld);
+bool aa_init(lbm_ctx* c, const double* rho0, const double* ux0, const double* uy0, hipStream_t s);
+bool aa_step(lbm_ctx* c, int mode, hipStream_t s);
+bool aa_macros(lbm_ctx* c, double* const out[7], hipStream_t s);
+bool aa_populations(lbm_ctx* c, double* f_out, hipStream_t s);
 int resolve_variant(const lbm_params& p);
 }  // namespace lbmk

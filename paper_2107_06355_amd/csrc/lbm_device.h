@@ -1114,8 +1114,9 @@ inline int validate(const lbm_params* p)
         lbm_set_error("lbm: tile_rows must be 0 (automatic), -1 (timed at lbm_init), 10..18 (FP32) or 5..10 (FP64)");
         return LBM_EINVAL;
     }
-    if (p->kernel_variant < 0 || p->kernel_variant > LBM_VARIANT_BLOCK2) {
-        lbm_set_error("lbm: kernel_variant must be 0 (automatic), 1 (row march), 2 (row block) or 3 (two-step block)");
+    if (p->kernel_variant < 0 || p->kernel_variant > LBM_VARIANT_AA) {
+        lbm_set_error("lbm: kernel_variant must be 0 (automatic), 1 (row march), 2 (row block), 3 (two-step block) "
+                      "or 4 (in-place AA)");
         return LBM_EINVAL;
     }
     if (p->band_rows < 0 || p->band_rows > 4096) {

@@ -410,6 +410,10 @@ int partial_slots(const lbm_params& p)
         const int n2 = two_step_waves_max(p);
         n = n2 > n ? n2 : n;
     }
+    if (resolve_variant(p) == LBM_VARIANT_AA) {
+        const int na = aa_slots(p);
+        n = na > n ? na : n;
+    }
     return n;
 }
 
@@ -655,7 +659,8 @@ int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* 
     int strips, seg_h, nseg, blk;
     decompose(*p, &strips, &seg_h, &nseg, &blk);
     size_t a, b, d;
-    const size_t ws = ws_layout(partial_slots(*p), &a, &b, &d);
+    size_t ws = ws_layout(partial_slots(*p), &a, &b, &d);
+    if (resolve_variant(*p) == LBM_VARIANT_AA) ws += aa_psi_bytes(*p, ld);  // the psi plane
     if (ld_out) *ld_out = ld;
     if (pop_bytes_out) *pop_bytes_out = bytes;
     if (ws_bytes_out) *ws_bytes_out = ws;
@@ -703,7 +708,12 @@ int check_init(const lbm_params* p, void* f_a, void* f_b, const double* rho0, si
 {
     int st = validate(p);
     if (st != LBM_OK) return st;
-    if (!f_a || !f_b || f_a == f_b || !rho0) {
+    if (resolve_variant(*p) == LBM_VARIANT_AA) {
+        if (!f_a || f_b || !rho0) {
+            lbm_set_error("lbm_init: the in-place AA variant takes one population buffer (f_b NULL); rho0 non-NULL");
+            return LBM_EINVAL;
+        }
+    } else if (!f_a || !f_b || f_a == f_b || !rho0) {
         lbm_set_error("lbm_init: population buffers must be non-NULL and distinct; rho0 non-NULL");
         return LBM_EINVAL;
     }
@@ -773,14 +783,16 @@ int init_ctx(lbm_ctx* c, const lbm_params* p, void* f_a, void* f_b, void* ws, si
     c->ld = ld;
     c->plane = (size_t)ld * p->ny;
     c->pop_bytes = pop_bytes;
+    c->aa = resolve_variant(*p) == LBM_VARIANT_AA;
     c->buf[0] = f_a;
-    c->buf[1] = f_b;
+    c->buf[1] = c->aa ? f_a : f_b;
     c->cur = 0;
     c->step = 0;
     c->ws = (char*)ws;
     c->ws_bytes = ws_bytes;
     size_t op, oh, orr;
-    ws_layout(partial_slots(*p), &op, &oh, &orr);
+    const size_t ws_base = ws_layout(partial_slots(*p), &op, &oh, &orr);
+    c->aa_psi = c->aa ? c->ws + ws_base : nullptr;
     c->err = (unsigned*)c->ws;
     c->partials = (double*)(c->ws + op);
     c->redblk = (double*)(c->ws + oh - (size_t)kRedBlocks * 3 * sizeof(double));
@@ -794,6 +806,7 @@ int init_ctx(lbm_ctx* c, const lbm_params* p, void* f_a, void* f_b, void* ws, si
     if (!hip_ok(hipMemcpyAsync(c->err, init_err, sizeof(init_err), hipMemcpyHostToDevice, s), "lbm_init error word") ||
         !hip_ok(hipStreamSynchronize(s), "lbm_init sync"))
         return LBM_EHIP;
+    if (c->aa) return aa_init(c, rho0, ux0, uy0, s) ? LBM_OK : LBM_EHIP;
     StepArgs A = c->args;
     A.dst = c->buf[0];
     dim3 g((p->nx + 127) / 128, p->ny);
@@ -920,6 +933,20 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
             return LBM_ESTATE;
         }
     }
+    if (c->aa) {
+        // in place, two launches per step (psi plane, then the update); no records or checkpoints
+        for (int64_t k = 0; k < nsteps; ++k) {
+            const bool red = re > 0 && (c->step % re) == 0;
+            if (!aa_step(c, red ? MODE_STEP_REDUCE : MODE_STEP, s)) return LBM_EHIP;
+            if (red) {
+                double* row = c->hist + 4 * (c->hist_count % kHistCap);
+                if (!launch_reduce_n(c, aa_slots(c->P), row, (long long)c->step, 1, s)) return LBM_EHIP;
+                c->hist_count++;
+            }
+            c->step++;
+        }
+        return LBM_OK;
+    }
     for (int64_t k = 0; k < nsteps; ++k) {
         if (c->ckpt_K > 0 && c->step % c->ckpt_K == 0) {
             const int64_t slot = c->step / c->ckpt_K;
@@ -1012,7 +1039,10 @@ int lbm_macros(lbm_ctx* c, double* rho, double* ux, double* uy, double* psi, dou
     A.o_fx = Fx;
     A.o_fy = Fy;
     const bool f32 = c->P.prec == LBM_FP32_SHIFTED;
-    if (A.blk) {
+    if (c->aa) {
+        double* const out[7] = {rho, ux, uy, psi, p, Fx, Fy};
+        if (!aa_macros(c, out, s) || !launch_reduce_n(c, aa_slots(c->P), c->red, 0LL, 0, s)) return LBM_EHIP;
+    } else if (A.blk) {
         if (f32) hipLaunchKernelGGL((k_step_blk<float, MODE_MACROS>), dim3(c->grid), dim3(64 * kBlkWaves), 0, s, A);
         else hipLaunchKernelGGL((k_step_blk<double, MODE_MACROS>), dim3(c->grid), dim3(64 * kBlkWaves), 0, s, A);
     } else {
@@ -1020,7 +1050,7 @@ int lbm_macros(lbm_ctx* c, double* rho, double* ux, double* uy, double* psi, dou
         else hipLaunchKernelGGL((k_step<double, MODE_MACROS>), dim3(c->grid), dim3(256), 0, s, A);
     }
     if (!hip_ok(hipGetLastError(), "k_step(macros) launch")) return LBM_EHIP;
-    if (!launch_reduce(c, c->red, 0LL, 0, s)) return LBM_EHIP;
+    if (!c->aa && !launch_reduce(c, c->red, 0LL, 0, s)) return LBM_EHIP;
     double h[3];
     if (!hip_ok(hipMemcpyAsync(h, c->red, sizeof(h), hipMemcpyDeviceToHost, s), "macros copy") ||
         !hip_ok(hipStreamSynchronize(s), "macros sync"))
@@ -1033,6 +1063,7 @@ int lbm_populations(lbm_ctx* c, double* f_out, void* stream)
 {
     if (!c || !f_out) return LBM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    if (c->aa) return aa_populations(c, f_out, s) ? LBM_OK : LBM_EHIP;
     StepArgs A = c->args;
     A.src = c->buf[c->cur];
     dim3 g((c->P.nx + 127) / 128, c->P.ny);

@@ -20,7 +20,7 @@ LBM_OK, LBM_EINVAL, LBM_EUNSTABLE, LBM_EHIP, LBM_ESTATE, LBM_ENOROOT = 0, -1, -2
 FP64, FP32_SHIFTED = 0, 1
 BASE_CS, BASE_PR = 0, 1
 SHAPE_NONE, SHAPE_SMOOTH, SHAPE_MODSMOOTH, SHAPE_PENG = 0, 1, 2, 3
-VARIANT_AUTO, VARIANT_MARCH, VARIANT_BLOCK, VARIANT_BLOCK2 = 0, 1, 2, 3
+VARIANT_AUTO, VARIANT_MARCH, VARIANT_BLOCK, VARIANT_BLOCK2, VARIANT_AA = 0, 1, 2, 3, 4
 BATCH_AUTO, BATCH_PERSISTENT, BATCH_GROUPED = 0, 1, 2
 
 
@@ -231,7 +231,8 @@ def describe(P: LbmParams) -> tuple[int, int, int]:
 
 # ---------------------------------------------------------------------------- lattice
 class Lattice:
-    """A lattice whose populations live in two torch byte tensors on a HIP device."""
+    """A lattice whose populations live in two torch byte tensors on a HIP device (one for
+    VARIANT_AA, which updates it in place)."""
 
     def __init__(self, P: LbmParams, rho0, ux0=None, uy0=None, device="cuda", stream=None,
                  static_workspace: bool = False):
@@ -246,7 +247,9 @@ class Lattice:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ld, pop_bytes, ws_bytes = layout(P)
         self.pop_bytes = pop_bytes
-        self.f = [torch.empty(pop_bytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        nbuf = 1 if P.kernel_variant == VARIANT_AA else 2
+        self.f = [torch.empty(pop_bytes, dtype=torch.uint8, device=self.device) for _ in range(nbuf)]
+        fb = self.f[1].data_ptr() if nbuf == 2 else None
         self.ws = None if static_workspace else torch.zeros(ws_bytes, dtype=torch.uint8, device=self.device)
         shp = (self.ny, self.nx)
         r = self._dev(rho0, shp)
@@ -255,10 +258,10 @@ class Lattice:
         h = C.c_void_p(0)
         up, vp_ = (u.data_ptr() if u is not None else None), (v.data_ptr() if v is not None else None)
         if static_workspace:
-            _check(load().lbm_init_static(C.byref(h), C.byref(P), self.f[0].data_ptr(), self.f[1].data_ptr(),
+            _check(load().lbm_init_static(C.byref(h), C.byref(P), self.f[0].data_ptr(), fb,
                                           r.data_ptr(), up, vp_, self._s()), "lbm_init_static")
         else:
-            _check(load().lbm_init(C.byref(h), C.byref(P), self.f[0].data_ptr(), self.f[1].data_ptr(),
+            _check(load().lbm_init(C.byref(h), C.byref(P), self.f[0].data_ptr(), fb,
                                    self.ws.data_ptr(), ws_bytes, r.data_ptr(), up, vp_, self._s()), "lbm_init")
         self._keep = (r, u, v)
         self._h = h

@@ -4,7 +4,7 @@
 50,000 steps, and the 2048 x 1024 droplet impact on a film between walls (Tr = 0.47, density
 ratio 3.07e4) over its first 2,000 steps, each from its initial state with the launch sequence
 bench.py times (two-step launches in the tile shape lbm_init times as fastest, a reduction every 100
-steps).  The oracle's fields are
+steps), and with the in-place AA variant (one population buffer, two launches per step).  The oracle's fields are
 stored by tests/golden/make_fullsize_goldens.py (FP64 oracle only): the density and the forced
 velocity on a grid of sample nodes and along one full row and one full column.
 
@@ -48,23 +48,24 @@ FP32_TARGETS = {
 }
 
 
-def _run(lbm, name, prec, steps):
+def _run(lbm, name, prec, steps, variant=0):
+    vk = dict(tile_rows=-1) if variant == 0 else dict(kernel_variant=variant)
     if name == "static_droplet_512":
         r = STATIC_DROPLET_512
         e, s = lbm.eos_build(lbm.make_eos(**r["eos"]))
-        P = lbm.make_params(r["nx"], r["ny"], e, sigma=s, tau=r["tau"], prec=prec, reduce_every=100,
-                            tile_rows=-1)
+        P = lbm.make_params(r["nx"], r["ny"], e, sigma=s, tau=r["tau"], prec=prec, reduce_every=100, **vk)
         L = lbm.Lattice(P, static_droplet_fields(r, e.rho_v, e.rho_l), device="cuda:0")
     else:
         r = DROP_IMPACT_2048
         e, s = lbm.eos_build(lbm.make_eos(**r["eos"]))
         rho, ux, uy = drop_impact_fields(r, e.rho_v, e.rho_l)
         P = lbm.make_params(r["nx"], r["ny"], e, sigma=s, tau=drop_impact_tau(r), prec=prec, walls=True,
-                            rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v, reduce_every=100, tile_rows=-1)
+                            rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v, reduce_every=100, **vk)
         L = lbm.Lattice(P, rho, ux, uy, device="cuda:0")
-    assert lbm.describe(P)[0] == lbm.VARIANT_BLOCK2
-    print("# %s %s: two-step tiles of %d rows, %d wavefronts" % (name, "fp64" if prec == lbm.FP64 else "fp32",
-                                                                 *L.tile_shape()))
+    if variant == 0:
+        assert lbm.describe(P)[0] == lbm.VARIANT_BLOCK2
+        print("# %s %s: two-step tiles of %d rows, %d wavefronts" % (name, "fp64" if prec == lbm.FP64 else "fp32",
+                                                                     *L.tile_shape()))
     L.step(steps)
     L.check()
     m = L.macros()
@@ -74,15 +75,16 @@ def _run(lbm, name, prec, steps):
     return out
 
 
+@pytest.mark.parametrize("variant", [0, 4], ids=["two-step", "aa"])
 @pytest.mark.parametrize("name", ["static_droplet_512", "drop_impact_2048"])
 @pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
-def test_full_length_against_oracle(gpu_lib, name, prec_name):
+def test_full_length_against_oracle(gpu_lib, name, prec_name, variant):
     lbm = gpu_lib
     if not os.path.exists(fullsize.path(name)):
         pytest.skip("stored oracle result missing: run tests/golden/make_fullsize_goldens.py")
     g = fullsize.load(name)
     prec = lbm.FP64 if prec_name == "fp64" else lbm.FP32_SHIFTED
-    (rho, ux, uy), hist = _run(lbm, name, prec, g["steps"])
+    (rho, ux, uy), hist = _run(lbm, name, prec, g["steps"], variant)
     assert np.isfinite(rho).all() and rho.min() > 0
     r = fullsize.compare(name, g, rho, ux, uy, mass0=g["mass0"])
     drift = float(np.abs(hist[:, 1] / hist[0, 1] - 1).max())
@@ -99,7 +101,7 @@ def test_full_length_against_oracle(gpu_lib, name, prec_name):
             assert v <= tol, (k, v, tol)
         if name == "drop_impact_2048":
             # the FP32 distance against 2^29 times the FP64 distance of the same flow
-            (r64, u64x, u64y), _ = _run(lbm, name, lbm.FP64, g["steps"])
+            (r64, u64x, u64y), _ = _run(lbm, name, lbm.FP64, g["steps"], variant)
             d64 = fullsize.compare(name, g, r64, u64x, u64y)
             for k in ("u_linf", "rho_vapor_nodes_max_rel_err"):
                 print("# %s: fp32 %.2e, fp64 %.2e, ratio / 2^29 = %.2f" % (k, r[k], d64[k], r[k] / d64[k] / 2 ** 29))

@@ -52,9 +52,10 @@ def rel_f_err(L, OL):
 # ---------------------------------------------------------------- FP64 elementwise parity
 VARIANTS = [(1, 0), (1, 1), (1, 3), (2, 0)]  # (kernel variant, band rows): march auto/1/3 rows, row block
 VARIANT_IDS = ["march", "march-h1", "march-h3", "block"]
-# periodic lattices also run the two-step block (58 x 10 tiles, two steps per launch)
-VARIANTS_P = VARIANTS + [(3, 0)]
-VARIANT_IDS_P = VARIANT_IDS + ["block2"]
+# periodic lattices also run the two-step block (58 x 10 tiles, two steps per launch), and every
+# list with it the in-place AA variant (odd step counts end in its swapped layout)
+VARIANTS_P = VARIANTS + [(3, 0), (4, 0)]
+VARIANT_IDS_P = VARIANT_IDS + ["block2", "aa"]
 
 
 @pytest.mark.parametrize("variant,band", VARIANTS_P, ids=VARIANT_IDS_P)
@@ -89,7 +90,7 @@ def test_fp64_shaped_eos_droplet(gpu_lib, shape_kw):
     assert rel_f_err(L, OL) < 1e-12
 
 
-@pytest.mark.parametrize("variant", [2, 3], ids=["block", "block2"])
+@pytest.mark.parametrize("variant", [2, 3, 4], ids=["block", "block2", "aa"])
 def test_fp64_droplet_1000_steps(gpu_lib, variant):
     """FP64 path over 1000 steps (shaped PR droplet, MRT, Li forcing) against the oracle run of the
     same length: the rounding-order differences stay at the 1e-12 level on a relaxing droplet."""
@@ -115,8 +116,9 @@ def test_fp64_walls_variable_tau_moving_droplet(gpu_lib, variant, band):
     assert rel_f_err(L, OL) < 1e-12
 
 
+@pytest.mark.parametrize("variant", [3, 4], ids=["block2", "aa"])
 @pytest.mark.parametrize("nx,ny,liquid_floor", [(61, 3, False), (60, 11, False), (7, 27, True), (130, 1, True)])
-def test_fp64_walls_two_step_short_channels(gpu_lib, nx, ny, liquid_floor):
+def test_fp64_walls_two_step_short_channels(gpu_lib, nx, ny, liquid_floor, variant):
     """Walled lattices shorter than the two-step tile and its ring (1 to 27 rows; one row is a
     wall row at both ends), a planar interface across x, after 1, 2 and 31 steps.  The floor's
     solid density is rho_l where the channel is tall or short enough to stay stable with it."""
@@ -126,17 +128,19 @@ def test_fp64_walls_two_step_short_channels(gpu_lib, nx, ny, liquid_floor):
     rho0 = rho0 * (1 + 0.01 * random_field(nx, ny, 1.0, 1.0, seed=nx + 100 * ny))
     wall = (e.rho_l if liquid_floor else e.rho_v, e.rho_v)
     for steps in (1, 2, 31):
-        L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, steps, tau=TAU_MRT, walls=True, wall=wall, variant=3)
+        L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, steps, tau=TAU_MRT, walls=True, wall=wall,
+                               variant=variant)
         assert rel_f_err(L, OL) < 1e-12, (nx, ny, steps)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3], ids=["march", "block", "block2"])
-def test_fp64_macros_match_oracle(gpu_lib, variant):
+@pytest.mark.parametrize("variant,steps", [(1, 30), (2, 30), (3, 30), (4, 30), (4, 31)],
+                         ids=["march", "block", "block2", "aa", "aa-odd"])
+def test_fp64_macros_match_oracle(gpu_lib, variant, steps):
     kw = dict(Tr=0.6)
     e, _, _, _ = both_eos(gpu_lib, **kw)
     nx, ny = 75, 66
     rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=15, W=6)
-    L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, 30, tau=TAU_MRT, variant=variant)
+    L, OL, _, _ = run_pair(gpu_lib, nx, ny, kw, rho0, steps, tau=TAU_MRT, variant=variant)
     g = {k: v.cpu().numpy() if hasattr(v, "cpu") else v for k, v in L.macros().items()}
     m = OL.macros()
     for k in ("rho", "ux", "uy", "psi", "p", "Fx", "Fy"):
@@ -186,8 +190,8 @@ def test_fp32_shift_reference_ablation(gpu_lib):
     assert err["rho_l"] > 1e-3 and err["rho_l"] > 30 * err["rho_v"]
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["march", "block"])
-def test_fp32_one_step_elementwise(gpu_lib, variant):
+@pytest.mark.parametrize("variant,t0", [(1, 50), (2, 50), (4, 50), (4, 51)], ids=["march", "block", "aa", "aa-odd"])
+def test_fp32_one_step_elementwise(gpu_lib, variant, t0):
     """One FP32-shifted step from an FP32-representable state against the FP64 oracle step.
 
     Inputs are identical, so the difference is the FP32 arithmetic of one collision: each
@@ -201,7 +205,7 @@ def test_fp32_one_step_elementwise(gpu_lib, variant):
     P = gpu_lib.make_params(nx, ny, e, sigma=s, tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7], prec=gpu_lib.FP32_SHIFTED,
                             kernel_variant=variant)
     L = gpu_lib.Lattice(P, rho0, device="cuda:0")
-    L.step(50)
+    L.step(t0)
     f_t = L.populations().cpu().numpy()
     L.step(1)
     f_g = L.populations().cpu().numpy()
@@ -254,7 +258,7 @@ def test_fp32_two_step_launch_elementwise(gpu_lib):
     assert np.abs(f[3] - f[2]).max() <= 1e-6 * dev
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3], ids=["march", "block", "block2"])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4], ids=["march", "block", "block2", "aa"])
 def test_fp32_mass_drift_droplet(gpu_lib, variant):
     """FP64 per-node rest population keeps the FP32-shifted mass exact: drift <= 1e-10 relative."""
     kw = dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
@@ -449,7 +453,7 @@ def test_unstable_state_is_reported(gpu_lib):
 def test_invalid_parameters_rejected(gpu_lib):
     e, _ = gpu_lib.eos_build(gpu_lib.make_eos(Tr=0.7))
     for bad in (dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.5, 0.5]), dict(G=1.0), dict(prec=1, rho_ref=-1.0),
-                dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.8, 0.9]), dict(kernel_variant=4)):
+                dict(tau=[1, 1, 1, 1, 1, 1, 1, 0.8, 0.9]), dict(kernel_variant=5)):
         P = gpu_lib.make_params(8, 8, e, **bad)
         with pytest.raises(gpu_lib.LbmError) as ei:
             gpu_lib.Lattice(P, np.full((8, 8), e.rho_v), device="cuda:0")

@@ -220,6 +220,32 @@ def test_tile_rows_outside_the_shapes_are_refused():
         assert rc == lbm.LBM_EINVAL and b"tile_rows" in lbm.load().lbm_last_error(), (prec, h, rc)
 
 
+def test_aa_variant_takes_one_buffer_and_a_psi_plane():
+    """LBM_VARIANT_AA: the workspace grows by one psi plane in the storage precision (and holds one
+    FP64 partial triple per 64 x 4 block), and lbm_init refuses a second population buffer before
+    touching a device; variants beyond AA are refused."""
+    e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
+    for prec, tsz in ((lbm.FP32_SHIFTED, 4), (lbm.FP64, 8)):
+        for nx, ny in ((64, 64), (130, 37), (1000, 1000)):
+            P = lbm.make_params(nx, ny, e, sigma=s, prec=prec, kernel_variant=lbm.VARIANT_AA)
+            Pm = lbm.make_params(nx, ny, e, sigma=s, prec=prec, kernel_variant=lbm.VARIANT_MARCH)
+            ld, pb, wb = lbm.layout(P)
+            assert (ld, pb) == lbm.layout(Pm)[:2]
+            assert lbm.describe(P)[0] == lbm.VARIANT_AA
+            blocks = -(-nx // 64) * -(-ny // 4)
+            assert wb >= 256 + blocks * 3 * 8 + 4096 * 4 * 8 + ld * ny * tsz, (prec, nx, ny)
+    P = lbm.make_params(64, 64, e, sigma=s, kernel_variant=lbm.VARIANT_AA)
+    ld, pb, wb = lbm.layout(P)
+    f, g, ws = (C.c_char * pb)(), (C.c_char * pb)(), (C.c_char * wb)()
+    rho = (C.c_double * (64 * 64))()
+    ctx = C.c_void_p()
+    rc = lbm.load().lbm_init(C.byref(ctx), C.byref(P), f, g, ws, wb, rho, None, None, None)
+    assert rc == lbm.LBM_EINVAL and b"AA" in lbm.load().lbm_last_error()
+    P = lbm.make_params(64, 64, e, sigma=s, kernel_variant=lbm.VARIANT_AA + 1)
+    rc = lbm.load().lbm_init(C.byref(ctx), C.byref(P), f, None, ws, wb, rho, None, None, None)
+    assert rc == lbm.LBM_EINVAL and b"kernel_variant" in lbm.load().lbm_last_error()
+
+
 def test_bench_reduction_schedule_puts_a_reducing_step_in_every_window():
     """Whatever --steps and --warmup are, the timed window [warmup, warmup + steps) holds at least one
     step t with t % reduce_every == 0, and the count the bench reports is the true count."""
