@@ -191,9 +191,11 @@ int lbm_init_static(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, co
 
 /* The two-step tile a context runs (LBM_VARIANT_BLOCK2): output rows and
  * wavefronts per workgroup, as lbm_describe reports them, after lbm_init's
- * timing when tile_rows = -1 (lbm_init then times 3 launches of each
- * candidate on f_b, reading the initial state in f_a, and synchronises the
- * stream).  LBM_EINVAL for a null context or another variant. */
+ * timing when tile_rows = -1 (lbm_init then runs the lattice from its
+ * initial state for a few launches of each candidate, alternating f_a and f_b
+ * as lbm_step does, times them with HIP events, writes the initial state
+ * again and synchronises the stream).  LBM_EINVAL for a null context or
+ * another variant. */
 int lbm_tile_shape(const lbm_ctx* ctx, int* rows_out, int* waves_out);
 
 /* Advance nsteps time steps (Eq. LBE).  Asynchronous: device-side

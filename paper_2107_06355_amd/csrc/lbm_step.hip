@@ -723,11 +723,12 @@ int check_init(const lbm_params* p, void* f_a, void* f_b, const double* rho0, si
     return LBM_OK;
 }
 
-// tile_rows = -1: time each candidate two-step tile shape on the second population buffer,
-// reading the initial state, and keep the fastest.  Three rounds over the candidates, each
-// candidate one launch to warm up and then 3 timed, and a candidate's time is its best round,
-// so that a stall in one round does not decide.  The error word is reset afterwards: the
-// timed launches take the lattice's first two steps, which the real run repeats.
+// tile_rows = -1: time each candidate two-step tile shape and keep the fastest.  The timed
+// launches advance the lattice from its initial state, alternating the two population
+// buffers as a run does (so that each launch reads what the one before it wrote, as in the
+// L2 and the MALL of a real run); the caller writes the initial state again afterwards.
+// Three rounds over the candidates, each candidate one launch to warm up and then 4 timed,
+// and a candidate's time is its best round, so that a stall in one round does not decide.
 int time_tile_shapes(lbm_ctx* c, hipStream_t s)
 {
     TwoStepShape cand[kMaxShapes];
@@ -746,9 +747,11 @@ int time_tile_shapes(lbm_ctx* c, hipStream_t s)
         for (int i = 0; i < n && ok; ++i) {
             c->shape = cand[i];
             fill_args(c);
-            for (int r = 0; r < 4 && ok; ++r) {
+            for (int r = 0; r < 5 && ok; ++r) {
                 if (r == 1) ok = hip_ok(hipEventRecord(e0, s), "tile timing");
                 if (ok) ok = f32 ? launch_step2<float>(c, nullptr, s) : launch_step2<double>(c, nullptr, s);
+                c->cur ^= 1;
+                c->step += 2;
             }
             float ms = 0.0f;
             ok = ok && hip_ok(hipEventRecord(e1, s), "tile timing") && hip_ok(hipEventSynchronize(e1), "tile timing") &&
@@ -761,13 +764,11 @@ int time_tile_shapes(lbm_ctx* c, hipStream_t s)
         if (best_ms[i] < best_ms[best]) best = i;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    c->cur = 0;
+    c->step = 0;
     if (!ok) return LBM_EHIP;
     c->shape = cand[best];
     fill_args(c);
-    const unsigned init_err[2] = {0u, 0xffffffffu};
-    if (!hip_ok(hipMemcpyAsync(c->err, init_err, sizeof(init_err), hipMemcpyHostToDevice, s), "lbm_init error word") ||
-        !hip_ok(hipStreamSynchronize(s), "lbm_init sync"))
-        return LBM_EHIP;
     return LBM_OK;
 }
 
@@ -807,14 +808,25 @@ int init_ctx(lbm_ctx* c, const lbm_params* p, void* f_a, void* f_b, void* ws, si
         !hip_ok(hipStreamSynchronize(s), "lbm_init sync"))
         return LBM_EHIP;
     if (c->aa) return aa_init(c, rho0, ux0, uy0, s) ? LBM_OK : LBM_EHIP;
-    StepArgs A = c->args;
-    A.dst = c->buf[0];
-    dim3 g((p->nx + 127) / 128, p->ny);
-    if (p->prec == LBM_FP32_SHIFTED) hipLaunchKernelGGL(k_init<float>, g, dim3(128), 0, s, A, rho0, ux0, uy0);
-    else hipLaunchKernelGGL(k_init<double>, g, dim3(128), 0, s, A, rho0, ux0, uy0);
-    if (!hip_ok(hipGetLastError(), "k_init launch")) return LBM_EHIP;
-    if (c->blk2 && p->tile_rows == -1) return time_tile_shapes(c, s);
-    return LBM_OK;
+    // tile_rows = -1: the candidate shapes are timed on the lattice's own run from the initial
+    // state, which is then written again (and the error word cleared) for the real run
+    const bool timed = c->blk2 && p->tile_rows == -1;
+    for (int pass = 0; pass < (timed ? 2 : 1); ++pass) {
+        StepArgs A = c->args;
+        A.dst = c->buf[0];
+        dim3 g((p->nx + 127) / 128, p->ny);
+        if (p->prec == LBM_FP32_SHIFTED) hipLaunchKernelGGL(k_init<float>, g, dim3(128), 0, s, A, rho0, ux0, uy0);
+        else hipLaunchKernelGGL(k_init<double>, g, dim3(128), 0, s, A, rho0, ux0, uy0);
+        if (!hip_ok(hipGetLastError(), "k_init launch")) return LBM_EHIP;
+        if (timed && pass == 0) {
+            const int st = time_tile_shapes(c, s);
+            if (st != LBM_OK) return st;
+            if (!hip_ok(hipMemcpyAsync(c->err, init_err, sizeof(init_err), hipMemcpyHostToDevice, s),
+                        "lbm_init error word"))
+                return LBM_EHIP;
+        }
+    }
+    return timed ? (hip_ok(hipStreamSynchronize(s), "lbm_init sync") ? LBM_OK : LBM_EHIP) : LBM_OK;
 }
 
 // Workspace of lbm_init_static: one file-scope array per GPU (each device the library runs

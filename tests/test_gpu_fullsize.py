@@ -251,11 +251,10 @@ def test_tile_heights_give_identical_populations(gpu_lib, prec_name, case):
     _check_vapor(lbm, prec, out[heights[0]], f_o, e, 8)
 
 
-# tile_rows = -1: lbm_init times the candidate tile shapes on the lattice's own populations and keeps
-# the fastest.  The timing launches write only the second population buffer, so the lattice starts
-# from its initial state whichever shape wins; the 2048 x 1024 drop impact (the benchmark's lattice)
-# must then match a lattice built with that height explicitly, bit for bit, after 100 steps with a
-# reduction every 10 steps.
+# tile_rows = -1: lbm_init times the candidate tile shapes on the lattice's own run from its initial
+# state, keeps the fastest and writes the initial state again; the 2048 x 1024 drop impact (the
+# benchmark's lattice) must then match a lattice built with that height explicitly, bit for bit, after
+# 100 steps with a reduction every 10 steps.
 @pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
 def test_timed_tile_shape_matches_the_explicit_one(gpu_lib, prec_name):
     from lbm_inputs import DROP_IMPACT_2048, drop_impact_fields, drop_impact_tau
