@@ -661,6 +661,8 @@ def main():
     ap.add_argument("--only", default="", help="fp32 | fp64: time one precision of the workload legs")
     ap.add_argument("--sweep", default="2048,4096,8192,16384", help="lattice sides of the HBM sweep")
     ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--batched-steps", type=int, default=20000, help="timed steps of the batched leg")
+    ap.add_argument("--aa-steps", type=int, default=1000, help="timed steps of the AA leg on the impact lattice")
     ap.add_argument("--tile-rows", default="-1,-1",
                     help="two-step tile height FP32,FP64 (lbm_params.tile_rows): -1 timed at lattice creation, "
                          "0 the library's rule, 10..18 / 5..10 a fixed height")
@@ -749,9 +751,9 @@ def main():
     if "sweep" in legs:
         out["sweep"] = sweep_leg(lbm, [int(v) for v in args.sweep.split(",") if v.strip()], args.sweep_steps, args.only)
     if "aa" in legs:
-        out["aa"] = aa_leg(lbm)
+        out["aa"] = aa_leg(lbm, steps=args.aa_steps, big_steps=max(2, args.aa_steps // 50))
     if "batched" in legs:
-        out["batched"] = batched_leg(lbm)
+        out["batched"] = batched_leg(lbm, steps=args.batched_steps)
     if "fd" in legs:
         out["fd"] = fd_leg(lbm)
         out["fd_4096"] = fd_leg(lbm, n=4096, steps=50)
