@@ -183,7 +183,8 @@ int lbm_init(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, void* ws,
  * (a later call on the same device ends the earlier one; lbm_destroy on it
  * does nothing).  LBM_EINVAL when the lattice needs more workspace than
  * 16 MiB (lbm_layout's ws_bytes: two-step lattices up to about 4096 x 4096
- * fit), LBM_EHIP when the array's device address cannot be looked up.  The
+ * fit) or for tile_rows = -1 (its timing creates HIP events), LBM_EHIP when
+ * the array's device address cannot be looked up.  The
  * array keeps the last call's contents, and every call on one GPU shares it:
  * calls that overlap on one GPU race. */
 int lbm_init_static(lbm_ctx** ctx, const lbm_params* p, void* f_a, void* f_b, const double* rho0,

@@ -904,6 +904,11 @@ int lbm_init_static(lbm_ctx** out, const lbm_params* p, void* f_a, void* f_b, co
     size_t need;
     int st = check_init(p, f_a, f_b, rho0, &need);
     if (st != LBM_OK) return st;
+    if (p->tile_rows == -1) {
+        // the timing creates HIP events: not for callers that cannot allocate
+        lbm_set_error("lbm_init_static: tile_rows = -1 (timed tile shapes) is not available here; use 0 or a height");
+        return LBM_EINVAL;
+    }
     if (need > kScratchBytes) {
         char buf[160];
         std::snprintf(buf, sizeof(buf), "lbm_init_static: the lattice needs %zu bytes of workspace, more than the "

@@ -220,6 +220,19 @@ def test_tile_rows_outside_the_shapes_are_refused():
         assert rc == lbm.LBM_EINVAL and b"tile_rows" in lbm.load().lbm_last_error(), (prec, h, rc)
 
 
+def test_static_init_refuses_timed_tile_shapes():
+    """lbm_init_static allocates nothing, so it refuses tile_rows = -1 (whose timing creates HIP events)
+    before touching a device."""
+    e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
+    P = lbm.make_params(64, 64, e, sigma=s, tile_rows=-1)
+    ld, pb, wb = lbm.layout(P)
+    f, g = (C.c_char * pb)(), (C.c_char * pb)()
+    rho = (C.c_double * (64 * 64))()
+    ctx = C.c_void_p()
+    rc = lbm.load().lbm_init_static(C.byref(ctx), C.byref(P), f, g, rho, None, None, None)
+    assert rc == lbm.LBM_EINVAL and b"tile_rows" in lbm.load().lbm_last_error()
+
+
 def test_aa_variant_takes_one_buffer_and_a_psi_plane():
     """LBM_VARIANT_AA: the workspace grows by one psi plane in the storage precision (and holds one
     FP64 partial triple per 64 x 4 block), and lbm_init refuses a second population buffer before
