@@ -69,6 +69,8 @@ def kernel_name(lbm, P, shape=None):
         return "k_step<%s, 0>" % t, 1
     if var == lbm.VARIANT_BLOCK:
         return "k_step_blk<%s, 0>" % t, 1
+    if var == lbm.VARIANT_AA:
+        return "k_aa_step<%s, false, 0>" % t, 1  # with k_aa_psi, and the odd-step instances
     nt = 2 * lbm.layout(P)[1] <= STREAM_BYTES
     # one row per wavefront: tiles of waves - 6 rows; two: up to 2 waves - 6
     kern = "k_step2_rows2" if rows > waves - 6 else "k_step2_blk"

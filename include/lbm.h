@@ -157,7 +157,8 @@ int lbm_layout(const lbm_params* p, int* ld_out, size_t* pop_bytes_out, size_t* 
  * workgroup (rows + 6 = wavefronts x rows per wavefront; two rows per
  * wavefront when rows + 6 < 2 x wavefronts + 1, i.e. rows > wavefronts - 6).
  * With tile_rows = -1 this is the shape before lbm_init times the candidates:
- * lbm_tile_shape reports the one a context runs. */
+ * lbm_tile_shape reports the one a context runs.  LBM_VARIANT_AA: 4 rows and
+ * 4 wavefronts per workgroup. */
 int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int* waves_out);
 
 /* Create a context over caller buffers f_a, f_b (lbm_layout bytes each) and

@@ -681,6 +681,10 @@ int lbm_describe(const lbm_params* p, int* variant_out, int* band_rows_out, int*
         const TwoStepShape sh = two_step_shape(*p);
         if (band_rows_out) *band_rows_out = sh.rows;
         if (waves_out) *waves_out = sh.waves;
+    } else if (v == LBM_VARIANT_AA) {
+        // 256-thread workgroups of 4 rows x 64 columns, one wavefront per row
+        if (band_rows_out) *band_rows_out = 4;
+        if (waves_out) *waves_out = 4;
     } else {
         if (band_rows_out) *band_rows_out = seg_h;
         if (waves_out) *waves_out = nw;

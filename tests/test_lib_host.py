@@ -244,7 +244,7 @@ def test_aa_variant_takes_one_buffer_and_a_psi_plane():
             Pm = lbm.make_params(nx, ny, e, sigma=s, prec=prec, kernel_variant=lbm.VARIANT_MARCH)
             ld, pb, wb = lbm.layout(P)
             assert (ld, pb) == lbm.layout(Pm)[:2]
-            assert lbm.describe(P)[0] == lbm.VARIANT_AA
+            assert lbm.describe(P) == (lbm.VARIANT_AA, 4, 4)
             blocks = -(-nx // 64) * -(-ny // 4)
             assert wb >= 256 + blocks * 3 * 8 + 4096 * 4 * 8 + ld * ny * tsz, (prec, nx, ny)
     P = lbm.make_params(64, 64, e, sigma=s, kernel_variant=lbm.VARIANT_AA)
