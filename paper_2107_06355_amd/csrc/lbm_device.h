@@ -147,6 +147,7 @@ struct StepArgs {
     double tau_v, dtau_drho, tau_lo, tau_hi, rho_v_tau;
     double rho_ref;
     double psi_lo, psi_hi;
+    int unit_rates;          // tau = 1 for e, eps, q_x and q_y (node_collide skips those moments)
     Coef<double> cd;
     Coef<float> cf;
     DevEos eos;
@@ -422,10 +423,6 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
     const T s58 = (gp[5] + gp[6]) + (gp[7] + gp[8]);
     T jx, jy;
     node_j<T>(gp, jx, jy);
-    const T me = -4 * g0t - s14 + 2 * s58;
-    const T mq = 4 * g0t - 2 * s14 + s58;
-    const T mqx = -2 * (gp[1] - gp[3]) + ((gp[5] - gp[6]) - (gp[7] - gp[8]));
-    const T mqy = -2 * (gp[2] - gp[4]) + ((gp[5] + gp[6]) - (gp[7] + gp[8]));
     const T mxx = (gp[1] - gp[2]) + (gp[3] - gp[4]);
     const T mxy = (gp[5] - gp[6]) + (gp[7] - gp[8]);
     // forced velocity (Eq. Momentum)
@@ -451,7 +448,6 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
     if (MODE == MODE_MACROS) return false;
     // rates (Eq. RelaxationMatrix; Eq. RelaxationTime on the shear moments)
     const Coef<T>& K = coef<T>(A);
-    const T se = K.se, sq = K.sq, sqx = K.sqx, sqy = K.sqy;
     T snu = K.snu, hnu = K.hnu;
     if (A.var_tau) {
         double tau = A.tau_v + A.dtau_drho * (rho_d - A.rho_v_tau);
@@ -471,10 +467,24 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
     const T Se = (T)6 * uF * K.he + K.le * F2;
     const T Sq = -(T)6 * uF * K.hq - K.lq * F2;
     // relaxed moments m* = m - Lambda (m - m^eq) + (I - Lambda/2) S
-    const T ne = (me - se * (me - eqe) + Se) * (T)(1.0 / 36.0);
-    const T nq = (mq - sq * (mq - eqq) + Sq) * (T)(1.0 / 36.0);
-    const T nqx = (mqx - sqx * (mqx + rho * ux) - K.hqx * Fx) * (T)(1.0 / 12.0);
-    const T nqy = (mqy - sqy * (mqy + rho * uy) - K.hqy * Fy) * (T)(1.0 / 12.0);
+    T ne, nq, nqx, nqy;
+    if (A.unit_rates) {
+        // rate 1 for e, eps, q_x, q_y: m* = m^eq + (I - Lambda/2) S, whatever m is, so those
+        // four moments of the populations are not formed
+        ne = (eqe + Se) * (T)(1.0 / 36.0);
+        nq = (eqq + Sq) * (T)(1.0 / 36.0);
+        nqx = (-(rho * ux) - K.hqx * Fx) * (T)(1.0 / 12.0);
+        nqy = (-(rho * uy) - K.hqy * Fy) * (T)(1.0 / 12.0);
+    } else {
+        const T me = -4 * g0t - s14 + 2 * s58;
+        const T mq = 4 * g0t - 2 * s14 + s58;
+        const T mqx = -2 * (gp[1] - gp[3]) + ((gp[5] - gp[6]) - (gp[7] - gp[8]));
+        const T mqy = -2 * (gp[2] - gp[4]) + ((gp[5] + gp[6]) - (gp[7] + gp[8]));
+        ne = (me - K.se * (me - eqe) + Se) * (T)(1.0 / 36.0);
+        nq = (mq - K.sq * (mq - eqq) + Sq) * (T)(1.0 / 36.0);
+        nqx = (mqx - K.sqx * (mqx + rho * ux) - K.hqx * Fx) * (T)(1.0 / 12.0);
+        nqy = (mqy - K.sqy * (mqy + rho * uy) - K.hqy * Fy) * (T)(1.0 / 12.0);
+    }
     const T nxx = (mxx - snu * (mxx - eqxx) + hnu * (T)2 * (ux * Fx - uy * Fy)) * (T)0.25;
     const T nxy = (mxy - snu * (mxy - eqxy) + hnu * (ux * Fy + uy * Fx)) * (T)0.25;
     const T n0 = dr * (T)(1.0 / 9.0);
@@ -1086,6 +1096,7 @@ inline void fill_coef(StepArgs& A, const double tau[9], double G, double sigma)
     c.G = G;
     c.two_inv_G = 2.0 / G;
     A.cd = c;
+    A.unit_rates = tau[1] == 1.0 && tau[2] == 1.0 && tau[4] == 1.0 && tau[6] == 1.0;
     A.cf = Coef<float>{(float)c.se, (float)c.sq, (float)c.sqx, (float)c.sqy, (float)c.snu,
                        (float)c.he, (float)c.hq, (float)c.hqx, (float)c.hqy, (float)c.hnu,
                        (float)c.le, (float)c.lq, (float)c.G, (float)c.two_inv_G};
