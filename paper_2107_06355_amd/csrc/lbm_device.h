@@ -491,16 +491,21 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
     const T njx = (jx + Fx) * (T)(1.0 / 6.0);
     const T njy = (jy + Fy) * (T)(1.0 / 6.0);
     // f* = M^-1 m* = M^T diag(1/9,1/36,1/36,1/6,1/12,1/6,1/12,1/4,1/4) m*
+    // the rows of M^T pair up as +-: each pair shares its sum and difference terms
     const T a14 = n0 - ne - 2 * nq;
     const T a58 = n0 + 2 * ne + nq;
-    o[1] = a14 + njx - 2 * nqx + nxx;
-    o[2] = a14 + njy - 2 * nqy - nxx;
-    o[3] = a14 - njx + 2 * nqx + nxx;
-    o[4] = a14 - njy + 2 * nqy - nxx;
-    o[5] = a58 + njx + nqx + njy + nqy + nxy;
-    o[6] = a58 - njx - nqx + njy + nqy - nxy;
-    o[7] = a58 - njx - nqx - njy - nqy + nxy;
-    o[8] = a58 + njx + nqx - njy - nqy - nxy;
+    const T px = njx - 2 * nqx, py = njy - 2 * nqy;
+    const T c13 = a14 + nxx, c24 = a14 - nxx;
+    o[1] = c13 + px;
+    o[3] = c13 - px;
+    o[2] = c24 + py;
+    o[4] = c24 - py;
+    const T X = njx + nqx, Y = njy + nqy;
+    const T dp = a58 + nxy, dm = a58 - nxy, sp = X + Y, sm = X - Y;
+    o[5] = dp + sp;
+    o[7] = dp - sp;
+    o[6] = dm - sm;
+    o[8] = dm + sm;
     // rest population: exact node mass in FP64 (conserved by the collision)
     o0 = drp - ((((double)o[1] + (double)o[2]) + ((double)o[3] + (double)o[4])) +
                 (((double)o[5] + (double)o[6]) + ((double)o[7] + (double)o[8])));

@@ -205,7 +205,12 @@ def test_recorded_forward_keeps_reductions_and_limits(gpu_lib):
     B.step(23)
     ha, hb = A.history(), B.history()
     assert ha.shape == hb.shape == (5, 4)
-    np.testing.assert_allclose(ha, hb, rtol=1e-13, atol=1e-16)
+    np.testing.assert_array_equal(ha[:, 0], hb[:, 0])
+    np.testing.assert_allclose(ha[:, 1], hb[:, 1], rtol=1e-13, atol=0)
+    # the momenta of the static droplet are zero up to rounding, summed in two orders (the recording
+    # forward reduces with the row-block kernel, the plain one inside its two-step launch): they agree
+    # to the rounding of 2100 terms rho u, far below 1e-15 of the mass
+    np.testing.assert_allclose(ha[:, 2:], hb[:, 2:], rtol=0, atol=1e-15 * hb[0, 1])
     np.testing.assert_allclose(A.populations().cpu().numpy(), B.populations().cpu().numpy(), rtol=1e-14, atol=0)
     with pytest.raises(lbm.LbmError) as ei:
         A.step(1)
