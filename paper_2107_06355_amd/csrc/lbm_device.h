@@ -459,48 +459,59 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
     const T uF = ux * Fx + uy * Fy;
     const T F2 = Ftx * Ftx + Fty * Fty;  // |F|^2/psi^2
     // equilibrium deviation moments (M f^eq minus the rho_ref rest state)
-    const T eqe = -2 * dr + 3 * rho * u2;
-    const T eqq = dr - 3 * rho * u2;
     const T eqxx = rho * (ux * ux - uy * uy);
     const T eqxy = rho * ux * uy;
-    // Eq. LiFS source, multiplied by (I - Lambda/2)
+    // Eq. LiFS source of e, multiplied by (I - Lambda/2)
     const T Se = (T)6 * uF * K.he + K.le * F2;
-    const T Sq = -(T)6 * uF * K.hq - K.lq * F2;
-    // relaxed moments m* = m - Lambda (m - m^eq) + (I - Lambda/2) S
-    T ne, nq, nqx, nqy;
+    // relaxed moments m* = m - Lambda (m - m^eq) + (I - Lambda/2) S, folded into the parts of
+    // f* = M^T D m* that the pairs of populations share: a14 (1-4) and a58 (5-8) isotropic,
+    // px, py (axis pairs) and X, Y (diagonal pairs) from j* and q*
+    const T n0 = dr * (T)(1.0 / 9.0);
+    const T njx = (jx + Fx) * (T)(1.0 / 6.0);
+    const T njy = (jy + Fy) * (T)(1.0 / 6.0);
+    T a14, a58, px, py, X, Y;
     if (A.unit_rates) {
-        // rate 1 for e, eps, q_x, q_y: m* = m^eq + (I - Lambda/2) S, whatever m is, so those
-        // four moments of the populations are not formed
-        ne = (eqe + Se) * (T)(1.0 / 36.0);
-        nq = (eqq + Sq) * (T)(1.0 / 36.0);
-        nqx = (-(rho * ux) - K.hqx * Fx) * (T)(1.0 / 12.0);
-        nqy = (-(rho * uy) - K.hqy * Fy) * (T)(1.0 / 12.0);
+        // rate 1 for e, eps, q_x, q_y: m* = m^eq + (I - Lambda/2) S for them, whatever m is,
+        // so those four moments of the populations are not formed.  With tau_e = tau_eps the
+        // eps source is -S_e, and with e^eq = -2 drho + 3 rho u^2, eps^eq = drho - 3 rho u^2
+        // the isotropic parts reduce to drho/9 + Z and drho/36 + Z, Z = (3 rho u^2 + S_e)/36.
+        // q^eq = -rho u = -(j + F/2) (Eq. Momentum) and (1 - s/2) F = F/2 give q* = -(j + F),
+        // i.e. the q part of each pair is -1/2 of its j part (j* = j + F).
+        const T Z = ((T)3 * rho * u2 + Se) * (T)(1.0 / 36.0);
+        a14 = n0 + Z;
+        a58 = dr * (T)(1.0 / 36.0) + Z;
+        px = (T)2 * njx;
+        py = (T)2 * njy;
+        X = (T)0.5 * njx;
+        Y = (T)0.5 * njy;
     } else {
+        const T eqe = -2 * dr + 3 * rho * u2;
+        const T eqq = dr - 3 * rho * u2;
+        const T Sq = -(T)6 * uF * K.hq - K.lq * F2;
         const T me = -4 * g0t - s14 + 2 * s58;
         const T mq = 4 * g0t - 2 * s14 + s58;
         const T mqx = -2 * (gp[1] - gp[3]) + ((gp[5] - gp[6]) - (gp[7] - gp[8]));
         const T mqy = -2 * (gp[2] - gp[4]) + ((gp[5] + gp[6]) - (gp[7] + gp[8]));
-        ne = (me - K.se * (me - eqe) + Se) * (T)(1.0 / 36.0);
-        nq = (mq - K.sq * (mq - eqq) + Sq) * (T)(1.0 / 36.0);
-        nqx = (mqx - K.sqx * (mqx + rho * ux) - K.hqx * Fx) * (T)(1.0 / 12.0);
-        nqy = (mqy - K.sqy * (mqy + rho * uy) - K.hqy * Fy) * (T)(1.0 / 12.0);
+        const T ne = (me - K.se * (me - eqe) + Se) * (T)(1.0 / 36.0);
+        const T nq = (mq - K.sq * (mq - eqq) + Sq) * (T)(1.0 / 36.0);
+        const T nqx = (mqx - K.sqx * (mqx + rho * ux) - K.hqx * Fx) * (T)(1.0 / 12.0);
+        const T nqy = (mqy - K.sqy * (mqy + rho * uy) - K.hqy * Fy) * (T)(1.0 / 12.0);
+        a14 = n0 - ne - 2 * nq;
+        a58 = n0 + 2 * ne + nq;
+        px = njx - 2 * nqx;
+        py = njy - 2 * nqy;
+        X = njx + nqx;
+        Y = njy + nqy;
     }
     const T nxx = (mxx - snu * (mxx - eqxx) + hnu * (T)2 * (ux * Fx - uy * Fy)) * (T)0.25;
     const T nxy = (mxy - snu * (mxy - eqxy) + hnu * (ux * Fy + uy * Fx)) * (T)0.25;
-    const T n0 = dr * (T)(1.0 / 9.0);
-    const T njx = (jx + Fx) * (T)(1.0 / 6.0);
-    const T njy = (jy + Fy) * (T)(1.0 / 6.0);
     // f* = M^-1 m* = M^T diag(1/9,1/36,1/36,1/6,1/12,1/6,1/12,1/4,1/4) m*
     // the rows of M^T pair up as +-: each pair shares its sum and difference terms
-    const T a14 = n0 - ne - 2 * nq;
-    const T a58 = n0 + 2 * ne + nq;
-    const T px = njx - 2 * nqx, py = njy - 2 * nqy;
     const T c13 = a14 + nxx, c24 = a14 - nxx;
     o[1] = c13 + px;
     o[3] = c13 - px;
     o[2] = c24 + py;
     o[4] = c24 - py;
-    const T X = njx + nqx, Y = njy + nqy;
     const T dp = a58 + nxy, dm = a58 - nxy, sp = X + Y, sm = X - Y;
     o[5] = dp + sp;
     o[7] = dp - sp;
