@@ -124,6 +124,9 @@ struct Coef {
     T he, hq, hqx, hqy, hnu;   // 1 - s/2 (the (I - Lambda/2) factor of the source)
     T le, lq;                  // Eq. LiFS: 12 sigma (1 - s/2) / (tau - 1/2) for e and eps
     T G, two_inv_G;            // Eq. ShanChenForce and Eq. InteractionPotential
+    // node_collide's folded constants: (1 - s_nu)/4, s_nu/4, (1 - s_nu/2)/2, (1 - s_nu/2)/4 of the
+    // shear moments (constant rates only), and (1 - s_e/2)/6, le/36 of the e source
+    T sh1, sh2, sh3, sh4, he6, le36;
 };
 
 struct StepArgs {
@@ -448,12 +451,15 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
     if (MODE == MODE_MACROS) return false;
     // rates (Eq. RelaxationMatrix; Eq. RelaxationTime on the shear moments)
     const Coef<T>& K = coef<T>(A);
-    T snu = K.snu, hnu = K.hnu;
+    T sh1 = K.sh1, sh2 = K.sh2, sh3 = K.sh3, sh4 = K.sh4;
     if (A.var_tau) {
         double tau = A.tau_v + A.dtau_drho * (rho_d - A.rho_v_tau);
         tau = fmin(fmax(tau, A.tau_lo), A.tau_hi);
-        snu = (T)(1.0 / tau);
-        hnu = (T)1 - (T)0.5 * snu;
+        const T snu = (T)(1.0 / tau), hnu = (T)1 - (T)0.5 * snu;
+        sh1 = ((T)1 - snu) * (T)0.25;
+        sh2 = snu * (T)0.25;
+        sh3 = hnu * (T)0.5;
+        sh4 = hnu * (T)0.25;
     }
     const T u2 = ux * ux + uy * uy;
     const T uF = ux * Fx + uy * Fy;
@@ -461,30 +467,31 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
     // equilibrium deviation moments (M f^eq minus the rho_ref rest state)
     const T eqxx = rho * (ux * ux - uy * uy);
     const T eqxy = rho * ux * uy;
-    // Eq. LiFS source of e, multiplied by (I - Lambda/2)
-    const T Se = (T)6 * uF * K.he + K.le * F2;
     // relaxed moments m* = m - Lambda (m - m^eq) + (I - Lambda/2) S, folded into the parts of
     // f* = M^T D m* that the pairs of populations share: a14 (1-4) and a58 (5-8) isotropic,
     // px, py (axis pairs) and X, Y (diagonal pairs) from j* and q*
     const T n0 = dr * (T)(1.0 / 9.0);
-    const T njx = (jx + Fx) * (T)(1.0 / 6.0);
-    const T njy = (jy + Fy) * (T)(1.0 / 6.0);
+    const T jFx = jx + Fx, jFy = jy + Fy;  // j* = j + F
     T a14, a58, px, py, X, Y;
     if (A.unit_rates) {
         // rate 1 for e, eps, q_x, q_y: m* = m^eq + (I - Lambda/2) S for them, whatever m is,
         // so those four moments of the populations are not formed.  With tau_e = tau_eps the
-        // eps source is -S_e, and with e^eq = -2 drho + 3 rho u^2, eps^eq = drho - 3 rho u^2
-        // the isotropic parts reduce to drho/9 + Z and drho/36 + Z, Z = (3 rho u^2 + S_e)/36.
-        // q^eq = -rho u = -(j + F/2) (Eq. Momentum) and (1 - s/2) F = F/2 give q* = -(j + F),
-        // i.e. the q part of each pair is -1/2 of its j part (j* = j + F).
-        const T Z = ((T)3 * rho * u2 + Se) * (T)(1.0 / 36.0);
+        // eps source is -S_e (Eq. LiFS), and with e^eq = -2 drho + 3 rho u^2, eps^eq = drho -
+        // 3 rho u^2 the isotropic parts reduce to drho/9 + Z and drho/36 + Z, Z = (3 rho u^2 +
+        // S_e)/36.  q^eq = -rho u = -(j + F/2) (Eq. Momentum) and (1 - s/2) F = F/2 give q* =
+        // -(j + F): the j and q parts of each pair add up to (j + F)/3 on the axes and
+        // (j + F)/12 on the diagonals.
+        const T Z = (rho * u2) * (T)(1.0 / 12.0) + (uF * K.he6 + F2 * K.le36);
         a14 = n0 + Z;
         a58 = dr * (T)(1.0 / 36.0) + Z;
-        px = (T)2 * njx;
-        py = (T)2 * njy;
-        X = (T)0.5 * njx;
-        Y = (T)0.5 * njy;
+        px = jFx * (T)(1.0 / 3.0);
+        py = jFy * (T)(1.0 / 3.0);
+        X = jFx * (T)(1.0 / 12.0);
+        Y = jFy * (T)(1.0 / 12.0);
     } else {
+        const T njx = jFx * (T)(1.0 / 6.0), njy = jFy * (T)(1.0 / 6.0);
+        // Eq. LiFS sources of e and eps, multiplied by (I - Lambda/2)
+        const T Se = (T)6 * uF * K.he + K.le * F2;
         const T eqe = -2 * dr + 3 * rho * u2;
         const T eqq = dr - 3 * rho * u2;
         const T Sq = -(T)6 * uF * K.hq - K.lq * F2;
@@ -503,8 +510,9 @@ __device__ __forceinline__ bool node_collide(const StepArgs& A, const Lane& L, i
         X = njx + nqx;
         Y = njy + nqy;
     }
-    const T nxx = (mxx - snu * (mxx - eqxx) + hnu * (T)2 * (ux * Fx - uy * Fy)) * (T)0.25;
-    const T nxy = (mxy - snu * (mxy - eqxy) + hnu * (ux * Fy + uy * Fx)) * (T)0.25;
+    // shear moments (Eq. RelaxationTime when var_tau): (m - s (m - m^eq) + (1 - s/2) S) / 4
+    const T nxx = mxx * sh1 + (eqxx * sh2 + (ux * Fx - uy * Fy) * sh3);
+    const T nxy = mxy * sh1 + (eqxy * sh2 + (ux * Fy + uy * Fx) * sh4);
     // f* = M^-1 m* = M^T diag(1/9,1/36,1/36,1/6,1/12,1/6,1/12,1/4,1/4) m*
     // the rows of M^T pair up as +-: each pair shares its sum and difference terms
     const T c13 = a14 + nxx, c24 = a14 - nxx;
@@ -1111,11 +1119,18 @@ inline void fill_coef(StepArgs& A, const double tau[9], double G, double sigma)
     c.lq = 12.0 * sigma * c.hq / (tau[2] - 0.5);
     c.G = G;
     c.two_inv_G = 2.0 / G;
+    c.sh1 = (1.0 - s[7]) * 0.25;
+    c.sh2 = s[7] * 0.25;
+    c.sh3 = c.hnu * 0.5;
+    c.sh4 = c.hnu * 0.25;
+    c.he6 = c.he / 6.0;
+    c.le36 = c.le / 36.0;
     A.cd = c;
     A.unit_rates = tau[1] == 1.0 && tau[2] == 1.0 && tau[4] == 1.0 && tau[6] == 1.0;
     A.cf = Coef<float>{(float)c.se, (float)c.sq, (float)c.sqx, (float)c.sqy, (float)c.snu,
                        (float)c.he, (float)c.hq, (float)c.hqx, (float)c.hqy, (float)c.hnu,
-                       (float)c.le, (float)c.lq, (float)c.G, (float)c.two_inv_G};
+                       (float)c.le, (float)c.lq, (float)c.G, (float)c.two_inv_G, (float)c.sh1, (float)c.sh2,
+                       (float)c.sh3, (float)c.sh4, (float)c.he6, (float)c.le36};
 }
 
 inline int validate(const lbm_params* p)
