@@ -707,8 +707,11 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
     // between the halves): both kernels are latency-bound at the sizes the adjoint runs,
     // and each fills the issue slots the other leaves.  The recomputation touches only
     // the lattice's population buffers and its half of the records; the transposed steps
-    // only lambda, the accumulators and the other half.
-    const bool piped = !recorded && S > 1 && rec_bytes >= 2 * L.rec_bytes;
+    // only lambda, the accumulators and the other half.  FP32-shifted storage only: the
+    // FP64 transposed step holds a whole CU per workgroup (96 VGPRs), and sharing the CUs
+    // with the recomputation made the FP64 adjoint slower (measured at 512^2: 106.8 ms on
+    // one stream, 110.5 ms on two; FP32 64.7 ms against 60.8 ms).
+    const bool piped = !recorded && S > 1 && rec_bytes >= 2 * L.rec_bytes && P.prec == LBM_FP32_SHIFTED;
     AuxStream aux;
     if (piped && !aux.open(s)) return LBM_EHIP;
     hipStream_t sr = piped ? aux.s : s;  // the recomputation's stream

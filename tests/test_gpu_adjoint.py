@@ -138,9 +138,10 @@ def test_adjoint_one_segment_equals_many(gpu_lib):
 
 
 # A record buffer of two segments makes lbm_adjoint recompute the next segment on a second stream
-# while the transposed steps run over the current one.  The same kernels run on the same data in
-# the same order on each stream, so the gradients equal those of the one-stream schedule bit for bit:
-# small lattices of both kinds and a 256 x 256 droplet (14 segments, ragged last) in both precisions.
+# while the transposed steps run over the current one (FP32-shifted storage; FP64 keeps one stream).
+# The same kernels run on the same data in the same order on each stream, so the gradients equal those
+# of the one-stream schedule bit for bit: small lattices of both kinds and a 256 x 256 droplet (14
+# segments, ragged last) in both precisions.
 @pytest.mark.parametrize("case", ["droplet", "walls", "droplet256"])
 @pytest.mark.parametrize("prec_name", ["fp64", "fp32"])
 def test_overlapped_recomputation_equals_one_stream(gpu_lib, case, prec_name):
