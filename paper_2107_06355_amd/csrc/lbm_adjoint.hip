@@ -164,10 +164,12 @@ __device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T
     const T n7 = ((mu[1] - mu[2]) + (mu[3] - mu[4])) * (T)0.25;
     const T n8 = ((mu[5] - mu[6]) + (mu[7] - mu[8])) * (T)0.25;
     // m*_k = m_k - s_k (m_k - m^eq_k) + (1 - s_k/2) S_k: direct, equilibrium and source adjoints
-    const T d1 = n1 * ((T)1 - K.se), E1 = n1 * K.se, Q1 = n1 * K.he;
-    const T d2 = n2 * ((T)1 - K.sq), E2 = n2 * K.sq, Q2 = n2 * K.hq;
-    const T d4 = n4 * ((T)1 - K.sqx), E4 = n4 * K.sqx, Q4 = n4 * K.hqx;
-    const T d6 = n6 * ((T)1 - K.sqy), E6 = n6 * K.sqy, Q6 = n6 * K.hqy;
+    // (rate 1 for e, eps, q_x, q_y: no direct part, the equilibrium part whole, half the source)
+    const bool u1 = S.unit_rates;
+    const T d1 = u1 ? (T)0 : n1 * ((T)1 - K.se), E1 = u1 ? n1 : n1 * K.se, Q1 = u1 ? (T)0.5 * n1 : n1 * K.he;
+    const T d2 = u1 ? (T)0 : n2 * ((T)1 - K.sq), E2 = u1 ? n2 : n2 * K.sq, Q2 = u1 ? (T)0.5 * n2 : n2 * K.hq;
+    const T d4 = u1 ? (T)0 : n4 * ((T)1 - K.sqx), E4 = u1 ? n4 : n4 * K.sqx, Q4 = u1 ? (T)0.5 * n4 : n4 * K.hqx;
+    const T d6 = u1 ? (T)0 : n6 * ((T)1 - K.sqy), E6 = u1 ? n6 : n6 * K.sqy, Q6 = u1 ? (T)0.5 * n6 : n6 * K.hqy;
     const T d7 = n7 * ((T)1 - K.snu), E7 = n7 * K.snu, Q7 = n7 * K.hnu;
     const T d8 = n8 * ((T)1 - K.snu), E8 = n8 * K.snu, Q8 = n8 * K.hnu;
     // conserved moments: m*_0 = rho, m*_3 = j_x + F_x, m*_5 = j_y + F_y
@@ -200,6 +202,20 @@ __device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T
     o.dftx = dftx;
     o.dfty = dfty;
     // rho = sum f, j = sum f c, m_k = sum M_ki f_i
+    if (u1) {
+        // d1 = d2 = d4 = d6 = 0
+        o.df[0] = drho;
+        const T cp = drho + d7, cm = drho - d7, dp = drho + d8, dm = drho - d8, sp = djx + djy, sm = djx - djy;
+        o.df[1] = cp + djx;
+        o.df[3] = cp - djx;
+        o.df[2] = cm + djy;
+        o.df[4] = cm - djy;
+        o.df[5] = dp + sp;
+        o.df[7] = dp - sp;
+        o.df[6] = dm - sm;
+        o.df[8] = dm + sm;
+        return;
+    }
     o.df[0] = drho - 4 * d1 + 4 * d2;
     const T b14 = drho - d1 - 2 * d2;
     o.df[1] = b14 + djx - 2 * d4 + d7;
