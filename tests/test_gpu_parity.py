@@ -190,26 +190,31 @@ def test_fp32_shift_reference_ablation(gpu_lib):
     assert err["rho_l"] > 1e-3 and err["rho_l"] > 30 * err["rho_v"]
 
 
-@pytest.mark.parametrize("variant,t0", [(1, 50), (2, 50), (4, 50), (4, 51)], ids=["march", "block", "aa", "aa-odd"])
-def test_fp32_one_step_elementwise(gpu_lib, variant, t0):
+@pytest.mark.parametrize("rates", ["unit", "mrt"])
+@pytest.mark.parametrize("variant,t0", [(1, 50), (2, 50), (3, 50), (4, 50), (4, 51)],
+                         ids=["march", "block", "block2", "aa", "aa-odd"])
+def test_fp32_one_step_elementwise(gpu_lib, variant, t0, rates):
     """One FP32-shifted step from an FP32-representable state against the FP64 oracle step.
 
     Inputs are identical, so the difference is the FP32 arithmetic of one collision: each
     stored deviation carries ~2^-24 relative rounding of the moment terms it sums; the
-    bound 2e-6 * max|f - w rho_ref| allows ~30 roundings of the largest term.
+    bound 2e-6 * max|f - w rho_ref| allows ~30 roundings of the largest term.  Both collision
+    forms: rate 1 for e, eps, q (the folded form) and general MRT rates.  (The two-step block
+    takes a single step here: the step after an even count is a one-step launch when it is the
+    last one.)
     """
+    tau = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7] if rates == "unit" else [1.0, 1.1, 1.25, 1.0, 1.15, 1.0, 1.15, 0.8, 0.8]
     kw = dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
     e, s, eo, so = both_eos(gpu_lib, **kw)
     nx, ny = 128, 96
     rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=25, W=20)
-    P = gpu_lib.make_params(nx, ny, e, sigma=s, tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7], prec=gpu_lib.FP32_SHIFTED,
-                            kernel_variant=variant)
+    P = gpu_lib.make_params(nx, ny, e, sigma=s, tau=tau, prec=gpu_lib.FP32_SHIFTED, kernel_variant=variant)
     L = gpu_lib.Lattice(P, rho0, device="cuda:0")
     L.step(t0)
     f_t = L.populations().cpu().numpy()
     L.step(1)
     f_g = L.populations().cpu().numpy()
-    OL = O.Lattice(O.make_params(nx, ny, eo, sigma=so, tau=[1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]))
+    OL = O.Lattice(O.make_params(nx, ny, eo, sigma=so, tau=tau))
     OL.set_f(f_t)
     OL.run(1)
     f_o = OL.get_f()
@@ -229,13 +234,15 @@ def _assert_vapor_density(f_g, f_o, e, steps):
     assert err <= 1e-6 * steps, err
 
 
-def test_fp32_two_step_launch_elementwise(gpu_lib):
+@pytest.mark.parametrize("rates", ["unit", "mrt"])
+def test_fp32_two_step_launch_elementwise(gpu_lib, rates):
     """One two-step launch (LDS-held intermediate state) from an FP32-representable state against
-    two FP64 oracle steps, and against two launches of the one-step block kernel."""
+    two FP64 oracle steps, and against two launches of the one-step block kernel; both collision
+    forms (rate 1 for e, eps, q, and general MRT rates)."""
     kw = dict(base=1, a=2 / 49, b=2 / 21, omega=0.344, Tr=0.5, scale=0.25, shape=1, alpha=0.3, k_vap=4.0)
     e, s, eo, so = both_eos(gpu_lib, **kw)
     nx, ny = 128, 96
-    tau = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7]
+    tau = [1, 1, 1, 1, 1, 1, 1, 0.7, 0.7] if rates == "unit" else [1.0, 1.1, 1.25, 1.0, 1.15, 1.0, 1.15, 0.8, 0.8]
     rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=25, W=20)
     f = {}
     for variant in (2, 3):
