@@ -42,8 +42,10 @@ struct AdjArgs {
     const void* lam_in;  // lambda^{t+1}: 9 planes [ny][ld]
     void* lam_out;       // lambda^t
     const void* rec;     // step t: drho, j_x, j_y, psi planes [ny][nx]
+    const void* rec_lo;  // step t - 1 (two transposed steps per launch)
     double* acc;         // [blocks][kAcc] running sums
     int strips;          // column strips of kAdjW outputs
+    int strips2;         // column strips of kAdj2W outputs (two steps per launch)
     size_t lplane, rplane;
     double c_e, c_q;     // 1/(tau_e - 1/2), 1/(tau_eps - 1/2) of Eq. LiFS
     double inv_G;
@@ -84,33 +86,48 @@ __device__ __forceinline__ T ldT(const void* base, size_t i)
 // node coordinates with periodic wrap in x and y (walls handled by the callers)
 __device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
 
-// psi and F~ at (x, y) from the recorded psi plane (ghost psi beyond the walls)
+// what the transposed step at (x, y) reads of record rec: drho, j and the 3 x 3 psi stencil
+// (ghost psi beyond the walls)
 template <typename T>
-__device__ __forceinline__ void rec_force(const AdjArgs& A, int x, int y, T& psi, T& ftx, T& fty)
+struct RecNode {
+    T dr, jx, jy;
+    T p[9];  // rows y - 1, y, y + 1; columns x - 1, x, x + 1
+};
+
+template <typename T>
+__device__ __forceinline__ void rec_load(const AdjArgs& A, const void* rec, int x, int y, RecNode<T>& R)
 {
     const StepArgs& S = A.S;
-    const T* ps = (const T*)A.rec + 3 * A.rplane;
+    const size_t o = (size_t)y * S.nx + x;
+    R.dr = ((const T*)rec)[o];
+    R.jx = ((const T*)rec)[A.rplane + o];
+    R.jy = ((const T*)rec)[2 * A.rplane + o];
+    const T* ps = (const T*)rec + 3 * A.rplane;
     const int xm = x == 0 ? S.nx - 1 : x - 1, xp = x == S.nx - 1 ? 0 : x + 1;
+    // the rows above and below with the periodic wrap (always in the lattice); beyond a wall
+    // the loaded values are replaced by the ghost psi, so no load waits on a branch
+    const T* rm = ps + (size_t)(y == 0 ? S.ny - 1 : y - 1) * S.nx;
     const T* rc = ps + (size_t)y * S.nx;
-    T lm, cm, rm, ln, cn, rn;
-    if (S.walls && y == 0) {
-        lm = cm = rm = (T)S.psi_lo;
-    } else {
-        const T* r = ps + (size_t)(y == 0 ? S.ny - 1 : y - 1) * S.nx;
-        lm = r[xm];
-        cm = r[x];
-        rm = r[xp];
-    }
-    if (S.walls && y == S.ny - 1) {
-        ln = cn = rn = (T)S.psi_hi;
-    } else {
-        const T* r = ps + (size_t)(y == S.ny - 1 ? 0 : y + 1) * S.nx;
-        ln = r[xm];
-        cn = r[x];
-        rn = r[xp];
-    }
-    psi = rc[x];
-    force_tilde<T>(S, lm, cm, rm, rc[xm], rc[xp], ln, cn, rn, ftx, fty);
+    const T* rp = ps + (size_t)(y == S.ny - 1 ? 0 : y + 1) * S.nx;
+    const bool lo = S.walls && y == 0, hi = S.walls && y == S.ny - 1;
+    const T glo = (T)S.psi_lo, ghi = (T)S.psi_hi;
+    R.p[0] = lo ? glo : rm[xm];
+    R.p[1] = lo ? glo : rm[x];
+    R.p[2] = lo ? glo : rm[xp];
+    R.p[3] = rc[xm];
+    R.p[4] = rc[x];
+    R.p[5] = rc[xp];
+    R.p[6] = hi ? ghi : rp[xm];
+    R.p[7] = hi ? ghi : rp[x];
+    R.p[8] = hi ? ghi : rp[xp];
+}
+
+// psi and F~ (Eq. ShanChenForce) of a loaded record
+template <typename T>
+__device__ __forceinline__ void rec_force(const StepArgs& S, const RecNode<T>& R, T& psi, T& ftx, T& fty)
+{
+    psi = R.p[4];
+    force_tilde<T>(S, R.p[0], R.p[1], R.p[2], R.p[3], R.p[5], R.p[6], R.p[7], R.p[8], ftx, fty);
 }
 
 // mu_i = dL/df*_i(x) = lambda^{t+1}_i(x + c_i), or lambda^{t+1}_opp(i)(x) when x + c_i is solid
@@ -229,12 +246,64 @@ __device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T
     o.df[8] = b58 + djx + d4 - djy - d6 - d8;
 }
 
+// In the loop of a Smooth / Modified Smooth EOS (Sec. III.D): adds dL/dp(rho) = P times the
+// derivatives of p(rho) with respect to the loop coefficients to v.
+__device__ __forceinline__ void knot_adjoint(const DevEos& E, double rho, double P, double v[kAcc])
+{
+    // each branch sets its four terms; the sums below use fixed indices, so that v stays in
+    // registers
+    double pmax = 0, pmin = 0, rmax = 0, rmin = 0, b1 = 0, a1 = 0, b3 = 0, a3 = 0;
+    if (rho <= E.rho_max) {
+        const double dd = rho - E.rho_max, sq = sqrt(1.0 - dd * dd * E.inv_a1sq);
+        pmax = P;
+        b1 = -P * (1.0 - sq);
+        a1 = P * E.b1 * dd * dd * E.inv_a1sq * E.inv_a1sq / (2.0 * sq);
+        rmax = P * E.b1 * dd * E.inv_a1sq / sq;
+    } else if (rho < E.rho_min) {
+        const double tt = (rho - E.rho_max) * E.inv_L;
+        const double h = tt * tt * (3.0 - 2.0 * tt), hp = 6.0 * tt * (1.0 - tt);
+        pmax = P * (1.0 - h);
+        pmin = P * h;
+        rmax = P * (E.p_min - E.p_max) * hp * (tt - 1.0) * E.inv_L;
+        rmin = P * (E.p_min - E.p_max) * hp * (-tt) * E.inv_L;
+    } else {
+        const double dd = rho - E.rho_min, sq = sqrt(1.0 - dd * dd * E.inv_a3sq);
+        pmin = P;
+        b3 = P * (1.0 - sq);
+        a3 = -P * E.b3 * dd * dd * E.inv_a3sq * E.inv_a3sq / (2.0 * sq);
+        rmin = -P * E.b3 * dd * E.inv_a3sq / sq;
+    }
+    v[A_PMAX] += pmax;
+    v[A_PMIN] += pmin;
+    v[A_RMAX] += rmax;
+    v[A_RMIN] += rmin;
+    v[A_B1] += b1;
+    v[A_A1] += a1;
+    v[A_B3] += b3;
+    v[A_A3] += a3;
+}
+
+__device__ __forceinline__ bool knot_node(const DevEos& E, double rho)
+{
+    return (E.shape == LBM_SHAPE_SMOOTH || E.shape == LBM_SHAPE_MODSMOOTH) && rho > E.rho_v && rho < E.rho_l;
+}
+
+// the loop-coefficient part of psi_adjoint alone, for a node whose dL/dpsi is known
+template <typename T>
+__device__ __forceinline__ void knot_adjoint_of(const AdjArgs& A, double rho, T psi, T dpsi, double v[kAcc])
+{
+    if (psi > (T)0 && knot_node(A.S.eos, rho)) {
+        const double inv_gpsi = A.inv_G / (double)psi;
+        knot_adjoint(A.S.eos, rho, (double)dpsi * inv_gpsi, v);
+    }
+}
+
 // dL/drho(x) through psi(rho(x)) (Eq. InteractionPotential: psi' = (p' - 1/3)/(G psi),
 // dpsi/dp = 1/(G psi)) for a given dL/dpsi(x); also adds the psi part of dL/dG to vG and,
-// in the loop of a Smooth / Modified Smooth EOS (Sec. III.D), dL/dp(rho(x)) times the
-// derivatives of p with respect to the loop coefficients to v.
+// with knots set, the loop-coefficient derivatives (knot_adjoint) to v.
 template <typename T>
-__device__ __forceinline__ T psi_adjoint(const AdjArgs& A, double rho, T psi, T dpsi, double v[kAcc], T& vG)
+__device__ __forceinline__ T psi_adjoint(const AdjArgs& A, double rho, T psi, T dpsi, double* v, T& vG,
+                                         bool knots = true)
 {
     const StepArgs& S = A.S;
     const DevEos& E = S.eos;
@@ -251,29 +320,7 @@ __device__ __forceinline__ T psi_adjoint(const AdjArgs& A, double rho, T psi, T 
         } else {
             const double inv_gpsi = A.inv_G / (double)psi;
             drho_eos = (T)((dev_eos_dp(E, rho) - 1.0 / 3.0) * inv_gpsi * (double)dpsi);
-            const double P = (double)dpsi * inv_gpsi;  // dL/dp(rho(x))
-            if (in_loop && (E.shape == LBM_SHAPE_SMOOTH || E.shape == LBM_SHAPE_MODSMOOTH)) {
-                if (rho <= E.rho_max) {
-                    const double dd = rho - E.rho_max, sq = sqrt(1.0 - dd * dd * E.inv_a1sq);
-                    v[A_PMAX] += P;
-                    v[A_B1] += -P * (1.0 - sq);
-                    v[A_A1] += P * E.b1 * dd * dd * E.inv_a1sq * E.inv_a1sq / (2.0 * sq);
-                    v[A_RMAX] += P * E.b1 * dd * E.inv_a1sq / sq;
-                } else if (rho < E.rho_min) {
-                    const double tt = (rho - E.rho_max) * E.inv_L;
-                    const double h = tt * tt * (3.0 - 2.0 * tt), hp = 6.0 * tt * (1.0 - tt);
-                    v[A_PMAX] += P * (1.0 - h);
-                    v[A_PMIN] += P * h;
-                    v[A_RMAX] += P * (E.p_min - E.p_max) * hp * (tt - 1.0) * E.inv_L;
-                    v[A_RMIN] += P * (E.p_min - E.p_max) * hp * (-tt) * E.inv_L;
-                } else {
-                    const double dd = rho - E.rho_min, sq = sqrt(1.0 - dd * dd * E.inv_a3sq);
-                    v[A_PMIN] += P;
-                    v[A_B3] += P * (1.0 - sq);
-                    v[A_A3] += -P * E.b3 * dd * dd * E.inv_a3sq * E.inv_a3sq / (2.0 * sq);
-                    v[A_RMIN] += -P * E.b3 * dd * E.inv_a3sq / sq;
-                }
-            }
+            if (knots && knot_node(E, rho)) knot_adjoint(E, rho, (double)dpsi * inv_gpsi, v);
         }
     }
     return drho_eos;
@@ -334,17 +381,18 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
     const bool fluid = S.walls ? (y >= 0 && y < S.ny) : true;
     const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y))
                            : (S.ny >= 11 ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
-    const size_t o = (size_t)yw * S.nx + x;
     // running sum of accumulator k of this workgroup, read early (updated at the end by lane 0 of wave k)
     const double acc_prev = (k < kAcc && lane == 0) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
 
     T mu[9];
     pull_adjoint<T>(A, x, yw, mu);
+    RecNode<T> rn;
+    rec_load<T>(A, A.rec, x, yw, rn);
     T psi, ftx, fty;
-    rec_force<T>(A, x, yw, psi, ftx, fty);
-    const T dr = ldT<T>(A.rec, o);
+    rec_force<T>(S, rn, psi, ftx, fty);
+    const T dr = rn.dr;
     LocalAdj<T> L;
-    local_adjoint<T>(A, mu, dr, ldT<T>(A.rec, A.rplane + o), ldT<T>(A.rec, 2 * A.rplane + o), psi, ftx, fty, L);
+    local_adjoint<T>(A, mu, dr, rn.jx, rn.jy, psi, ftx, fty, L);
     sfx[k][lane] = fluid ? L.dftx : (T)0;
     sfy[k][lane] = fluid ? L.dfty : (T)0;
     __syncthreads();
@@ -377,6 +425,153 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
     if (k < kAcc) {
         double s = 0.0;
         for (int w = 0; w < kAdjWaves; ++w) s += sred[k][w][lane];
+        s = wave_sum(s);
+        if (lane == 0) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
+    }
+}
+
+// Two transposed steps per launch: lambda^{t+1} -> lambda^t -> lambda^{t-1}, with lambda^t and
+// the dL/dF~ of both steps kept in LDS.  lambda^{t-1}(x) depends on lambda^{t+1} within two
+// nodes of x (the pull and the transpose of Eq. ShanChenForce each reach one node) and on the
+// records of both steps, so a workgroup of NW waves (one lattice row each) computes the first
+// step on NW x 64 nodes, its output on the inner (NW - 2) x 62, the second step's local part on
+// (NW - 4) x 60 and its output on (NW - 6) x 58: those 58-column, (NW - 6)-row tiles partition
+// the lattice.  Each tile adds the parameter derivatives of its own nodes for both steps.
+constexpr int kAdj2W = 58;  // output columns per wave
+
+template <int NW>
+struct Adj2Lds {
+    static constexpr int R = NW - 6;  // output rows per workgroup
+    static constexpr size_t lam_bytes(size_t tsz) { return 8 * NW * 64 * tsz; }
+    static constexpr size_t red_bytes = (size_t)kAcc * R * 64 * sizeof(double);
+    static constexpr size_t union_bytes(size_t tsz) { return lam_bytes(tsz) > red_bytes ? lam_bytes(tsz) : red_bytes; }
+};
+
+// The kernel's AdjArgs argument (the first, at offset 0 of the argument segment) through a
+// pointer the compiler cannot follow: a phase that reads its constants from it reloads them
+// with scalar loads instead of keeping an earlier phase's scalar registers live.
+__device__ __forceinline__ const AdjArgs& reloaded_args()
+{
+    typedef const __attribute__((address_space(4))) AdjArgs KArgs;
+    KArgs* p = (KArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(const AdjArgs*)p;
+}
+
+template <typename T, bool NT, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_adj2_blk(AdjArgs A)
+{
+    constexpr int R = Adj2Lds<NW>::R;
+    __shared__ T sfx[NW][64], sfy[NW][64];
+    // lambda^t, populations 1..8 ([i - 1][wave][lane]); after the second step the same
+    // memory holds the workgroup sum's staging ([accumulator][output row][lane])
+    __shared__ __align__(16) char ubuf[Adj2Lds<NW>::union_bytes(sizeof(T))];
+    T(*lam)[NW][64] = reinterpret_cast<T(*)[NW][64]>(ubuf);
+    double(*red)[R][64] = reinterpret_cast<double(*)[R][64]>(ubuf);
+    const StepArgs& S = A.S;
+    const int lane = threadIdx.x & 63;
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int strip = blockIdx.x % A.strips2, band = blockIdx.x / A.strips2;
+    const int xs = strip * kAdj2W - 3 + lane;  // unwrapped column of this lane
+    // xs lies in [-3, nx + 60] and y in [-3, ny + NW - 5]: one wrap each way on lattices at
+    // least 64 wide and NW tall, remainders otherwise
+    const int x = S.nx >= 64 ? wrapx(xs, S.nx) : ((xs % S.nx) + S.nx) % S.nx;
+    const int y = band * R - 3 + k;  // unwrapped row of this wave
+    const bool fluid = S.walls ? (y >= 0 && y < S.ny) : true;
+    const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y))
+                           : (S.ny >= NW ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
+    const bool own = k >= 3 && k < 3 + R && y < S.ny && lane >= 3 && lane < 3 + kAdj2W && xs < S.nx;
+    const double acc_prev = (k < kAcc && lane == 0) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
+    const T iG = adj_coef<T>(A).inv_G;
+    // what the first step leaves for the parameter sums of this node
+    T a_psi = 0, a_dpsi = 0, a_dr = 0, a_vG = 0, a_sig = 0;
+
+    // first step (record t), every node of the block
+    T psi, ftx, fty, dr;
+    LocalAdj<T> L;
+    RecNode<T> rb;  // record t - 1 of this node, loaded before the first barrier
+    {
+        T mu[9];
+        pull_adjoint<T>(A, x, yw, mu);
+        RecNode<T> ra;
+        rec_load<T>(A, A.rec, x, yw, ra);
+        rec_force<T>(S, ra, psi, ftx, fty);
+        dr = ra.dr;
+        local_adjoint<T>(A, mu, dr, ra.jx, ra.jy, psi, ftx, fty, L);
+    }
+    if (k >= 2 && k <= NW - 3) rec_load<T>(A, A.rec_lo, x, yw, rb);
+    sfx[k][lane] = fluid ? L.dftx : (T)0;
+    sfy[k][lane] = fluid ? L.dfty : (T)0;
+    __syncthreads();
+    T lam0 = 0;  // lambda^t_0 of this node
+    if (k >= 1 && k <= NW - 2) {
+        if (lane >= 1 && lane <= 62) {
+            T vG = (ftx * L.dftx + fty * L.dfty) * iG;
+            const T dpsi = L.dpsi + force_transpose<T, NW>(S, sfx, sfy, k, lane, y);
+            if (own) ghost_G<T>(A, y, L.dfty, vG);
+            // the loop-coefficient part waits until the end (knot_adjoint_of), so that no FP64
+            // sums are live through the second step
+            const T drho_eos = psi_adjoint<T>(A, S.rho_ref + (double)dr, psi, dpsi, nullptr, vG, false);
+            a_psi = psi;
+            a_dpsi = dpsi;
+            a_dr = dr;
+            a_vG = vG;
+            a_sig = L.dsig;
+            lam0 = L.df[0] + drho_eos;
+#pragma unroll
+            for (int i = 1; i < 9; ++i) lam[i - 1][k][lane] = L.df[i] + drho_eos;
+        }
+    }
+    __syncthreads();
+
+    // second step (record t - 1) on waves 2 .. NW - 3: lambda^t pulled from LDS
+    if (k >= 2 && k <= NW - 3) {
+        T mu[9];
+        const int lp = lane < 63 ? lane + 1 : 63, lm = lane > 0 ? lane - 1 : 0;
+        const bool top = S.walls && y == S.ny - 1, bot = S.walls && y == 0;
+        mu[0] = lam0;
+        mu[1] = lam[0][k][lp];
+        mu[3] = lam[2][k][lm];
+        mu[2] = top ? lam[3][k][lane] : lam[1][k + 1][lane];
+        mu[5] = top ? lam[6][k][lane] : lam[4][k + 1][lp];
+        mu[6] = top ? lam[7][k][lane] : lam[5][k + 1][lm];
+        mu[4] = bot ? lam[1][k][lane] : lam[3][k - 1][lane];
+        mu[7] = bot ? lam[4][k][lane] : lam[6][k - 1][lm];
+        mu[8] = bot ? lam[5][k][lane] : lam[7][k - 1][lp];
+        const AdjArgs& B = reloaded_args();
+        rec_force<T>(B.S, rb, psi, ftx, fty);
+        dr = rb.dr;
+        local_adjoint<T>(B, mu, dr, rb.jx, rb.jy, psi, ftx, fty, L);
+        sfx[k][lane] = fluid ? L.dftx : (T)0;
+        sfy[k][lane] = fluid ? L.dfty : (T)0;
+    }
+    __syncthreads();
+    double v[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (own) {
+        const AdjArgs& B = reloaded_args();
+        const StepArgs& SB = B.S;
+        knot_adjoint_of<T>(B, SB.rho_ref + (double)a_dr, a_psi, a_dpsi, v);
+        T vG = (ftx * L.dftx + fty * L.dfty) * adj_coef<T>(B).inv_G;
+        const T dpsi = L.dpsi + force_transpose<T, NW>(SB, sfx, sfy, k, lane, y);
+        ghost_G<T>(B, y, L.dfty, vG);
+        const T drho_eos = psi_adjoint<T>(B, SB.rho_ref + (double)dr, psi, dpsi, v, vG);
+        v[A_G] = (double)a_vG + (double)vG;
+        v[A_SIG] = (double)a_sig + (double)L.dsig;
+        T* Lo = (T*)B.lam_out;
+        const size_t li = (size_t)y * SB.ld + x;
+        for (int i = 0; i < 9; ++i) {
+            if constexpr (NT) __builtin_nontemporal_store((T)(L.df[i] + drho_eos), Lo + i * B.lplane + li);
+            else Lo[i * B.lplane + li] = L.df[i] + drho_eos;
+        }
+    }
+    // fixed-order workgroup sum over the output rows, then one wave per accumulator sums its
+    // 64 columns (the staging reuses lambda^t's LDS, read before the last barrier)
+    if (k >= 3 && k < 3 + R)
+        for (int i = 0; i < kAcc; ++i) red[i][k - 3][lane] = v[i];
+    __syncthreads();
+    if (k < kAcc) {
+        double s = 0.0;
+        for (int w = 0; w < R; ++w) s += red[k][w][lane];
         s = wave_sum(s);
         if (lane == 0) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
     }
@@ -506,9 +701,22 @@ void launch_adj_step(bool f32, bool nt, int blocks, hipStream_t s, const AdjArgs
     else hipLaunchKernelGGL((k_adj_blk<double, false>), g, b, 0, s, A);
 }
 
+constexpr int kAdj2Waves = 16;  // waves (rows) per workgroup of the two-step transposed kernel
+
+void launch_adj2_step(bool f32, bool nt, int blocks, hipStream_t s, const AdjArgs& A)
+{
+    const dim3 g(blocks), b(64 * kAdj2Waves);
+    if (f32 && nt) hipLaunchKernelGGL((k_adj2_blk<float, true, kAdj2Waves>), g, b, 0, s, A);
+    else if (f32) hipLaunchKernelGGL((k_adj2_blk<float, false, kAdj2Waves>), g, b, 0, s, A);
+    else if (nt) hipLaunchKernelGGL((k_adj2_blk<double, true, kAdj2Waves>), g, b, 0, s, A);
+    else hipLaunchKernelGGL((k_adj2_blk<double, false, kAdj2Waves>), g, b, 0, s, A);
+}
+
 struct AdjLayout {
     size_t tsz, rec_bytes, off_fT, off_lam0, off_lam1, off_acc, total;
-    int strips, blocks;
+    int strips, blocks;    // one transposed step per launch
+    int strips2, blocks2;  // two per launch
+    size_t nacc;           // accumulators: kAcc per workgroup of the larger grid
 };
 
 AdjLayout adj_layout(const lbm_params& p, int ld, size_t pop_bytes, int K)
@@ -520,6 +728,10 @@ AdjLayout adj_layout(const lbm_params& p, int ld, size_t pop_bytes, int K)
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     L.strips = (p.nx + kAdjW - 1) / kAdjW;
     L.blocks = L.strips * ((p.ny + kAdjRows - 1) / kAdjRows);
+    constexpr int R2 = Adj2Lds<kAdj2Waves>::R;
+    L.strips2 = (p.nx + kAdj2W - 1) / kAdj2W;
+    L.blocks2 = L.strips2 * ((p.ny + R2 - 1) / R2);
+    L.nacc = (size_t)(L.blocks > L.blocks2 ? L.blocks : L.blocks2) * kAcc;
     size_t o = 0;
     L.off_fT = o;
     o += al(pop_bytes);
@@ -528,9 +740,24 @@ AdjLayout adj_layout(const lbm_params& p, int ld, size_t pop_bytes, int K)
     L.off_lam1 = o;
     o += al(9 * lp * L.tsz);
     L.off_acc = o;
-    o += al((size_t)L.blocks * kAcc * sizeof(double));
+    o += al(L.nacc * sizeof(double));
     L.total = o;
     return L;
+}
+
+// Transposed steps from record rec (step t) down: two per launch when the record of step t - 1
+// is given (rec_lo), else one.  lambda moves from lam[li] to lam[li ^ 1].
+bool adj_launch(AdjArgs& A, const void* rec, const void* rec_lo, void* lam[2], int& li, bool f32, bool nt,
+                const AdjLayout& L, hipStream_t s)
+{
+    A.rec = rec;
+    A.rec_lo = rec_lo;
+    A.lam_in = lam[li];
+    A.lam_out = lam[li ^ 1];
+    if (rec_lo) launch_adj2_step(f32, nt, L.blocks2, s, A);
+    else launch_adj_step(f32, nt, L.blocks, s, A);
+    li ^= 1;
+    return hip_ok(hipGetLastError(), "adjoint step launch");
 }
 
 }  // namespace
@@ -675,7 +902,7 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
         return LBM_EHIP;
     void* lam[2] = {ab + L.off_lam0, ab + L.off_lam1};
     double* acc = (double*)(ab + L.off_acc);
-    const size_t nacc = (size_t)L.blocks * kAcc;
+    const size_t nacc = L.nacc;
     hipLaunchKernelGGL(k_zero, dim3(64), dim3(256), 0, s, acc, nacc);
     dim3 g1((P.nx + 127) / 128, P.ny);
 
@@ -684,6 +911,7 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
     A.S = c->args;
     A.acc = acc;
     A.strips = L.strips;
+    A.strips2 = L.strips2;
     A.lplane = lp;
     const bool nt = 2 * 9 * lp * L.tsz <= kStreamBytes;  // streaming lambda stores on small lattices
     A.rplane = nn;
@@ -709,13 +937,11 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
     int li = 0;
     if (recorded) {
         // the forward kept every step's record: transposed steps only, T_end - 1 down to 0
-        for (int64_t j = T_end - 1; j >= 0; --j) {
-            A.rec = (const char*)c->rec_all + (size_t)j * 4 * nn * L.tsz;
-            A.lam_in = lam[li];
-            A.lam_out = lam[li ^ 1];
-            launch_adj_step(f32, nt, L.blocks, s, A);
-            if (!hip_ok(hipGetLastError(), "adjoint step launch")) return LBM_EHIP;
-            li ^= 1;
+        for (int64_t j = T_end - 1; j >= 0; j -= j >= 1 ? 2 : 1) {
+            const char* r = (const char*)c->rec_all;
+            if (!adj_launch(A, r + (size_t)j * 4 * nn * L.tsz, j >= 1 ? r + (size_t)(j - 1) * 4 * nn * L.tsz : nullptr,
+                            lam, li, f32, nt, L, s))
+                return LBM_EHIP;
         }
     }
     // A record buffer of two segments lets the recomputation of segment k - 1 run on a
@@ -758,13 +984,10 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
         if (piped && !(hip_ok(hipEventRecord(aux.rec_ready[half], sr), "adjoint event") &&
                        hip_ok(hipStreamWaitEvent(s, aux.rec_ready[half], 0), "adjoint wait")))
             return LBM_EHIP;
-        for (int j = n - 1; j >= 0; --j) {
-            A.rec = (const char*)seg + (size_t)j * 4 * nn * L.tsz;
-            A.lam_in = lam[li];
-            A.lam_out = lam[li ^ 1];
-            launch_adj_step(f32, nt, L.blocks, s, A);
-            if (!hip_ok(hipGetLastError(), "adjoint step launch")) return LBM_EHIP;
-            li ^= 1;
+        for (int j = n - 1; j >= 0; j -= j >= 1 ? 2 : 1) {
+            if (!adj_launch(A, seg + (size_t)j * 4 * nn * L.tsz, j >= 1 ? seg + (size_t)(j - 1) * 4 * nn * L.tsz : nullptr,
+                            lam, li, f32, nt, L, s))
+                return LBM_EHIP;
         }
         if (piped) {
             if (!hip_ok(hipEventRecord(aux.adj_done[half], s), "adjoint event")) return LBM_EHIP;
