@@ -285,8 +285,8 @@ int lbm_set_recording(lbm_ctx* ctx, void* rec_buf, size_t rec_bytes, int64_t max
  * T is restored on return.  After a recorded forward rec_buf may be NULL (the
  * records are read from the recording buffer); after a checkpointed one it
  * holds one segment (lbm_adjoint_layout's rec_bytes for the same K), or two
- * (twice those bytes or more): then, in LBM_FP32_SHIFTED storage, the
- * recomputation of each segment runs on a second stream of the library's,
+ * (twice those bytes or more): then the recomputation of each segment runs on
+ * a second stream of the library's,
  * beside the transposed steps of the one after it, ordered against `stream` by
  * events.  The result is the same either way. */
 int lbm_adjoint(lbm_ctx* ctx, const double* dL_drho_T, void* rec_buf, size_t rec_bytes, void* adj_buf, size_t adj_bytes,

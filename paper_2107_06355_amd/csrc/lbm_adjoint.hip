@@ -83,6 +83,40 @@ __device__ __forceinline__ T ldT(const void* base, size_t i)
     return ((const T*)base)[i];
 }
 
+// 1/x for the adjoint's own divisions: the hardware estimate (FP32), or in FP64 the estimate
+// refined by two Newton steps (within an ulp or two of the IEEE quotient)
+__device__ __forceinline__ float arcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double arcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// 32-bit DPP move of each half of a double; lanes without a source (or outside row_mask)
+// read 0
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum of v over the 64 lanes, in lane 63, in a fixed order: a scan within each row of 16
+// lanes (row_shr 1, 2, 4, 8), then the row totals carried by row_bcast 15 and 31.
+__device__ __forceinline__ double wave_total63(double v)
+{
+    v += dpp_d<0x111, 0xf>(v);
+    v += dpp_d<0x112, 0xf>(v);
+    v += dpp_d<0x114, 0xf>(v);
+    v += dpp_d<0x118, 0xf>(v);
+    v += dpp_d<0x142, 0xa>(v);
+    v += dpp_d<0x143, 0xc>(v);
+    return v;
+}
+
 // node coordinates with periodic wrap in x and y (walls handled by the callers)
 __device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
 
@@ -163,7 +197,7 @@ __device__ __forceinline__ void local_adjoint(const AdjArgs& A, const T mu[9], T
     const Coef<T>& K = coef<T>(S);
     const T rho = (T)(S.rho_ref + (double)dr);
     const T Fx = psi * ftx, Fy = psi * fty;
-    const T inv = rcp(rho);
+    const T inv = arcp(rho);
     const T ux = (jx + (T)0.5 * Fx) * inv, uy = (jy + (T)0.5 * Fy) * inv;
     // nu = D^-1 M mu  (adjoint of f* = M^T D^-1 m*)
     const T m14 = (mu[1] + mu[2]) + (mu[3] + mu[4]);
@@ -293,7 +327,7 @@ template <typename T>
 __device__ __forceinline__ void knot_adjoint_of(const AdjArgs& A, double rho, T psi, T dpsi, double v[kAcc])
 {
     if (psi > (T)0 && knot_node(A.S.eos, rho)) {
-        const double inv_gpsi = A.inv_G / (double)psi;
+        const double inv_gpsi = A.inv_G * arcp((double)psi);
         knot_adjoint(A.S.eos, rho, (double)dpsi * inv_gpsi, v);
     }
 }
@@ -318,7 +352,7 @@ __device__ __forceinline__ T psi_adjoint(const AdjArgs& A, double rho, T psi, T 
             const float dp = rho <= E.rho_v ? E.fk_vap * dpb : dpb;
             drho_eos = (T)((dp - (1.0f / 3.0f)) * (float)dpsi * rcp((float)G * (float)psi));
         } else {
-            const double inv_gpsi = A.inv_G / (double)psi;
+            const double inv_gpsi = A.inv_G * arcp((double)psi);
             drho_eos = (T)((dev_eos_dp(E, rho) - 1.0 / 3.0) * inv_gpsi * (double)dpsi);
             if (knots && knot_node(E, rho)) knot_adjoint(E, rho, (double)dpsi * inv_gpsi, v);
         }
@@ -381,8 +415,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
     const bool fluid = S.walls ? (y >= 0 && y < S.ny) : true;
     const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y))
                            : (S.ny >= 11 ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
-    // running sum of accumulator k of this workgroup, read early (updated at the end by lane 0 of wave k)
-    const double acc_prev = (k < kAcc && lane == 0) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
+    // running sum of accumulator k of this workgroup, read early (updated at the end by lane 63 of wave k)
+    const double acc_prev = (k < kAcc && lane == 63) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
 
     T mu[9];
     pull_adjoint<T>(A, x, yw, mu);
@@ -425,8 +459,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
     if (k < kAcc) {
         double s = 0.0;
         for (int w = 0; w < kAdjWaves; ++w) s += sred[k][w][lane];
-        s = wave_sum(s);
-        if (lane == 0) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
+        s = wave_total63(s);
+        if (lane == 63) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
     }
 }
 
@@ -481,7 +515,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(
     const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y))
                            : (S.ny >= NW ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
     const bool own = k >= 3 && k < 3 + R && y < S.ny && lane >= 3 && lane < 3 + kAdj2W && xs < S.nx;
-    const double acc_prev = (k < kAcc && lane == 0) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
+    const double acc_prev = (k < kAcc && lane == 63) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
     const T iG = adj_coef<T>(A).inv_G;
     // what the first step leaves for the parameter sums of this node
     T a_psi = 0, a_dpsi = 0, a_dr = 0, a_vG = 0, a_sig = 0;
@@ -572,8 +606,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(
     if (k < kAcc) {
         double s = 0.0;
         for (int w = 0; w < R; ++w) s += red[k][w][lane];
-        s = wave_sum(s);
-        if (lane == 0) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
+        s = wave_total63(s);
+        if (lane == 63) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
     }
 }
 
@@ -602,7 +636,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_seed_u(AdjArgs A, const 
     const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y))
                            : (S.ny >= 11 ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
     const size_t o = (size_t)yw * S.nx + x;
-    const double acc_prev = (k < kAcc && lane == 0) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
+    const double acc_prev = (k < kAcc && lane == 63) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
 
     // the final state at (x, yw): pulled populations, rho, j, psi; dL/dF~ = psi dL/dF, dL/dF = g / (2 rho)
     const View<T> V = make_view<T>(fT, S.plane);
@@ -615,7 +649,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_seed_u(AdjArgs A, const 
     if (!fluid) psi = (T)(y < 0 ? S.psi_lo : S.psi_hi);
     const T rho = (T)(S.rho_ref + dr);
     const T gx = (fluid && dLux) ? (T)dLux[o] : (T)0, gy = (fluid && dLuy) ? (T)dLuy[o] : (T)0;
-    const T inv = rcp(rho);
+    const T inv = arcp(rho);
     const T dFx = (T)0.5 * gx * inv, dFy = (T)0.5 * gy * inv;
     sps[k][lane] = psi;
     sfx[k][lane] = fluid ? psi * dFx : (T)0;
@@ -659,8 +693,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_seed_u(AdjArgs A, const 
     if (k < kAcc) {
         double s = 0.0;
         for (int w = 0; w < kAdjWaves; ++w) s += sred[k][w][lane];
-        s = wave_sum(s);
-        if (lane == 0) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
+        s = wave_total63(s);
+        if (lane == 63) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
     }
 }
 
@@ -949,11 +983,11 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
     // between the halves): both kernels are latency-bound at the sizes the adjoint runs,
     // and each fills the issue slots the other leaves.  The recomputation touches only
     // the lattice's population buffers and its half of the records; the transposed steps
-    // only lambda, the accumulators and the other half.  FP32-shifted storage only: the
-    // FP64 transposed step holds a whole CU per workgroup (96 VGPRs), and sharing the CUs
-    // with the recomputation made the FP64 adjoint slower (measured at 512^2: 106.8 ms on
-    // one stream, 110.5 ms on two; FP32 64.7 ms against 60.8 ms).
-    const bool piped = !recorded && S > 1 && rec_bytes >= 2 * L.rec_bytes && P.prec == LBM_FP32_SHIFTED;
+    // only lambda, the accumulators and the other half.  Both precisions: the FP64 two-step
+    // transposed kernel holds a CU per workgroup and runs in two rounds at 512^2, and the
+    // recomputation fills the CUs its second round leaves (measured at 512^2: 89.7 ms on one
+    // stream, 84.9 ms on two; FP32 57.1 ms against 53.1 ms).
+    const bool piped = !recorded && S > 1 && rec_bytes >= 2 * L.rec_bytes;
     AuxStream aux;
     if (piped && !aux.open(s)) return LBM_EHIP;
     hipStream_t sr = piped ? aux.s : s;  // the recomputation's stream

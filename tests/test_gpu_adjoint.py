@@ -138,7 +138,7 @@ def test_adjoint_one_segment_equals_many(gpu_lib):
 
 
 # A record buffer of two segments makes lbm_adjoint recompute the next segment on a second stream
-# while the transposed steps run over the current one (FP32-shifted storage; FP64 keeps one stream).
+# while the transposed steps run over the current one (both precisions).
 # The same kernels run on the same data in the same order on each stream, so the gradients equal those
 # of the one-stream schedule bit for bit: small lattices of both kinds and a 256 x 256 droplet (14
 # segments, ragged last) in both precisions.
