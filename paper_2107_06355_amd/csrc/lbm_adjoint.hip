@@ -492,6 +492,16 @@ __device__ __forceinline__ const AdjArgs& reloaded_args()
     return *(const AdjArgs*)p;
 }
 
+// the arguments for the first step's output phase: reloaded in FP32, where the kernel's scalar
+// registers would otherwise spill; FP64 has room for them and keeps them (measured at 512^2:
+// FP32 two-step launch 19.2 -> 17.7 us with the reload, FP64 transposed steps 4% slower)
+template <typename T>
+__device__ __forceinline__ const AdjArgs& first_output_args(const AdjArgs& A)
+{
+    if constexpr (sizeof(T) == 4) return reloaded_args();
+    else return A;
+}
+
 template <typename T, bool NT, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_adj2_blk(AdjArgs A)
 {
@@ -516,7 +526,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(
                            : (S.ny >= NW ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
     const bool own = k >= 3 && k < 3 + R && y < S.ny && lane >= 3 && lane < 3 + kAdj2W && xs < S.nx;
     const double acc_prev = (k < kAcc && lane == 63) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
-    const T iG = adj_coef<T>(A).inv_G;
     // what the first step leaves for the parameter sums of this node
     T a_psi = 0, a_dpsi = 0, a_dr = 0, a_vG = 0, a_sig = 0;
 
@@ -540,12 +549,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(
     T lam0 = 0;  // lambda^t_0 of this node
     if (k >= 1 && k <= NW - 2) {
         if (lane >= 1 && lane <= 62) {
-            T vG = (ftx * L.dftx + fty * L.dfty) * iG;
-            const T dpsi = L.dpsi + force_transpose<T, NW>(S, sfx, sfy, k, lane, y);
-            if (own) ghost_G<T>(A, y, L.dfty, vG);
+            const AdjArgs& B = first_output_args<T>(A);
+            T vG = (ftx * L.dftx + fty * L.dfty) * adj_coef<T>(B).inv_G;
+            const T dpsi = L.dpsi + force_transpose<T, NW>(B.S, sfx, sfy, k, lane, y);
+            if (own) ghost_G<T>(B, y, L.dfty, vG);
             // the loop-coefficient part waits until the end (knot_adjoint_of), so that no FP64
             // sums are live through the second step
-            const T drho_eos = psi_adjoint<T>(A, S.rho_ref + (double)dr, psi, dpsi, nullptr, vG, false);
+            const T drho_eos = psi_adjoint<T>(B, B.S.rho_ref + (double)dr, psi, dpsi, nullptr, vG, false);
             a_psi = psi;
             a_dpsi = dpsi;
             a_dr = dr;
