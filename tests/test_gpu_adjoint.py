@@ -19,8 +19,17 @@ NAMES = ("rho_max", "p_max", "rho_min", "p_min", "G", "sigma")
 
 def _case(kind):
     e, s = O.eos_build(O.make_eos(**SMOOTH))
-    # the wide lattices (at least 64 columns) take the kernels' single-wrap column indexing
-    if kind in ("droplet", "droplet_wide"):
+    # the wide lattices (at least 64 columns) take the kernels' single-wrap column indexing; the
+    # short ones (fewer rows than a transposed workgroup has waves) the remainder row indexing
+    if kind == "droplet_short":
+        nx, ny = 37, 7
+        rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=3, W=4)
+        extra = {}
+    elif kind == "walls_short":
+        nx, ny = 40, 9
+        rho0, _, _ = droplet_on_film(nx, ny, e.rho_v, e.rho_l, R=2, h=2, gap=1, V=0.0, W=4)
+        extra = dict(walls=True, rho_wall_lo=e.rho_l, rho_wall_hi=e.rho_v)
+    elif kind in ("droplet", "droplet_wide"):
         nx, ny = (37, 29) if kind == "droplet" else (70, 29)
         rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=8, W=4)
         extra = {}
@@ -347,7 +356,7 @@ def _on_oracle_eos(lbm, e):
     return el
 
 
-@pytest.mark.parametrize("kind", ["droplet", "walls", "droplet_wide", "walls_wide"])
+@pytest.mark.parametrize("kind", ["droplet", "walls", "droplet_wide", "walls_wide", "droplet_short", "walls_short"])
 @pytest.mark.parametrize("mode", ["recorded", "checkpointed"])
 @pytest.mark.parametrize("target", ["rho", "rho_u"])
 def test_adjoint_fp64_matches_complex_step(gpu_lib, kind, mode, target):
