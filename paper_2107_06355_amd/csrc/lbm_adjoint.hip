@@ -1051,8 +1051,10 @@ int lbm_adjoint_fields(lbm_ctx* c, const double* dL_drho_T, const double* dL_dux
     if (!hip_ok(hipMemcpyAsync(h.data(), acc, nacc * sizeof(double), hipMemcpyDeviceToHost, s), "gradient copy") ||
         !hip_ok(hipStreamSynchronize(s), "adjoint sync"))
         return LBM_EHIP;
+    // every workgroup slot of both grids (the one-step and the two-step kernel tile the
+    // lattice differently; slots a grid does not reach stay zero)
     double a[kAcc] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (size_t b = 0; b < (size_t)L.blocks; ++b)
+    for (size_t b = 0; b < nacc / kAcc; ++b)
         for (int k = 0; k < kAcc; ++k) a[k] += h[b * kAcc + k];
     // chain the loop coefficients (b1, a1^2), (b3, a3^2) back to the four knots
     double gk[4] = {0, 0, 0, 0};
