@@ -165,11 +165,11 @@ __global__ __launch_bounds__(256) void k_aa_step(StepArgs A, const T* psi)
             aa_scatter<T, ODD>(make_wview<T>(A.dst, A.plane), A, n.x, n.y, o, o0);
     }
     if (MODE == MODE_STEP_REDUCE || MODE == MODE_MACROS) {
-        // fixed-order sums: lanes by wave_sum, then the four waves in order
+        // fixed-order sums: lanes by wave_total, then the four waves in order
         __shared__ double sm[kAaRows][3];
-        const double m = wave_sum(acc.m), jx = wave_sum(acc.x), jy = wave_sum(acc.y);
+        const double m = wave_total(acc.m), jx = wave_total(acc.x), jy = wave_total(acc.y);
         const int w = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) {
+        if ((threadIdx.x & 63) == kTotalLane) {
             sm[w][0] = m;
             sm[w][1] = jx;
             sm[w][2] = jy;

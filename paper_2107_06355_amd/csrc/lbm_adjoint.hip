@@ -93,30 +93,6 @@ __device__ __forceinline__ double arcp(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
-// 32-bit DPP move of each half of a double; lanes without a source (or outside row_mask)
-// read 0
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_d(double v)
-{
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
-    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-// Sum of v over the 64 lanes, in lane 63, in a fixed order: a scan within each row of 16
-// lanes (row_shr 1, 2, 4, 8), then the row totals carried by row_bcast 15 and 31.
-__device__ __forceinline__ double wave_total63(double v)
-{
-    v += dpp_d<0x111, 0xf>(v);
-    v += dpp_d<0x112, 0xf>(v);
-    v += dpp_d<0x114, 0xf>(v);
-    v += dpp_d<0x118, 0xf>(v);
-    v += dpp_d<0x142, 0xa>(v);
-    v += dpp_d<0x143, 0xc>(v);
-    return v;
-}
-
 // node coordinates with periodic wrap in x and y (walls handled by the callers)
 __device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
 
@@ -415,8 +391,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
     const bool fluid = S.walls ? (y >= 0 && y < S.ny) : true;
     const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y))
                            : (S.ny >= 11 ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
-    // running sum of accumulator k of this workgroup, read early (updated at the end by lane 63 of wave k)
-    const double acc_prev = (k < kAcc && lane == 63) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
+    // running sum of accumulator k of this workgroup, read early (updated at the end by lane kTotalLane of wave k)
+    const double acc_prev = (k < kAcc && lane == kTotalLane) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
 
     T mu[9];
     pull_adjoint<T>(A, x, yw, mu);
@@ -459,8 +435,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_blk(AdjArgs A)
     if (k < kAcc) {
         double s = 0.0;
         for (int w = 0; w < kAdjWaves; ++w) s += sred[k][w][lane];
-        s = wave_total63(s);
-        if (lane == 63) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
+        s = wave_total(s);
+        if (lane == kTotalLane) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
     }
 }
 
@@ -525,7 +501,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(
     const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y))
                            : (S.ny >= NW ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
     const bool own = k >= 3 && k < 3 + R && y < S.ny && lane >= 3 && lane < 3 + kAdj2W && xs < S.nx;
-    const double acc_prev = (k < kAcc && lane == 63) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
+    const double acc_prev = (k < kAcc && lane == kTotalLane) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
     // what the first step leaves for the parameter sums of this node
     T a_psi = 0, a_dpsi = 0, a_dr = 0, a_vG = 0, a_sig = 0;
 
@@ -616,8 +592,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(
     if (k < kAcc) {
         double s = 0.0;
         for (int w = 0; w < R; ++w) s += red[k][w][lane];
-        s = wave_total63(s);
-        if (lane == 63) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
+        s = wave_total(s);
+        if (lane == kTotalLane) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
     }
 }
 
@@ -646,7 +622,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_seed_u(AdjArgs A, const 
     const int yw = S.walls ? (y < 0 ? 0 : (y >= S.ny ? S.ny - 1 : y))
                            : (S.ny >= 11 ? wrapx(y, S.ny) : ((y % S.ny) + S.ny) % S.ny);
     const size_t o = (size_t)yw * S.nx + x;
-    const double acc_prev = (k < kAcc && lane == 63) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
+    const double acc_prev = (k < kAcc && lane == kTotalLane) ? A.acc[(size_t)blockIdx.x * kAcc + k] : 0.0;
 
     // the final state at (x, yw): pulled populations, rho, j, psi; dL/dF~ = psi dL/dF, dL/dF = g / (2 rho)
     const View<T> V = make_view<T>(fT, S.plane);
@@ -703,8 +679,8 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_adj_seed_u(AdjArgs A, const 
     if (k < kAcc) {
         double s = 0.0;
         for (int w = 0; w < kAdjWaves; ++w) s += sred[k][w][lane];
-        s = wave_total63(s);
-        if (lane == 63) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
+        s = wave_total(s);
+        if (lane == kTotalLane) A.acc[(size_t)blockIdx.x * kAcc + k] = acc_prev + s;
     }
 }
 

@@ -358,9 +358,29 @@ __device__ __forceinline__ T node_psi(const StepArgs& A, double drho, bool check
     return node_psi<T>(A, A.eos, drho, check, dstep);
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+// 32-bit DPP move of each half of a double; lanes without a source (or outside the row mask
+// ROWS) read 0
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum of v over the 64 lanes of a wave (all active), valid in lane kTotalLane, in a fixed
+// order: a scan within each row of 16 lanes (row_shr 1, 2, 4, 8), then the row totals
+// carried by row_bcast 15 and 31.  Six DPP steps and no LDS round trip.
+constexpr int kTotalLane = 63;
+__device__ __forceinline__ double wave_total(double v)
+{
+    v += dpp_d<0x111, 0xf>(v);
+    v += dpp_d<0x112, 0xf>(v);
+    v += dpp_d<0x114, 0xf>(v);
+    v += dpp_d<0x118, 0xf>(v);
+    v += dpp_d<0x142, 0xa>(v);
+    v += dpp_d<0x143, 0xc>(v);
     return v;
 }
 
@@ -868,8 +888,8 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
     if (MODE == MODE_STEP_REDUCE) {
         // FP64 mass and momentum of step t+1 (each node once: the tile's own), one partial per
         // (tile, wave) in tile order
-        const double m = wave_sum(acc.m), jx = wave_sum(acc.x), jy = wave_sum(acc.y);
-        if (l == 0) {
+        const double m = wave_total(acc.m), jx = wave_total(acc.x), jy = wave_total(acc.y);
+        if (l == kTotalLane) {
             const size_t w = ((size_t)band * ((A.nx + k2Cols - 1) / k2Cols) + strip) * k2WavesOf<T> + k;
             A.partials[3 * w + 0] = m;
             A.partials[3 * w + 1] = jx;
@@ -1047,8 +1067,8 @@ __device__ __forceinline__ void step2_tile_rows(const StepArgs& A, int strip, in
     if (MODE == MODE_STEP_REDUCE) {
         // FP64 mass and momentum of step t+1 (each node once: the tile's own), one partial per
         // (tile, wave) in tile order
-        const double m = wave_sum(acc.m), jx = wave_sum(acc.x), jy = wave_sum(acc.y);
-        if (l == 0) {
+        const double m = wave_total(acc.m), jx = wave_total(acc.x), jy = wave_total(acc.y);
+        if (l == kTotalLane) {
             const size_t w = ((size_t)band * ((A.nx + k2Cols - 1) / k2Cols) + strip) * NW + k;
             A.partials[3 * w + 0] = m;
             A.partials[3 * w + 1] = jx;

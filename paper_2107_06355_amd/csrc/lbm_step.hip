@@ -126,10 +126,10 @@ __global__ __launch_bounds__(256) LBM_OCCUPANCY_HINT
     }
     }
     if (MODE == MODE_STEP_REDUCE || MODE == MODE_MACROS) {
-        acc.m = wave_sum(acc.m);
-        acc.x = wave_sum(acc.x);
-        acc.y = wave_sum(acc.y);
-        if (L.lane == 0) {
+        acc.m = wave_total(acc.m);
+        acc.x = wave_total(acc.x);
+        acc.y = wave_total(acc.y);
+        if (L.lane == kTotalLane) {
             A.partials[3 * w + 0] = acc.m;
             A.partials[3 * w + 1] = acc.x;
             A.partials[3 * w + 2] = acc.y;
@@ -197,10 +197,10 @@ __global__ __launch_bounds__(64 * LBM_BLK_WAVES) void k_step_blk(StepArgs A)
         update_node<T, MODE>(A, L, r, R, dr, ps, Ftx, Fty, acc);
     }
     if (MODE == MODE_STEP_REDUCE || MODE == MODE_MACROS) {
-        acc.m = wave_sum(acc.m);
-        acc.x = wave_sum(acc.x);
-        acc.y = wave_sum(acc.y);
-        if (L.lane == 0) {
+        acc.m = wave_total(acc.m);
+        acc.x = wave_total(acc.x);
+        acc.y = wave_total(acc.y);
+        if (L.lane == kTotalLane) {
             const int wv = logical * kBlkWaves + k;
             A.partials[3 * wv + 0] = acc.m;
             A.partials[3 * wv + 1] = acc.x;
@@ -272,6 +272,41 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const double* partials, i
         a2 += partials[3 * i + 2];
     }
     block_sum3(a0, a1, a2, blocks + 3 * blockIdx.x);
+}
+
+// Up to kRedOneMax partials (the impact lattice's 27,648 among them) in one workgroup and one
+// launch: each thread sums its strided share in order, each wave its 64 lanes (wave_total),
+// and the first three threads the 16 wave totals in order.  The order depends only on n.
+// One launch instead of two saves the second launch's latency, which is most of what a
+// reduction of this size costs; past this size the one workgroup's loads would take longer.
+constexpr int kRedOneMax = 32768;
+__global__ __launch_bounds__(1024) void k_reduce_one(const double* partials, int n, double* out, long long step,
+                                                     int with_step)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int i = (int)threadIdx.x; i < n; i += 1024) {
+        a0 += partials[3 * i + 0];
+        a1 += partials[3 * i + 1];
+        a2 += partials[3 * i + 2];
+    }
+    a0 = wave_total(a0);
+    a1 = wave_total(a1);
+    a2 = wave_total(a2);
+    __shared__ double sh[3][16];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == kTotalLane) {
+        sh[0][w] = a0;
+        sh[1][w] = a1;
+        sh[2][w] = a2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double r = 0.0;
+        for (int k = 0; k < 16; ++k) r += sh[threadIdx.x][k];
+        const int o = with_step ? 1 : 0;
+        if (threadIdx.x == 0 && with_step) out[0] = (double)step;
+        out[o + threadIdx.x] = r;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_reduce_final(const double* blocks, int nblocks, double* out, long long step,
@@ -492,6 +527,10 @@ bool launch_reduce(lbm_ctx* c, double* out, long long step, int with_step, hipSt
 // the same over the first n partial slots
 bool launch_reduce_n(lbm_ctx* c, int n, double* out, long long step, int with_step, hipStream_t s)
 {
+    if (n <= kRedOneMax) {
+        hipLaunchKernelGGL(k_reduce_one, dim3(1), dim3(1024), 0, s, (const double*)c->partials, n, out, step, with_step);
+        return hip_ok(hipGetLastError(), "reduction launch");
+    }
     int nb = (n + 1023) / 1024;
     nb = nb < 1 ? 1 : (nb > kRedBlocks ? kRedBlocks : nb);
     const int chunk = (n + nb - 1) / nb;
