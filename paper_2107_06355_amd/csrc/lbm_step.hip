@@ -274,17 +274,34 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const double* partials, i
     block_sum3(a0, a1, a2, blocks + 3 * blockIdx.x);
 }
 
-// Up to kRedOneMax partials (the impact lattice's 27,648 among them) in one workgroup and one
+// Up to kRedOneMax partials (the 512^2 droplet's 7,488 among them) in one workgroup and one
 // launch: each thread sums its strided share in order, each wave its 64 lanes (wave_total),
 // and the first three threads the 16 wave totals in order.  The order depends only on n.
-// One launch instead of two saves the second launch's latency, which is most of what a
-// reduction of this size costs; past this size the one workgroup's loads would take longer.
-constexpr int kRedOneMax = 32768;
+// One launch instead of two saves the second launch's latency, which is most of what a small
+// reduction costs; one CU's loads set the limit (measured on MI355X: 7,488 partials 4.2 us
+// against 7.3 us for the two-pass pair, but 27,648 partials 10.8 us against 9.5 us).
+constexpr int kRedOneMax = 16384;
 __global__ __launch_bounds__(1024) void k_reduce_one(const double* partials, int n, double* out, long long step,
                                                      int with_step)
 {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int i = (int)threadIdx.x; i < n; i += 1024) {
+    int i = (int)threadIdx.x;
+    // eight of the thread's partials loaded before any is added, so that their loads overlap;
+    // the additions keep the order of i
+    for (; i + 7 * 1024 < n; i += 8 * 1024) {
+        double v[8][3];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[u][c] = partials[3 * (i + u * 1024) + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a0 += v[u][0];
+            a1 += v[u][1];
+            a2 += v[u][2];
+        }
+    }
+    for (; i < n; i += 1024) {
         a0 += partials[3 * i + 0];
         a1 += partials[3 * i + 1];
         a2 += partials[3 * i + 2];
