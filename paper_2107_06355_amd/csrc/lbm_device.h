@@ -753,6 +753,7 @@ struct Step2Lds {
     T sps[k2WavesOf<T>][64];            // psi of the tile grown by 3 (step t), then by 1 (step t+1)
     T smv[8][k2WavesOf<T> - 2][64];     // post-collision moving populations of step t (tile grown by 2)
     double sg0[k2WavesOf<T> - 2][64];   // and their FP64 rest population
+    double sred[k2WavesOf<T>][3];       // a reducing launch's wave totals (mass, momentum)
 };
 
 // Advance output tile (strip, band) of lattice A by two steps (see above).
@@ -886,14 +887,19 @@ __device__ __forceinline__ void step2_tile(const StepArgs& A, int strip, int ban
         }
     }
     if (MODE == MODE_STEP_REDUCE) {
-        // FP64 mass and momentum of step t+1 (each node once: the tile's own), one partial per
-        // (tile, wave) in tile order
+        // FP64 mass and momentum of step t+1 (each node once: the tile's own): each wave's
+        // total, then the waves in order, one partial per tile in tile order
         const double m = wave_total(acc.m), jx = wave_total(acc.x), jy = wave_total(acc.y);
         if (l == kTotalLane) {
-            const size_t w = ((size_t)band * ((A.nx + k2Cols - 1) / k2Cols) + strip) * k2WavesOf<T> + k;
-            A.partials[3 * w + 0] = m;
-            A.partials[3 * w + 1] = jx;
-            A.partials[3 * w + 2] = jy;
+            S.sred[k][0] = m;
+            S.sred[k][1] = jx;
+            S.sred[k][2] = jy;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            double r = 0.0;
+            for (int w = 0; w < k2WavesOf<T>; ++w) r += S.sred[w][threadIdx.x];
+            A.partials[3 * ((size_t)band * ((A.nx + k2Cols - 1) / k2Cols) + strip) + threadIdx.x] = r;
         }
     }
 }
@@ -905,6 +911,7 @@ struct Step2RowsLds {
     T sps[NR][64];                       // psi of the tile grown by 3 (step t), then by 1 (step t+1)
     T smv[8][NR - 2][64];                // post-collision moving populations of step t (tile grown by 2)
     double sg0[NR - 2][64];              // and their FP64 rest population
+    double sred[NW][3];                  // a reducing launch's wave totals (mass, momentum)
 };
 
 // step2_tile with RPW rows per wave: a workgroup of NW waves holds the NW * RPW rows of the
@@ -1065,14 +1072,19 @@ __device__ __forceinline__ void step2_tile_rows(const StepArgs& A, int strip, in
         }
     }
     if (MODE == MODE_STEP_REDUCE) {
-        // FP64 mass and momentum of step t+1 (each node once: the tile's own), one partial per
-        // (tile, wave) in tile order
+        // FP64 mass and momentum of step t+1 (each node once: the tile's own): each wave's
+        // total, then the waves in order, one partial per tile in tile order
         const double m = wave_total(acc.m), jx = wave_total(acc.x), jy = wave_total(acc.y);
         if (l == kTotalLane) {
-            const size_t w = ((size_t)band * ((A.nx + k2Cols - 1) / k2Cols) + strip) * NW + k;
-            A.partials[3 * w + 0] = m;
-            A.partials[3 * w + 1] = jx;
-            A.partials[3 * w + 2] = jy;
+            S.sred[k][0] = m;
+            S.sred[k][1] = jx;
+            S.sred[k][2] = jy;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            double r = 0.0;
+            for (int w = 0; w < NW; ++w) r += S.sred[w][threadIdx.x];
+            A.partials[3 * ((size_t)band * ((A.nx + k2Cols - 1) / k2Cols) + strip) + threadIdx.x] = r;
         }
     }
 }

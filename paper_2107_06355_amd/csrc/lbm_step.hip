@@ -432,13 +432,18 @@ int decompose(const lbm_params& p, int* strips, int* seg_h, int* nseg, int* blk)
     return *strips * *nseg;
 }
 
-// per-wave FP64 partial slots the workspace holds: the one-step layout, or one per (tile,
-// wave) of the two-step kernel when it may reduce
-// waves of one two-step launch: (tiles) x (waves per tile), one partial slot each
-// per-(tile, wave) partials of a reducing two-step launch with tile shape sh
+// FP64 partial slots the workspace holds: the one-step layout's one per wave, or, when the
+// two-step kernel may reduce, one per (tile, wave) of its launch (its reducing launch writes
+// one per tile, its waves summed in order; the slots keep room for a partial per wave)
 int two_step_waves(const lbm_params& p, const TwoStepShape& sh)
 {
     return ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + sh.rows - 1) / sh.rows) * sh.waves;
+}
+
+// partials of a reducing two-step launch: one per tile (its waves summed in order)
+int two_step_tiles(const lbm_params& p, const TwoStepShape& sh)
+{
+    return ((p.nx + k2Cols - 1) / k2Cols) * ((p.ny + sh.rows - 1) / sh.rows);
 }
 
 // the most any candidate shape of p needs (the workspace holds them)
@@ -1048,7 +1053,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps, void* stream)
                 return LBM_EHIP;
             if (red2) {
                 double* row = c->hist + 4 * (c->hist_count % kHistCap);
-                if (!launch_reduce_n(c, two_step_waves(c->P, c->shape), row, (long long)c->step + 1, 1, s))
+                if (!launch_reduce_n(c, two_step_tiles(c->P, c->shape), row, (long long)c->step + 1, 1, s))
                     return LBM_EHIP;
                 c->hist_count++;
             }

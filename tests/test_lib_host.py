@@ -116,9 +116,9 @@ def test_batch_layout_offsets():
 
 
 def test_workspace_holds_the_two_step_partials():
-    """A reducing step that ends a two-step launch leaves one FP64 partial triple per (tile, wave): the
-    workspace lbm_layout reports holds them, beside the error word, the per-block sums and the history
-    ring, whichever decomposition has more waves."""
+    """A reducing step that ends a two-step launch leaves one FP64 partial triple per tile (its waves
+    summed in order); the workspace lbm_layout reports keeps a slot per (tile, wave), beside the error
+    word, the per-block sums and the history ring, whichever decomposition has more waves."""
     e, s = lbm.eos_build(lbm.make_eos(Tr=0.7))
     for nx, ny, prec, waves, rows in ((512, 512, lbm.FP32_SHIFTED, 16, 10), (512, 512, lbm.FP64, 8, 10),
                                       (130, 37, lbm.FP64, 8, 10), (7, 3, lbm.FP32_SHIFTED, 16, 10),
