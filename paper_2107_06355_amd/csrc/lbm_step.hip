@@ -274,8 +274,9 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const double* partials, i
     block_sum3(a0, a1, a2, blocks + 3 * blockIdx.x);
 }
 
-// Up to kRedOneMax partials (the 512^2 droplet's 7,488 among them) in one workgroup and one
-// launch: each thread sums its strided share in order, each wave its 64 lanes (wave_total),
+// Up to kRedOneMax partials (a reducing two-step launch leaves one per tile: 468 at 512^2,
+// 2,304 on the 2048 x 1024 impact) in one workgroup and one launch: each thread sums its
+// strided share in order, each wave its 64 lanes (wave_total),
 // and the first three threads the 16 wave totals in order.  The order depends only on n.
 // One launch instead of two saves the second launch's latency, which is most of what a small
 // reduction costs; one CU's loads set the limit (measured on MI355X: 7,488 partials 4.2 us
