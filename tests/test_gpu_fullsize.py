@@ -287,3 +287,34 @@ def test_timed_tile_shape_matches_the_explicit_one(gpu_lib, prec_name):
     assert np.array_equal(res[-1][0], res[None][0])
     # same tiles, same order of the partial sums: the reductions agree bit for bit as well
     assert np.array_equal(res[-1][1], res[None][1])
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
+def test_two_step_reductions_past_one_launch_match_one_step(gpu_lib, prec_name):
+    """A reducing two-step launch leaves one FP64 partial per tile; up to 16384 of them are summed in
+    one launch, more in two passes.  On an 8192 x 2304 lattice (18,176 FP32 tiles of 58 x 18, 32,802
+    FP64 tiles of 58 x 10: the two-pass path) the history rows equal those of one-step launches (per-wave
+    partials, another summation order) to the bounds of the small-lattice test."""
+    lbm = gpu_lib
+    e, s = lbm.eos_build(lbm.make_eos(**EOS_KW))
+    nx, ny = 8192, 2304
+    rho0 = droplet_density(nx, ny, e.rho_v, e.rho_l, R=600, W=20)
+    prec = lbm.FP64 if prec_name == "fp64" else lbm.FP32_SHIFTED
+    h = []
+    for variant in (lbm.VARIANT_BLOCK2, lbm.VARIANT_BLOCK):
+        P = lbm.make_params(nx, ny, e, sigma=s, tau=TAU, prec=prec, reduce_every=2, kernel_variant=variant)
+        L = lbm.Lattice(P, rho0, device="cuda:0")
+        if variant == lbm.VARIANT_BLOCK2:
+            rows, _ = L.tile_shape()
+            assert -(-nx // 58) * -(-ny // rows) > 16384, rows
+        L.step(5)
+        L.check()
+        h.append(L.history())
+        L.close()
+    assert h[0].shape == h[1].shape == (3, 4)
+    np.testing.assert_array_equal(h[0][:, 0], [0, 2, 4])
+    np.testing.assert_array_equal(h[1][:, 0], [0, 2, 4])
+    m = h[1][0, 1]
+    tol = 1e-13 if prec == lbm.FP64 else 1e-9
+    assert np.abs(h[0][:, 1] - h[1][:, 1]).max() <= tol * m, h[0][:, 1] - h[1][:, 1]
+    assert np.abs(h[0][:, 2:] - h[1][:, 2:]).max() <= (1e-12 if prec == lbm.FP64 else 1e-8) * m
